@@ -1,0 +1,213 @@
+"""Plain FP64 CPU oracle for the D2Q9 BGK lattice-Boltzmann step (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package.  The GPU library shares no code with it:
+the oracle is plain C (``lbm_oracle.c``, compiled with gcc) plus an exact-rational
+brute force in pure Python (``exact.py``).
+
+Array conventions (numpy, C order):
+  mask   uint8  [ny, nx]      0 fluid, 1 solid
+  f      float64 [9, ny, nx]  canonical pre-collision populations f_i(x, t), the
+                              left-hand side of the LB update (Sec. 2.2, Eq. 3);
+                              solid slots are 0
+  alpha  float64 [ny, nx]     Brinkman drag coefficient (None = 0)
+
+Pins (tests/test_oracle_*.py) check it against what the paper and the mathematics
+fix: closed-form moments of the equilibrium (Eq. 6) and of the forcing term,
+conservation of mass and momentum, the equilibrium fixed point, lattice symmetry,
+the exact steady and start-up Poiseuille profiles, the Taylor-Green decay rate
+(viscosity from Eq. 5), the Brinkman momentum recurrence, exact-rational brute force
+on 4x4 lattices, and finite differences of the forward map for the gradient.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        L.oracle_constants.argtypes = [_ip, _ip, _dp, _ip]
+        L.oracle_equilibrium.argtypes = [ctypes.c_double] * 3 + [_dp]
+        L.oracle_guo_source.argtypes = [ctypes.c_double] * 4 + [_dp]
+        L.oracle_node_velocity.argtypes = [_dp] + [ctypes.c_double] * 3 + [_dp]
+        L.oracle_collide.argtypes = [_dp] + [ctypes.c_double] * 4 + [_dp]
+        L.oracle_collide_jacobian.argtypes = [_dp] + [ctypes.c_double] * 4 + [_dp, _dp, _dp]
+        L.oracle_init.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, _dp, _dp, _dp]
+        L.oracle_init.restype = ctypes.c_int
+        L.oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, _dp, ctypes.c_long, ctypes.c_int]
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_macroscopic.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
+                                         ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.oracle_macroscopic.restype = ctypes.c_int
+        L.oracle_objective_outlet_ux.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp,
+                                                 ctypes.c_double, ctypes.c_double, _dp,
+                                                 ctypes.c_int, _dp]
+        L.oracle_objective_outlet_ux.restype = ctypes.c_int
+        L.oracle_outlet_ux_gradient.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                _dp, ctypes.c_long, ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_outlet_ux_gradient.restype = ctypes.c_int
+        L.oracle_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _mask(m):
+    m = np.ascontiguousarray(m, dtype=np.uint8)
+    if m.ndim != 2:
+        raise ValueError("mask must be [ny, nx]")
+    return m
+
+
+def constants():
+    """(cx, cy, w, opp) as the oracle uses them."""
+    cx = (ctypes.c_int * 9)()
+    cy = (ctypes.c_int * 9)()
+    w = (ctypes.c_double * 9)()
+    opp = (ctypes.c_int * 9)()
+    lib().oracle_constants(cx, cy, w, opp)
+    return (np.array(cx[:]), np.array(cy[:]), np.array(w[:]), np.array(opp[:]))
+
+
+def equilibrium(rho, ux, uy):
+    out = np.zeros(9)
+    lib().oracle_equilibrium(rho, ux, uy, _d(out))
+    return out
+
+
+def guo_source(ux, uy, Fx, Fy):
+    out = np.zeros(9)
+    lib().oracle_guo_source(ux, uy, Fx, Fy, _d(out))
+    return out
+
+
+def node_velocity(f, alpha=0.0, g=(0.0, 0.0)):
+    f = _f64(f)
+    out = np.zeros(3)
+    lib().oracle_node_velocity(_d(f), alpha, g[0], g[1], _d(out))
+    return out
+
+
+def collide(f, omega, alpha=0.0, g=(0.0, 0.0)):
+    f = _f64(f)
+    out = np.zeros(9)
+    lib().oracle_collide(_d(f), alpha, g[0], g[1], omega, _d(out))
+    return out
+
+
+def collide_jacobian(f, omega, alpha=0.0, g=(0.0, 0.0)):
+    """(d fstar/d f [9,9], d fstar/d alpha [9], d fstar/d g [9,2])."""
+    f = _f64(f)
+    dfdf = np.zeros((9, 9))
+    dfda = np.zeros(9)
+    dfdg = np.zeros((9, 2))
+    lib().oracle_collide_jacobian(_d(f), alpha, g[0], g[1], omega, _d(dfdf), _d(dfda), _d(dfdg))
+    return dfdf, dfda, dfdg
+
+
+def init(mask, rho0=None, ux0=None, uy0=None):
+    m = _mask(mask)
+    ny, nx = m.shape
+    f = np.zeros((9, ny, nx))
+    rho0, ux0, uy0 = _f64(rho0), _f64(ux0), _f64(uy0)
+    rc = lib().oracle_init(nx, ny, m.ctypes.data_as(_u8p), _d(rho0), _d(ux0), _d(uy0), _d(f))
+    if rc:
+        raise ValueError("oracle_init failed")
+    return f
+
+
+def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0):
+    """Advance a copy of f by `steps` time steps; returns the new array."""
+    m = _mask(mask)
+    ny, nx = m.shape
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    if f.shape != (9, ny, nx):
+        raise ValueError("f must be [9, ny, nx]")
+    alpha = _f64(alpha)
+    rc = lib().oracle_run(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, g[0], g[1], _d(alpha),
+                          int(steps), int(threads))
+    if rc:
+        raise ValueError(f"oracle_run failed ({rc})")
+    return f
+
+
+def macroscopic(mask, f, g=(0.0, 0.0), alpha=None):
+    m = _mask(mask)
+    ny, nx = m.shape
+    f = _f64(f)
+    rho, ux, uy = (np.zeros((ny, nx)) for _ in range(3))
+    alpha = _f64(alpha)
+    lib().oracle_macroscopic(nx, ny, m.ctypes.data_as(_u8p), _d(f), g[0], g[1], _d(alpha),
+                             _d(rho), _d(ux), _d(uy))
+    return rho, ux, uy
+
+
+def objective_outlet_ux(mask, f, x_out, g=(0.0, 0.0), alpha=None):
+    m = _mask(mask)
+    ny, nx = m.shape
+    f = _f64(f)
+    J = ctypes.c_double()
+    rc = lib().oracle_objective_outlet_ux(nx, ny, m.ctypes.data_as(_u8p), _d(f), g[0], g[1],
+                                          _d(_f64(alpha)), x_out, ctypes.byref(J))
+    if rc:
+        raise ValueError("no fluid node in the outlet column")
+    return J.value
+
+
+def outlet_ux_gradient(mask, f0, tau, steps, x_out, g=(0.0, 0.0), alpha=None):
+    """(J, dJ/dalpha [ny, nx], dJ/dg [2]) by reverse mode over `steps` steps from f0."""
+    m = _mask(mask)
+    ny, nx = m.shape
+    f0 = _f64(f0)
+    ga = np.zeros((ny, nx))
+    gg = np.zeros(2)
+    J = ctypes.c_double()
+    rc = lib().oracle_outlet_ux_gradient(nx, ny, m.ctypes.data_as(_u8p), _d(f0), tau, g[0], g[1],
+                                         _d(_f64(alpha)), int(steps), int(x_out), ctypes.byref(J),
+                                         _d(ga), _d(gg))
+    if rc:
+        raise ValueError(f"oracle_outlet_ux_gradient failed ({rc})")
+    return J.value, ga, gg
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())

@@ -1,0 +1,168 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module holds geometry masks and initial / parameter fields only; it contains none
+of the lattice-Boltzmann arithmetic, and neither the GPU library nor the oracle imports
+the other through it.  Every generator is deterministic for a given seed.
+
+Workloads (the paper measures on synthetic geometries of its own; these stand in):
+  * channel: solid rows y = 0 and y = ny - 1, periodic in x (channel flow, Sec. 4.1);
+  * Taylor-Green vortex: fully periodic, all fluid (stands in for the dense-geometry
+    timing of Sec. 4.3, which used an all-fluid cavity: same traffic per node);
+  * porous medium: random solid discs on a square domain with walls at y = 0 and
+    y = ny - 1 (the sparse geometries of Sec. 4.3, built from circles of random radius);
+  * Brinkman field: a smooth random drag-coefficient field in [0, 1].
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def channel_mask(nx: int, ny: int) -> np.ndarray:
+    """uint8 [ny, nx]: 1 on rows 0 and ny-1, 0 elsewhere."""
+    m = np.zeros((ny, nx), dtype=np.uint8)
+    m[0, :] = 1
+    m[ny - 1, :] = 1
+    return m
+
+
+def all_fluid(nx: int, ny: int) -> np.ndarray:
+    return np.zeros((ny, nx), dtype=np.uint8)
+
+
+def taylor_green(n: int, u0: float = 0.01, ny: int | None = None):
+    """Decaying Taylor-Green vortex on a periodic n x n lattice (node indices x, y),
+    k = 2 pi / n:  u_x = -u0 cos(k x) sin(k y),  u_y = u0 sin(k x) cos(k y),
+    rho = 1 - (3 u0^2 / 4) (cos 2kx + cos 2ky)  (pressure p = rho / 3).
+    Returns (rho, ux, uy) as float64 [n, n]."""
+    ny = n if ny is None else ny
+    if ny != n:
+        raise ValueError("the Taylor-Green initial field is defined on square lattices here")
+    k = 2.0 * math.pi / n
+    x = np.arange(n, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    ux = -u0 * np.cos(k * x) * np.sin(k * y)
+    uy = u0 * np.sin(k * x) * np.cos(k * y)
+    rho = 1.0 - 0.75 * u0 * u0 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    return (np.ascontiguousarray(rho), np.ascontiguousarray(ux), np.ascontiguousarray(uy))
+
+
+def random_fields(nx: int, ny: int, seed: int, rho_spread: float = 0.05, u_amp: float = 0.05):
+    """Random smooth-free fields: rho in [1-spread, 1+spread], |u_a| <= u_amp."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + rho_spread * (2.0 * rng.random((ny, nx)) - 1.0)
+    ux = u_amp * (2.0 * rng.random((ny, nx)) - 1.0)
+    uy = u_amp * (2.0 * rng.random((ny, nx)) - 1.0)
+    return rho, ux, uy
+
+
+def random_mask(nx: int, ny: int, seed: int, solid_fraction: float = 0.2,
+                walls: bool = False) -> np.ndarray:
+    """Independent random solid nodes (a harsh bounce-back test geometry)."""
+    rng = np.random.default_rng(seed)
+    m = (rng.random((ny, nx)) < solid_fraction).astype(np.uint8)
+    if walls:
+        m[0, :] = 1
+        m[ny - 1, :] = 1
+    if not (m == 0).any():
+        m[ny // 2, nx // 2] = 0
+    return m
+
+
+def porous_discs(n: int, phi: float, seed: int | None = None, rmin: int = 8, rmax: int = 64,
+                 jam_limit: int = 5000, ny: int | None = None):
+    """Porous medium of random solid discs with fluid fraction close to `phi`.
+
+    Square n x ny domain (ny defaults to n); solid rows y = 0 and y = ny - 1; periodic in x.
+    Radii are uniform integers in [rmin, rmax]; centres uniform in [0, n) x [1, ny - 1).
+    Node (x, y) is solid if dx^2 + dy^2 <= r^2 (dx periodic in x, dy not wrapped).
+    Discs are placed without overlap (centre distance >= r1 + r2 + 1) until the solid
+    fraction reaches 1 - phi; after `jam_limit` consecutive rejected candidates, overlap
+    is allowed (random non-overlapping placement jams well below 80 % coverage).
+
+    Returns (mask uint8 [ny, n], info dict with the achieved fluid fraction, the number of
+    discs and whether overlap had to be allowed)."""
+    ny = n if ny is None else ny
+    if seed is None:
+        seed = 1000 + int(round(100 * phi))
+    rng = np.random.default_rng(seed)
+    m = np.zeros((ny, n), dtype=np.uint8)
+    m[0, :] = 1
+    m[ny - 1, :] = 1
+    target_solid = int(math.ceil((1.0 - phi) * n * ny))
+    solid = int(m.sum())
+    # clear[y, x] = min over placed discs j of (|(x, y) - c_j| - r_j), kept exactly where it
+    # can still reject a candidate (below rmax + 1); a candidate (c, r) is free of overlap
+    # iff clear[c] >= r + 1, which is the pairwise rule |c - c_j| >= r + r_j + 1.
+    clear = np.full((ny, n), np.inf)
+    k = 0
+    rejects = 0
+    overlap = False
+    batch = 4096
+    while solid < target_solid:
+        rs = rng.integers(rmin, rmax + 1, size=batch)
+        cxs = rng.integers(0, n, size=batch)
+        cys = rng.integers(1, ny - 1, size=batch)
+        j = 0
+        while j < batch and solid < target_solid:
+            if not overlap:
+                ok = clear[cys[j:], cxs[j:]] >= rs[j:] + 1
+                idx = np.flatnonzero(ok)
+                first = j + int(idx[0]) if idx.size else batch
+                gap = first - j
+                if rejects + gap >= jam_limit:
+                    # jammed: the candidate after the jam_limit-th consecutive rejection on
+                    # is accepted with overlap allowed
+                    j = j + (jam_limit - rejects)
+                    rejects = 0
+                    overlap = True
+                    continue
+                rejects += gap
+                if first >= batch:
+                    break
+                j = first
+            r, cx, cy = int(rs[j]), int(cxs[j]), int(cys[j])
+            j += 1
+            rejects = 0
+            k += 1
+            y0, y1 = max(cy - r, 0), min(cy + r, ny - 1)
+            ys = np.arange(y0, y1 + 1)[:, None]
+            xs = np.arange(cx - r, cx + r + 1)[None, :]
+            inside = (xs - cx) ** 2 + (ys - cy) ** 2 <= r * r
+            cols = np.mod(xs[0], n)
+            block = m[y0:y1 + 1][:, cols]
+            solid += int((inside & (block == 0)).sum())
+            block[inside] = 1
+            m[y0:y1 + 1, cols] = block
+            if not overlap:
+                reach = r + rmax + 1
+                wy0, wy1 = max(cy - reach, 0), min(cy + reach, ny - 1)
+                wys = np.arange(wy0, wy1 + 1)[:, None]
+                wxs = np.arange(cx - reach, cx + reach + 1)[None, :]
+                dist = np.sqrt(((wxs - cx) ** 2 + (wys - cy) ** 2).astype(np.float64)) - r
+                wcols = np.mod(wxs[0], n)
+                win = clear[wy0:wy1 + 1][:, wcols]
+                clear[wy0:wy1 + 1, wcols] = np.minimum(win, dist)
+    info = {
+        "phi_target": phi,
+        "phi_achieved": float((m == 0).sum()) / (n * ny),
+        "discs": k,
+        "overlap_allowed": overlap,
+        "seed": seed,
+    }
+    return m, info
+
+
+def brinkman_alpha(nx: int, ny: int, seed: int = 7, sigma: float = 8.0) -> np.ndarray:
+    """Smooth random drag-coefficient field in [0, 1]: white noise (seeded) filtered by a
+    Gaussian of width `sigma` nodes (periodic, by FFT), standardised to s, then
+    alpha = (1 + tanh(2 (s - 1))) / 2.  Mostly close to 0 with blobs close to 1."""
+    rng = np.random.default_rng(seed)
+    noise = rng.standard_normal((ny, nx))
+    ky = np.fft.fftfreq(ny)[:, None]
+    kx = np.fft.fftfreq(nx)[None, :]
+    filt = np.exp(-2.0 * (math.pi ** 2) * (sigma ** 2) * (kx ** 2 + ky ** 2))
+    s = np.real(np.fft.ifft2(np.fft.fft2(noise) * filt))
+    s = (s - s.mean()) / (s.std() + 1e-300)
+    return np.ascontiguousarray(0.5 * (1.0 + np.tanh(2.0 * (s - 1.0))))
