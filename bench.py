@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D2Q9 stream-and-collide step on one MI355X.
+
+Default workload: decaying Taylor-Green vortex on a fully periodic 4096 x 4096 lattice
+(u0 = 0.01, wavenumber 2 pi / N, tau = 0.6), FP64 populations, dense A-B layout; W
+untimed warm-up steps, then K timed steps bracketed by device synchronisation (the
+paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on stdout:
+
+  value     = GLUPS = fluid nodes * K / time / 1e9 of the whole job (one GPU);
+  roofline  = algorithmic bytes per step kernel ((18 * pop_bytes + 1) per fluid node)
+              / average kernel duration from HIP events on the stream the kernels run
+              on, against the MI355X HBM peak (8 TB/s);
+  cpu_baseline = the FP64 CPU oracle on the host cores, a bounded number of steps of
+              the same 4096^2 workload;
+  variants  = the same measurement for the other storage types and the AA layout
+              (and, with --suite full, the porous / sparse layouts and the adjoint).
+
+Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 100] [--suite default|full]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD public specification
+METRIC = "GLUPS & % HBM peak (dense/sparse D2Q9, fp64/fp32/16b); adjoint step cost vs fwd"
+POP_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+PAPER_CONTEXT = {
+    "hardware": "GTX Titan Xp (547.68 GB/s), Taichi dense layout, lid-driven cavity",
+    "fp64_dense_max_glups": 2.65, "fp64_dense_max_U_B": 0.696,
+    "fp32_dense_max_glups": 5.37, "fp32_dense_max_U_B": 0.705,
+    "source": "Table 2",
+}
+
+
+def log(msg):
+    sys.stderr.write(msg + "\n")
+    sys.stderr.flush()
+
+
+def algorithmic_bytes_per_node(dtype, drag=False):
+    """18 populations moved (read + write) plus the node-type byte (+4 B drag field)."""
+    return 18 * POP_BYTES[dtype] + 1 + (4 if drag else 0)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2108_13241_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    rec = data.get(kernel_key)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_steps(lat, steps, warmup):
+    """(seconds for `steps` steps, per-step ms) with HIP events on the lattice's stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    lat.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return ms / 1e3, ms / max(steps, 1)
+
+
+def measure_dense(lbm, n, dtype, layout, steps, warmup, fields):
+    import synthetic
+    m = synthetic.all_fluid(n, n)
+    lat = lbm.Lattice(m, 0.6, dtype=dtype, layout=layout)
+    lat.init_equilibrium(*fields)
+    secs, ms = time_steps(lat, steps, warmup)
+    info = lat.info()
+    mass_ok = None
+    lat.close()
+    nf = info["n_fluid"]
+    glups = nf * steps / secs / 1e9
+    bpn = algorithmic_bytes_per_node(dtype)
+    return {"workload": f"taylor-green {n}^2", "dtype": dtype, "layout": layout,
+            "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
+            "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
+            "paper_U_B_bytes": 18 * POP_BYTES[dtype], "bytes_per_node": bpn,
+            "mass_check": mass_ok}
+
+
+def measure_copy(lbm, nbytes, reps=20):
+    """Achievable read+write bandwidth of a plain 16-byte copy kernel (a10)."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        lbm.copy_kernel(a, b, nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lbm.copy_kernel(a, b, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return {"bytes": nbytes, "gbps": 2 * nbytes / s / 1e9, "frac_of_peak": 2 * nbytes / s / 1e9 / HBM_PEAK_GBPS}
+
+
+def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask):
+    lat = lbm.Lattice(mask, 0.6, force=(1e-6, 0.0), dtype=dtype, layout=layout)
+    secs, ms = time_steps(lat, steps, warmup)
+    info = lat.info()
+    lat.close()
+    nf = info["n_fluid"]
+    glups = nf * steps / secs / 1e9
+    bpn = algorithmic_bytes_per_node(dtype)
+    out = {"workload": f"porous discs {n}^2 phi={phi}", "dtype": dtype, "layout": layout,
+           "n_fluid": nf, "glups_per_fluid_node": glups, "ms_per_step": ms,
+           "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
+           "bytes_moved_per_step": info["bytes_moved_per_step"]}
+    if layout == "tiled16":
+        out["tile_occupancy"] = nf / max(1, info["n_tiles"] * 256)
+    return out
+
+
+def measure_adjoint(lbm, steps=200):
+    """Adjoint kernel time per step vs forward step time (1024 x 256 channel, FP32)."""
+    import torch
+
+    import synthetic
+    nx, ny = 1024, 256
+    m = synthetic.channel_mask(nx, ny)
+    alpha = synthetic.brinkman_alpha(nx, ny, seed=7, sigma=8.0).astype(np.float32)
+    lat = lbm.Lattice(m, 0.8, force=(1e-5, 0.0), dtype="f32", layout="dense_ab")
+    lat.set_porosity(alpha)
+    fwd_s, fwd_ms = time_steps(lat, steps, 20)
+    sb = lat.state_bytes()
+    state = torch.empty(sb, dtype=torch.uint8, device="cuda")
+    lat.save_state(state)
+    ab, _ = lat.adjoint_bytes()
+    mu = [torch.zeros(ab, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    ga = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    gg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lat.adjoint_seed_outlet_ux(nx - 1, 1.0, mu[0], ga, gg)
+    for k in range(20):
+        lat.adjoint_step(state, mu[k % 2], mu[1 - k % 2], ga, gg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        lat.adjoint_step(state, mu[k % 2], mu[1 - k % 2], ga, gg)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / steps
+    lat.close()
+    return {"workload": "channel 1024x256 with drag field, f32", "forward_ms_per_step": fwd_ms,
+            "adjoint_ms_per_step": adj_ms, "adjoint_over_forward": adj_ms / fwd_ms,
+            "amortised_with_recompute": (adj_ms + fwd_ms) / fwd_ms}
+
+
+def cpu_baseline(n, fields, budget_s=12.0):
+    """The FP64 oracle (as it is) on the host cores, a bounded number of steps."""
+    import oracle
+    import synthetic
+    m = synthetic.all_fluid(n, n)
+    f = oracle.init(m, *fields)
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    f = oracle.run(m, f, 0.6, 1, threads=threads)
+    one = time.perf_counter() - t0
+    steps = int(max(1, min(50, budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.run(m, f, 0.6, steps, threads=threads)
+    secs = time.perf_counter() - t0
+    return {"value": n * n * steps / secs / 1e9, "unit": "GLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the taylor-green {n}^2 FP64 workload "
+                      f"({secs:.1f} s, OpenMP over rows)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--suite", default="default", choices=["default", "full", "headline"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-reps", type=int, default=20)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py measures one GPU: this build runs the step on a single MI355X and has "
+              "no multi-GPU path (run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2108_13241_amd as lbm
+    import synthetic
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lbm.load()
+    n = args.size
+    fields = synthetic.taylor_green(n, 0.01)
+
+    log(f"[bench] headline: taylor-green {n}^2 f64 dense_ab, {args.warmup}+{args.steps} steps")
+    head = measure_dense(lbm, n, "f64", "dense_ab", args.steps, args.warmup, fields)
+    log(f"[bench]   {head['glups']:.2f} GLUPS, {head['hbm_gbps']:.0f} GB/s")
+    variants = []
+    if args.suite == "headline":
+        c = measure_copy(lbm, 1 << 30, reps=args.copy_reps)
+        log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
+        variants.append({"workload": "copy kernel 1 GiB", **c})
+    if args.suite in ("default", "full"):
+        for dtype, layout in [("f32", "dense_ab"), ("f64", "dense_aa"), ("f32", "dense_aa"),
+                              ("f16s", "dense_ab"), ("bf16s", "dense_ab")]:
+            r = measure_dense(lbm, n, dtype, layout, args.steps, args.warmup, fields)
+            log(f"[bench]   {dtype} {layout}: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
+            variants.append(r)
+        c = measure_copy(lbm, 1 << 30)
+        log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
+        variants.append({"workload": "copy kernel 1 GiB", **c})
+    if args.suite == "full":
+        for nn in (1024, 2048):
+            f2 = synthetic.taylor_green(nn, 0.01)
+            for dtype in ("f64", "f32"):
+                for layout in ("dense_ab", "dense_aa"):
+                    r = measure_dense(lbm, nn, dtype, layout, args.steps, args.warmup, f2)
+                    log(f"[bench]   {nn} {dtype} {layout}: {r['glups']:.2f} GLUPS")
+                    variants.append(r)
+        for phi in (0.9, 0.5, 0.2):
+            mask, info = synthetic.porous_discs(n, phi)
+            log(f"[bench]   porous phi={phi}: achieved {info['phi_achieved']:.3f}")
+            for dtype in ("f32", "f64"):
+                for layout in ("dense_ab", "tiled16", "indirect"):
+                    r = measure_porous(lbm, n, phi, dtype, layout, args.steps // 2,
+                                       args.warmup // 2, mask)
+                    log(f"[bench]   phi={phi} {dtype} {layout}: "
+                        f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid")
+                    variants.append(r)
+        a = measure_adjoint(lbm)
+        log(f"[bench]   adjoint/forward = {a['adjoint_over_forward']:.2f}")
+        variants.append(a)
+
+    bpn = algorithmic_bytes_per_node("f64")
+    bytes_per_launch = bpn * n * n
+    achieved = bytes_per_launch / (head["ms_per_step"] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": measured_traffic("k_step_dense_ab_f64_tgv4096"),
+                "kernel": "k_step_dense_ab<F64>", "bytes_per_launch": bytes_per_launch,
+                "bytes_per_node": bpn}
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(n, fields)
+        log(f"[bench]   {cpu['value'] * 1e3:.1f} MLUPS on {cpu['cores']} threads")
+    out = {
+        "metric": METRIC, "value": head["glups"], "unit": "GLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"taylor-green vortex {n}x{n}, fully periodic, u0=0.01, "
+                               f"tau=0.6, dense A-B layout, FP64 populations",
+                   "nodes": n * n, "layout": "dense_ab", "tau": 0.6},
+        "hbm_frac_of_peak": head["frac_of_peak"],
+        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+        "paper_context": PAPER_CONTEXT,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

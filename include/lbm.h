@@ -1,0 +1,262 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) D2Q9 lattice-Boltzmann library.
+ *
+ * The library advances the D2Q9 BGK lattice-Boltzmann method of Tomczak,
+ * "Data-Oriented Language Implementation of Lattice-Boltzmann Method for Dense
+ * and Sparse Geometries" (arXiv 2108.13241): the fused stream-and-collide time
+ * step of Algorithm 1 (pull scheme, Sec. 3) with the moments of Eq. 2, the BGK
+ * operator of Eqs. 3-5, the equilibrium of Eq. 6 and bounce-back walls marked
+ * by a node-type field (Sec. 3), on dense meshes and on sparse geometries
+ * (Sec. 4.3: tiles of 16 x 16 nodes, and a per-fluid-node indirect list).
+ * Beyond the paper it adds a body force (Guo forcing), a per-node Brinkman drag
+ * coefficient, 16-bit shifted population storage and a hand-written adjoint.
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an lbm_status (0 = LBM_OK).  Nothing aborts or throws
+ *    across the ABI.  On LBM_ERR_INVALID / LBM_ERR_UNSUPPORTED nothing changed.
+ *    A device failure returns LBM_ERR_DEVICE and marks the context broken: later
+ *    calls on it return LBM_ERR_STATE.  lbm_last_error() explains the failure.
+ *  - Host arrays are owned by the caller and only read (or written) during the
+ *    call.  "Device" pointers are HIP device addresses on the context's device,
+ *    owned by the caller; the library only reads / writes them on its stream.
+ *  - 2-D host and device fields are row-major [ny][nx] (x fastest), no padding.
+ *  - Node types (mask): 0 = fluid, 1 = solid.  Both axes are periodic; walls come
+ *    only from solid nodes.  Bounce-back is the halfway, link-wise rule: a
+ *    population that would stream into a solid node returns to its origin node
+ *    with the opposite direction in the same step.
+ *  - Populations are numbered as in the paper's Fig. 1: 0 rest, 1 (+x), 2 (+y),
+ *    3 (-x), 4 (-y), 5 (+x+y), 6 (-x+y), 7 (-x-y), 8 (+x-y).
+ *  - "Canonical" populations f_i(x, t) are the pre-collision (post-streaming)
+ *    values, the left-hand side of Eq. 3, as FP64 [9][ny][nx]; solid slots = 0.
+ *    Whatever the layout stores internally, the canonical view is the same.
+ *  - One context is not thread-safe; separate contexts are independent.
+ *    All work is enqueued on the context's stream (lbm_set_stream); calls that
+ *    return host data synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; owned by the library until lbm_destroy */
+
+/* Population storage type.  F64 / F32 store f_i and compute in that type.
+ * F16_SHIFTED / BF16_SHIFTED store the deviation f_i - w_i (rho0 = 1) in 16 bits
+ * (round to nearest even) and compute in FP32. */
+typedef enum {
+    LBM_F64 = 0,
+    LBM_F32 = 1,
+    LBM_F16_SHIFTED = 2,
+    LBM_BF16_SHIFTED = 3
+} lbm_dtype;
+
+/* Memory layout of the populations.
+ *  DENSE_AB : two full lattices [9][ny][pitch] (structure of arrays), pull
+ *             scheme, swapped every step (Algorithm 1, Sec. 3).
+ *  DENSE_AA : one full lattice updated in place with the AA access pattern
+ *             (the single-copy scheme Sec. 3 mentions): even steps read and
+ *             write each node's own slots, odd steps read from and write to the
+ *             neighbours.
+ *  TILED16  : two lattices holding only the non-empty 16 x 16 tiles, compacted
+ *             in row-major tile order, with a tile-neighbour table ("pointer
+ *             tile" of Sec. 4.3).  Requires nx and ny to be multiples of 16.
+ *  INDIRECT : two lattices holding only fluid nodes (row-major compaction) and
+ *             a per-node neighbour table (the fluid-index-array approach of
+ *             Sec. 1). */
+typedef enum {
+    LBM_DENSE_AB = 0,
+    LBM_DENSE_AA = 1,
+    LBM_TILED16 = 2,
+    LBM_INDIRECT = 3
+} lbm_layout;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID = -1,     /* bad argument; nothing changed */
+    LBM_ERR_NOMEM = -2,       /* device or host allocation failed */
+    LBM_ERR_DEVICE = -3,      /* HIP runtime error; the context is now broken */
+    LBM_ERR_UNSUPPORTED = -4, /* valid request this build does not implement */
+    LBM_ERR_STATE = -5        /* context broken by an earlier device error */
+} lbm_status;
+
+/* Geometry and size summary of a context. */
+typedef struct {
+    int32_t nx, ny;
+    int32_t dtype, layout;
+    int64_t n_nodes;         /* nx * ny */
+    int64_t n_fluid;         /* fluid nodes: the ones counted for LUPS (Eq. 8) */
+    int64_t n_tiles;         /* TILED16: non-empty tiles; else 0 */
+    int64_t time_step;       /* steps taken since the last (re)initialisation */
+    int32_t pop_bytes;       /* bytes per stored population: 8, 4 or 2 */
+    int32_t has_porosity;    /* 1 once lbm_set_porosity gave a non-NULL field */
+    double bytes_per_fluid_node; /* algorithmic bytes per fluid node per step:
+                                    18 * pop_bytes + 1 (node type) [+4 with drag] */
+    double bytes_moved_per_step; /* bytes the step kernel touches in DRAM per step
+                                    under ideal caching (tiles count whole tiles,
+                                    INDIRECT adds 32 B/node of neighbour table) */
+    size_t device_bytes;     /* device memory held by the context */
+} lbm_info_t;
+
+/* Device allocator hook (process-wide).  Every device buffer a context owns is
+ * taken from alloc(bytes, user) and returned with free(ptr, user).  Passing
+ * NULL, NULL restores hipMalloc / hipFree.  Contexts keep the hook they were
+ * created with. */
+typedef void *(*lbm_alloc_fn)(size_t bytes, void *user);
+typedef void (*lbm_free_fn)(void *ptr, void *user);
+int lbm_set_allocator(lbm_alloc_fn alloc, lbm_free_fn free_fn, void *user);
+
+/* Create a lattice (Sec. 3: node-type field; Eq. 5: omega = 1 / tau).
+ *  out       receives the context (NULL on failure).
+ *  nx, ny    mesh size, >= 1 each (TILED16: multiples of 16).
+ *  node_type host uint8 [ny][nx], values 0 (fluid) / 1 (solid); copied.
+ *  tau       relaxation time, > 1/2 (viscosity nu = (tau - 1/2) / 3).
+ *  force     host double[2] = body-force acceleration (g_x, g_y); NULL = 0.
+ *            It enters through Guo's forcing term with force density
+ *            F = rho (g - alpha u).
+ * The lattice starts at rest (rho = 1, u = 0; Algorithm 1 initialisation) on
+ * the current HIP device, using the default stream until lbm_set_stream.
+ * Errors: INVALID (sizes, tau, non-finite force, mask value), UNSUPPORTED
+ * (layout constraint), NOMEM, DEVICE. */
+int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, double tau,
+               const double *force, lbm_dtype dtype, lbm_layout layout);
+
+/* Enqueue all later work on `hip_stream` (a hipStream_t; NULL = default stream).
+ * Work already enqueued on the previous stream is waited for first. */
+int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
+
+/* Algorithm 1 initialisation: f_i = f^eq_i(rho0, u0) (Eq. 6) at every fluid
+ * node, as the canonical state at time 0.  Host FP64 [ny][nx] fields; NULL
+ * means rho0 = 1 / u0 = 0.  Resets the step counter to 0. */
+int lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy);
+
+/* Per-node Brinkman drag coefficient alpha (host FP32 [ny][nx], each in [0, 1];
+ * NULL removes the drag).  The collision uses u = (m / rho + g / 2) / (1 + alpha / 2)
+ * and F = rho (g - alpha u).  Errors: INVALID for values outside [0, 1]. */
+int lbm_set_porosity(lbm_ctx *ctx, const float *alpha);
+
+/* Replace the body force (host double[2], finite). */
+int lbm_set_force(lbm_ctx *ctx, const double *force);
+
+/* Enqueue n >= 0 time steps (Algorithm 1, one fused stream-collide kernel per
+ * step).  Asynchronous: returns once enqueued. */
+int lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Macroscopic fields (Eq. 2, with the half-force / drag velocity) of the
+ * current canonical state into host FP64 [ny][nx] arrays; solid nodes get 0.
+ * Any pointer may be NULL.  Synchronises the stream. */
+int lbm_macroscopic(lbm_ctx *ctx, double *rho, double *ux, double *uy);
+
+/* Same as lbm_macroscopic into caller-owned device FP64 [ny][nx] buffers
+ * (any may be NULL).  Asynchronous. */
+int lbm_macroscopic_device(lbm_ctx *ctx, void *rho, void *ux, void *uy);
+
+/* Canonical populations (see the conventions) to / from host FP64 [9][ny][nx].
+ * Set ignores solid slots and converts to the storage type (16-bit storage
+ * rounds to nearest even).  Both synchronise the stream. */
+int lbm_get_populations(lbm_ctx *ctx, double *f);
+int lbm_set_populations(lbm_ctx *ctx, const double *f);
+
+/* Total mass sum of rho over fluid nodes (FP64 reduction on the device, fixed
+ * summation order, so repeatable).  Synchronises the stream. */
+int lbm_mass(lbm_ctx *ctx, double *mass);
+
+/* Raw state checkpoints: bytes of the stored lattice (one lattice for every
+ * layout; the step parity of the context is not part of it), and device-to-
+ * device copies of it on the context's stream.  A state saved at step t and
+ * loaded later reproduces the run from t bitwise (DENSE_AA: load only at a
+ * step with the same parity as at save time). */
+int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
+int lbm_save_state(lbm_ctx *ctx, void *dev_dst);
+int lbm_load_state(lbm_ctx *ctx, const void *dev_src);
+
+/* J = mean of u_x over the fluid nodes of column x_col (0 <= x_col < nx),
+ * computed in FP64 on the device from the canonical state.  Synchronises.
+ * Errors: INVALID if the column has no fluid node. */
+int lbm_objective_outlet_ux(lbm_ctx *ctx, int32_t x_col, double *J);
+
+/* ---- Adjoint (reverse mode of the step; DENSE_AB, F64 and F32 only) ------
+ * An adjoint field lambda is dense [9][ny][pitch] in the compute type (FP64
+ * for F64, FP32 for F32); lbm_adjoint_bytes gives its size and the pitch.
+ * lambda_t = dJ / df(t) with f the canonical populations.  Gradients are FP64
+ * device buffers owned by the caller and ACCUMULATED into (+=):
+ *   grad_alpha_dev [ny][nx], grad_g_dev [2]. */
+int lbm_adjoint_bytes(const lbm_ctx *ctx, size_t *bytes, int32_t *pitch);
+
+/* lambda_T for J = dJ * mean outlet u_x over column x_col, from the current
+ * canonical state, written to mu_dev; the direct dJ/dalpha and dJ/dg terms of
+ * the objective are added to the gradients. */
+int lbm_adjoint_seed_outlet_ux(lbm_ctx *ctx, int32_t x_col, double dJ, void *mu_dev,
+                               double *grad_alpha_dev, double *grad_g_dev);
+
+/* One adjoint step: given the raw state saved (lbm_save_state) at step t and
+ * lambda_{t+1} in mu_in_dev, write lambda_t to mu_out_dev and add this step's
+ * parameter sensitivities to the gradients.  mu_in and mu_out must differ. */
+int lbm_adjoint_step(lbm_ctx *ctx, const void *state_t_dev, const void *mu_in_dev,
+                     void *mu_out_dev, double *grad_alpha_dev, double *grad_g_dev);
+
+/* Checkpointed forward run: advance T steps from the current state, saving the
+ * raw state before steps 0, K, 2K, ... into ckpt_dev (ceil(T / K) slots of
+ * lbm_state_bytes each, caller-owned). */
+int lbm_run_checkpointed(lbm_ctx *ctx, int64_t T, int64_t K, void *ckpt_dev);
+
+/* Checkpointed adjoint of J = dJ * mean outlet u_x (column x_col) after the T
+ * steps of lbm_run_checkpointed: the current state must be the state at T.
+ * Segments are replayed from the last to the first: each reloads its
+ * checkpoint, recomputes its K states into seg_dev (K slots of state bytes,
+ * caller-owned), then runs its adjoint steps backwards.  Gradients accumulate
+ * into grad_alpha_dev / grad_g_dev.  The context's state is left at step T. */
+int lbm_adjoint_checkpointed(lbm_ctx *ctx, int64_t T, int64_t K, const void *ckpt_dev,
+                             void *seg_dev, int32_t x_col, double dJ, double *grad_alpha_dev,
+                             double *grad_g_dev);
+
+/* Summary of the context (sizes, fluid count, bytes per step, device memory). */
+int lbm_get_info(const lbm_ctx *ctx, lbm_info_t *info);
+
+/* ---- Host-only geometry planning (no device needed) ----------------------
+ * Compacted tile list for TILED16: tiles are 16 x 16 nodes; a tile is kept if
+ * it holds at least one fluid node; tiles are numbered in row-major tile order.
+ *  n_tiles        out: number of kept tiles.
+ *  tile_xy        out (may be NULL): int32 [n_tiles][2] tile coordinates (tx, ty).
+ *  tile_nbr       out (may be NULL): int32 [n_tiles][9]: entry d is the index of
+ *                 the kept tile at (tx + c_d.x, ty + c_d.y) (periodic), -1 if
+ *                 that tile is empty; entry 0 is the tile itself.
+ * Call with NULL outputs to learn n_tiles first.  Errors: INVALID, UNSUPPORTED
+ * (nx or ny not a multiple of 16). */
+int lbm_plan_tiles(int32_t nx, int32_t ny, const uint8_t *node_type, int64_t *n_tiles,
+                   int32_t *tile_xy, int32_t *tile_nbr);
+
+/* Compacted fluid list for INDIRECT: fluid nodes in row-major order.
+ *  n_fluid   out: number of fluid nodes.
+ *  fluid_xy  out (may be NULL): int32 [n_fluid][2] node coordinates.
+ *  nbr       out (may be NULL): int32 [8][n_fluid]: nbr[i-1][n] is the index of
+ *            the fluid node at x_n - c_i (periodic) for i = 1..8, or -1 when that
+ *            node is solid (the population bounces back).
+ * Call with NULL outputs to learn n_fluid first. */
+int lbm_plan_indirect(int32_t nx, int32_t ny, const uint8_t *node_type, int64_t *n_fluid,
+                      int32_t *fluid_xy, int32_t *nbr);
+
+/* ---- Measurement aid ---------------------------------------------------------
+ * Device copy kernel with the same access width as the step kernels, used to
+ * calibrate the achievable DRAM bandwidth (the copy experiment of Sec. 4.2).
+ * Copies `bytes` (a multiple of 16) from src to dst on `hip_stream`. */
+int lbm_copy_kernel(const void *src, void *dst, size_t bytes, void *hip_stream);
+
+/* Static description of a status code; never NULL. */
+const char *lbm_error_string(int status);
+/* Message of the last failure on ctx; with ctx == NULL, the calling thread's
+ * last failure outside a context (e.g. lbm_create).  Never NULL. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Release the context and every device buffer it holds (NULL is a no-op). */
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

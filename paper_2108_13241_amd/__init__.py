@@ -1,0 +1,262 @@
+"""MI355X-native D2Q9 lattice-Boltzmann library: Python binding of include/lbm.h.
+
+Every step of the method runs in the HIP kernels of ``liblbm_hip.so``; this module only
+marshals arguments.  PyTorch supplies device memory (its caching allocator is
+registered with ``lbm_set_allocator``) and streams (``torch.cuda.current_stream``).
+
+    import paper_2108_13241_amd as lbm
+    lat = lbm.Lattice(mask, tau=0.8, force=(1e-6, 0.0), dtype="f64", layout="dense_ab")
+    lat.step(2000)
+    rho, ux, uy = lat.macroscopic()
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import DTYPES, LAYOUTS, POP_BYTES, LbmError, LbmInfo, check, load
+
+__all__ = ["Lattice", "LbmError", "DTYPES", "LAYOUTS", "plan_tiles", "plan_indirect",
+           "copy_kernel", "ChannelObjective", "load"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+# ------------------------------------------------------------ torch memory --
+_torch_blocks = {}
+_alloc_cb = None
+_free_cb = None
+
+
+def _install_torch_allocator():
+    """Route the library's device allocations through torch's caching allocator."""
+    global _alloc_cb, _free_cb
+    if _alloc_cb is not None:
+        return
+    import torch
+
+    from ._lib import ALLOC_FN, FREE_FN
+
+    def _alloc(nbytes, _user):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        except Exception:  # noqa: BLE001 - report NULL to the library (LBM_ERR_NOMEM)
+            return None
+        p = t.data_ptr()
+        _torch_blocks[p] = t
+        return p
+
+    def _free(ptr, _user):
+        _torch_blocks.pop(ptr, None)
+
+    _alloc_cb = ALLOC_FN(_alloc)
+    _free_cb = FREE_FN(_free)
+    check(load().lbm_set_allocator(ctypes.cast(_alloc_cb, ctypes.c_void_p),
+                                   ctypes.cast(_free_cb, ctypes.c_void_p), None))
+
+
+def _uninstall_torch_allocator():
+    """Back to hipMalloc / hipFree for contexts created from now on."""
+    global _alloc_cb, _free_cb
+    check(load().lbm_set_allocator(None, None, None))
+    _alloc_cb = _free_cb = None
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or an int address / None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+class Lattice:
+    """One D2Q9 lattice on the current GPU (a thin wrapper of lbm_ctx)."""
+
+    def __init__(self, mask, tau, force=(0.0, 0.0), dtype="f64", layout="dense_ab",
+                 stream=None, torch_memory=True):
+        import torch
+
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.ndim != 2:
+            raise ValueError("mask must be [ny, nx]")
+        self.ny, self.nx = mask.shape
+        self.mask = mask
+        self.dtype = dtype
+        self.layout = layout
+        self._lib = load()
+        if torch_memory:
+            _install_torch_allocator()
+        else:
+            _uninstall_torch_allocator()
+        self._ctx = ctypes.c_void_p()
+        g = (ctypes.c_double * 2)(float(force[0]), float(force[1]))
+        st = self._lib.lbm_create(ctypes.byref(self._ctx), self.nx, self.ny,
+                                  mask.ctypes.data_as(_u8p), float(tau), g, DTYPES[dtype],
+                                  LAYOUTS[layout])
+        check(st, None)
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream())
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, status):
+        check(status, self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def set_stream(self, stream):
+        """stream: torch.cuda.Stream, a raw hipStream_t address, or 0 (default stream)."""
+        raw = getattr(stream, "cuda_stream", stream)
+        self.stream = stream
+        self._check(self._lib.lbm_set_stream(self._ctx, ctypes.c_void_p(int(raw or 0))))
+
+    # -- state -----------------------------------------------------------------
+    def init_equilibrium(self, rho=None, ux=None, uy=None):
+        s = (self.ny, self.nx)
+        rho, ux, uy = _f64(rho, s), _f64(ux, s), _f64(uy, s)
+        self._check(self._lib.lbm_init_equilibrium(self._ctx, _dptr(rho), _dptr(ux), _dptr(uy)))
+
+    def set_porosity(self, alpha):
+        if alpha is None:
+            self._check(self._lib.lbm_set_porosity(self._ctx, None))
+            return
+        a = np.ascontiguousarray(alpha, dtype=np.float32)
+        if a.shape != (self.ny, self.nx):
+            raise ValueError("alpha must be [ny, nx]")
+        self._check(self._lib.lbm_set_porosity(self._ctx,
+                                               a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def set_force(self, g):
+        arr = (ctypes.c_double * 2)(float(g[0]), float(g[1]))
+        self._check(self._lib.lbm_set_force(self._ctx, arr))
+
+    def step(self, n=1):
+        self._check(self._lib.lbm_step(self._ctx, int(n)))
+
+    def macroscopic(self):
+        out = [np.zeros((self.ny, self.nx)) for _ in range(3)]
+        self._check(self._lib.lbm_macroscopic(self._ctx, *[_dptr(o) for o in out]))
+        return tuple(out)
+
+    def macroscopic_device(self, rho=None, ux=None, uy=None):
+        self._check(self._lib.lbm_macroscopic_device(self._ctx, _ptr(rho), _ptr(ux), _ptr(uy)))
+
+    def get_populations(self):
+        f = np.zeros((9, self.ny, self.nx))
+        self._check(self._lib.lbm_get_populations(self._ctx, _dptr(f)))
+        return f
+
+    def set_populations(self, f):
+        f = _f64(f, (9, self.ny, self.nx))
+        self._check(self._lib.lbm_set_populations(self._ctx, _dptr(f)))
+
+    def mass(self):
+        m = ctypes.c_double()
+        self._check(self._lib.lbm_mass(self._ctx, ctypes.byref(m)))
+        return m.value
+
+    def state_bytes(self):
+        b = ctypes.c_size_t()
+        self._check(self._lib.lbm_state_bytes(self._ctx, ctypes.byref(b)))
+        return b.value
+
+    def save_state(self, dst):
+        self._check(self._lib.lbm_save_state(self._ctx, _ptr(dst)))
+
+    def load_state(self, src):
+        self._check(self._lib.lbm_load_state(self._ctx, _ptr(src)))
+
+    def objective_outlet_ux(self, x_col):
+        J = ctypes.c_double()
+        self._check(self._lib.lbm_objective_outlet_ux(self._ctx, int(x_col), ctypes.byref(J)))
+        return J.value
+
+    def info(self):
+        i = LbmInfo()
+        self._check(self._lib.lbm_get_info(self._ctx, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in LbmInfo._fields_}
+
+    # -- adjoint -----------------------------------------------------------------
+    def adjoint_bytes(self):
+        b = ctypes.c_size_t()
+        p = ctypes.c_int32()
+        self._check(self._lib.lbm_adjoint_bytes(self._ctx, ctypes.byref(b), ctypes.byref(p)))
+        return b.value, p.value
+
+    def adjoint_seed_outlet_ux(self, x_col, dJ, mu, grad_alpha, grad_g):
+        self._check(self._lib.lbm_adjoint_seed_outlet_ux(self._ctx, int(x_col), float(dJ),
+                                                         _ptr(mu), _ptr(grad_alpha),
+                                                         _ptr(grad_g)))
+
+    def adjoint_step(self, state, mu_in, mu_out, grad_alpha, grad_g):
+        self._check(self._lib.lbm_adjoint_step(self._ctx, _ptr(state), _ptr(mu_in), _ptr(mu_out),
+                                               _ptr(grad_alpha), _ptr(grad_g)))
+
+    def run_checkpointed(self, T, K, ckpt):
+        self._check(self._lib.lbm_run_checkpointed(self._ctx, int(T), int(K), _ptr(ckpt)))
+
+    def adjoint_checkpointed(self, T, K, ckpt, seg, x_col, dJ, grad_alpha, grad_g):
+        self._check(self._lib.lbm_adjoint_checkpointed(self._ctx, int(T), int(K), _ptr(ckpt),
+                                                        _ptr(seg), int(x_col), float(dJ),
+                                                        _ptr(grad_alpha), _ptr(grad_g)))
+
+
+# ------------------------------------------------------------ host planning --
+def plan_tiles(mask):
+    """(tile_xy [n, 2], tile_nbr [n, 9]) of the compacted 16x16 tile list."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    ny, nx = m.shape
+    L = load()
+    n = ctypes.c_int64()
+    check(L.lbm_plan_tiles(nx, ny, m.ctypes.data_as(_u8p), ctypes.byref(n), None, None))
+    xy = np.zeros((n.value, 2), dtype=np.int32)
+    nb = np.zeros((n.value, 9), dtype=np.int32)
+    check(L.lbm_plan_tiles(nx, ny, m.ctypes.data_as(_u8p), ctypes.byref(n),
+                           xy.ctypes.data_as(_i32p), nb.ctypes.data_as(_i32p)))
+    return xy, nb
+
+
+def plan_indirect(mask):
+    """(fluid_xy [n, 2], nbr [8, n]) of the compacted fluid-node list."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    ny, nx = m.shape
+    L = load()
+    n = ctypes.c_int64()
+    check(L.lbm_plan_indirect(nx, ny, m.ctypes.data_as(_u8p), ctypes.byref(n), None, None))
+    xy = np.zeros((n.value, 2), dtype=np.int32)
+    nb = np.zeros((8, n.value), dtype=np.int32)
+    check(L.lbm_plan_indirect(nx, ny, m.ctypes.data_as(_u8p), ctypes.byref(n),
+                              xy.ctypes.data_as(_i32p), nb.ctypes.data_as(_i32p)))
+    return xy, nb
+
+
+def copy_kernel(src, dst, nbytes, stream=None):
+    raw = getattr(stream, "cuda_stream", stream) or 0
+    check(load().lbm_copy_kernel(_ptr(src), _ptr(dst), int(nbytes), ctypes.c_void_p(int(raw))))
+
+
+from .adjoint import ChannelObjective  # noqa: E402

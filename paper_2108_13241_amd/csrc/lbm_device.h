@@ -1,0 +1,170 @@
+// Device-side building blocks of the D2Q9 step: lattice constants, storage
+// codecs, the collision (one function shared by every layout, so that all
+// layouts produce bitwise-identical populations), and small launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// D2Q9 lattice velocities in the paper's Fig. 1 numbering (Sec. 2.2):
+// 0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+x,+y), 6 (-x,+y), 7 (-x,-y), 8 (+x,-y).
+__device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// Equilibrium weights of Eq. 6.
+__device__ constexpr double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// Node-type codes held in the type array (one byte per node).
+enum : uint8_t {
+    kFluid = 0,     // fluid node whose 8 neighbours are all fluid
+    kSolid = 1,     // solid node: no populations, never updated
+    kBoundary = 2,  // fluid node with at least one solid neighbour; its
+                    // solid-neighbour bits are in the nmask array:
+                    // bit i-1 set <=> node x - c_i is solid (i = 1..8)
+};
+
+// Solid-neighbour set of a node as a 9-bit mask: bit i set <=> node x - c_i is
+// solid (bit 0 never set).  Interior fluid nodes need no nmask read.
+__device__ __forceinline__ unsigned solid_bits(uint8_t code, const uint8_t *__restrict__ nmask,
+                                               uint32_t idx)
+{
+    return code == kBoundary ? (unsigned)nmask[idx] << 1 : 0u;
+}
+
+// ---------------------------------------------------------------- storage --
+// A codec maps a stored population (mem) to the compute type (real) and back.
+// kShift = false: the stored value is f_i itself (FP64).
+// kShift = true : the stored value is the deviation h_i = f_i - w_i * rho0 with
+//                 rho0 = 1 (FP32, FP16, BF16), and the collision works on h_i
+//                 directly.  Near rest |h_i| << w_i, so rounding a deviation to
+//                 the storage type costs far less absolute accuracy than rounding
+//                 f_i itself.
+// ld / st convert between storage and compute representation; canon / from_canon
+// convert between storage and the canonical FP64 populations f_i.
+struct F64 {
+    using mem = double;
+    using real = double;
+    static constexpr bool kShift = false;
+    static __device__ __forceinline__ real ld(mem v, int) { return v; }
+    static __device__ __forceinline__ mem st(real v, int) { return v; }
+    static __device__ __forceinline__ double canon(real v, int) { return v; }
+    static __device__ __forceinline__ mem from_canon(double f, int) { return f; }
+};
+template <class M>
+struct Shifted {
+    using mem = M;
+    using real = float;
+    static constexpr bool kShift = true;
+    static __device__ __forceinline__ real ld(mem v, int) { return (float)v; }
+    static __device__ __forceinline__ mem st(real v, int) { return (mem)v; }
+    static __device__ __forceinline__ double canon(real v, int i) { return (double)v + kW[i]; }
+    static __device__ __forceinline__ mem from_canon(double f, int i)
+    {
+        return (mem)(float)(f - kW[i]);
+    }
+};
+using F32 = Shifted<float>;
+using F16S = Shifted<_Float16>;
+using BF16S = Shifted<__bf16>;
+
+// -------------------------------------------------------------- collision --
+// Collision at one fluid node, in place on f (right-hand side of Eq. 3):
+//   rho = sum f_i, m = sum c_i f_i                        (Eq. 2)
+//   u   = (m / rho + g / 2) / (1 + alpha / 2)             (half-force, drag)
+//   F   = rho (g - alpha u)
+//   f_i <- f_i - omega (f_i - f^eq_i) + (1 - omega / 2) S_i
+// with f^eq of Eq. 6, omega = 1 / tau (Eq. 5) and Guo's forcing term
+//   S_i = w_i [3 (c_i - u) . F + 9 (c_i . u)(c_i . F)].
+// With g = 0 and alpha = 0 it is exactly the BGK update of Eqs. 3-6.
+// SHIFT: f holds deviations h_i = f_i - w_i.  Since sum w_i = 1 and
+// sum w_i c_i = 0, rho = 1 + sum h_i and m = sum c_i h_i, and the update keeps
+// its form with f^eq_i - w_i = w_i (sum h + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)).
+template <class R, bool DRAG, bool SHIFT>
+__device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, const R gy,
+                                        const R alpha)
+{
+    const R sum = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const R rho = SHIFT ? R(1) + sum : sum;
+    const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const R my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const R inv_rho = R(1) / rho;
+    R ux = mx * inv_rho + R(0.5) * gx;
+    R uy = my * inv_rho + R(0.5) * gy;
+    R Fx, Fy;
+    if constexpr (DRAG) {
+        const R invD = R(1) / (R(1) + R(0.5) * alpha);
+        ux *= invD;
+        uy *= invD;
+        Fx = rho * (gx - alpha * ux);
+        Fy = rho * (gy - alpha * uy);
+    } else {
+        Fx = rho * gx;
+        Fy = rho * gy;
+    }
+    const R usq = R(1.5) * (ux * ux + uy * uy);
+    const R uF = ux * Fx + uy * Fy;
+    const R keep = R(1) - omega;
+    const R guo = R(1) - R(0.5) * omega;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R cu = R(kCx[i]) * ux + R(kCy[i]) * uy;
+        const R cF = R(kCx[i]) * Fx + R(kCy[i]) * Fy;
+        const R w = R(kW[i]);
+        const R feq = SHIFT ? w * (sum + rho * (R(3) * cu + R(4.5) * cu * cu - usq))
+                            : w * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
+        const R S = w * (R(3) * (cF - uF) + R(9) * cu * cF);
+        f[i] = keep * f[i] + omega * feq + guo * S;
+    }
+}
+
+// Macroscopic moments of the canonical populations (Eq. 2 with the same
+// corrected velocity the collision uses), in FP64.
+__device__ __forceinline__ void moments(const double (&f)[9], double gx, double gy, double alpha,
+                                        double &rho, double &ux, double &uy)
+{
+    rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const double mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const double my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const double invD = 1.0 / (1.0 + 0.5 * alpha);
+    ux = (mx / rho + 0.5 * gx) * invD;
+    uy = (my / rho + 0.5 * gy) * invD;
+}
+
+// ------------------------------------------------------------- launching --
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap the hardware block index so that XCD j processes one contiguous
+// range of logical blocks: neighbouring blocks, which share cache lines at
+// their edges, then run on the same XCD.  A bijection on [0, n).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n)
+{
+    const uint32_t q = n >> 3, r = n & 7u, j = b & 7u, k = b >> 3;
+    return j * q + (j < r ? j : r) + k;
+}
+
+// Periodic neighbour coordinates.
+__device__ __forceinline__ int wrap_dec(int a, int n) { return a == 0 ? n - 1 : a - 1; }
+__device__ __forceinline__ int wrap_inc(int a, int n) { return a == n - 1 ? 0 : a + 1; }
+
+// nb[i] = in-plane offset of node x - c_i (periodic) in a dense [ny][pitch]
+// plane; nb[0] = the node itself.
+__device__ __forceinline__ void dense_offsets(int x, int y, int nx, int ny, int pitch,
+                                              uint32_t (&nb)[9])
+{
+    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+    const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+    const uint32_t r0 = (uint32_t)y * pitch, rm = (uint32_t)ym * pitch, rp = (uint32_t)yp * pitch;
+    nb[0] = r0 + x;
+    nb[1] = r0 + xm;  // c1 = (+1, 0)
+    nb[2] = rm + x;   // c2 = (0, +1)
+    nb[3] = r0 + xp;  // c3 = (-1, 0)
+    nb[4] = rp + x;   // c4 = (0, -1)
+    nb[5] = rm + xm;  // c5 = (+1, +1)
+    nb[6] = rm + xp;  // c6 = (-1, +1)
+    nb[7] = rp + xp;  // c7 = (-1, -1)
+    nb[8] = rp + xm;  // c8 = (+1, -1)
+}
+
+}  // namespace lbm

@@ -1,0 +1,729 @@
+// HIP kernels for gfx950: the fused D2Q9 stream-and-collide step (Algorithm 1,
+// pull scheme) on four layouts, plus initialisation, canonical views,
+// macroscopic fields and FP64 reductions.
+//
+// Memory layouts (structure of arrays, Sec. 3):
+//  dense    : plane i holds f_i of every node, row-major [ny][pitch]
+//  tiled    : plane i holds f_i of every kept 16x16 tile, [n_tiles][16][16]
+//  indirect : plane i holds f_i of every fluid node, [n_fluid (padded)]
+// Offsets inside one lattice are 32-bit element indices (the runtime checks
+// 9 * plane < 2^32).
+#include "lbm_device.h"
+#include "lbm_launch.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Direction index d with c_d = (ox, oy) (the paper's Fig. 1 numbering).
+__host__ __device__ constexpr int dir_of(int ox, int oy)
+{
+    return (ox == 0 && oy == 0)     ? 0
+           : (ox == 1 && oy == 0)   ? 1
+           : (ox == 0 && oy == 1)   ? 2
+           : (ox == -1 && oy == 0)  ? 3
+           : (ox == 0 && oy == -1)  ? 4
+           : (ox == 1 && oy == 1)   ? 5
+           : (ox == -1 && oy == 1)  ? 6
+           : (ox == -1 && oy == -1) ? 7
+                                    : 8;
+}
+
+// ------------------------------------------------------------ addressing --
+// Tiled layout: nb[i] = offset of node x - c_i, which may lie in one of the
+// neighbouring tiles (tile_nbr row `tn` of the current tile k).  When that
+// tile is absent the offset is meaningless, but the node is then solid and
+// the caller never uses it.
+__device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const int32_t (&tn)[9],
+                                              uint32_t (&nb)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int cx = kCx[i], cy = kCy[i];
+        const int sx = lx - cx, sy = ly - cy;
+        const bool bx = cx != 0 && (unsigned)sx > 15u;
+        const bool by = cy != 0 && (unsigned)sy > 15u;
+        int32_t kk = (int32_t)k;
+        if (cx != 0 && cy != 0)
+            kk = bx ? (by ? tn[dir_of(-cx, -cy)] : tn[dir_of(-cx, 0)]) : (by ? tn[dir_of(0, -cy)] : kk);
+        else if (cx != 0)
+            kk = bx ? tn[dir_of(-cx, 0)] : kk;
+        else if (cy != 0)
+            kk = by ? tn[dir_of(0, -cy)] : kk;
+        nb[i] = (uint32_t)kk * kTileNodes + (uint32_t)(((sy & 15) << 4) | (sx & 15));
+    }
+}
+
+// ---------------------------------------------------------------- gathers --
+// Pull gather of Algorithm 1: f_i(x) = s_i(x - c_i), or, when x - c_i is solid
+// (bit i of sm), the halfway bounce-back value s_opp(i)(x).
+template <class ST>
+__device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__ s, uint32_t plane,
+                                            const uint32_t (&nb)[9], unsigned sm,
+                                            typename ST::real (&f)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * plane + nb[0]
+                                            : (uint32_t)i * plane + nb[i];
+        f[i] = ST::ld(s[o], i);
+    }
+}
+
+// AA pattern, odd step read (and the canonical view after an odd number of
+// steps): f_i(x) = A_opp(i)(x - c_i), or A_i(x) when x - c_i is solid.
+template <class ST>
+__device__ __forceinline__ void aa_odd_gather(const typename ST::mem *__restrict__ s,
+                                              uint32_t plane, const uint32_t (&nb)[9], unsigned sm,
+                                              typename ST::real (&f)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)i * plane + nb[0]
+                                            : (uint32_t)kOpp[i] * plane + nb[i];
+        f[i] = ST::ld(s[o], i);
+    }
+}
+
+template <class ST>
+__device__ __forceinline__ void local_gather(const typename ST::mem *__restrict__ s,
+                                             uint32_t plane, uint32_t own,
+                                             typename ST::real (&f)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = ST::ld(s[(uint32_t)i * plane + own], i);
+}
+
+// ------------------------------------------------------------- step: dense --
+template <class ST, bool DRAG>
+__global__ __launch_bounds__(kBlock) void k_step_dense_ab(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
+    const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
+    const float *__restrict__ alpha, int nx, int ny, int pitch, uint32_t plane, uint32_t nbx,
+    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy)
+{
+    using R = typename ST::real;
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const int y = (int)(L / nbx);
+    const int x = (int)(L - (uint32_t)y * nbx) * kBlock + (int)threadIdx.x;
+    if (x >= nx)
+        return;
+    const uint32_t own = (uint32_t)y * pitch + x;
+    const uint8_t t = type[own];
+    if (t == kSolid)
+        return;
+    const unsigned sm = solid_bits(t, nmask, own);
+    uint32_t nb[9];
+    dense_offsets(x, y, nx, ny, pitch, nb);
+    R f[9];
+    pull_gather<ST>(src, plane, nb, sm, f);
+    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        dst[(uint32_t)i * plane + own] = ST::st(f[i], i);
+}
+
+// AA pattern (single lattice A).  Even step: read A_i(x), write the
+// post-collision f_i to A_opp(i)(x).  Odd step: read f_i = A_opp(i)(x - c_i)
+// (A_i(x) if x - c_i is solid), write f_i to A_i(x + c_i) (A_opp(i)(x) if
+// x + c_i is solid).  Slot A_j(z) is read and written by one node only
+// (z - c_j if it is fluid, else z), so there is no race.
+template <class ST, bool DRAG, bool ODD>
+__global__ __launch_bounds__(kBlock) void k_step_dense_aa(
+    typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
+    const uint8_t *__restrict__ nmask, const float *__restrict__ alpha, int nx, int ny, int pitch,
+    uint32_t plane, uint32_t nbx, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy)
+{
+    using R = typename ST::real;
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const int y = (int)(L / nbx);
+    const int x = (int)(L - (uint32_t)y * nbx) * kBlock + (int)threadIdx.x;
+    if (x >= nx)
+        return;
+    const uint32_t own = (uint32_t)y * pitch + x;
+    const uint8_t t = type[own];
+    if (t == kSolid)
+        return;
+    R f[9];
+    if constexpr (!ODD) {
+        local_gather<ST>(A, plane, own, f);
+        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            A[(uint32_t)kOpp[i] * plane + own] = ST::st(f[i], i);
+    } else {
+        const unsigned sm = solid_bits(t, nmask, own);
+        uint32_t nb[9];
+        dense_offsets(x, y, nx, ny, pitch, nb);
+        aa_odd_gather<ST>(A, plane, nb, sm, f);
+        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
+            const uint32_t o = ((sm >> kOpp[i]) & 1u) ? (uint32_t)kOpp[i] * plane + own
+                                                      : (uint32_t)i * plane + nb[kOpp[i]];
+            A[o] = ST::st(f[i], i);
+        }
+    }
+}
+
+// ------------------------------------------------------------- step: tiled --
+template <class ST, bool DRAG>
+__global__ __launch_bounds__(kTileNodes) void k_step_tiled(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
+    const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
+    const float *__restrict__ alpha, const int32_t *__restrict__ tile_nbr, uint32_t n_tiles,
+    uint32_t plane, typename ST::real omega, typename ST::real gx, typename ST::real gy)
+{
+    using R = typename ST::real;
+    const uint32_t k = xcd_remap(blockIdx.x, n_tiles);
+    const int t = (int)threadIdx.x, lx = t & 15, ly = t >> 4;
+    const uint32_t own = k * kTileNodes + t;
+    const uint8_t ty = type[own];
+    if (ty == kSolid)
+        return;
+    const unsigned sm = solid_bits(ty, nmask, own);
+    int32_t tn[9];
+#pragma unroll
+    for (int d = 0; d < 9; ++d)
+        tn[d] = tile_nbr[k * 9 + d];
+    uint32_t nb[9];
+    tiled_offsets(k, lx, ly, tn, nb);
+    R f[9];
+    pull_gather<ST>(src, plane, nb, sm, f);
+    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        dst[(uint32_t)i * plane + own] = ST::st(f[i], i);
+}
+
+// ---------------------------------------------------------- step: indirect --
+// nbr[(i-1) * plane + n] = compacted index of node x_n - c_i, or -1 (solid).
+__device__ __forceinline__ unsigned indirect_offsets(const int32_t *__restrict__ nbr,
+                                                     uint32_t plane, uint32_t n,
+                                                     uint32_t (&nb)[9])
+{
+    unsigned sm = 0;
+    nb[0] = n;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const int32_t j = nbr[(uint32_t)(i - 1) * plane + n];
+        sm |= (j < 0 ? 1u : 0u) << i;
+        nb[i] = (uint32_t)j;
+    }
+    return sm;
+}
+
+template <class ST, bool DRAG>
+__global__ __launch_bounds__(kBlock) void k_step_indirect(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
+    const int32_t *__restrict__ nbr, const float *__restrict__ alpha, uint32_t n_fluid,
+    uint32_t plane, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy)
+{
+    using R = typename ST::real;
+    const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
+    if (n >= n_fluid)
+        return;
+    uint32_t nb[9];
+    const unsigned sm = indirect_offsets(nbr, plane, n, nb);
+    R f[9];
+    pull_gather<ST>(src, plane, nb, sm, f);
+    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        dst[(uint32_t)i * plane + n] = ST::st(f[i], i);
+}
+
+// ------------------------------------------------ canonical-view plumbing --
+// Canonical FP64 buffers are [9][ny][pitch] with the dense pitch.
+// Gather mode of the dense layouts: A-B pull, AA after an even / odd number of steps.
+enum Mode : int { kPull = 0, kAAEven = 1, kAAOdd = 2 };
+
+// Canonical populations of the fluid node handled by thread `gid`; returns
+// false for padding and solid nodes.  Also returns the node's coordinates and
+// drag coefficient.
+template <class ST>
+__device__ __forceinline__ bool canonical_at(const DevState &s, const typename ST::mem *st,
+                                             int mode, uint32_t gid, int &x, int &y,
+                                             double (&fd)[9], double &al)
+{
+    using R = typename ST::real;
+    R f[9];
+    if (s.layout == kDenseAB || s.layout == kDenseAA) {
+        y = (int)(gid / (uint32_t)s.pitch);
+        x = (int)(gid - (uint32_t)y * s.pitch);
+        if (y >= s.ny || x >= s.nx)
+            return false;
+        const uint8_t t = s.type[gid];
+        if (t == kSolid)
+            return false;
+        const unsigned sm = solid_bits(t, s.nmask, gid);
+        uint32_t nb[9];
+        dense_offsets(x, y, s.nx, s.ny, s.pitch, nb);
+        if (mode == kPull)
+            pull_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
+        else if (mode == kAAEven)
+            local_gather<ST>(st, (uint32_t)s.plane, gid, f);
+        else
+            aa_odd_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
+        al = s.alpha ? (double)s.alpha[gid] : 0.0;
+    } else if (s.layout == kTiled16) {
+        const uint32_t k = gid / kTileNodes;
+        if (k >= (uint32_t)s.n_tiles)
+            return false;
+        const int t = (int)(gid - k * kTileNodes), lx = t & 15, ly = t >> 4;
+        const uint8_t ty = s.type[gid];
+        if (ty == kSolid)
+            return false;
+        const unsigned sm = solid_bits(ty, s.nmask, gid);
+        int32_t tn[9];
+        for (int d = 0; d < 9; ++d)
+            tn[d] = s.tile_nbr[k * 9 + d];
+        uint32_t nb[9];
+        tiled_offsets(k, lx, ly, tn, nb);
+        pull_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
+        x = s.tile_xy[2 * k] * kTile + lx;
+        y = s.tile_xy[2 * k + 1] * kTile + ly;
+        al = s.alpha ? (double)s.alpha[gid] : 0.0;
+    } else {
+        if (gid >= (uint32_t)s.n_fluid)
+            return false;
+        uint32_t nb[9];
+        const unsigned sm = indirect_offsets(s.nbr, (uint32_t)s.plane, gid, nb);
+        pull_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
+        x = s.fluid_xy[2 * gid];
+        y = s.fluid_xy[2 * gid + 1];
+        al = s.alpha ? (double)s.alpha[gid] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        fd[i] = ST::canon(f[i], i);
+    return true;
+}
+
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double ws[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+        ws[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i)
+            s += ws[i];
+    return s;  // valid in thread 0
+}
+
+struct OpCanonical {
+    double *fc;
+    uint32_t plane_c;
+    int pitch;
+    static constexpr bool kReduce = false;
+    __device__ double operator()(int x, int y, const double (&f)[9], double) const
+    {
+        const uint32_t o = (uint32_t)y * pitch + x;
+        for (int i = 0; i < 9; ++i)
+            fc[(uint32_t)i * plane_c + o] = f[i];
+        return 0.0;
+    }
+};
+
+struct OpMacro {
+    double *rho, *ux, *uy;
+    int opitch;
+    double gx, gy;
+    static constexpr bool kReduce = false;
+    __device__ double operator()(int x, int y, const double (&f)[9], double al) const
+    {
+        double r, u, v;
+        moments(f, gx, gy, al, r, u, v);
+        const size_t o = (size_t)y * opitch + x;
+        if (rho)
+            rho[o] = r;
+        if (ux)
+            ux[o] = u;
+        if (uy)
+            uy[o] = v;
+        return 0.0;
+    }
+};
+
+struct OpMass {
+    static constexpr bool kReduce = true;
+    __device__ double operator()(int, int, const double (&f)[9], double) const
+    {
+        return f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    }
+};
+
+struct OpColumnUx {
+    int x_col;
+    double gx, gy;
+    static constexpr bool kReduce = true;
+    __device__ double operator()(int x, int, const double (&f)[9], double al) const
+    {
+        if (x != x_col)
+            return 0.0;
+        double r, u, v;
+        moments(f, gx, gy, al, r, u, v);
+        return u;
+    }
+};
+
+template <class ST, class Op>
+__global__ __launch_bounds__(kBlock) void k_visit(DevState s, const typename ST::mem *st, int mode,
+                                                  Op op, double *partials)
+{
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    int x = 0, y = 0;
+    double f[9], al = 0.0;
+    double c = 0.0;
+    if (canonical_at<ST>(s, st, mode, gid, x, y, f, al))
+        c = op(x, y, f, al);
+    if constexpr (Op::kReduce) {
+        const double b = block_sum(c);
+        if (threadIdx.x == 0)
+            partials[blockIdx.x] = b;
+    }
+}
+
+// Fixed-order sum of the block partials (one block).
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restrict__ partials,
+                                                         uint32_t n, double *out)
+{
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock)
+        s += partials[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0)
+        *out = s;
+}
+
+// ------------------------------------------------------------ initial state --
+// Equilibrium (Eq. 6) at every node of a dense canonical buffer (solid slots
+// are filled too; nothing reads them).
+__global__ __launch_bounds__(kBlock) void k_equilibrium(int nx, int ny, int pitch,
+                                                        const double *__restrict__ rho,
+                                                        const double *__restrict__ ux,
+                                                        const double *__restrict__ uy,
+                                                        double *__restrict__ fc)
+{
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    const int y = (int)(gid / (uint32_t)pitch), x = (int)(gid - (uint32_t)y * pitch);
+    if (y >= ny || x >= nx)
+        return;
+    const size_t n = (size_t)y * nx + x;
+    const double r = rho ? rho[n] : 1.0, u = ux ? ux[n] : 0.0, v = uy ? uy[n] : 0.0;
+    const double usq = 1.5 * (u * u + v * v);
+    const uint32_t plane = (uint32_t)ny * pitch;
+    for (int i = 0; i < 9; ++i) {
+        const double cu = kCx[i] * u + kCy[i] * v;
+        fc[(uint32_t)i * plane + gid] = kW[i] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
+    }
+}
+
+// Canonical -> stored state.  For a pull A-B lattice the stored slot s_j(z)
+// must stream into f_j: s_j(z) = f_j(z + c_j) if z + c_j is fluid, else
+// f_opp(j)(z) (the inverse of the pull gather).  AA even: s_j(z) = f_j(z).
+// AA odd: s_j(z) = f_opp(j)(z - c_j) if z - c_j is fluid, else f_j(z).
+template <class ST>
+__global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem *st, int mode,
+                                                    const double *__restrict__ fc)
+{
+    using R = typename ST::real;
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    int x, y;
+    unsigned sm;
+    uint32_t own;
+    if (s.layout == kDenseAB || s.layout == kDenseAA) {
+        y = (int)(gid / (uint32_t)s.pitch);
+        x = (int)(gid - (uint32_t)y * s.pitch);
+        if (y >= s.ny || x >= s.nx)
+            return;
+        const uint8_t t = s.type[gid];
+        if (t == kSolid)
+            return;
+        sm = solid_bits(t, s.nmask, gid);
+        own = gid;
+    } else if (s.layout == kTiled16) {
+        const uint32_t k = gid / kTileNodes;
+        if (k >= (uint32_t)s.n_tiles)
+            return;
+        const int t = (int)(gid - k * kTileNodes);
+        const uint8_t ty = s.type[gid];
+        if (ty == kSolid)
+            return;
+        sm = solid_bits(ty, s.nmask, gid);
+        x = s.tile_xy[2 * k] * kTile + (t & 15);
+        y = s.tile_xy[2 * k + 1] * kTile + (t >> 4);
+        own = gid;
+    } else {
+        if (gid >= (uint32_t)s.n_fluid)
+            return;
+        uint32_t tmp[9];
+        sm = indirect_offsets(s.nbr, (uint32_t)s.plane, gid, tmp);
+        x = s.fluid_xy[2 * gid];
+        y = s.fluid_xy[2 * gid + 1];
+        own = gid;
+    }
+    uint32_t nb[9];  // canonical (dense-pitch) offsets of z - c_i
+    dense_offsets(x, y, s.nx, s.ny, s.pitch, nb);
+    const uint32_t pc = (uint32_t)s.ny * s.pitch;
+    for (int j = 0; j < 9; ++j) {
+        double v;
+        if (mode == kAAEven) {
+            v = fc[(uint32_t)j * pc + nb[0]];
+        } else if (mode == kAAOdd) {
+            v = ((sm >> j) & 1u) ? fc[(uint32_t)j * pc + nb[0]]
+                                 : fc[(uint32_t)kOpp[j] * pc + nb[j]];
+        } else {
+            // z + c_j is node z - c_opp(j)
+            v = ((sm >> kOpp[j]) & 1u) ? fc[(uint32_t)kOpp[j] * pc + nb[0]]
+                                       : fc[(uint32_t)j * pc + nb[kOpp[j]]];
+        }
+        st[(uint32_t)j * s.plane + own] = ST::from_canon(v, j);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double *p, size_t n, double v)
+{
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src,
+                                                   uint4 *__restrict__ dst, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- dispatch --
+template <class ST>
+hipError_t step_typed(const DevState &s, int64_t t, int cur)
+{
+    using M = typename ST::mem;
+    using R = typename ST::real;
+    const R om = (R)s.omega, gx = (R)s.gx, gy = (R)s.gy;
+    const bool drag = s.alpha != nullptr;
+    const M *src = (const M *)s.f[cur];
+    M *dst = (M *)s.f[1 - cur];
+    if (s.layout == kDenseAB || s.layout == kDenseAA) {
+        const uint32_t nbx = (uint32_t)((s.nx + kBlock - 1) / kBlock);
+        const uint32_t nblocks = nbx * (uint32_t)s.ny;
+        if (s.layout == kDenseAB) {
+            if (drag)
+                k_step_dense_ab<ST, true><<<nblocks, kBlock, 0, s.stream>>>(
+                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, (uint32_t)s.plane,
+                    nbx, nblocks, om, gx, gy);
+            else
+                k_step_dense_ab<ST, false><<<nblocks, kBlock, 0, s.stream>>>(
+                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, (uint32_t)s.plane,
+                    nbx, nblocks, om, gx, gy);
+        } else {
+            M *A = (M *)s.f[0];
+            const bool odd = (t & 1) != 0;
+#define LBM_AA(D, O)                                                                          \
+    k_step_dense_aa<ST, D, O><<<nblocks, kBlock, 0, s.stream>>>(                             \
+        A, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, (uint32_t)s.plane, nbx, nblocks, om, \
+        gx, gy)
+            if (drag) {
+                if (odd)
+                    LBM_AA(true, true);
+                else
+                    LBM_AA(true, false);
+            } else {
+                if (odd)
+                    LBM_AA(false, true);
+                else
+                    LBM_AA(false, false);
+            }
+#undef LBM_AA
+        }
+    } else if (s.layout == kTiled16) {
+        const uint32_t nt = (uint32_t)s.n_tiles;
+        if (nt == 0)
+            return hipSuccess;
+        if (drag)
+            k_step_tiled<ST, true><<<nt, kTileNodes, 0, s.stream>>>(
+                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, (uint32_t)s.plane, om, gx, gy);
+        else
+            k_step_tiled<ST, false><<<nt, kTileNodes, 0, s.stream>>>(
+                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, (uint32_t)s.plane, om, gx, gy);
+    } else {
+        const uint32_t nf = (uint32_t)s.n_fluid;
+        if (nf == 0)
+            return hipSuccess;
+        const uint32_t nblocks = (nf + kBlock - 1) / kBlock;
+        if (drag)
+            k_step_indirect<ST, true><<<nblocks, kBlock, 0, s.stream>>>(
+                src, dst, s.nbr, s.alpha, nf, (uint32_t)s.plane, nblocks, om, gx, gy);
+        else
+            k_step_indirect<ST, false><<<nblocks, kBlock, 0, s.stream>>>(
+                src, dst, s.nbr, s.alpha, nf, (uint32_t)s.plane, nblocks, om, gx, gy);
+    }
+    return hipGetLastError();
+}
+
+int mode_of(const DevState &s, int64_t t)
+{
+    if (s.layout == kDenseAA)
+        return (t & 1) ? kAAOdd : kAAEven;
+    return kPull;
+}
+
+// The lattice the canonical view is read from.
+const void *view_lattice(const DevState &s, int cur)
+{
+    return s.layout == kDenseAA ? s.f[0] : s.f[cur];
+}
+
+template <class ST, class Op>
+hipError_t visit_typed(const DevState &s, int64_t t, int cur, const Op &op, double *partials)
+{
+    const int64_t nb = visit_blocks(s);
+    if (nb == 0)
+        return hipSuccess;
+    k_visit<ST, Op><<<(uint32_t)nb, kBlock, 0, s.stream>>>(
+        s, (const typename ST::mem *)view_lattice(s, cur), mode_of(s, t), op, partials);
+    return hipGetLastError();
+}
+
+template <class Op>
+hipError_t visit(const DevState &s, int64_t t, int cur, const Op &op, double *partials)
+{
+    switch (s.dtype) {
+    case kF64: return visit_typed<F64>(s, t, cur, op, partials);
+    case kF32: return visit_typed<F32>(s, t, cur, op, partials);
+    case kF16S: return visit_typed<F16S>(s, t, cur, op, partials);
+    case kBF16S: return visit_typed<BF16S>(s, t, cur, op, partials);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class Op>
+hipError_t reduce(const DevState &s, int64_t t, int cur, const Op &op, double *out)
+{
+    const int64_t nb = visit_blocks(s);
+    if (nb > s.red_capacity)
+        return hipErrorInvalidValue;
+    if (nb == 0)
+        return launch_fill(out, 1, 0.0, s.stream);
+    hipError_t e = visit(s, t, cur, op, s.red_partials);
+    if (e != hipSuccess)
+        return e;
+    k_sum_partials<<<1, kBlock, 0, s.stream>>>(s.red_partials, (uint32_t)nb, out);
+    return hipGetLastError();
+}
+
+template <class ST>
+hipError_t scatter_typed(const DevState &s, int64_t t, int cur, const double *fc)
+{
+    const int64_t nb = visit_blocks(s);
+    if (nb == 0)
+        return hipSuccess;
+    void *dst = s.layout == kDenseAA ? s.f[0] : s.f[cur];
+    k_scatter<ST><<<(uint32_t)nb, kBlock, 0, s.stream>>>(s, (typename ST::mem *)dst,
+                                                         mode_of(s, t), fc);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t visit_blocks(const DevState &s)
+{
+    if (s.layout == kDenseAB || s.layout == kDenseAA)
+        return ((int64_t)s.ny * s.pitch + kBlock - 1) / kBlock;
+    if (s.layout == kTiled16)
+        return s.n_tiles;  // kTileNodes == kBlock
+    return (s.n_fluid + kBlock - 1) / kBlock;
+}
+
+hipError_t launch_step(const DevState &s, int64_t t, int cur)
+{
+    switch (s.dtype) {
+    case kF64: return step_typed<F64>(s, t, cur);
+    case kF32: return step_typed<F32>(s, t, cur);
+    case kF16S: return step_typed<F16S>(s, t, cur);
+    case kBF16S: return step_typed<BF16S>(s, t, cur);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const double *fc)
+{
+    switch (s.dtype) {
+    case kF64: return scatter_typed<F64>(s, t, cur, fc);
+    case kF32: return scatter_typed<F32>(s, t, cur, fc);
+    case kF16S: return scatter_typed<F16S>(s, t, cur, fc);
+    case kBF16S: return scatter_typed<BF16S>(s, t, cur, fc);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_equilibrium(const DevState &s, const double *rho, const double *ux,
+                              const double *uy, double *fc)
+{
+    const int64_t n = (int64_t)s.ny * s.pitch;
+    const uint32_t blocks = (uint32_t)((n + kBlock - 1) / kBlock);
+    k_equilibrium<<<blocks, kBlock, 0, s.stream>>>(s.nx, s.ny, s.pitch, rho, ux, uy, fc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_canonical(const DevState &s, int64_t t, int cur, double *fc)
+{
+    OpCanonical op{fc, (uint32_t)s.ny * (uint32_t)s.pitch, s.pitch};
+    return visit(s, t, cur, op, nullptr);
+}
+
+hipError_t launch_macroscopic(const DevState &s, int64_t t, int cur, double *rho, double *ux,
+                              double *uy)
+{
+    OpMacro op{rho, ux, uy, s.nx, s.gx, s.gy};
+    return visit(s, t, cur, op, nullptr);
+}
+
+hipError_t launch_mass(const DevState &s, int64_t t, int cur, double *out)
+{
+    return reduce(s, t, cur, OpMass{}, out);
+}
+
+hipError_t launch_column_ux(const DevState &s, int64_t t, int cur, int x_col, double *out)
+{
+    return reduce(s, t, cur, OpColumnUx{x_col, s.gx, s.gy}, out);
+}
+
+hipError_t launch_fill(double *p, size_t n, double v, hipStream_t stream)
+{
+    if (n == 0)
+        return hipSuccess;
+    size_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 65536)
+        blocks = 65536;
+    k_fill<<<(uint32_t)blocks, kBlock, 0, stream>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t stream)
+{
+    const size_t n = bytes / 16;
+    if (n == 0)
+        return hipSuccess;
+    size_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 262144)
+        blocks = 262144;
+    k_copy16<<<(uint32_t)blocks, kBlock, 0, stream>>>((const uint4 *)src, (uint4 *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,85 @@
+// Internal interface between the host runtime (lbm_runtime.cpp) and the HIP
+// kernels (lbm_kernels.hip, lbm_adjoint.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Dtype : int { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+enum Layout : int { kDenseAB = 0, kDenseAA = 1, kTiled16 = 2, kIndirect = 3 };
+
+constexpr int kTile = 16;
+constexpr int kTileNodes = kTile * kTile;
+
+// Everything a kernel launch needs to know about a context's device state.
+struct DevState {
+    int dtype = 0, layout = 0;
+    int nx = 0, ny = 0;
+    int pitch = 0;        // dense: row pitch in elements (multiple of 64)
+    size_t plane = 0;     // elements per population plane of one lattice
+    void *f[2] = {nullptr, nullptr};  // lattices (f[1] unused by DENSE_AA)
+    const uint8_t *type = nullptr;    // node-type codes (dense / tiled)
+    const uint8_t *nmask = nullptr;   // solid-neighbour bits (dense / tiled)
+    const float *alpha = nullptr;     // drag coefficient, same indexing as type
+                                      // (INDIRECT: per compacted node); may be null
+    const int32_t *tile_xy = nullptr, *tile_nbr = nullptr;  // TILED16
+    const int32_t *nbr = nullptr, *fluid_xy = nullptr;      // INDIRECT
+    int64_t n_tiles = 0, n_fluid = 0;
+    double omega = 1.0, gx = 0.0, gy = 0.0;
+    hipStream_t stream = nullptr;
+    double *red_partials = nullptr;   // reduction scratch (>= red_capacity doubles)
+    unsigned *red_counter = nullptr;  // zero between reductions
+    int64_t red_capacity = 0;
+};
+
+// Number of thread blocks the visit / reduction kernels use for this layout.
+int64_t visit_blocks(const DevState &s);
+
+// One time step from lattice `cur` (A-B layouts write lattice 1 - cur).  For
+// DENSE_AA, t is the number of steps already taken (its parity picks the
+// even or odd kernel).
+hipError_t launch_step(const DevState &s, int64_t t, int cur);
+
+// Canonical populations fc (device FP64 [9][ny][nx]) -> stored state at step t.
+hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const double *fc);
+// Equilibrium (Eq. 6) from device FP64 [ny][nx] fields (null = rest) -> fc.
+hipError_t launch_equilibrium(const DevState &s, const double *rho, const double *ux,
+                              const double *uy, double *fc);
+// Stored state -> canonical fc (solid slots untouched: clear them first).
+hipError_t launch_gather_canonical(const DevState &s, int64_t t, int cur, double *fc);
+// Macroscopic fields of fluid nodes (solid entries untouched).
+hipError_t launch_macroscopic(const DevState &s, int64_t t, int cur, double *rho, double *ux,
+                              double *uy);
+// Deterministic FP64 sums over fluid nodes into *out (device): total mass, or
+// the sum of u_x over the fluid nodes of column x_col.
+hipError_t launch_mass(const DevState &s, int64_t t, int cur, double *out);
+hipError_t launch_column_ux(const DevState &s, int64_t t, int cur, int x_col, double *out);
+
+hipError_t launch_fill(double *p, size_t n, double v, hipStream_t stream);
+hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t stream);
+
+// ---- adjoint (DENSE_AB, F64 / F32) --------------------------------------
+// Adjoint fields are dense [9][ny][pitch] in the compute type.  dJ/dg block
+// partials are pairs (x, y) per block.
+int64_t adjoint_blocks(const DevState &s);       // blocks of one adjoint step
+int64_t adjoint_seed_blocks(const DevState &s);  // blocks of the seed kernel
+// lambda_T of J = scale * sum of u_x over the fluid nodes of column x_col, read
+// from the stored lattice `state`; direct dJ/dalpha terms into grad_alpha (if
+// a drag field is set) and dJ/dg partials (one pair per seed block).
+hipError_t launch_adjoint_seed_raw(const DevState &s, const void *state, int x_col, double scale,
+                                   void *mu, double *grad_alpha, double *partials);
+// One reverse step: state = stored lattice at step t, mu_in = lambda_{t+1};
+// writes lambda_t, adds to grad_alpha, writes (accumulate = 0) or adds
+// (accumulate = 1) the per-block dJ/dg partials.
+hipError_t launch_adjoint_step_raw(const DevState &s, const void *state, const void *mu_in,
+                                   void *mu_out, double *grad_alpha, double *partials,
+                                   int accumulate);
+// grad_g[0..1] += fixed-order sum of n partial pairs.
+hipError_t launch_partials_into(const double *partials, int64_t n, double *grad_g,
+                                hipStream_t stream);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
+
+}  // namespace lbm

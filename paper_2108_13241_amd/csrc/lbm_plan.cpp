@@ -1,0 +1,118 @@
+// Geometry preprocessing: the node-type field with its neighbour bits (Sec. 3
+// stores a node type plus a bitmask of present neighbours), the compacted list
+// of non-empty 16 x 16 tiles with a tile-neighbour table (the "pointer tile"
+// layout of Sec. 4.3), and the compacted fluid-node list with a per-node
+// neighbour table (fluid index array, Sec. 1).
+#include "lbm_plan.h"
+
+namespace lbm {
+namespace plan {
+
+static inline int wrapi(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+uint8_t solid_neighbours(const uint8_t *mask, int nx, int ny, int x, int y)
+{
+    uint8_t bits = 0;
+    for (int i = 1; i < 9; ++i) {
+        const int sx = wrapi(x - kHostCx[i], nx), sy = wrapi(y - kHostCy[i], ny);
+        if (mask[(size_t)sy * nx + sx] != 0)
+            bits |= (uint8_t)(1u << (i - 1));
+    }
+    return bits;
+}
+
+void dense_types(const uint8_t *mask, int nx, int ny, int pitch, std::vector<uint8_t> &type,
+                 std::vector<uint8_t> &nmask)
+{
+    type.assign((size_t)ny * pitch, 1);
+    nmask.assign((size_t)ny * pitch, 0);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t o = (size_t)y * pitch + x;
+            if (mask[(size_t)y * nx + x] != 0)
+                continue;
+            const uint8_t b = solid_neighbours(mask, nx, ny, x, y);
+            type[o] = b ? 2 : 0;
+            nmask[o] = b;
+        }
+}
+
+Tiles tiles16(const uint8_t *mask, int nx, int ny)
+{
+    Tiles t;
+    const int tx_n = nx / 16, ty_n = ny / 16;
+    t.index_of.assign((size_t)tx_n * ty_n, -1);
+    for (int ty = 0; ty < ty_n; ++ty)
+        for (int tx = 0; tx < tx_n; ++tx) {
+            bool any = false;
+            for (int ly = 0; ly < 16 && !any; ++ly)
+                for (int lx = 0; lx < 16; ++lx)
+                    if (mask[(size_t)(ty * 16 + ly) * nx + tx * 16 + lx] == 0) {
+                        any = true;
+                        break;
+                    }
+            if (any) {
+                t.index_of[(size_t)ty * tx_n + tx] = (int32_t)t.n_tiles++;
+                t.xy.push_back(tx);
+                t.xy.push_back(ty);
+            }
+        }
+    t.nbr.assign((size_t)t.n_tiles * 9, -1);
+    for (int64_t k = 0; k < t.n_tiles; ++k) {
+        const int tx = t.xy[2 * k], ty = t.xy[2 * k + 1];
+        for (int d = 0; d < 9; ++d) {
+            const int ux = wrapi(tx + kHostCx[d], tx_n), uy = wrapi(ty + kHostCy[d], ty_n);
+            t.nbr[(size_t)k * 9 + d] = t.index_of[(size_t)uy * tx_n + ux];
+        }
+    }
+    return t;
+}
+
+void tiled_types(const uint8_t *mask, int nx, int ny, const Tiles &t, std::vector<uint8_t> &type,
+                 std::vector<uint8_t> &nmask)
+{
+    type.assign((size_t)t.n_tiles * 256, 1);
+    nmask.assign((size_t)t.n_tiles * 256, 0);
+    for (int64_t k = 0; k < t.n_tiles; ++k)
+        for (int l = 0; l < 256; ++l) {
+            const int x = t.xy[2 * k] * 16 + (l & 15), y = t.xy[2 * k + 1] * 16 + (l >> 4);
+            if (mask[(size_t)y * nx + x] != 0)
+                continue;
+            const uint8_t b = solid_neighbours(mask, nx, ny, x, y);
+            type[(size_t)k * 256 + l] = b ? 2 : 0;
+            nmask[(size_t)k * 256 + l] = b;
+        }
+}
+
+Fluid fluid_list(const uint8_t *mask, int nx, int ny)
+{
+    Fluid f;
+    f.index_of.assign((size_t)nx * ny, -1);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            if (mask[(size_t)y * nx + x] == 0) {
+                f.index_of[(size_t)y * nx + x] = (int32_t)f.n_fluid++;
+                f.xy.push_back(x);
+                f.xy.push_back(y);
+            }
+    return f;
+}
+
+void indirect_neighbours(const Fluid &fl, int nx, int ny, int64_t plane, std::vector<int32_t> &nbr)
+{
+    nbr.assign((size_t)8 * plane, -1);
+    for (int64_t n = 0; n < fl.n_fluid; ++n) {
+        const int x = fl.xy[2 * n], y = fl.xy[2 * n + 1];
+        for (int i = 1; i < 9; ++i) {
+            const int sx = wrapi(x - kHostCx[i], nx), sy = wrapi(y - kHostCy[i], ny);
+            nbr[(size_t)(i - 1) * plane + n] = fl.index_of[(size_t)sy * nx + sx];
+        }
+    }
+}
+
+}  // namespace plan
+}  // namespace lbm

@@ -1,0 +1,838 @@
+// C ABI of the D2Q9 lattice-Boltzmann library: context management, argument
+// checks, geometry preprocessing, device buffers and kernel sequencing.  All
+// arithmetic of the method runs in the HIP kernels; this file only plans,
+// allocates, copies and enqueues.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lbm_launch.h"
+#include "lbm_plan.h"
+
+namespace {
+
+struct Allocator {
+    lbm_alloc_fn alloc = nullptr;
+    lbm_free_fn free = nullptr;
+    void *user = nullptr;
+};
+
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+thread_local std::string t_last_error = "no error";
+
+int fail_tl(int status, const std::string &msg)
+{
+    t_last_error = msg;
+    return status;
+}
+
+int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm::DevState s;
+    Allocator alloc;
+    int device = 0;
+    int64_t t = 0;  // steps since (re)initialisation
+    int cur = 0;    // A-B layouts: lattice holding the current state
+    bool broken = false;
+    std::string last_error = "no error";
+    std::vector<uint8_t> mask;  // host copy [ny][nx]
+    std::vector<std::pair<void *, size_t>> owned;
+    size_t device_bytes = 0;
+    int pop_bytes = 8;
+    float *alpha_buf = nullptr;
+    lbm::plan::Tiles tiles;
+    lbm::plan::Fluid fluid;
+    int64_t n_fluid = 0;
+    double *red_out = nullptr;  // device scratch for reduction results
+    // adjoint scratch (allocated on first use)
+    double *adj_partials = nullptr;
+    int64_t adj_capacity = 0;
+    void *mu_buf[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+int fail(lbm_ctx *c, int status, const std::string &msg)
+{
+    c->last_error = msg;
+    return status;
+}
+
+int fail_device(lbm_ctx *c, hipError_t e, const char *what)
+{
+    c->broken = true;
+    c->last_error = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+    return LBM_ERR_DEVICE;
+}
+
+#define LBM_HIP(c, expr)                                  \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess)                             \
+            return fail_device((c), e_, #expr);           \
+    } while (0)
+
+#define LBM_CHECK_CTX(c)                                                        \
+    do {                                                                        \
+        if (!(c))                                                               \
+            return fail_tl(LBM_ERR_INVALID, "context is NULL");                 \
+        if ((c)->broken)                                                        \
+            return fail((c), LBM_ERR_STATE, "context broken by an earlier error: " + (c)->last_error); \
+    } while (0)
+
+void *raw_alloc(const Allocator &a, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 256;
+    if (a.alloc)
+        return a.alloc(bytes, a.user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        return nullptr;
+    return p;
+}
+
+void raw_free(const Allocator &a, void *p)
+{
+    if (!p)
+        return;
+    if (a.free)
+        a.free(p, a.user);
+    else
+        (void)hipFree(p);
+}
+
+// Owned device buffer (released in lbm_destroy).
+void *own_alloc(lbm_ctx *c, size_t bytes)
+{
+    void *p = raw_alloc(c->alloc, bytes);
+    if (p) {
+        c->owned.emplace_back(p, bytes);
+        c->device_bytes += bytes;
+    }
+    return p;
+}
+
+// Scoped temporary device buffer.
+struct Temp {
+    lbm_ctx *c;
+    void *p = nullptr;
+    Temp(lbm_ctx *c_, size_t bytes) : c(c_) { p = raw_alloc(c->alloc, bytes); }
+    ~Temp()
+    {
+        if (p) {
+            (void)hipStreamSynchronize(c->s.stream);
+            raw_free(c->alloc, p);
+        }
+    }
+    Temp(const Temp &) = delete;
+    Temp &operator=(const Temp &) = delete;
+};
+
+int pop_bytes_of(int dtype) { return dtype == LBM_F64 ? 8 : dtype == LBM_F32 ? 4 : 2; }
+
+size_t canonical_bytes(const lbm_ctx *c) { return (size_t)9 * c->s.ny * c->s.pitch * sizeof(double); }
+
+// Canonical host [9][ny][nx] <-> device [9][ny][pitch].
+int canonical_to_host(lbm_ctx *c, const double *fc_dev, double *host)
+{
+    const size_t w = (size_t)c->s.nx * sizeof(double);
+    LBM_HIP(c, hipMemcpy2DAsync(host, w, fc_dev, (size_t)c->s.pitch * sizeof(double), w,
+                                (size_t)9 * c->s.ny, hipMemcpyDeviceToHost, c->s.stream));
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int scatter_from_device_canonical(lbm_ctx *c, const double *fc_dev)
+{
+    LBM_HIP(c, lbm::launch_scatter_canonical(c->s, c->t, c->cur, fc_dev));
+    return LBM_OK;
+}
+
+int init_state(lbm_ctx *c, const double *rho, const double *ux, const double *uy)
+{
+    const size_t field = (size_t)c->s.nx * c->s.ny * sizeof(double);
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    const double *h[3] = {rho, ux, uy};
+    Temp d0(c, h[0] ? field : 0), d1(c, h[1] ? field : 0), d2(c, h[2] ? field : 0);
+    Temp *d[3] = {&d0, &d1, &d2};
+    const double *dp[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < 3; ++k)
+        if (h[k]) {
+            if (!d[k]->p)
+                return fail(c, LBM_ERR_NOMEM, "cannot allocate the field staging buffer");
+            LBM_HIP(c, hipMemcpyAsync(d[k]->p, h[k], field, hipMemcpyHostToDevice, c->s.stream));
+            dp[k] = (const double *)d[k]->p;
+        }
+    c->t = 0;
+    c->cur = 0;
+    LBM_HIP(c, lbm::launch_equilibrium(c->s, dp[0], dp[1], dp[2], (double *)fc.p));
+    int rc = scatter_from_device_canonical(c, (const double *)fc.p);
+    if (rc)
+        return rc;
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+bool finite2(const double *v) { return !v || (std::isfinite(v[0]) && std::isfinite(v[1])); }
+
+}  // namespace
+
+extern "C" {
+
+int lbm_set_allocator(lbm_alloc_fn alloc, lbm_free_fn free_fn, void *user)
+{
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail_tl(LBM_ERR_INVALID, "allocator and free function must both be set or both NULL");
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_fn;
+    g_alloc.user = user;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c)
+{
+    if (!c)
+        return;
+    (void)hipStreamSynchronize(c->s.stream);
+    for (auto &b : c->owned)
+        raw_free(c->alloc, b.first);
+    delete c;
+}
+
+int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, double tau,
+               const double *force, lbm_dtype dtype, lbm_layout layout)
+{
+    if (!out)
+        return fail_tl(LBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1)
+        return fail_tl(LBM_ERR_INVALID, "nx and ny must be >= 1");
+    if (!node_type)
+        return fail_tl(LBM_ERR_INVALID, "node_type is NULL");
+    if (!std::isfinite(tau) || !(tau > 0.5))
+        return fail_tl(LBM_ERR_INVALID, "tau must be finite and > 1/2");
+    if (!finite2(force))
+        return fail_tl(LBM_ERR_INVALID, "force must be finite");
+    if ((int)dtype < 0 || (int)dtype > 3)
+        return fail_tl(LBM_ERR_INVALID, "unknown dtype");
+    if ((int)layout < 0 || (int)layout > 3)
+        return fail_tl(LBM_ERR_INVALID, "unknown layout");
+    const size_t nn = (size_t)nx * ny;
+    for (size_t k = 0; k < nn; ++k)
+        if (node_type[k] > 1)
+            return fail_tl(LBM_ERR_INVALID, "node_type values must be 0 (fluid) or 1 (solid)");
+    if (layout == LBM_TILED16 && (nx % 16 != 0 || ny % 16 != 0))
+        return fail_tl(LBM_ERR_UNSUPPORTED, "TILED16 needs nx and ny to be multiples of 16");
+    const int64_t pitch = round_up(nx, 64);
+    if ((int64_t)9 * ny * pitch >= (int64_t(1) << 32))
+        return fail_tl(LBM_ERR_UNSUPPORTED, "mesh too large for 32-bit lattice offsets");
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c)
+        return fail_tl(LBM_ERR_NOMEM, "cannot allocate the context");
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        c->alloc = g_alloc;
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail_tl(LBM_ERR_DEVICE, "no HIP device");
+    }
+    lbm::DevState &s = c->s;
+    s.dtype = dtype;
+    s.layout = layout;
+    s.nx = nx;
+    s.ny = ny;
+    s.pitch = (int)pitch;
+    s.omega = 1.0 / tau;
+    s.gx = force ? force[0] : 0.0;
+    s.gy = force ? force[1] : 0.0;
+    s.stream = nullptr;
+    c->pop_bytes = pop_bytes_of(dtype);
+    c->mask.assign(node_type, node_type + nn);
+    for (size_t k = 0; k < nn; ++k)
+        c->n_fluid += node_type[k] == 0;
+
+    // Geometry preprocessing (host) and device index structures.
+    std::vector<uint8_t> type, nmask;
+    auto fail_create = [&](int st, const std::string &m) {
+        t_last_error = m;
+        lbm_destroy(c);
+        return st;
+    };
+    auto upload = [&](const void *h, size_t bytes, void **dst) -> int {
+        *dst = own_alloc(c, bytes);
+        if (!*dst)
+            return LBM_ERR_NOMEM;
+        if (bytes && hipMemcpy(*dst, h, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return LBM_ERR_DEVICE;
+        return LBM_OK;
+    };
+    int rc = LBM_OK;
+    void *p = nullptr;
+    if (layout == LBM_DENSE_AB || layout == LBM_DENSE_AA) {
+        lbm::plan::dense_types(node_type, nx, ny, (int)pitch, type, nmask);
+        s.plane = (size_t)ny * pitch;
+    } else if (layout == LBM_TILED16) {
+        c->tiles = lbm::plan::tiles16(node_type, nx, ny);
+        lbm::plan::tiled_types(node_type, nx, ny, c->tiles, type, nmask);
+        s.n_tiles = c->tiles.n_tiles;
+        s.plane = (size_t)std::max<int64_t>(s.n_tiles, 1) * lbm::kTileNodes;
+        if ((rc = upload(c->tiles.xy.data(), c->tiles.xy.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the tile list");
+        s.tile_xy = (const int32_t *)p;
+        if ((rc = upload(c->tiles.nbr.data(), c->tiles.nbr.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the tile-neighbour table");
+        s.tile_nbr = (const int32_t *)p;
+    } else {
+        c->fluid = lbm::plan::fluid_list(node_type, nx, ny);
+        s.n_fluid = c->fluid.n_fluid;
+        s.plane = (size_t)round_up(std::max<int64_t>(s.n_fluid, 1), 64);
+        std::vector<int32_t> nbr;
+        lbm::plan::indirect_neighbours(c->fluid, nx, ny, (int64_t)s.plane, nbr);
+        if ((rc = upload(c->fluid.xy.data(), c->fluid.xy.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the fluid list");
+        s.fluid_xy = (const int32_t *)p;
+        if ((rc = upload(nbr.data(), nbr.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the neighbour table");
+        s.nbr = (const int32_t *)p;
+    }
+    if ((uint64_t)9 * s.plane >= (uint64_t(1) << 32))
+        return fail_create(LBM_ERR_UNSUPPORTED, "lattice too large for 32-bit offsets");
+    if (!type.empty()) {
+        if ((rc = upload(type.data(), type.size(), &p)))
+            return fail_create(rc, "cannot upload the node types");
+        s.type = (const uint8_t *)p;
+        if ((rc = upload(nmask.data(), nmask.size(), &p)))
+            return fail_create(rc, "cannot upload the neighbour masks");
+        s.nmask = (const uint8_t *)p;
+    }
+    const size_t lattice = (size_t)9 * s.plane * c->pop_bytes;
+    const int nlat = layout == LBM_DENSE_AA ? 1 : 2;
+    for (int k = 0; k < nlat; ++k) {
+        s.f[k] = own_alloc(c, lattice);
+        if (!s.f[k])
+            return fail_create(LBM_ERR_NOMEM, "cannot allocate the lattice");
+    }
+    s.red_capacity = std::max<int64_t>(lbm::visit_blocks(s), 1);
+    s.red_partials = (double *)own_alloc(c, (size_t)s.red_capacity * sizeof(double));
+    c->red_out = (double *)own_alloc(c, 8 * sizeof(double));
+    if (!s.red_partials || !c->red_out)
+        return fail_create(LBM_ERR_NOMEM, "cannot allocate reduction scratch");
+    rc = init_state(c, nullptr, nullptr, nullptr);
+    if (rc)
+        return fail_create(rc, c->last_error);
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_set_stream(lbm_ctx *c, void *hip_stream)
+{
+    LBM_CHECK_CTX(c);
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    c->s.stream = (hipStream_t)hip_stream;
+    return LBM_OK;
+}
+
+int lbm_init_equilibrium(lbm_ctx *c, const double *rho, const double *ux, const double *uy)
+{
+    LBM_CHECK_CTX(c);
+    const size_t nn = (size_t)c->s.nx * c->s.ny;
+    for (size_t k = 0; k < nn; ++k) {
+        if (c->mask[k] != 0)
+            continue;
+        if ((rho && !(std::isfinite(rho[k]) && rho[k] > 0)) || (ux && !std::isfinite(ux[k])) ||
+            (uy && !std::isfinite(uy[k])))
+            return fail(c, LBM_ERR_INVALID, "initial fields must be finite with rho > 0");
+    }
+    return init_state(c, rho, ux, uy);
+}
+
+int lbm_set_porosity(lbm_ctx *c, const float *alpha)
+{
+    LBM_CHECK_CTX(c);
+    lbm::DevState &s = c->s;
+    if (!alpha) {
+        s.alpha = nullptr;
+        return LBM_OK;
+    }
+    const size_t nn = (size_t)s.nx * s.ny;
+    for (size_t k = 0; k < nn; ++k)
+        if (!(alpha[k] >= 0.0f && alpha[k] <= 1.0f))
+            return fail(c, LBM_ERR_INVALID, "alpha values must lie in [0, 1]");
+    std::vector<float> a;
+    if (s.layout == LBM_DENSE_AB || s.layout == LBM_DENSE_AA) {
+        a.assign((size_t)s.ny * s.pitch, 0.0f);
+        for (int y = 0; y < s.ny; ++y)
+            std::memcpy(&a[(size_t)y * s.pitch], alpha + (size_t)y * s.nx, (size_t)s.nx * 4);
+    } else if (s.layout == LBM_TILED16) {
+        a.assign(s.plane, 0.0f);
+        for (int64_t k = 0; k < s.n_tiles; ++k)
+            for (int l = 0; l < lbm::kTileNodes; ++l) {
+                const int x = c->tiles.xy[2 * k] * 16 + (l & 15);
+                const int y = c->tiles.xy[2 * k + 1] * 16 + (l >> 4);
+                a[(size_t)k * lbm::kTileNodes + l] = alpha[(size_t)y * s.nx + x];
+            }
+    } else {
+        a.assign(s.plane, 0.0f);
+        for (int64_t n = 0; n < s.n_fluid; ++n)
+            a[n] = alpha[(size_t)c->fluid.xy[2 * n + 1] * s.nx + c->fluid.xy[2 * n]];
+    }
+    if (!c->alpha_buf) {
+        c->alpha_buf = (float *)own_alloc(c, a.size() * sizeof(float));
+        if (!c->alpha_buf)
+            return fail(c, LBM_ERR_NOMEM, "cannot allocate the porosity field");
+    }
+    LBM_HIP(c, hipMemcpyAsync(c->alpha_buf, a.data(), a.size() * sizeof(float),
+                              hipMemcpyHostToDevice, c->s.stream));
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    s.alpha = c->alpha_buf;
+    return LBM_OK;
+}
+
+int lbm_set_force(lbm_ctx *c, const double *force)
+{
+    LBM_CHECK_CTX(c);
+    if (!force || !finite2(force))
+        return fail(c, LBM_ERR_INVALID, "force must be two finite numbers");
+    c->s.gx = force[0];
+    c->s.gy = force[1];
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n)
+{
+    LBM_CHECK_CTX(c);
+    if (n < 0)
+        return fail(c, LBM_ERR_INVALID, "n must be >= 0");
+    for (int64_t k = 0; k < n; ++k) {
+        LBM_HIP(c, lbm::launch_step(c->s, c->t, c->cur));
+        if (c->s.layout != LBM_DENSE_AA)
+            c->cur ^= 1;
+        ++c->t;
+    }
+    return LBM_OK;
+}
+
+int lbm_macroscopic_device(lbm_ctx *c, void *rho, void *ux, void *uy)
+{
+    LBM_CHECK_CTX(c);
+    const size_t nn = (size_t)c->s.nx * c->s.ny;
+    double *o[3] = {(double *)rho, (double *)ux, (double *)uy};
+    for (double *p : o)
+        if (p)
+            LBM_HIP(c, lbm::launch_fill(p, nn, 0.0, c->s.stream));
+    LBM_HIP(c, lbm::launch_macroscopic(c->s, c->t, c->cur, o[0], o[1], o[2]));
+    return LBM_OK;
+}
+
+int lbm_macroscopic(lbm_ctx *c, double *rho, double *ux, double *uy)
+{
+    LBM_CHECK_CTX(c);
+    const size_t bytes = (size_t)c->s.nx * c->s.ny * sizeof(double);
+    Temp d(c, 3 * bytes);
+    if (!d.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the output staging buffer");
+    char *b = (char *)d.p;
+    int rc = lbm_macroscopic_device(c, rho ? b : nullptr, ux ? b + bytes : nullptr,
+                                    uy ? b + 2 * bytes : nullptr);
+    if (rc)
+        return rc;
+    double *h[3] = {rho, ux, uy};
+    for (int k = 0; k < 3; ++k)
+        if (h[k])
+            LBM_HIP(c, hipMemcpyAsync(h[k], b + k * bytes, bytes, hipMemcpyDeviceToHost,
+                                      c->s.stream));
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx *c, double *f)
+{
+    LBM_CHECK_CTX(c);
+    if (!f)
+        return fail(c, LBM_ERR_INVALID, "f is NULL");
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    LBM_HIP(c, lbm::launch_fill((double *)fc.p, canonical_bytes(c) / 8, 0.0, c->s.stream));
+    LBM_HIP(c, lbm::launch_gather_canonical(c->s, c->t, c->cur, (double *)fc.p));
+    return canonical_to_host(c, (const double *)fc.p, f);
+}
+
+int lbm_set_populations(lbm_ctx *c, const double *f)
+{
+    LBM_CHECK_CTX(c);
+    if (!f)
+        return fail(c, LBM_ERR_INVALID, "f is NULL");
+    const size_t nn = (size_t)c->s.nx * c->s.ny;
+    for (int i = 0; i < 9; ++i)
+        for (size_t k = 0; k < nn; ++k)
+            if (c->mask[k] == 0 && !std::isfinite(f[i * nn + k]))
+                return fail(c, LBM_ERR_INVALID, "populations must be finite at fluid nodes");
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    const size_t w = (size_t)c->s.nx * sizeof(double);
+    LBM_HIP(c, hipMemcpy2DAsync(fc.p, (size_t)c->s.pitch * sizeof(double), f, w, w,
+                                (size_t)9 * c->s.ny, hipMemcpyHostToDevice, c->s.stream));
+    int rc = scatter_from_device_canonical(c, (const double *)fc.p);
+    if (rc)
+        return rc;
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_mass(lbm_ctx *c, double *mass)
+{
+    LBM_CHECK_CTX(c);
+    if (!mass)
+        return fail(c, LBM_ERR_INVALID, "mass is NULL");
+    LBM_HIP(c, lbm::launch_mass(c->s, c->t, c->cur, c->red_out));
+    LBM_HIP(c, hipMemcpyAsync(mass, c->red_out, sizeof(double), hipMemcpyDeviceToHost,
+                              c->s.stream));
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes)
+        return fail_tl(LBM_ERR_INVALID, "NULL argument");
+    *bytes = (size_t)9 * c->s.plane * c->pop_bytes;
+    return LBM_OK;
+}
+
+static void *state_lattice(lbm_ctx *c) { return c->s.layout == LBM_DENSE_AA ? c->s.f[0] : c->s.f[c->cur]; }
+
+int lbm_save_state(lbm_ctx *c, void *dev_dst)
+{
+    LBM_CHECK_CTX(c);
+    if (!dev_dst)
+        return fail(c, LBM_ERR_INVALID, "destination is NULL");
+    size_t b = 0;
+    lbm_state_bytes(c, &b);
+    LBM_HIP(c, hipMemcpyAsync(dev_dst, state_lattice(c), b, hipMemcpyDeviceToDevice, c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx *c, const void *dev_src)
+{
+    LBM_CHECK_CTX(c);
+    if (!dev_src)
+        return fail(c, LBM_ERR_INVALID, "source is NULL");
+    size_t b = 0;
+    lbm_state_bytes(c, &b);
+    LBM_HIP(c, hipMemcpyAsync(state_lattice(c), dev_src, b, hipMemcpyDeviceToDevice, c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_objective_outlet_ux(lbm_ctx *c, int32_t x_col, double *J)
+{
+    LBM_CHECK_CTX(c);
+    if (!J || x_col < 0 || x_col >= c->s.nx)
+        return fail(c, LBM_ERR_INVALID, "bad outlet column or NULL J");
+    int64_t n_out = 0;
+    for (int y = 0; y < c->s.ny; ++y)
+        n_out += c->mask[(size_t)y * c->s.nx + x_col] == 0;
+    if (n_out == 0)
+        return fail(c, LBM_ERR_INVALID, "the outlet column has no fluid node");
+    LBM_HIP(c, lbm::launch_column_ux(c->s, c->t, c->cur, x_col, c->red_out));
+    double sum = 0.0;
+    LBM_HIP(c, hipMemcpyAsync(&sum, c->red_out, sizeof(double), hipMemcpyDeviceToHost,
+                              c->s.stream));
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    *J = sum / (double)n_out;
+    return LBM_OK;
+}
+
+static int adjoint_supported(lbm_ctx *c)
+{
+    if (c->s.layout != LBM_DENSE_AB || (c->s.dtype != LBM_F64 && c->s.dtype != LBM_F32))
+        return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
+    return LBM_OK;
+}
+
+static size_t adjoint_field_bytes(const lbm_ctx *c)
+{
+    return (size_t)9 * c->s.ny * c->s.pitch * (c->s.dtype == LBM_F64 ? 8 : 4);
+}
+
+// Per-block dJ/dg partial pairs for the seed and step kernels.
+static int ensure_adjoint_scratch(lbm_ctx *c)
+{
+    const int64_t need = 2 * std::max(lbm::adjoint_blocks(c->s), lbm::adjoint_seed_blocks(c->s));
+    if (c->adj_capacity >= need)
+        return LBM_OK;
+    c->adj_partials = (double *)own_alloc(c, (size_t)need * sizeof(double));
+    if (!c->adj_partials)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate adjoint scratch");
+    c->adj_capacity = need;
+    return LBM_OK;
+}
+
+static int outlet_count(lbm_ctx *c, int32_t x_col, int64_t *n_out)
+{
+    if (x_col < 0 || x_col >= c->s.nx)
+        return fail(c, LBM_ERR_INVALID, "outlet column out of range");
+    int64_t n = 0;
+    for (int y = 0; y < c->s.ny; ++y)
+        n += c->mask[(size_t)y * c->s.nx + x_col] == 0;
+    if (n == 0)
+        return fail(c, LBM_ERR_INVALID, "the outlet column has no fluid node");
+    *n_out = n;
+    return LBM_OK;
+}
+
+static int check_grads(lbm_ctx *c, double *grad_alpha, double *grad_g)
+{
+    if (!grad_g)
+        return fail(c, LBM_ERR_INVALID, "grad_g_dev is NULL");
+    if (c->s.alpha && !grad_alpha)
+        return fail(c, LBM_ERR_INVALID, "grad_alpha_dev is NULL while a porosity field is set");
+    return LBM_OK;
+}
+
+int lbm_adjoint_bytes(const lbm_ctx *c, size_t *bytes, int32_t *pitch)
+{
+    if (!c || !bytes)
+        return fail_tl(LBM_ERR_INVALID, "NULL argument");
+    if (c->s.layout != LBM_DENSE_AB || (c->s.dtype != LBM_F64 && c->s.dtype != LBM_F32))
+        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
+    *bytes = adjoint_field_bytes(c);
+    if (pitch)
+        *pitch = c->s.pitch;
+    return LBM_OK;
+}
+
+static int seed_impl(lbm_ctx *c, const void *state, int32_t x_col, double dJ, void *mu,
+                     double *grad_alpha, double *grad_g)
+{
+    int64_t n_out = 0;
+    int rc = outlet_count(c, x_col, &n_out);
+    if (rc)
+        return rc;
+    if ((rc = ensure_adjoint_scratch(c)))
+        return rc;
+    LBM_HIP(c, lbm::launch_adjoint_seed_raw(c->s, state, x_col, dJ / (double)n_out, mu, grad_alpha,
+                                            c->adj_partials));
+    LBM_HIP(c, lbm::launch_partials_into(c->adj_partials, lbm::adjoint_seed_blocks(c->s), grad_g,
+                                         c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_adjoint_seed_outlet_ux(lbm_ctx *c, int32_t x_col, double dJ, void *mu_dev,
+                               double *grad_alpha_dev, double *grad_g_dev)
+{
+    LBM_CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc)
+        return rc;
+    if (!mu_dev || !std::isfinite(dJ))
+        return fail(c, LBM_ERR_INVALID, "mu_dev is NULL or dJ is not finite");
+    if ((rc = check_grads(c, grad_alpha_dev, grad_g_dev)))
+        return rc;
+    return seed_impl(c, state_lattice(c), x_col, dJ, mu_dev, grad_alpha_dev, grad_g_dev);
+}
+
+int lbm_adjoint_step(lbm_ctx *c, const void *state_t_dev, const void *mu_in_dev, void *mu_out_dev,
+                     double *grad_alpha_dev, double *grad_g_dev)
+{
+    LBM_CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc)
+        return rc;
+    if (!state_t_dev || !mu_in_dev || !mu_out_dev || mu_in_dev == mu_out_dev)
+        return fail(c, LBM_ERR_INVALID, "state / mu buffers must be non-NULL and mu_in != mu_out");
+    if ((rc = check_grads(c, grad_alpha_dev, grad_g_dev)))
+        return rc;
+    if ((rc = ensure_adjoint_scratch(c)))
+        return rc;
+    LBM_HIP(c, lbm::launch_adjoint_step_raw(c->s, state_t_dev, mu_in_dev, mu_out_dev,
+                                            grad_alpha_dev, c->adj_partials, 0));
+    LBM_HIP(c, lbm::launch_partials_into(c->adj_partials, lbm::adjoint_blocks(c->s), grad_g_dev,
+                                         c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_run_checkpointed(lbm_ctx *c, int64_t T, int64_t K, void *ckpt_dev)
+{
+    LBM_CHECK_CTX(c);
+    if (T < 0 || K < 1 || (T > 0 && !ckpt_dev))
+        return fail(c, LBM_ERR_INVALID, "need T >= 0, K >= 1 and a checkpoint buffer");
+    size_t sb = 0;
+    lbm_state_bytes(c, &sb);
+    for (int64_t s = 0; s < T; ++s) {
+        if (s % K == 0) {
+            int rc = lbm_save_state(c, (char *)ckpt_dev + (size_t)(s / K) * sb);
+            if (rc)
+                return rc;
+        }
+        int rc = lbm_step(c, 1);
+        if (rc)
+            return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_adjoint_checkpointed(lbm_ctx *c, int64_t T, int64_t K, const void *ckpt_dev, void *seg_dev,
+                             int32_t x_col, double dJ, double *grad_alpha_dev, double *grad_g_dev)
+{
+    LBM_CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc)
+        return rc;
+    if (T < 0 || K < 1 || (T > 0 && (!ckpt_dev || (K > 1 && !seg_dev))) || !std::isfinite(dJ))
+        return fail(c, LBM_ERR_INVALID, "bad T / K / buffers / dJ");
+    if ((rc = check_grads(c, grad_alpha_dev, grad_g_dev)))
+        return rc;
+    for (int k = 0; k < 2; ++k)
+        if (!c->mu_buf[k] && !(c->mu_buf[k] = own_alloc(c, adjoint_field_bytes(c))))
+            return fail(c, LBM_ERR_NOMEM, "cannot allocate the adjoint fields");
+    size_t sb = 0;
+    lbm_state_bytes(c, &sb);
+    if ((rc = seed_impl(c, state_lattice(c), x_col, dJ, c->mu_buf[0], grad_alpha_dev, grad_g_dev)))
+        return rc;
+    const int64_t nb = lbm::adjoint_blocks(c->s);
+    LBM_HIP(c, lbm::launch_zero(c->adj_partials, 2 * nb, c->s.stream));
+    int mu = 0;
+    // Replay state: a copy of the device description whose lattices point into
+    // the checkpoint and segment buffers; the context's own lattices (the
+    // state at T) are never written.
+    lbm::DevState r = c->s;
+    const int64_t nseg = (T + K - 1) / K;
+    std::vector<const void *> st((size_t)K);
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t t0 = seg * K, len = std::min<int64_t>(K, T - t0);
+        st[0] = (const char *)ckpt_dev + (size_t)seg * sb;
+        for (int64_t j = 1; j < len; ++j) {
+            st[j] = (const char *)seg_dev + (size_t)j * sb;
+            r.f[0] = const_cast<void *>(st[j - 1]);
+            r.f[1] = const_cast<void *>(st[j]);
+            LBM_HIP(c, lbm::launch_step(r, t0 + j - 1, 0));
+        }
+        for (int64_t j = len - 1; j >= 0; --j) {
+            LBM_HIP(c, lbm::launch_adjoint_step_raw(c->s, st[j], c->mu_buf[mu], c->mu_buf[1 - mu],
+                                                    grad_alpha_dev, c->adj_partials, 1));
+            mu ^= 1;
+        }
+    }
+    LBM_HIP(c, lbm::launch_partials_into(c->adj_partials, nb, grad_g_dev, c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_get_info(const lbm_ctx *c, lbm_info_t *info)
+{
+    if (!c || !info)
+        return fail_tl(LBM_ERR_INVALID, "NULL argument");
+    const lbm::DevState &s = c->s;
+    std::memset(info, 0, sizeof(*info));
+    info->nx = s.nx;
+    info->ny = s.ny;
+    info->dtype = s.dtype;
+    info->layout = s.layout;
+    info->n_nodes = (int64_t)s.nx * s.ny;
+    info->n_fluid = c->n_fluid;
+    info->n_tiles = s.n_tiles;
+    info->time_step = c->t;
+    info->pop_bytes = c->pop_bytes;
+    info->has_porosity = s.alpha != nullptr;
+    const double drag = s.alpha ? 4.0 : 0.0;
+    info->bytes_per_fluid_node = 18.0 * c->pop_bytes + 1.0 + drag;
+    const double pops = 18.0 * c->pop_bytes;
+    if (s.layout == LBM_DENSE_AB || s.layout == LBM_DENSE_AA)
+        info->bytes_moved_per_step = (pops + drag) * c->n_fluid + 1.0 * info->n_nodes;
+    else if (s.layout == LBM_TILED16)
+        info->bytes_moved_per_step = (pops + 1.0 + drag) * (double)s.n_tiles * lbm::kTileNodes;
+    else
+        info->bytes_moved_per_step = (pops + 32.0 + drag) * c->n_fluid;
+    info->device_bytes = c->device_bytes;
+    return LBM_OK;
+}
+
+int lbm_plan_tiles(int32_t nx, int32_t ny, const uint8_t *node_type, int64_t *n_tiles,
+                   int32_t *tile_xy, int32_t *tile_nbr)
+{
+    if (nx < 1 || ny < 1 || !node_type || !n_tiles)
+        return fail_tl(LBM_ERR_INVALID, "bad arguments");
+    if (nx % 16 != 0 || ny % 16 != 0)
+        return fail_tl(LBM_ERR_UNSUPPORTED, "nx and ny must be multiples of 16");
+    for (size_t k = 0; k < (size_t)nx * ny; ++k)
+        if (node_type[k] > 1)
+            return fail_tl(LBM_ERR_INVALID, "node_type values must be 0 or 1");
+    lbm::plan::Tiles t = lbm::plan::tiles16(node_type, nx, ny);
+    *n_tiles = t.n_tiles;
+    if (tile_xy)
+        std::memcpy(tile_xy, t.xy.data(), t.xy.size() * sizeof(int32_t));
+    if (tile_nbr)
+        std::memcpy(tile_nbr, t.nbr.data(), t.nbr.size() * sizeof(int32_t));
+    return LBM_OK;
+}
+
+int lbm_plan_indirect(int32_t nx, int32_t ny, const uint8_t *node_type, int64_t *n_fluid,
+                      int32_t *fluid_xy, int32_t *nbr)
+{
+    if (nx < 1 || ny < 1 || !node_type || !n_fluid)
+        return fail_tl(LBM_ERR_INVALID, "bad arguments");
+    for (size_t k = 0; k < (size_t)nx * ny; ++k)
+        if (node_type[k] > 1)
+            return fail_tl(LBM_ERR_INVALID, "node_type values must be 0 or 1");
+    lbm::plan::Fluid f = lbm::plan::fluid_list(node_type, nx, ny);
+    *n_fluid = f.n_fluid;
+    if (fluid_xy)
+        std::memcpy(fluid_xy, f.xy.data(), f.xy.size() * sizeof(int32_t));
+    if (nbr) {
+        std::vector<int32_t> t;
+        lbm::plan::indirect_neighbours(f, nx, ny, f.n_fluid, t);
+        std::memcpy(nbr, t.data(), t.size() * sizeof(int32_t));
+    }
+    return LBM_OK;
+}
+
+int lbm_copy_kernel(const void *src, void *dst, size_t bytes, void *hip_stream)
+{
+    if (!src || !dst || bytes % 16 != 0)
+        return fail_tl(LBM_ERR_INVALID, "copy needs non-NULL buffers and a multiple of 16 bytes");
+    hipError_t e = lbm::launch_copy16(src, dst, bytes, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return fail_tl(LBM_ERR_DEVICE, std::string("copy kernel: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+const char *lbm_error_string(int status)
+{
+    switch (status) {
+    case LBM_OK: return "success";
+    case LBM_ERR_INVALID: return "invalid argument";
+    case LBM_ERR_NOMEM: return "out of memory";
+    case LBM_ERR_DEVICE: return "device (HIP runtime) error";
+    case LBM_ERR_UNSUPPORTED: return "unsupported request";
+    case LBM_ERR_STATE: return "context broken by an earlier device error";
+    }
+    return "unknown status";
+}
+
+const char *lbm_last_error(const lbm_ctx *c)
+{
+    if (!c)
+        return t_last_error.c_str();
+    return c->last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports every
+function include/lbm.h declares, argument validation fails with the documented status
+before touching the device, and the geometry planners agree with brute force."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(lbm_\w+)\s*\(", hdr,
+                                 flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2108_13241_amd as m
+    return m.load()
+
+
+def test_all_declared_symbols_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 28
+    from paper_2108_13241_amd._lib import SIGNATURES
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in SIGNATURES, n
+
+
+def test_error_strings(lib):
+    for st in (0, -1, -2, -3, -4, -5):
+        assert lib.lbm_error_string(st)
+    assert lib.lbm_error_string(42) == b"unknown status"
+
+
+def _create(lib, nx, ny, mask, tau=0.8, force=(0.0, 0.0), dtype=0, layout=0):
+    import ctypes
+    ctx = ctypes.c_void_p()
+    g = (ctypes.c_double * 2)(*force)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    st = lib.lbm_create(ctypes.byref(ctx), nx, ny,
+                        m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tau, g, dtype, layout)
+    return st, ctx
+
+
+@pytest.mark.parametrize("kw,status", [
+    ({"tau": 0.5}, -1), ({"tau": float("nan")}, -1), ({"force": (float("inf"), 0.0)}, -1),
+    ({"dtype": 7}, -1), ({"layout": 9}, -1), ({"layout": 2}, -4)])
+def test_create_validation(lib, kw, status):
+    m = np.zeros((10, 20), np.uint8)
+    st, ctx = _create(lib, 20, 10, m, **kw)
+    assert st == status
+    assert not ctx.value
+    assert lib.lbm_last_error(None)
+
+
+def test_create_rejects_bad_mask(lib):
+    m = np.zeros((8, 8), np.uint8)
+    m[3, 3] = 2
+    st, _ = _create(lib, 8, 8, m)
+    assert st == -1
+    assert b"node_type" in lib.lbm_last_error(None)
+
+
+def test_null_context(lib):
+    import ctypes
+    assert lib.lbm_step(None, 1) == -1
+    assert lib.lbm_mass(None, ctypes.byref(ctypes.c_double())) == -1
+    lib.lbm_destroy(None)
+
+
+def test_allocator_pairing(lib):
+    import ctypes
+    from paper_2108_13241_amd._lib import ALLOC_FN
+    cb = ALLOC_FN(lambda n, u: None)
+    assert lib.lbm_set_allocator(ctypes.cast(cb, ctypes.c_void_p), None, None) == -1
+    assert lib.lbm_set_allocator(None, None, None) == 0
+
+
+def _brute_tiles(m):
+    ny, nx = m.shape
+    tyn, txn = ny // 16, nx // 16
+    keep = {}
+    for ty in range(tyn):
+        for tx in range(txn):
+            if (m[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] == 0).any():
+                keep[(tx, ty)] = len(keep)
+    cx = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    cy = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    xy = np.array(list(keep.keys()), dtype=np.int32).reshape(-1, 2)
+    nb = np.full((len(keep), 9), -1, np.int32)
+    for (tx, ty), k in keep.items():
+        for d in range(9):
+            nb[k, d] = keep.get(((tx + cx[d]) % txn, (ty + cy[d]) % tyn), -1)
+    return xy, nb
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_plan_tiles_vs_brute_force(seed):
+    import paper_2108_13241_amd as lbm
+    m, _ = synthetic.porous_discs(128, 0.4, seed=seed, rmin=6, rmax=20)
+    m[:, 32:64] = 1
+    xy, nb = lbm.plan_tiles(m)
+    bxy, bnb = _brute_tiles(m)
+    assert np.array_equal(xy, bxy)
+    assert np.array_equal(nb, bnb)
+    assert np.all(nb[:, 0] == np.arange(len(nb)))
+
+
+def test_plan_tiles_rejects_ragged():
+    import paper_2108_13241_amd as lbm
+    with pytest.raises(lbm.LbmError):
+        lbm.plan_tiles(np.zeros((20, 32), np.uint8))
+
+
+@pytest.mark.parametrize("shape", [(37, 23), (64, 64), (1, 9)])
+def test_plan_indirect_vs_brute_force(shape):
+    import paper_2108_13241_amd as lbm
+    nx, ny = shape
+    m = synthetic.random_mask(nx, ny, seed=nx + ny, solid_fraction=0.3)
+    xy, nb = lbm.plan_indirect(m)
+    fl = [(x, y) for y in range(ny) for x in range(nx) if m[y, x] == 0]
+    assert [tuple(p) for p in xy] == fl
+    index = {p: k for k, p in enumerate(fl)}
+    cx = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    cy = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    for k, (x, y) in enumerate(fl):
+        for i in range(1, 9):
+            src = ((x - cx[i]) % nx, (y - cy[i]) % ny)
+            assert nb[i - 1, k] == index.get(src, -1)
+
+
+def test_porous_generator_deterministic():
+    a, ia = synthetic.porous_discs(256, 0.5, rmin=4, rmax=16)
+    b, ib = synthetic.porous_discs(256, 0.5, rmin=4, rmax=16)
+    assert np.array_equal(a, b)
+    assert abs(ia["phi_achieved"] - 0.5) < 0.01
+    assert (a[0] == 1).all() and (a[-1] == 1).all()

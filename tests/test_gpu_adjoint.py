@@ -1,0 +1,160 @@
+"""GPU adjoint: hand-written reverse step against the FP64 CPU adjoint and against
+central finite differences of the GPU forward run.
+
+Case (the adjoint configuration): channel with solid rows 0 and ny-1, periodic in x,
+tau = 0.8, body force g = (1e-5, 0), smooth random drag field alpha (seed 7, sigma 8),
+J = mean u_x over the outlet column x = nx - 1 after T steps from rest.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_13241_amd as m
+    m.load()
+    return m
+
+
+def _case(nx, ny, sigma=8.0):
+    m = synthetic.channel_mask(nx, ny)
+    alpha = synthetic.brinkman_alpha(nx, ny, seed=7, sigma=sigma).astype(np.float32)
+    return m, alpha, (1e-5, 0.0)
+
+
+def gpu_gradient(lbm, m, alpha, g, tau, T, dtype, K=None):
+    import torch
+    ny, nx = m.shape
+    lat = lbm.Lattice(m, tau, force=g, dtype=dtype, layout="dense_ab")
+    lat.set_porosity(alpha)
+    K = K or max(1, math.ceil(math.sqrt(T)))
+    sb = lat.state_bytes()
+    ckpt = torch.empty(max(1, math.ceil(T / K)) * sb, dtype=torch.uint8, device="cuda")
+    seg = torch.empty(K * sb, dtype=torch.uint8, device="cuda")
+    lat.run_checkpointed(T, K, ckpt)
+    J = lat.objective_outlet_ux(nx - 1)
+    ga = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    gg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lat.adjoint_checkpointed(T, K, ckpt, seg, nx - 1, 1.0, ga, gg)
+    torch.cuda.synchronize()
+    out = (J, ga.cpu().numpy(), gg.cpu().numpy())
+    lat.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-3)])
+def test_adjoint_vs_cpu_adjoint_64x16(lbm, oracle_mod, dtype, tol):
+    """64 x 16 copy of the adjoint case, T = 2000, sqrt(T) checkpointing on the GPU vs the
+    oracle's reverse mode that keeps every state.  Normwise relative error."""
+    announce(f"adjoint 64x16 T=2000 {dtype}")
+    m, alpha, g = _case(64, 16, sigma=3.0)
+    T = 2000
+    J, ga, gg = gpu_gradient(lbm, m, alpha, g, 0.8, T, dtype)
+    Jr, gar, ggr = oracle_mod.outlet_ux_gradient(m, oracle_mod.init(m), 0.8, T, 63, g=g,
+                                                 alpha=alpha.astype(np.float64))
+    assert abs(J - Jr) <= tol * abs(Jr)
+    assert np.linalg.norm(ga - gar) <= tol * np.linalg.norm(gar)
+    assert np.linalg.norm(gg - ggr) <= tol * np.linalg.norm(ggr)
+
+
+def test_checkpointed_equals_stepwise(lbm):
+    """The checkpointed driver and the one-step entry points (every state kept) give
+    bitwise-identical gradients."""
+    import torch
+    announce("adjoint checkpointed vs stepwise")
+    m, alpha, g = _case(96, 24, sigma=4.0)
+    T, ny, nx = 57, 24, 96
+    J, ga, gg = gpu_gradient(lbm, m, alpha, g, 0.8, T, "f64", K=8)
+    lat = lbm.Lattice(m, 0.8, force=g, dtype="f64", layout="dense_ab")
+    lat.set_porosity(alpha)
+    sb = lat.state_bytes()
+    states = torch.empty((T + 1, sb), dtype=torch.uint8, device="cuda")
+    for t in range(T):
+        lat.save_state(states[t])
+        lat.step(1)
+    ab, _ = lat.adjoint_bytes()
+    mu = [torch.zeros(ab, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    ga2 = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    gg2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lat.adjoint_seed_outlet_ux(nx - 1, 1.0, mu[0], ga2, gg2)
+    for t in range(T - 1, -1, -1):
+        k = (T - 1 - t) % 2
+        lat.adjoint_step(states[t], mu[k], mu[1 - k], ga2, gg2)
+    torch.cuda.synchronize()
+    assert np.array_equal(ga2.cpu().numpy(), ga)
+    # dJ/dg partials are summed per step here and once at the end by the driver
+    assert np.allclose(gg2.cpu().numpy(), gg, rtol=1e-13, atol=0)
+    lat.close()
+
+
+def test_adjoint_vs_finite_differences_1024x256(lbm):
+    """The full adjoint configuration (1024 x 256, T = 2000, FP64 forward): dJ/dalpha on
+    32 nodes (16 of the largest |gradient|, 16 uniform) and dJ/dg against central
+    differences of the GPU forward.  alpha is stored in FP32, so each difference divides
+    by the FP32-representable perturbation actually applied."""
+    announce("adjoint FD 1024x256 T=2000 f64")
+    nx, ny, T, tau = 1024, 256, 2000, 0.8
+    m, alpha, g = _case(nx, ny)
+    J, ga, gg = gpu_gradient(lbm, m, alpha, g, tau, T, "f64")
+
+    def Jof(a, gv):
+        lat = lbm.Lattice(m, tau, force=gv, dtype="f64", layout="dense_ab")
+        lat.set_porosity(a)
+        lat.step(T)
+        v = lat.objective_outlet_ux(nx - 1)
+        lat.close()
+        return v
+
+    rng = np.random.default_rng(11)
+    h = 1e-3
+    a_flat = alpha.ravel()
+    # central differences need alpha +- 2h inside [0, 1]
+    ok = np.flatnonzero((m.ravel() == 0) & (a_flat >= 2 * h) & (a_flat <= 1 - 2 * h))
+    order = np.argsort(-np.abs(ga.ravel()[ok]))
+    top = ok[order[: max(16, len(order) // 10)]]
+    picks = list(rng.choice(top, 16, replace=False)) + list(rng.choice(ok, 16, replace=False))
+    gmax = np.abs(ga).max()
+
+    def central(y, x, hh):
+        ap, am = alpha.copy(), alpha.copy()
+        ap[y, x] = np.float32(alpha[y, x] + hh)
+        am[y, x] = np.float32(alpha[y, x] - hh)
+        heff = float(ap[y, x]) - float(am[y, x])  # the FP32 perturbation actually applied
+        return (Jof(ap, g) - Jof(am, g)) / heff
+
+    for k, idx in enumerate(picks):
+        y, x = divmod(int(idx), nx)
+        fd = (4 * central(y, x, h / 2) - central(y, x, h)) / 3  # Richardson: O(h^4)
+        tol = 1e-5 * abs(ga[y, x]) if k < 16 else 1e-6 * gmax
+        assert abs(fd - ga[y, x]) <= tol, (k, y, x, float(alpha[y, x]), fd, ga[y, x])
+    hg = 1e-7
+    fd = (Jof(alpha, (g[0] + hg, g[1])) - Jof(alpha, (g[0] - hg, g[1]))) / (2 * hg)
+    assert fd == pytest.approx(gg[0], rel=1e-6)
+
+
+def test_autograd_function(lbm):
+    """ChannelObjective.apply / backward agrees with the C-ABI driver."""
+    import torch
+    announce("autograd ChannelObjective")
+    m, alpha, g = _case(128, 32, sigma=4.0)
+    a = torch.tensor(alpha, dtype=torch.float32, device="cuda", requires_grad=True)
+    gt = torch.tensor(g, dtype=torch.float64, device="cuda", requires_grad=True)
+    spec = {"mask": m, "tau": 0.8, "steps": 300, "x_out": 127, "dtype": "f64"}
+    J = lbm.ChannelObjective.apply(a, gt, spec)
+    J.backward()
+    J2, ga, gg = gpu_gradient(lbm, m, alpha, g, 0.8, 300, "f64")
+    assert float(J) == pytest.approx(J2, rel=1e-14)
+    ga64, gg64 = lbm.ChannelObjective.last_grads
+    assert np.array_equal(ga64.cpu().numpy(), ga)
+    assert np.allclose(gt.grad.cpu().numpy(), gg, rtol=1e-14)
+    assert a.grad.dtype == torch.float32
