@@ -45,9 +45,10 @@ extern "C" {
 
 typedef struct lbm_ctx lbm_ctx; /* opaque; owned by the library until lbm_destroy */
 
-/* Population storage type.  F64 / F32 store f_i and compute in that type.
- * F16_SHIFTED / BF16_SHIFTED store the deviation f_i - w_i (rho0 = 1) in 16 bits
- * (round to nearest even) and compute in FP32. */
+/* Population storage type.  F64 stores f_i and computes in FP64.  F32,
+ * F16_SHIFTED and BF16_SHIFTED store the deviation f_i - w_i (rho0 = 1), in 32 or
+ * 16 bits (round to nearest even), and compute in FP32 on the deviations, which
+ * keeps FP32 within 1e-5 relative of FP64 where storing f_i itself does not. */
 typedef enum {
     LBM_F64 = 0,
     LBM_F32 = 1,
@@ -56,15 +57,17 @@ typedef enum {
 } lbm_dtype;
 
 /* Memory layout of the populations.
- *  DENSE_AB : two full lattices [9][ny][pitch] (structure of arrays), pull
- *             scheme, swapped every step (Algorithm 1, Sec. 3).
+ *  DENSE_AB : two full lattices, pull scheme, swapped every step (Algorithm 1,
+ *             Sec. 3).  Structure of arrays within chunks of 64 nodes along a
+ *             row: each chunk stores its 9 populations as 9 runs of 64.
  *  DENSE_AA : one full lattice updated in place with the AA access pattern
  *             (the single-copy scheme Sec. 3 mentions): even steps read and
  *             write each node's own slots, odd steps read from and write to the
  *             neighbours.
  *  TILED16  : two lattices holding only the non-empty 16 x 16 tiles, compacted
- *             in row-major tile order, with a tile-neighbour table ("pointer
- *             tile" of Sec. 4.3).  Requires nx and ny to be multiples of 16.
+ *             in row-major tile order (each tile stores its 9 populations as 9
+ *             runs of 256), with a tile-neighbour table ("pointer tile" of
+ *             Sec. 4.3).  Requires nx and ny to be multiples of 16.
  *  INDIRECT : two lattices holding only fluid nodes (row-major compaction) and
  *             a per-node neighbour table (the fluid-index-array approach of
  *             Sec. 1). */
@@ -180,8 +183,10 @@ int lbm_load_state(lbm_ctx *ctx, const void *dev_src);
 int lbm_objective_outlet_ux(lbm_ctx *ctx, int32_t x_col, double *J);
 
 /* ---- Adjoint (reverse mode of the step; DENSE_AB, F64 and F32 only) ------
- * An adjoint field lambda is dense [9][ny][pitch] in the compute type (FP64
- * for F64, FP32 for F32); lbm_adjoint_bytes gives its size and the pitch.
+ * An adjoint field lambda holds 9 values per node of the padded [ny][pitch]
+ * mesh in the compute type (FP64 for F64, FP32 for F32), in the library's
+ * internal chunked layout: callers treat it as an opaque device buffer of
+ * lbm_adjoint_bytes bytes (which also reports the row pitch).
  * lambda_t = dJ / df(t) with f the canonical populations.  Gradients are FP64
  * device buffers owned by the caller and ACCUMULATED into (+=):
  *   grad_alpha_dev [ny][nx], grad_g_dev [2]. */

@@ -130,13 +130,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(
     typename ST::real *__restrict__ mu_out, const uint8_t *__restrict__ type,
     const uint8_t *__restrict__ nmask, const float *__restrict__ alpha,
     double *__restrict__ grad_alpha, double *__restrict__ partials, int accumulate, int nx, int ny,
-    int pitch, uint32_t plane, uint32_t nbx, uint32_t nblocks, typename ST::real omega,
-    typename ST::real gx, typename ST::real gy)
+    int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy)
 {
     using R = typename ST::real;
     const uint32_t L = xcd_remap(blockIdx.x, nblocks);
-    const int y = (int)(L / nbx);
-    const int x = (int)(L - (uint32_t)y * nbx) * kBlock + (int)threadIdx.x;
+    const int y = (int)(L / bpr);
+    const int x = (int)(L - (uint32_t)y * bpr) * kBlock + (int)threadIdx.x;
     double gxs = 0.0, gys = 0.0;
     if (x < nx) {
         const uint32_t own = (uint32_t)y * pitch + x;
@@ -144,17 +144,17 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(
         if (t != kSolid) {
             const unsigned sm = solid_bits(t, nmask, own);
             uint32_t nb[9];
-            dense_offsets(x, y, nx, ny, pitch, nb);
+            dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
             R f[9], nu[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 // forward pull: f_i(x) = s_i(x - c_i) or s_opp(i)(x)
-                const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * plane + own
-                                                    : (uint32_t)i * plane + nb[i];
+                const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
+                                                    : (uint32_t)i * kChunk + nb[i];
                 f[i] = ST::ld(state[o], i);
                 // reverse pull: x + c_i is node x - c_opp(i)
-                const uint32_t q = ((sm >> kOpp[i]) & 1u) ? (uint32_t)kOpp[i] * plane + own
-                                                          : (uint32_t)i * plane + nb[kOpp[i]];
+                const uint32_t q = ((sm >> kOpp[i]) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
+                                                          : (uint32_t)i * kChunk + nb[kOpp[i]];
                 nu[i] = mu_in[q];
             }
             const R al = DRAG ? (R)alpha[own] : R(0);
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(
             collide_vjp<R, DRAG, ST::kShift>(f, nu, omega, gx, gy, al, fb, ab, gbx, gby);
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                mu_out[(uint32_t)i * plane + own] = fb[i];
+                store_nt(&mu_out[(uint32_t)i * kChunk + nb[0]], fb[i]);
             if (DRAG)
                 grad_alpha[(size_t)y * nx + x] += (double)ab;
             gxs = (double)gbx;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(
     const typename ST::mem *__restrict__ state, typename ST::real *__restrict__ mu,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
     const float *__restrict__ alpha, double *__restrict__ grad_alpha, double *__restrict__ partials,
-    int x_col, double scale, int nx, int ny, int pitch, uint32_t plane, double gx, double gy)
+    int x_col, double scale, int nx, int ny, int pitch, double gx, double gy)
 {
     using R = typename ST::real;
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
@@ -199,12 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(
         if (x == x_col && type[gid] != kSolid) {
             const unsigned sm = solid_bits(type[gid], nmask, gid);
             uint32_t nb[9];
-            dense_offsets(x, y, nx, ny, pitch, nb);
+            dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
             double f[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * plane + gid
-                                                    : (uint32_t)i * plane + nb[i];
+                const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
+                                                    : (uint32_t)i * kChunk + nb[i];
                 f[i] = ST::canon(ST::ld(state[o], i), i);
             }
             const double al = alpha ? (double)alpha[gid] : 0.0;
@@ -220,11 +220,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(
                 grad_alpha[(size_t)y * nx + x] += scale * (-0.5 * ux * invD);
             gxs = scale * 0.5 * invD;
         }
-        if (x < pitch) {
+        const uint32_t base = dense_base(x, y, (uint32_t)pitch / kChunk);
 #pragma unroll
-            for (int j = 0; j < 9; ++j)
-                mu[(uint32_t)j * plane + gid] = lam[j];
-        }
+        for (int j = 0; j < 9; ++j)
+            mu[(uint32_t)j * kChunk + base] = lam[j];
     }
     double gys = 0.0;
     block_sum2(gxs, gys);
@@ -261,19 +260,19 @@ hipError_t step_typed(const DevState &s, const void *state, const void *mu_in, v
                       double *grad_alpha, double *partials, int accumulate)
 {
     using R = typename ST::real;
-    const uint32_t nbx = (uint32_t)((s.nx + kBlock - 1) / kBlock);
-    const uint32_t nblocks = nbx * (uint32_t)s.ny;
+    const uint32_t bpr = (uint32_t)((s.nx + kBlock - 1) / kBlock);
+    const uint32_t nblocks = bpr * (uint32_t)s.ny;
     const R om = (R)s.omega, gx = (R)s.gx, gy = (R)s.gy;
     if (s.alpha)
         k_adjoint_step<ST, true><<<nblocks, kBlock, 0, s.stream>>>(
             (const typename ST::mem *)state, (const R *)mu_in, (R *)mu_out, s.type, s.nmask,
-            s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, (uint32_t)s.plane, nbx,
-            nblocks, om, gx, gy);
+            s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
+            gy);
     else
         k_adjoint_step<ST, false><<<nblocks, kBlock, 0, s.stream>>>(
             (const typename ST::mem *)state, (const R *)mu_in, (R *)mu_out, s.type, s.nmask,
-            s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, (uint32_t)s.plane, nbx,
-            nblocks, om, gx, gy);
+            s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
+            gy);
     return hipGetLastError();
 }
 
@@ -304,11 +303,11 @@ hipError_t launch_adjoint_seed_raw(const DevState &s, const void *state, int x_c
     if (s.dtype == kF64)
         k_adjoint_seed<F64><<<blocks, kBlock, 0, s.stream>>>(
             (const double *)state, (double *)mu, s.type, s.nmask, s.alpha, grad_alpha, partials,
-            x_col, scale, s.nx, s.ny, s.pitch, (uint32_t)s.plane, s.gx, s.gy);
+            x_col, scale, s.nx, s.ny, s.pitch, s.gx, s.gy);
     else if (s.dtype == kF32)
         k_adjoint_seed<F32><<<blocks, kBlock, 0, s.stream>>>(
             (const float *)state, (float *)mu, s.type, s.nmask, s.alpha, grad_alpha, partials,
-            x_col, scale, s.nx, s.ny, s.pitch, (uint32_t)s.plane, s.gx, s.gy);
+            x_col, scale, s.nx, s.ny, s.pitch, s.gx, s.gy);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

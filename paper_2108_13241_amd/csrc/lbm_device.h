@@ -148,23 +148,62 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n)
 __device__ __forceinline__ int wrap_dec(int a, int n) { return a == 0 ? n - 1 : a - 1; }
 __device__ __forceinline__ int wrap_inc(int a, int n) { return a == n - 1 ? 0 : a + 1; }
 
-// nb[i] = in-plane offset of node x - c_i (periodic) in a dense [ny][pitch]
-// plane; nb[0] = the node itself.
-__device__ __forceinline__ void dense_offsets(int x, int y, int nx, int ny, int pitch,
-                                              uint32_t (&nb)[9])
+// ---------------------------------------------------------- population layouts --
+// Populations are stored array-of-structures-of-arrays: the nodes are cut into
+// chunks, and a chunk holds its 9 populations one after another, each as a run
+// of consecutive nodes.  Population i of the node with base offset b sits at
+// b + i * stride.  A 64-lane wavefront then reads or writes 9 contiguous runs
+// inside one chunk instead of 9 far-apart planes, which keeps the DRAM access
+// stream close to a copy's.
+//  dense rows : chunks of 64 nodes along x; node (x, y) -> chunk y * cpr + x / 64
+//               (cpr = pitch / 64 chunks per row), stride 64
+//  node lists : chunks of 64 consecutive list entries, stride 64
+//  tiles      : one chunk per 16 x 16 tile (256 nodes), stride 256
+constexpr uint32_t kChunk = 64;
+constexpr uint32_t kTileStride = 256;
+
+__device__ __forceinline__ uint32_t dense_base(int x, int y, uint32_t cpr)
+{
+    return ((uint32_t)y * cpr + ((uint32_t)x >> 6)) * (9u * kChunk) + ((uint32_t)x & 63u);
+}
+__device__ __forceinline__ uint32_t list_base(uint32_t n)
+{
+    return (n >> 6) * (9u * kChunk) + (n & 63u);
+}
+__device__ __forceinline__ uint32_t tile_base(uint32_t k, uint32_t t)
+{
+    return k * (9u * kTileStride) + t;
+}
+
+// nb[i] = base offset of node x - c_i (periodic) in the dense layout;
+// nb[0] = the node itself.
+__device__ __forceinline__ void dense_bases(int x, int y, int nx, int ny, uint32_t cpr,
+                                            uint32_t (&nb)[9])
 {
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-    const uint32_t r0 = (uint32_t)y * pitch, rm = (uint32_t)ym * pitch, rp = (uint32_t)yp * pitch;
-    nb[0] = r0 + x;
-    nb[1] = r0 + xm;  // c1 = (+1, 0)
-    nb[2] = rm + x;   // c2 = (0, +1)
-    nb[3] = r0 + xp;  // c3 = (-1, 0)
-    nb[4] = rp + x;   // c4 = (0, -1)
-    nb[5] = rm + xm;  // c5 = (+1, +1)
-    nb[6] = rm + xp;  // c6 = (-1, +1)
-    nb[7] = rp + xp;  // c7 = (-1, -1)
-    nb[8] = rp + xm;  // c8 = (+1, -1)
+    nb[0] = dense_base(x, y, cpr);
+    nb[1] = dense_base(xm, y, cpr);   // c1 = (+1, 0)
+    nb[2] = dense_base(x, ym, cpr);   // c2 = (0, +1)
+    nb[3] = dense_base(xp, y, cpr);   // c3 = (-1, 0)
+    nb[4] = dense_base(x, yp, cpr);   // c4 = (0, -1)
+    nb[5] = dense_base(xm, ym, cpr);  // c5 = (+1, +1)
+    nb[6] = dense_base(xp, ym, cpr);  // c6 = (-1, +1)
+    nb[7] = dense_base(xp, yp, cpr);  // c7 = (-1, -1)
+    nb[8] = dense_base(xm, yp, cpr);  // c8 = (+1, -1)
+}
+
+// Streaming stores: the lattice written by a step is not read again until the
+// next step, so the stores bypass the caches' retention (nontemporal).
+template <class T>
+__device__ __forceinline__ void store_nt(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+template <>
+__device__ __forceinline__ void store_nt<__bf16>(__bf16 *p, __bf16 v)
+{
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short *)p);
 }
 
 }  // namespace lbm

@@ -2,12 +2,13 @@
 // pull scheme) on four layouts, plus initialisation, canonical views,
 // macroscopic fields and FP64 reductions.
 //
-// Memory layouts (structure of arrays, Sec. 3):
-//  dense    : plane i holds f_i of every node, row-major [ny][pitch]
-//  tiled    : plane i holds f_i of every kept 16x16 tile, [n_tiles][16][16]
-//  indirect : plane i holds f_i of every fluid node, [n_fluid (padded)]
+// Population layouts (see lbm_device.h): dense and node-list lattices are cut
+// into chunks of 64 nodes, tiled lattices into 16 x 16 tiles; each chunk holds
+// its 9 populations as consecutive runs (direction stride 64, or 256 for
+// tiles).  Node-type, neighbour-bit and drag arrays are indexed per node:
+// dense [ny][pitch], tiled [n_tiles][256], indirect [n_fluid].
 // Offsets inside one lattice are 32-bit element indices (the runtime checks
-// 9 * plane < 2^32).
+// 9 * nodes < 2^32).
 #include "lbm_device.h"
 #include "lbm_launch.h"
 
@@ -31,8 +32,8 @@ __host__ __device__ constexpr int dir_of(int ox, int oy)
 }
 
 // ------------------------------------------------------------ addressing --
-// Tiled layout: nb[i] = offset of node x - c_i, which may lie in one of the
-// neighbouring tiles (tile_nbr row `tn` of the current tile k).  When that
+// Tiled layout: nb[i] = base offset of node x - c_i, which may lie in one of
+// the neighbouring tiles (tile_nbr row `tn` of the current tile k).  When that
 // tile is absent the offset is meaningless, but the node is then solid and
 // the caller never uses it.
 __device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const int32_t (&tn)[9],
@@ -51,22 +52,41 @@ __device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const 
             kk = bx ? tn[dir_of(-cx, 0)] : kk;
         else if (cy != 0)
             kk = by ? tn[dir_of(0, -cy)] : kk;
-        nb[i] = (uint32_t)kk * kTileNodes + (uint32_t)(((sy & 15) << 4) | (sx & 15));
+        nb[i] = tile_base((uint32_t)kk, (uint32_t)(((sy & 15) << 4) | (sx & 15)));
     }
+}
+
+// Indirect layout: nbr[(i-1) * nbr_stride + n] = compacted index of node
+// x_n - c_i, or -1 (solid).  Returns the solid-neighbour bits; nb[i] = base
+// offset of the source node.
+__device__ __forceinline__ unsigned indirect_offsets(const int32_t *__restrict__ nbr,
+                                                     uint32_t nbr_stride, uint32_t n,
+                                                     uint32_t (&nb)[9])
+{
+    unsigned sm = 0;
+    nb[0] = list_base(n);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const int32_t j = nbr[(uint32_t)(i - 1) * nbr_stride + n];
+        sm |= (j < 0 ? 1u : 0u) << i;
+        nb[i] = list_base((uint32_t)j);
+    }
+    return sm;
 }
 
 // ---------------------------------------------------------------- gathers --
 // Pull gather of Algorithm 1: f_i(x) = s_i(x - c_i), or, when x - c_i is solid
-// (bit i of sm), the halfway bounce-back value s_opp(i)(x).
+// (bit i of sm), the halfway bounce-back value s_opp(i)(x).  ds = direction
+// stride of the layout, nb = node base offsets.
 template <class ST>
-__device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__ s, uint32_t plane,
+__device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__ s, uint32_t ds,
                                             const uint32_t (&nb)[9], unsigned sm,
                                             typename ST::real (&f)[9])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * plane + nb[0]
-                                            : (uint32_t)i * plane + nb[i];
+        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * ds + nb[0]
+                                            : (uint32_t)i * ds + nb[i];
         f[i] = ST::ld(s[o], i);
     }
 }
@@ -74,26 +94,34 @@ __device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__
 // AA pattern, odd step read (and the canonical view after an odd number of
 // steps): f_i(x) = A_opp(i)(x - c_i), or A_i(x) when x - c_i is solid.
 template <class ST>
-__device__ __forceinline__ void aa_odd_gather(const typename ST::mem *__restrict__ s,
-                                              uint32_t plane, const uint32_t (&nb)[9], unsigned sm,
+__device__ __forceinline__ void aa_odd_gather(const typename ST::mem *__restrict__ s, uint32_t ds,
+                                              const uint32_t (&nb)[9], unsigned sm,
                                               typename ST::real (&f)[9])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)i * plane + nb[0]
-                                            : (uint32_t)kOpp[i] * plane + nb[i];
+        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)i * ds + nb[0]
+                                            : (uint32_t)kOpp[i] * ds + nb[i];
         f[i] = ST::ld(s[o], i);
     }
 }
 
 template <class ST>
-__device__ __forceinline__ void local_gather(const typename ST::mem *__restrict__ s,
-                                             uint32_t plane, uint32_t own,
-                                             typename ST::real (&f)[9])
+__device__ __forceinline__ void local_gather(const typename ST::mem *__restrict__ s, uint32_t ds,
+                                             uint32_t own, typename ST::real (&f)[9])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        f[i] = ST::ld(s[(uint32_t)i * plane + own], i);
+        f[i] = ST::ld(s[(uint32_t)i * ds + own], i);
+}
+
+// Node of a dense step thread: 256-lane row segments, XCD-remapped.
+__device__ __forceinline__ bool dense_node(uint32_t bpr, uint32_t nblocks, int nx, int &x, int &y)
+{
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    y = (int)(L / bpr);
+    x = (int)(L - (uint32_t)y * bpr) * kBlock + (int)threadIdx.x;
+    return x < nx;
 }
 
 // ------------------------------------------------------------- step: dense --
@@ -101,28 +129,26 @@ template <class ST, bool DRAG>
 __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
-    const float *__restrict__ alpha, int nx, int ny, int pitch, uint32_t plane, uint32_t nbx,
-    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    const float *__restrict__ alpha, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
+    typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
-    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
-    const int y = (int)(L / nbx);
-    const int x = (int)(L - (uint32_t)y * nbx) * kBlock + (int)threadIdx.x;
-    if (x >= nx)
+    int x, y;
+    if (!dense_node(bpr, nblocks, nx, x, y))
         return;
-    const uint32_t own = (uint32_t)y * pitch + x;
-    const uint8_t t = type[own];
+    const uint32_t n = (uint32_t)y * pitch + x;
+    const uint8_t t = type[n];
     if (t == kSolid)
         return;
-    const unsigned sm = solid_bits(t, nmask, own);
+    const unsigned sm = solid_bits(t, nmask, n);
     uint32_t nb[9];
-    dense_offsets(x, y, nx, ny, pitch, nb);
+    dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
     R f[9];
-    pull_gather<ST>(src, plane, nb, sm, f);
-    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+    pull_gather<ST>(src, kChunk, nb, sm, f);
+    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        dst[(uint32_t)i * plane + own] = ST::st(f[i], i);
+        store_nt(&dst[(uint32_t)i * kChunk + nb[0]], ST::st(f[i], i));
 }
 
 // AA pattern (single lattice A).  Even step: read A_i(x), write the
@@ -134,38 +160,37 @@ template <class ST, bool DRAG, bool ODD>
 __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
     const uint8_t *__restrict__ nmask, const float *__restrict__ alpha, int nx, int ny, int pitch,
-    uint32_t plane, uint32_t nbx, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
     typename ST::real gy)
 {
     using R = typename ST::real;
-    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
-    const int y = (int)(L / nbx);
-    const int x = (int)(L - (uint32_t)y * nbx) * kBlock + (int)threadIdx.x;
-    if (x >= nx)
+    int x, y;
+    if (!dense_node(bpr, nblocks, nx, x, y))
         return;
-    const uint32_t own = (uint32_t)y * pitch + x;
-    const uint8_t t = type[own];
+    const uint32_t n = (uint32_t)y * pitch + x;
+    const uint8_t t = type[n];
     if (t == kSolid)
         return;
     R f[9];
     if constexpr (!ODD) {
-        local_gather<ST>(A, plane, own, f);
-        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+        const uint32_t own = dense_base(x, y, (uint32_t)pitch / kChunk);
+        local_gather<ST>(A, kChunk, own, f);
+        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            A[(uint32_t)kOpp[i] * plane + own] = ST::st(f[i], i);
+            store_nt(&A[(uint32_t)kOpp[i] * kChunk + own], ST::st(f[i], i));
     } else {
-        const unsigned sm = solid_bits(t, nmask, own);
+        const unsigned sm = solid_bits(t, nmask, n);
         uint32_t nb[9];
-        dense_offsets(x, y, nx, ny, pitch, nb);
-        aa_odd_gather<ST>(A, plane, nb, sm, f);
-        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+        dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
+        aa_odd_gather<ST>(A, kChunk, nb, sm, f);
+        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
-            const uint32_t o = ((sm >> kOpp[i]) & 1u) ? (uint32_t)kOpp[i] * plane + own
-                                                      : (uint32_t)i * plane + nb[kOpp[i]];
-            A[o] = ST::st(f[i], i);
+            const uint32_t o = ((sm >> kOpp[i]) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
+                                                      : (uint32_t)i * kChunk + nb[kOpp[i]];
+            store_nt(&A[o], ST::st(f[i], i));
         }
     }
 }
@@ -176,16 +201,16 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
     const float *__restrict__ alpha, const int32_t *__restrict__ tile_nbr, uint32_t n_tiles,
-    uint32_t plane, typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
     const uint32_t k = xcd_remap(blockIdx.x, n_tiles);
     const int t = (int)threadIdx.x, lx = t & 15, ly = t >> 4;
-    const uint32_t own = k * kTileNodes + t;
-    const uint8_t ty = type[own];
+    const uint32_t n = k * kTileNodes + t;
+    const uint8_t ty = type[n];
     if (ty == kSolid)
         return;
-    const unsigned sm = solid_bits(ty, nmask, own);
+    const unsigned sm = solid_bits(ty, nmask, n);
     int32_t tn[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d)
@@ -193,35 +218,19 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     uint32_t nb[9];
     tiled_offsets(k, lx, ly, tn, nb);
     R f[9];
-    pull_gather<ST>(src, plane, nb, sm, f);
-    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[own] : R(0));
+    pull_gather<ST>(src, kTileStride, nb, sm, f);
+    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        dst[(uint32_t)i * plane + own] = ST::st(f[i], i);
+        store_nt(&dst[(uint32_t)i * kTileStride + nb[0]], ST::st(f[i], i));
 }
 
 // ---------------------------------------------------------- step: indirect --
-// nbr[(i-1) * plane + n] = compacted index of node x_n - c_i, or -1 (solid).
-__device__ __forceinline__ unsigned indirect_offsets(const int32_t *__restrict__ nbr,
-                                                     uint32_t plane, uint32_t n,
-                                                     uint32_t (&nb)[9])
-{
-    unsigned sm = 0;
-    nb[0] = n;
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const int32_t j = nbr[(uint32_t)(i - 1) * plane + n];
-        sm |= (j < 0 ? 1u : 0u) << i;
-        nb[i] = (uint32_t)j;
-    }
-    return sm;
-}
-
 template <class ST, bool DRAG>
 __global__ __launch_bounds__(kBlock) void k_step_indirect(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const int32_t *__restrict__ nbr, const float *__restrict__ alpha, uint32_t n_fluid,
-    uint32_t plane, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    uint32_t nbr_stride, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
     typename ST::real gy)
 {
     using R = typename ST::real;
@@ -229,30 +238,27 @@ __global__ __launch_bounds__(kBlock) void k_step_indirect(
     if (n >= n_fluid)
         return;
     uint32_t nb[9];
-    const unsigned sm = indirect_offsets(nbr, plane, n, nb);
+    const unsigned sm = indirect_offsets(nbr, nbr_stride, n, nb);
     R f[9];
-    pull_gather<ST>(src, plane, nb, sm, f);
+    pull_gather<ST>(src, kChunk, nb, sm, f);
     collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        dst[(uint32_t)i * plane + n] = ST::st(f[i], i);
+        store_nt(&dst[(uint32_t)i * kChunk + nb[0]], ST::st(f[i], i));
 }
 
 // ------------------------------------------------ canonical-view plumbing --
-// Canonical FP64 buffers are [9][ny][pitch] with the dense pitch.
+// Canonical FP64 buffers are [9][ny][pitch] (plain planes, dense pitch).
 // Gather mode of the dense layouts: A-B pull, AA after an even / odd number of steps.
 enum Mode : int { kPull = 0, kAAEven = 1, kAAOdd = 2 };
 
-// Canonical populations of the fluid node handled by thread `gid`; returns
-// false for padding and solid nodes.  Also returns the node's coordinates and
-// drag coefficient.
-template <class ST>
-__device__ __forceinline__ bool canonical_at(const DevState &s, const typename ST::mem *st,
-                                             int mode, uint32_t gid, int &x, int &y,
-                                             double (&fd)[9], double &al)
+// Stored-state addressing of the node handled by visit thread `gid` (dense:
+// gid = y * pitch + x; tiled: gid = tile * 256 + t; indirect: gid = n).
+// Returns false for padding and solid nodes; else the coordinates, the
+// solid-neighbour bits, the direction stride and the node base offsets.
+__device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x, int &y,
+                                        unsigned &sm, uint32_t &ds, uint32_t (&nb)[9])
 {
-    using R = typename ST::real;
-    R f[9];
     if (s.layout == kDenseAB || s.layout == kDenseAA) {
         y = (int)(gid / (uint32_t)s.pitch);
         x = (int)(gid - (uint32_t)y * s.pitch);
@@ -261,44 +267,55 @@ __device__ __forceinline__ bool canonical_at(const DevState &s, const typename S
         const uint8_t t = s.type[gid];
         if (t == kSolid)
             return false;
-        const unsigned sm = solid_bits(t, s.nmask, gid);
-        uint32_t nb[9];
-        dense_offsets(x, y, s.nx, s.ny, s.pitch, nb);
-        if (mode == kPull)
-            pull_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
-        else if (mode == kAAEven)
-            local_gather<ST>(st, (uint32_t)s.plane, gid, f);
-        else
-            aa_odd_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
-        al = s.alpha ? (double)s.alpha[gid] : 0.0;
+        sm = solid_bits(t, s.nmask, gid);
+        dense_bases(x, y, s.nx, s.ny, (uint32_t)s.pitch / kChunk, nb);
+        ds = kChunk;
     } else if (s.layout == kTiled16) {
         const uint32_t k = gid / kTileNodes;
         if (k >= (uint32_t)s.n_tiles)
             return false;
-        const int t = (int)(gid - k * kTileNodes), lx = t & 15, ly = t >> 4;
+        const int t = (int)(gid - k * kTileNodes);
         const uint8_t ty = s.type[gid];
         if (ty == kSolid)
             return false;
-        const unsigned sm = solid_bits(ty, s.nmask, gid);
+        sm = solid_bits(ty, s.nmask, gid);
         int32_t tn[9];
         for (int d = 0; d < 9; ++d)
             tn[d] = s.tile_nbr[k * 9 + d];
-        uint32_t nb[9];
-        tiled_offsets(k, lx, ly, tn, nb);
-        pull_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
-        x = s.tile_xy[2 * k] * kTile + lx;
-        y = s.tile_xy[2 * k + 1] * kTile + ly;
-        al = s.alpha ? (double)s.alpha[gid] : 0.0;
+        tiled_offsets(k, t & 15, t >> 4, tn, nb);
+        x = s.tile_xy[2 * k] * kTile + (t & 15);
+        y = s.tile_xy[2 * k + 1] * kTile + (t >> 4);
+        ds = kTileStride;
     } else {
         if (gid >= (uint32_t)s.n_fluid)
             return false;
-        uint32_t nb[9];
-        const unsigned sm = indirect_offsets(s.nbr, (uint32_t)s.plane, gid, nb);
-        pull_gather<ST>(st, (uint32_t)s.plane, nb, sm, f);
+        sm = indirect_offsets(s.nbr, (uint32_t)s.plane, gid, nb);
         x = s.fluid_xy[2 * gid];
         y = s.fluid_xy[2 * gid + 1];
-        al = s.alpha ? (double)s.alpha[gid] : 0.0;
+        ds = kChunk;
     }
+    return true;
+}
+
+// Canonical populations (FP64) of the fluid node handled by thread `gid`.
+template <class ST>
+__device__ __forceinline__ bool canonical_at(const DevState &s, const typename ST::mem *st,
+                                             int mode, uint32_t gid, int &x, int &y,
+                                             double (&fd)[9], double &al)
+{
+    using R = typename ST::real;
+    unsigned sm = 0;
+    uint32_t ds = 0, nb[9];
+    if (!node_at(s, gid, x, y, sm, ds, nb))
+        return false;
+    R f[9];
+    if (mode == kAAEven)
+        local_gather<ST>(st, ds, nb[0], f);
+    else if (mode == kAAOdd)
+        aa_odd_gather<ST>(st, ds, nb, sm, f);
+    else
+        pull_gather<ST>(st, ds, nb, sm, f);
+    al = s.alpha ? (double)s.alpha[gid] : 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         fd[i] = ST::canon(f[i], i);
@@ -438,44 +455,28 @@ template <class ST>
 __global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem *st, int mode,
                                                     const double *__restrict__ fc)
 {
-    using R = typename ST::real;
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     int x, y;
-    unsigned sm;
-    uint32_t own;
-    if (s.layout == kDenseAB || s.layout == kDenseAA) {
-        y = (int)(gid / (uint32_t)s.pitch);
-        x = (int)(gid - (uint32_t)y * s.pitch);
-        if (y >= s.ny || x >= s.nx)
-            return;
-        const uint8_t t = s.type[gid];
-        if (t == kSolid)
-            return;
-        sm = solid_bits(t, s.nmask, gid);
-        own = gid;
-    } else if (s.layout == kTiled16) {
-        const uint32_t k = gid / kTileNodes;
-        if (k >= (uint32_t)s.n_tiles)
-            return;
-        const int t = (int)(gid - k * kTileNodes);
-        const uint8_t ty = s.type[gid];
-        if (ty == kSolid)
-            return;
-        sm = solid_bits(ty, s.nmask, gid);
-        x = s.tile_xy[2 * k] * kTile + (t & 15);
-        y = s.tile_xy[2 * k + 1] * kTile + (t >> 4);
-        own = gid;
-    } else {
-        if (gid >= (uint32_t)s.n_fluid)
-            return;
-        uint32_t tmp[9];
-        sm = indirect_offsets(s.nbr, (uint32_t)s.plane, gid, tmp);
-        x = s.fluid_xy[2 * gid];
-        y = s.fluid_xy[2 * gid + 1];
-        own = gid;
+    unsigned sm = 0;
+    uint32_t ds = 0, nbs[9];
+    if (!node_at(s, gid, x, y, sm, ds, nbs))
+        return;
+    uint32_t nb[9];  // canonical (plain planes, dense pitch) offsets of z - c_i
+    {
+        const int xm = wrap_dec(x, s.nx), xp = wrap_inc(x, s.nx);
+        const int ym = wrap_dec(y, s.ny), yp = wrap_inc(y, s.ny);
+        const uint32_t p = (uint32_t)s.pitch;
+        const uint32_t r0 = (uint32_t)y * p, rm = (uint32_t)ym * p, rp = (uint32_t)yp * p;
+        nb[0] = r0 + x;
+        nb[1] = r0 + xm;
+        nb[2] = rm + x;
+        nb[3] = r0 + xp;
+        nb[4] = rp + x;
+        nb[5] = rm + xm;
+        nb[6] = rm + xp;
+        nb[7] = rp + xp;
+        nb[8] = rp + xm;
     }
-    uint32_t nb[9];  // canonical (dense-pitch) offsets of z - c_i
-    dense_offsets(x, y, s.nx, s.ny, s.pitch, nb);
     const uint32_t pc = (uint32_t)s.ny * s.pitch;
     for (int j = 0; j < 9; ++j) {
         double v;
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem
             v = ((sm >> kOpp[j]) & 1u) ? fc[(uint32_t)kOpp[j] * pc + nb[0]]
                                        : fc[(uint32_t)j * pc + nb[kOpp[j]]];
         }
-        st[(uint32_t)j * s.plane + own] = ST::from_canon(v, j);
+        st[(uint32_t)j * ds + nbs[0]] = ST::from_canon(v, j);
     }
 }
 
@@ -504,8 +505,13 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src
                                                    uint4 *__restrict__ dst, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * kBlock)
-        dst[i] = src[i];
+         i += (size_t)gridDim.x * kBlock) {
+        const uint4 v = src[i];
+        __builtin_nontemporal_store(v.x, &dst[i].x);
+        __builtin_nontemporal_store(v.y, &dst[i].y);
+        __builtin_nontemporal_store(v.z, &dst[i].z);
+        __builtin_nontemporal_store(v.w, &dst[i].w);
+    }
 }
 
 // ---------------------------------------------------------------- dispatch --
@@ -519,24 +525,23 @@ hipError_t step_typed(const DevState &s, int64_t t, int cur)
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
     if (s.layout == kDenseAB || s.layout == kDenseAA) {
-        const uint32_t nbx = (uint32_t)((s.nx + kBlock - 1) / kBlock);
-        const uint32_t nblocks = nbx * (uint32_t)s.ny;
+        const uint32_t bpr = (uint32_t)((s.nx + kBlock - 1) / kBlock);
+        const uint32_t nblocks = bpr * (uint32_t)s.ny;
         if (s.layout == kDenseAB) {
             if (drag)
                 k_step_dense_ab<ST, true><<<nblocks, kBlock, 0, s.stream>>>(
-                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, (uint32_t)s.plane,
-                    nbx, nblocks, om, gx, gy);
+                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
+                    gy);
             else
                 k_step_dense_ab<ST, false><<<nblocks, kBlock, 0, s.stream>>>(
-                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, (uint32_t)s.plane,
-                    nbx, nblocks, om, gx, gy);
+                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
+                    gy);
         } else {
             M *A = (M *)s.f[0];
             const bool odd = (t & 1) != 0;
-#define LBM_AA(D, O)                                                                          \
-    k_step_dense_aa<ST, D, O><<<nblocks, kBlock, 0, s.stream>>>(                             \
-        A, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, (uint32_t)s.plane, nbx, nblocks, om, \
-        gx, gy)
+#define LBM_AA(D, O)                                                                           \
+    k_step_dense_aa<ST, D, O><<<nblocks, kBlock, 0, s.stream>>>(                              \
+        A, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx, gy)
             if (drag) {
                 if (odd)
                     LBM_AA(true, true);
@@ -556,10 +561,10 @@ hipError_t step_typed(const DevState &s, int64_t t, int cur)
             return hipSuccess;
         if (drag)
             k_step_tiled<ST, true><<<nt, kTileNodes, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, (uint32_t)s.plane, om, gx, gy);
+                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, om, gx, gy);
         else
             k_step_tiled<ST, false><<<nt, kTileNodes, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, (uint32_t)s.plane, om, gx, gy);
+                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, om, gx, gy);
     } else {
         const uint32_t nf = (uint32_t)s.n_fluid;
         if (nf == 0)
