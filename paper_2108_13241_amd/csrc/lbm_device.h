@@ -59,7 +59,16 @@ struct Shifted {
     using real = float;
     static constexpr bool kShift = true;
     static __device__ __forceinline__ real ld(mem v, int) { return (float)v; }
-    static __device__ __forceinline__ mem st(real v, int) { return (mem)v; }
+    static __device__ __forceinline__ mem st(real v, int)
+    {
+        // Round to FP32 first, then to the 16-bit format: the empty asm keeps
+        // the compiler from fusing the last FP32 FMA with the conversion (a
+        // mixed-precision FMA rounds once), which it might do in some kernels
+        // and not in others; every layout must round the same way.
+        if constexpr (sizeof(M) == 2)
+            asm volatile("" : "+v"(v));
+        return (mem)v;
+    }
     static __device__ __forceinline__ double canon(real v, int i) { return (double)v + kW[i]; }
     static __device__ __forceinline__ mem from_canon(double f, int i)
     {
@@ -71,6 +80,19 @@ using F16S = Shifted<_Float16>;
 using BF16S = Shifted<__bf16>;
 
 // -------------------------------------------------------------- collision --
+// 1 / v: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32,
+// where the storage and arithmetic tolerance is far looser.
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+__device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
+
+// c . v for the first direction of the k-th opposite pair (c = (1,0), (0,1),
+// (1,1), (-1,1)), written out so no multiplication by a zero component is left.
+template <class R>
+__device__ __forceinline__ R pair_dot(int k, R vx, R vy)
+{
+    return k == 0 ? vx : k == 1 ? vy : k == 2 ? vx + vy : vy - vx;
+}
+
 // Collision at one fluid node, in place on f (right-hand side of Eq. 3):
 //   rho = sum f_i, m = sum c_i f_i                        (Eq. 2)
 //   u   = (m / rho + g / 2) / (1 + alpha / 2)             (half-force, drag)
@@ -82,7 +104,13 @@ using BF16S = Shifted<__bf16>;
 // SHIFT: f holds deviations h_i = f_i - w_i.  Since sum w_i = 1 and
 // sum w_i c_i = 0, rho = 1 + sum h_i and m = sum c_i h_i, and the update keeps
 // its form with f^eq_i - w_i = w_i (sum h + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)).
-template <class R, bool DRAG, bool SHIFT>
+// FORCE = false (g = 0, no drag) drops the forcing terms, which are then
+// exactly zero.  Opposite directions i, opp(i) share everything but the sign
+// of the terms odd in c_i, so they are updated as a pair:
+//   f^eq_{i, opp} = w (C0 + 4.5 rho (c.u)^2) +- 3 w rho (c.u),
+//   S_{i, opp}    = w (9 (c.u)(c.F) - 3 u.F) +- 3 w (c.F),
+// with C0 = rho (1 - 1.5 u.u), or sum h - 1.5 rho u.u for deviations.
+template <class R, bool DRAG, bool SHIFT, bool FORCE = true>
 __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, const R gy,
                                         const R alpha)
 {
@@ -90,33 +118,57 @@ __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, co
     const R rho = SHIFT ? R(1) + sum : sum;
     const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R inv_rho = R(1) / rho;
-    R ux = mx * inv_rho + R(0.5) * gx;
-    R uy = my * inv_rho + R(0.5) * gy;
-    R Fx, Fy;
-    if constexpr (DRAG) {
-        const R invD = R(1) / (R(1) + R(0.5) * alpha);
-        ux *= invD;
-        uy *= invD;
-        Fx = rho * (gx - alpha * ux);
-        Fy = rho * (gy - alpha * uy);
-    } else {
-        Fx = rho * gx;
-        Fy = rho * gy;
+    const R inv_rho = recip(rho);
+    R ux = mx * inv_rho, uy = my * inv_rho;
+    R Fx = R(0), Fy = R(0);
+    if constexpr (FORCE) {
+        ux += R(0.5) * gx;
+        uy += R(0.5) * gy;
+        if constexpr (DRAG) {
+            const R invD = recip(R(1) + R(0.5) * alpha);
+            ux *= invD;
+            uy *= invD;
+            Fx = rho * (gx - alpha * ux);
+            Fy = rho * (gy - alpha * uy);
+        } else {
+            Fx = rho * gx;
+            Fy = rho * gy;
+        }
     }
     const R usq = R(1.5) * (ux * ux + uy * uy);
-    const R uF = ux * Fx + uy * Fy;
+    const R C0 = SHIFT ? sum - rho * usq : rho - rho * usq;
     const R keep = R(1) - omega;
     const R guo = R(1) - R(0.5) * omega;
+    const R uF = ux * Fx + uy * Fy;
+    // rest population
+    {
+        const R w = R(kW[0]);
+        R s = keep * f[0] + omega * (w * C0);
+        if constexpr (FORCE)
+            s += guo * (w * (R(-3) * uF));
+        f[0] = s;
+    }
+    // pairs (i, opp(i)) with c_i = (1,0), (0,1), (1,1), (-1,1)
+    constexpr int P[4] = {1, 2, 5, 6};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const R cu = R(kCx[i]) * ux + R(kCy[i]) * uy;
-        const R cF = R(kCx[i]) * Fx + R(kCy[i]) * Fy;
+    for (int k = 0; k < 4; ++k) {
+        const int i = P[k], j = kOpp[i];
         const R w = R(kW[i]);
-        const R feq = SHIFT ? w * (sum + rho * (R(3) * cu + R(4.5) * cu * cu - usq))
-                            : w * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
-        const R S = w * (R(3) * (cF - uF) + R(9) * cu * cF);
-        f[i] = keep * f[i] + omega * feq + guo * S;
+        const R cu = pair_dot(k, ux, uy);
+        const R wr = w * rho;
+        const R even = w * C0 + R(4.5) * wr * (cu * cu);
+        const R odd = R(3) * wr * cu;
+        R a = keep * f[i] + omega * (even + odd);
+        R b = keep * f[j] + omega * (even - odd);
+        if constexpr (FORCE) {
+            const R cF = pair_dot(k, Fx, Fy);
+            const R se = w * (R(9) * cu * cF - R(3) * uF);
+            const R so = R(3) * w * cF;
+            a += guo * (se + so);
+            b += guo * (se - so);
+        }
+        f[i] = a;
+        f[j] = b;
     }
 }
 

@@ -8,7 +8,8 @@
 // tiles).  Node-type, neighbour-bit and drag arrays are indexed per node:
 // dense [ny][pitch], tiled [n_tiles][256], indirect [n_fluid].
 // Offsets inside one lattice are 32-bit element indices (the runtime checks
-// 9 * nodes < 2^32).
+// 9 * nodes < 2^32).  The indirect layout's neighbours use the compact
+// row-rank description of lbm_plan.h (6 bytes per node).
 #include "lbm_device.h"
 #include "lbm_launch.h"
 
@@ -56,21 +57,41 @@ __device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const 
     }
 }
 
-// Indirect layout: nbr[(i-1) * nbr_stride + n] = compacted index of node
-// x_n - c_i, or -1 (solid).  Returns the solid-neighbour bits; nb[i] = base
-// offset of the source node.
-__device__ __forceinline__ unsigned indirect_offsets(const int32_t *__restrict__ nbr,
-                                                     uint32_t nbr_stride, uint32_t n,
-                                                     uint32_t (&nb)[9])
+// Indirect layout, compact neighbour description (see lbm_plan.h): info[n]
+// holds the solid-neighbour bits and an edge flag; pk[n] the offsets
+// q_{y-1} - n and q_{y+1} - n (int16 each) of the row-major ranks of (x, y-1)
+// and (x, y+1), or, for edge nodes, a row of the plain edge table.  Returns
+// the solid-neighbour bits; nb[i] = base offset of the source node x - c_i
+// (meaningless where that node is solid, which the caller never uses).
+__device__ __forceinline__ unsigned indirect_offsets(const uint32_t *__restrict__ pk,
+                                                     const uint16_t *__restrict__ info,
+                                                     const int32_t *__restrict__ edge,
+                                                     uint32_t n, uint32_t (&nb)[9])
 {
-    unsigned sm = 0;
-    nb[0] = list_base(n);
+    const unsigned inf = info[n];
+    const unsigned sm = (inf & 0xFFu) << 1;
+    const uint32_t p = pk[n];
+    uint32_t src[9];
+    src[0] = n;
+    if (!(inf & 0x100u)) {
+        const uint32_t qd = n + (uint32_t)(int32_t)(int16_t)(p & 0xFFFFu);  // rank of (x, y-1)
+        const uint32_t qu = n + (uint32_t)(int32_t)(int16_t)(p >> 16);      // rank of (x, y+1)
+        src[1] = n - 1;                                 // (x-1, y)
+        src[3] = n + 1;                                 // (x+1, y)
+        src[2] = qd;                                    // (x, y-1)
+        src[5] = qd - 1;                                // (x-1, y-1)
+        src[6] = qd + (((sm >> 2) & 1u) ^ 1u);          // (x+1, y-1)
+        src[4] = qu;                                    // (x, y+1)
+        src[8] = qu - 1;                                // (x-1, y+1)
+        src[7] = qu + (((sm >> 4) & 1u) ^ 1u);          // (x+1, y+1)
+    } else {
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const int32_t j = nbr[(uint32_t)(i - 1) * nbr_stride + n];
-        sm |= (j < 0 ? 1u : 0u) << i;
-        nb[i] = list_base((uint32_t)j);
+        for (int i = 1; i < 9; ++i)
+            src[i] = (uint32_t)edge[p * 8u + (uint32_t)(i - 1)];
     }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        nb[i] = list_base(src[i]);
     return sm;
 }
 
@@ -83,6 +104,12 @@ __device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__
                                             const uint32_t (&nb)[9], unsigned sm,
                                             typename ST::real (&f)[9])
 {
+    if (sm == 0) {  // interior node: no bounce-back
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            f[i] = ST::ld(s[(uint32_t)i * ds + nb[i]], i);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * ds + nb[0]
@@ -124,8 +151,71 @@ __device__ __forceinline__ bool dense_node(uint32_t bpr, uint32_t nblocks, int n
     return x < nx;
 }
 
+// Dense addressing split into row and column parts: node (x, y) has base
+// offset row_off(y) + col_off(x).  A step workgroup is one row segment, so the
+// three row offsets (rows y-1, y, y+1) are uniform (scalar registers) and each
+// lane keeps three column offsets (columns x-1, x, x+1), which stay below 2^28
+// so that loads use a scalar base plus a 32-bit lane offset.
+struct DenseRC {
+    uint32_t r[3];  // rows y-1, y, y+1
+    uint32_t c[3];  // columns x-1, x, x+1
+};
+
+__device__ __forceinline__ uint32_t col_off(int x)
+{
+    return ((((uint32_t)x >> 6) * (9u * kChunk)) | ((uint32_t)x & 63u)) & 0x0FFFFFFFu;
+}
+
+__device__ __forceinline__ DenseRC dense_rc(int x, int y, int nx, int ny, uint32_t cpr)
+{
+    DenseRC a;
+    const uint32_t row = cpr * (9u * kChunk);
+    a.r[0] = (uint32_t)wrap_dec(y, ny) * row;
+    a.r[1] = (uint32_t)y * row;
+    a.r[2] = (uint32_t)wrap_inc(y, ny) * row;
+    a.c[0] = col_off(wrap_dec(x, nx));
+    a.c[1] = col_off(x);
+    a.c[2] = col_off(wrap_inc(x, nx));
+    return a;
+}
+
+// Element of population plane `i` at row slot `ri`, column slot `ci` of a
+// dense lattice: scalar part i * 64 + r[ri], lane part c[ci].
+template <class M>
+__device__ __forceinline__ M &dense_at(M *__restrict__ s, const DenseRC &a, int i, int ri, int ci)
+{
+    M *p = s + ((uint32_t)i * kChunk + a.r[ri]);
+    return p[a.c[ci]];
+}
+
+// Pull gather of the dense layout (same values as pull_gather with dense_bases):
+// the source of f_i is node x - c_i, i.e. row slot 1 - c_i.y, column slot 1 - c_i.x.
+template <class ST>
+__device__ __forceinline__ void dense_pull(const typename ST::mem *__restrict__ s,
+                                           const DenseRC &a, unsigned sm,
+                                           typename ST::real (&f)[9])
+{
+    using M = typename ST::mem;
+    M *sp = const_cast<M *>(s);
+    if (sm == 0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            f[i] = ST::ld(dense_at(sp, a, i, 1 - kCy[i], 1 - kCx[i]), i);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = ST::ld(((sm >> i) & 1u) ? dense_at(sp, a, kOpp[i], 1, 1)
+                                       : dense_at(sp, a, i, 1 - kCy[i], 1 - kCx[i]),
+                      i);
+}
+
 // ------------------------------------------------------------- step: dense --
-template <class ST, bool DRAG>
+// Physics variant of a step kernel: plain BGK (no body force, no drag), body
+// force, or body force with a drag field.
+enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2 };
+
+template <class ST, int PH>
 __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
@@ -133,6 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
+    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
     int x, y;
     if (!dense_node(bpr, nblocks, nx, x, y))
         return;
@@ -141,14 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     if (t == kSolid)
         return;
     const unsigned sm = solid_bits(t, nmask, n);
-    uint32_t nb[9];
-    dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
+    const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
     R f[9];
-    pull_gather<ST>(src, kChunk, nb, sm, f);
-    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+    dense_pull<ST>(src, a, sm, f);
+    collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        store_nt(&dst[(uint32_t)i * kChunk + nb[0]], ST::st(f[i], i));
+        store_nt(&dense_at(dst, a, i, 1, 1), ST::st(f[i], i));
 }
 
 // AA pattern (single lattice A).  Even step: read A_i(x), write the
@@ -156,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
 // (A_i(x) if x - c_i is solid), write f_i to A_i(x + c_i) (A_opp(i)(x) if
 // x + c_i is solid).  Slot A_j(z) is read and written by one node only
 // (z - c_j if it is fluid, else z), so there is no race.
-template <class ST, bool DRAG, bool ODD>
+template <class ST, int PH, bool ODD>
 __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
     const uint8_t *__restrict__ nmask, const float *__restrict__ alpha, int nx, int ny, int pitch,
@@ -164,6 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     typename ST::real gy)
 {
     using R = typename ST::real;
+    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
     int x, y;
     if (!dense_node(bpr, nblocks, nx, x, y))
         return;
@@ -171,32 +262,47 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     const uint8_t t = type[n];
     if (t == kSolid)
         return;
+    const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
     R f[9];
     if constexpr (!ODD) {
-        const uint32_t own = dense_base(x, y, (uint32_t)pitch / kChunk);
-        local_gather<ST>(A, kChunk, own, f);
-        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            store_nt(&A[(uint32_t)kOpp[i] * kChunk + own], ST::st(f[i], i));
+            f[i] = ST::ld(dense_at(A, a, i, 1, 1), i);
+        collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            store_nt(&dense_at(A, a, kOpp[i], 1, 1), ST::st(f[i], i));
     } else {
         const unsigned sm = solid_bits(t, nmask, n);
-        uint32_t nb[9];
-        dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
-        aa_odd_gather<ST>(A, kChunk, nb, sm, f);
-        collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+        if (sm == 0) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
-            const uint32_t o = ((sm >> kOpp[i]) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
-                                                      : (uint32_t)i * kChunk + nb[kOpp[i]];
-            store_nt(&A[o], ST::st(f[i], i));
+            for (int i = 0; i < 9; ++i)
+                f[i] = ST::ld(dense_at(A, a, kOpp[i], 1 - kCy[i], 1 - kCx[i]), i);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[i] = ST::ld(((sm >> i) & 1u) ? dense_at(A, a, i, 1, 1)
+                                               : dense_at(A, a, kOpp[i], 1 - kCy[i], 1 - kCx[i]),
+                              i);
+        }
+        collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+        // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
+        if (sm == 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                store_nt(&dense_at(A, a, i, 1 + kCy[i], 1 + kCx[i]), ST::st(f[i], i));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                store_nt(((sm >> kOpp[i]) & 1u) ? &dense_at(A, a, kOpp[i], 1, 1)
+                                                : &dense_at(A, a, i, 1 + kCy[i], 1 + kCx[i]),
+                         ST::st(f[i], i));
         }
     }
 }
 
 // ------------------------------------------------------------- step: tiled --
-template <class ST, bool DRAG>
+template <class ST, int PH>
 __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
@@ -204,6 +310,7 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
+    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
     const uint32_t k = xcd_remap(blockIdx.x, n_tiles);
     const int t = (int)threadIdx.x, lx = t & 15, ly = t >> 4;
     const uint32_t n = k * kTileNodes + t;
@@ -219,29 +326,30 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     tiled_offsets(k, lx, ly, tn, nb);
     R f[9];
     pull_gather<ST>(src, kTileStride, nb, sm, f);
-    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+    collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kTileStride + nb[0]], ST::st(f[i], i));
 }
 
 // ---------------------------------------------------------- step: indirect --
-template <class ST, bool DRAG>
+template <class ST, int PH>
 __global__ __launch_bounds__(kBlock) void k_step_indirect(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
-    const int32_t *__restrict__ nbr, const float *__restrict__ alpha, uint32_t n_fluid,
-    uint32_t nbr_stride, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
-    typename ST::real gy)
+    const uint32_t *__restrict__ pk, const uint16_t *__restrict__ info,
+    const int32_t *__restrict__ edge, const float *__restrict__ alpha, uint32_t n_fluid,
+    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
+    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
     const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
     if (n >= n_fluid)
         return;
     uint32_t nb[9];
-    const unsigned sm = indirect_offsets(nbr, nbr_stride, n, nb);
+    const unsigned sm = indirect_offsets(pk, info, edge, n, nb);
     R f[9];
     pull_gather<ST>(src, kChunk, nb, sm, f);
-    collide<R, DRAG, ST::kShift>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+    collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kChunk + nb[0]], ST::st(f[i], i));
@@ -289,7 +397,7 @@ __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x,
     } else {
         if (gid >= (uint32_t)s.n_fluid)
             return false;
-        sm = indirect_offsets(s.nbr, (uint32_t)s.plane, gid, nb);
+        sm = indirect_offsets(s.ind_pk, s.ind_info, s.ind_edge, gid, nb);
         x = s.fluid_xy[2 * gid];
         y = s.fluid_xy[2 * gid + 1];
         ds = kChunk;
@@ -515,68 +623,52 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src
 }
 
 // ---------------------------------------------------------------- dispatch --
-template <class ST>
-hipError_t step_typed(const DevState &s, int64_t t, int cur)
+template <class ST, int PH>
+void step_launch(const DevState &s, int64_t t, int cur)
 {
     using M = typename ST::mem;
     using R = typename ST::real;
     const R om = (R)s.omega, gx = (R)s.gx, gy = (R)s.gy;
-    const bool drag = s.alpha != nullptr;
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
     if (s.layout == kDenseAB || s.layout == kDenseAA) {
         const uint32_t bpr = (uint32_t)((s.nx + kBlock - 1) / kBlock);
         const uint32_t nblocks = bpr * (uint32_t)s.ny;
         if (s.layout == kDenseAB) {
-            if (drag)
-                k_step_dense_ab<ST, true><<<nblocks, kBlock, 0, s.stream>>>(
-                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
-                    gy);
-            else
-                k_step_dense_ab<ST, false><<<nblocks, kBlock, 0, s.stream>>>(
-                    src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
-                    gy);
+            k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
+                src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx, gy);
+        } else if (t & 1) {
+            k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, 0, s.stream>>>(
+                (M *)s.f[0], s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
+                gy);
         } else {
-            M *A = (M *)s.f[0];
-            const bool odd = (t & 1) != 0;
-#define LBM_AA(D, O)                                                                           \
-    k_step_dense_aa<ST, D, O><<<nblocks, kBlock, 0, s.stream>>>(                              \
-        A, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx, gy)
-            if (drag) {
-                if (odd)
-                    LBM_AA(true, true);
-                else
-                    LBM_AA(true, false);
-            } else {
-                if (odd)
-                    LBM_AA(false, true);
-                else
-                    LBM_AA(false, false);
-            }
-#undef LBM_AA
+            k_step_dense_aa<ST, PH, false><<<nblocks, kBlock, 0, s.stream>>>(
+                (M *)s.f[0], s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
+                gy);
         }
     } else if (s.layout == kTiled16) {
         const uint32_t nt = (uint32_t)s.n_tiles;
-        if (nt == 0)
-            return hipSuccess;
-        if (drag)
-            k_step_tiled<ST, true><<<nt, kTileNodes, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, om, gx, gy);
-        else
-            k_step_tiled<ST, false><<<nt, kTileNodes, 0, s.stream>>>(
+        if (nt > 0)
+            k_step_tiled<ST, PH><<<nt, kTileNodes, 0, s.stream>>>(
                 src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, om, gx, gy);
     } else {
         const uint32_t nf = (uint32_t)s.n_fluid;
-        if (nf == 0)
-            return hipSuccess;
         const uint32_t nblocks = (nf + kBlock - 1) / kBlock;
-        if (drag)
-            k_step_indirect<ST, true><<<nblocks, kBlock, 0, s.stream>>>(
-                src, dst, s.nbr, s.alpha, nf, (uint32_t)s.plane, nblocks, om, gx, gy);
-        else
-            k_step_indirect<ST, false><<<nblocks, kBlock, 0, s.stream>>>(
-                src, dst, s.nbr, s.alpha, nf, (uint32_t)s.plane, nblocks, om, gx, gy);
+        if (nf > 0)
+            k_step_indirect<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
+                src, dst, s.ind_pk, s.ind_info, s.ind_edge, s.alpha, nf, nblocks, om, gx, gy);
     }
+}
+
+template <class ST>
+hipError_t step_typed(const DevState &s, int64_t t, int cur)
+{
+    if (s.alpha)
+        step_launch<ST, kDragged>(s, t, cur);
+    else if (s.gx != 0.0 || s.gy != 0.0)
+        step_launch<ST, kForced>(s, t, cur);
+    else
+        step_launch<ST, kBGK>(s, t, cur);
     return hipGetLastError();
 }
 

@@ -26,7 +26,10 @@ struct DevState {
     const float *alpha = nullptr;     // drag coefficient, same indexing as type
                                       // (INDIRECT: per compacted node); may be null
     const int32_t *tile_xy = nullptr, *tile_nbr = nullptr;  // TILED16
-    const int32_t *nbr = nullptr, *fluid_xy = nullptr;      // INDIRECT
+    const int32_t *fluid_xy = nullptr;                      // INDIRECT: [n][2]
+    const uint32_t *ind_pk = nullptr;                       // INDIRECT: packed row offsets
+    const uint16_t *ind_info = nullptr;                     // INDIRECT: solid bits + edge flag
+    const int32_t *ind_edge = nullptr;                      // INDIRECT: edge-node table [][8]
     int64_t n_tiles = 0, n_fluid = 0;
     double omega = 1.0, gx = 0.0, gy = 0.0;
     hipStream_t stream = nullptr;

@@ -114,5 +114,45 @@ void indirect_neighbours(const Fluid &fl, int nx, int ny, int64_t plane, std::ve
     }
 }
 
+IndirectCompact indirect_compact(const Fluid &fl, const uint8_t *mask, int nx, int ny,
+                                 int64_t plane)
+{
+    IndirectCompact out;
+    out.pk.assign((size_t)plane, 0);
+    out.info.assign((size_t)plane, 0);
+    // rank[y][x] = number of fluid nodes before (x, y) in row-major order
+    std::vector<int64_t> rank((size_t)nx * ny);
+    int64_t cnt = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            rank[(size_t)y * nx + x] = cnt;
+            cnt += mask[(size_t)y * nx + x] == 0;
+        }
+    for (int64_t n = 0; n < fl.n_fluid; ++n) {
+        const int x = fl.xy[2 * n], y = fl.xy[2 * n + 1];
+        const uint8_t bits = solid_neighbours(mask, nx, ny, x, y);
+        bool edge = x == 0 || x == nx - 1 || y == 0 || y == ny - 1;
+        int64_t dn = 0, up = 0;
+        if (!edge) {
+            dn = rank[(size_t)(y - 1) * nx + x] - n;
+            up = rank[(size_t)(y + 1) * nx + x] - n;
+            edge = dn < -32768 || dn > 32767 || up < -32768 || up > 32767;
+        }
+        out.info[n] = (uint16_t)(bits | (edge ? 0x100 : 0));
+        if (!edge) {
+            out.pk[n] = (uint32_t)(uint16_t)(int16_t)dn | ((uint32_t)(uint16_t)(int16_t)up << 16);
+        } else {
+            out.pk[n] = (uint32_t)out.n_edge++;
+            for (int i = 1; i < 9; ++i) {
+                const int sx = wrapi(x - kHostCx[i], nx), sy = wrapi(y - kHostCy[i], ny);
+                out.edge.push_back(fl.index_of[(size_t)sy * nx + sx]);
+            }
+        }
+    }
+    if (out.edge.empty())
+        out.edge.assign(8, -1);
+    return out;
+}
+
 }  // namespace plan
 }  // namespace lbm

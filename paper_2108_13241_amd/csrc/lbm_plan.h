@@ -45,5 +45,27 @@ Fluid fluid_list(const uint8_t *mask, int nx, int ny);
 // nbr[(i-1) * plane + n] = index of the fluid node at x_n - c_i, or -1.
 void indirect_neighbours(const Fluid &fl, int nx, int ny, int64_t plane, std::vector<int32_t> &nbr);
 
+// Compact neighbour description of the compacted fluid list (6 bytes per node
+// instead of 32).  For node n at (x, y) and a row r, let q_r be the index the
+// node (x, r) has or would have in the row-major compaction (the count of fluid
+// nodes before it).  Then the pull sources are
+//   (x-1, y) = n - 1, (x+1, y) = n + 1,
+//   (x, r) = q_r, (x-1, r) = q_r - 1, (x+1, r) = q_r + [(x, r) is fluid],
+// for r = y - 1 and y + 1, whenever the source is fluid (the solid bits say).
+// info[n] : bits 0..7 = solid-neighbour bits (bit i-1 <=> x - c_i solid),
+//           bit 8 = edge node (x or y on the mesh border, where periodic wrap
+//           breaks the row-major arithmetic, or an offset outside int16).
+// pk[n]   : (uint16)(q_{y-1} - n) | (uint16)(q_{y+1} - n) << 16 for interior
+//           nodes; for edge nodes the row of the edge table.
+// edge    : [n_edge][8] plain neighbour indices (as nbr) of the edge nodes.
+struct IndirectCompact {
+    std::vector<uint32_t> pk;
+    std::vector<uint16_t> info;
+    std::vector<int32_t> edge;
+    int64_t n_edge = 0;
+};
+IndirectCompact indirect_compact(const Fluid &fl, const uint8_t *mask, int nx, int ny,
+                                 int64_t plane);
+
 }  // namespace plan
 }  // namespace lbm

@@ -304,14 +304,20 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
         c->fluid = lbm::plan::fluid_list(node_type, nx, ny);
         s.n_fluid = c->fluid.n_fluid;
         s.plane = (size_t)round_up(std::max<int64_t>(s.n_fluid, 1), 64);
-        std::vector<int32_t> nbr;
-        lbm::plan::indirect_neighbours(c->fluid, nx, ny, (int64_t)s.plane, nbr);
+        lbm::plan::IndirectCompact ic =
+            lbm::plan::indirect_compact(c->fluid, node_type, nx, ny, (int64_t)s.plane);
         if ((rc = upload(c->fluid.xy.data(), c->fluid.xy.size() * 4, &p)))
             return fail_create(rc, "cannot upload the fluid list");
         s.fluid_xy = (const int32_t *)p;
-        if ((rc = upload(nbr.data(), nbr.size() * 4, &p)))
-            return fail_create(rc, "cannot upload the neighbour table");
-        s.nbr = (const int32_t *)p;
+        if ((rc = upload(ic.pk.data(), ic.pk.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the neighbour offsets");
+        s.ind_pk = (const uint32_t *)p;
+        if ((rc = upload(ic.info.data(), ic.info.size() * 2, &p)))
+            return fail_create(rc, "cannot upload the neighbour bits");
+        s.ind_info = (const uint16_t *)p;
+        if ((rc = upload(ic.edge.data(), ic.edge.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the edge-node table");
+        s.ind_edge = (const int32_t *)p;
     }
     if ((uint64_t)9 * s.plane >= (uint64_t(1) << 32))
         return fail_create(LBM_ERR_UNSUPPORTED, "lattice too large for 32-bit offsets");
@@ -761,7 +767,7 @@ int lbm_get_info(const lbm_ctx *c, lbm_info_t *info)
     else if (s.layout == LBM_TILED16)
         info->bytes_moved_per_step = (pops + 1.0 + drag) * (double)s.n_tiles * lbm::kTileNodes;
     else
-        info->bytes_moved_per_step = (pops + 32.0 + drag) * c->n_fluid;
+        info->bytes_moved_per_step = (pops + 6.0 + drag) * c->n_fluid;
     info->device_bytes = c->device_bytes;
     return LBM_OK;
 }

@@ -23,6 +23,18 @@ DRIVER = textwrap.dedent(r"""
         std::vector<uint8_t> mask((size_t)nx * ny);
         for (auto &m : mask) { int v; if (std::scanf("%d", &v) != 1) return 2; m = (uint8_t)v; }
         std::vector<uint8_t> type, nmask;
+        if (tiled == 2) {
+            lbm::plan::Fluid fl = lbm::plan::fluid_list(mask.data(), nx, ny);
+            lbm::plan::IndirectCompact ic =
+                lbm::plan::indirect_compact(fl, mask.data(), nx, ny, fl.n_fluid);
+            for (long n = 0; n < fl.n_fluid; ++n) {
+                std::printf("%d %d %u %u", fl.xy[2 * n], fl.xy[2 * n + 1], (unsigned)ic.info[n], ic.pk[n]);
+                if (ic.info[n] & 0x100)
+                    for (int i = 0; i < 8; ++i) std::printf(" %d", ic.edge[ic.pk[n] * 8 + i]);
+                std::printf("\n");
+            }
+            return 0;
+        }
         if (!tiled) {
             lbm::plan::dense_types(mask.data(), nx, ny, pitch, type, nmask);
             for (int y = 0; y < ny; ++y)
@@ -97,3 +109,48 @@ def test_tiled_types(planner):
     rows = _run(planner, m, 0, True)
     for x, y, t, b in rows:
         assert (t, b) == _expected(m, x, y), (x, y)
+
+
+def _decode(rows):
+    """Neighbour indices from the compact description, by the documented rule."""
+    out = []
+    for n, r in enumerate(rows):
+        x, y, info, pk = r[:4]
+        bits = info & 0xFF
+        solid = lambda i: (bits >> (i - 1)) & 1
+        if info & 0x100:
+            src = list(r[4:12])
+        else:
+            dn = ((pk & 0xFFFF) ^ 0x8000) - 0x8000
+            up = ((pk >> 16) ^ 0x8000) - 0x8000
+            qd, qu = n + dn, n + up
+            src = [None] * 8
+            src[0] = n - 1          # dir 1: (x-1, y)
+            src[2] = n + 1          # dir 3: (x+1, y)
+            src[1] = qd             # dir 2: (x, y-1)
+            src[4] = qd - 1         # dir 5: (x-1, y-1)
+            src[5] = qd + (1 - solid(2))  # dir 6: (x+1, y-1)
+            src[3] = qu             # dir 4: (x, y+1)
+            src[7] = qu - 1         # dir 8: (x-1, y+1)
+            src[6] = qu + (1 - solid(4))  # dir 7: (x+1, y+1)
+        out.append([(-1 if solid(i) else src[i - 1]) for i in range(1, 9)])
+    return out
+
+
+@pytest.mark.parametrize("shape,frac", [((37, 23), 0.3), ((64, 40), 0.0), ((9, 7), 0.5)])
+def test_indirect_compact(planner, shape, frac):
+    import paper_2108_13241_amd as lbm
+    nx, ny = shape
+    m = synthetic.random_mask(nx, ny, seed=nx + 3 * ny, solid_fraction=frac)
+    ny_, nx_ = m.shape
+    inp = f"{nx} {ny} 0 2\n" + " ".join(str(int(v)) for v in m.ravel())
+    r = subprocess.run([planner], input=inp, capture_output=True, text=True)
+    assert r.returncode == 0
+    rows = [list(map(int, ln.split())) for ln in r.stdout.split("\n") if ln.strip()]
+    _, nbr = lbm.plan_indirect(m)  # plain table: nbr[i-1][n]
+    dec = _decode(rows)
+    assert len(dec) == nbr.shape[1]
+    for n, d in enumerate(dec):
+        assert d == list(nbr[:, n]), n
+    # interior nodes use the compact form
+    assert sum(1 for r in rows if not r[2] & 0x100) > 0
