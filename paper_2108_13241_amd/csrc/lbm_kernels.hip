@@ -142,10 +142,12 @@ __device__ __forceinline__ void local_gather(const typename ST::mem *__restrict_
         f[i] = ST::ld(s[(uint32_t)i * ds + own], i);
 }
 
-// Node of a dense step thread: 256-lane row segments, XCD-remapped.
-__device__ __forceinline__ bool dense_node(uint32_t bpr, uint32_t nblocks, int nx, int &x, int &y)
+// Node of a dense step thread: 256-lane row segments, XCD-remapped; L is the
+// segment index (row-major).
+__device__ __forceinline__ bool dense_node(uint32_t bpr, uint32_t nblocks, int nx, int &x, int &y,
+                                           uint32_t &L)
 {
-    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    L = xcd_remap(blockIdx.x, nblocks);
     y = (int)(L / bpr);
     x = (int)(L - (uint32_t)y * bpr) * kBlock + (int)threadIdx.x;
     return x < nx;
@@ -219,19 +221,26 @@ template <class ST, int PH>
 __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
-    const float *__restrict__ alpha, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
-    typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    const uint32_t *__restrict__ seg_interior, const float *__restrict__ alpha, int nx, int ny,
+    int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy)
 {
     using R = typename ST::real;
     constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
     int x, y;
-    if (!dense_node(bpr, nblocks, nx, x, y))
+    uint32_t L;
+    if (!dense_node(bpr, nblocks, nx, x, y, L))
         return;
     const uint32_t n = (uint32_t)y * pitch + x;
-    const uint8_t t = type[n];
-    if (t == kSolid)
-        return;
-    const unsigned sm = solid_bits(t, nmask, n);
+    // Segments of interior fluid nodes need neither the node type nor the
+    // neighbour bits, so their population loads issue at once.
+    unsigned sm = 0;
+    if (!seg_interior[L]) {
+        const uint8_t t = type[n];
+        if (t == kSolid)
+            return;
+        sm = solid_bits(t, nmask, n);
+    }
     const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
     R f[9];
     dense_pull<ST>(src, a, sm, f);
@@ -249,17 +258,19 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
 template <class ST, int PH, bool ODD>
 __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
-    const uint8_t *__restrict__ nmask, const float *__restrict__ alpha, int nx, int ny, int pitch,
-    uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
-    typename ST::real gy)
+    const uint8_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior,
+    const float *__restrict__ alpha, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
+    typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
     constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
     int x, y;
-    if (!dense_node(bpr, nblocks, nx, x, y))
+    uint32_t L;
+    if (!dense_node(bpr, nblocks, nx, x, y, L))
         return;
     const uint32_t n = (uint32_t)y * pitch + x;
-    const uint8_t t = type[n];
+    const bool interior = seg_interior[L] != 0;
+    const uint8_t t = interior ? (uint8_t)kFluid : type[n];
     if (t == kSolid)
         return;
     const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
@@ -273,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
         for (int i = 0; i < 9; ++i)
             store_nt(&dense_at(A, a, kOpp[i], 1, 1), ST::st(f[i], i));
     } else {
-        const unsigned sm = solid_bits(t, nmask, n);
+        const unsigned sm = interior ? 0u : solid_bits(t, nmask, n);
         if (sm == 0) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)
@@ -636,15 +647,16 @@ void step_launch(const DevState &s, int64_t t, int cur)
         const uint32_t nblocks = bpr * (uint32_t)s.ny;
         if (s.layout == kDenseAB) {
             k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx, gy);
+                src, dst, s.type, s.nmask, s.seg_interior, s.alpha, s.nx, s.ny, s.pitch, bpr,
+                nblocks, om, gx, gy);
         } else if (t & 1) {
             k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, 0, s.stream>>>(
-                (M *)s.f[0], s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
-                gy);
+                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.nx, s.ny, s.pitch, bpr,
+                nblocks, om, gx, gy);
         } else {
             k_step_dense_aa<ST, PH, false><<<nblocks, kBlock, 0, s.stream>>>(
-                (M *)s.f[0], s.type, s.nmask, s.alpha, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
-                gy);
+                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.nx, s.ny, s.pitch, bpr,
+                nblocks, om, gx, gy);
         }
     } else if (s.layout == kTiled16) {
         const uint32_t nt = (uint32_t)s.n_tiles;

@@ -23,6 +23,7 @@ struct DevState {
     void *f[2] = {nullptr, nullptr};  // lattices (f[1] unused by DENSE_AA)
     const uint8_t *type = nullptr;    // node-type codes (dense / tiled)
     const uint8_t *nmask = nullptr;   // solid-neighbour bits (dense / tiled)
+    const uint32_t *seg_interior = nullptr;  // dense: per 256-node row segment, 1 = all interior
     const float *alpha = nullptr;     // drag coefficient, same indexing as type
                                       // (INDIRECT: per compacted node); may be null
     const int32_t *tile_xy = nullptr, *tile_nbr = nullptr;  // TILED16

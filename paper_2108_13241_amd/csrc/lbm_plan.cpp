@@ -41,6 +41,20 @@ void dense_types(const uint8_t *mask, int nx, int ny, int pitch, std::vector<uin
         }
 }
 
+void dense_segment_flags(const std::vector<uint8_t> &type, int nx, int ny, int pitch, int seg,
+                         std::vector<uint32_t> &flags)
+{
+    const int bpr = (nx + seg - 1) / seg;
+    flags.assign((size_t)bpr * ny, 0);
+    for (int y = 0; y < ny; ++y)
+        for (int b = 0; b < bpr; ++b) {
+            bool all = true;
+            for (int x = b * seg; x < nx && x < (b + 1) * seg && all; ++x)
+                all = type[(size_t)y * pitch + x] == 0;
+            flags[(size_t)y * bpr + b] = all ? 1u : 0u;
+        }
+}
+
 Tiles tiles16(const uint8_t *mask, int nx, int ny)
 {
     Tiles t;

@@ -24,6 +24,12 @@ uint8_t solid_neighbours(const uint8_t *mask, int nx, int ny, int x, int y);
 void dense_types(const uint8_t *mask, int nx, int ny, int pitch, std::vector<uint8_t> &type,
                  std::vector<uint8_t> &nmask);
 
+// Per 256-node row segment of the dense step grid (bpr segments per row,
+// row-major): 1 if every node of the segment is an interior fluid node (type
+// code 0), else 0.  Such segments need no node-type or neighbour reads.
+void dense_segment_flags(const std::vector<uint8_t> &type, int nx, int ny, int pitch, int seg,
+                         std::vector<uint32_t> &flags);
+
 struct Tiles {
     int64_t n_tiles = 0;
     std::vector<int32_t> xy;   // [n_tiles][2]

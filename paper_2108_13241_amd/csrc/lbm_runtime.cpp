@@ -289,6 +289,11 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
     if (layout == LBM_DENSE_AB || layout == LBM_DENSE_AA) {
         lbm::plan::dense_types(node_type, nx, ny, (int)pitch, type, nmask);
         s.plane = (size_t)ny * pitch;
+        std::vector<uint32_t> seg;
+        lbm::plan::dense_segment_flags(type, nx, ny, (int)pitch, 256, seg);
+        if ((rc = upload(seg.data(), seg.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the segment flags");
+        s.seg_interior = (const uint32_t *)p;
     } else if (layout == LBM_TILED16) {
         c->tiles = lbm::plan::tiles16(node_type, nx, ny);
         lbm::plan::tiled_types(node_type, nx, ny, c->tiles, type, nmask);
