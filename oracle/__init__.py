@@ -11,6 +11,11 @@ Array conventions (numpy, C order):
                               left-hand side of the LB update (Sec. 2.2, Eq. 3);
                               solid slots are 0
   alpha  float64 [ny, nx]     Brinkman drag coefficient (None = 0)
+  bc     uint8  [ny, nx]      open-boundary code (Sec. 3, Zou-He): 0 none, 1..4 constant
+                              velocity with inward normal +x, -x, +y, -y, 5..8 constant
+                              pressure with the same normals (None = no open boundaries)
+  value  float64 [2, ny, nx]  boundary values: (u_x, u_y) at velocity nodes, (rho, -) at
+                              pressure nodes
 
 Pins (tests/test_oracle_*.py) check it against what the paper and the mathematics
 fix: closed-form moments of the equilibrium (Eq. 6) and of the forcing term,
@@ -79,6 +84,15 @@ def lib():
                                                 _dp, ctypes.c_long, ctypes.c_int, _dp, _dp, _dp]
         L.oracle_outlet_ux_gradient.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_zou_he.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, _dp]
+        L.oracle_zou_he.restype = ctypes.c_int
+        L.oracle_apply_boundaries.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _u8p, _dp, _dp]
+        L.oracle_apply_boundaries.restype = ctypes.c_int
+        L.oracle_run_bc.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp,
+                                    ctypes.c_long, ctypes.c_int]
+        L.oracle_run_bc.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -144,7 +158,46 @@ def collide_jacobian(f, omega, alpha=0.0, g=(0.0, 0.0)):
     return dfdf, dfda, dfdg
 
 
-def init(mask, rho0=None, ux0=None, uy0=None):
+def zou_he(f, kind, normal, value):
+    """One Zou-He boundary node: kind "velocity" (value = (u_x, u_y)) or "pressure"
+    (value = (rho, -)), inward unit normal (n_x, n_y) along an axis."""
+    f = _f64(f)
+    out = np.zeros(9)
+    k = {"velocity": 1, "pressure": 2}[kind]
+    rc = lib().oracle_zou_he(_d(f), k, int(normal[0]), int(normal[1]), float(value[0]),
+                             float(value[1]), _d(out))
+    if rc:
+        raise ValueError("bad normal")
+    return out
+
+
+def _bc_args(m, bc, value):
+    if bc is None:
+        return None, None
+    ny, nx = m.shape
+    bc = np.ascontiguousarray(bc, dtype=np.uint8)
+    value = np.ascontiguousarray(value, dtype=np.float64)
+    if bc.shape != (ny, nx) or value.shape != (2, ny, nx):
+        raise ValueError("bc must be [ny, nx] and value [2, ny, nx]")
+    return bc, value
+
+
+def apply_boundaries(mask, f, bc, value):
+    """Return a copy of f with the open-boundary conditions applied."""
+    m = _mask(mask)
+    ny, nx = m.shape
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    bc, value = _bc_args(m, bc, value)
+    rc = lib().oracle_apply_boundaries(nx, ny, m.ctypes.data_as(_u8p), bc.ctypes.data_as(_u8p),
+                                       _d(value), _d(f))
+    if rc:
+        raise ValueError("bad boundary code (or a code at a solid node)")
+    return f
+
+
+def init(mask, rho0=None, ux0=None, uy0=None, bc=None, value=None):
+    """Equilibrium initial state (Algorithm 1, first loop); with open boundaries the
+    boundary conditions are then applied, so that every state satisfies them."""
     m = _mask(mask)
     ny, nx = m.shape
     f = np.zeros((9, ny, nx))
@@ -152,10 +205,12 @@ def init(mask, rho0=None, ux0=None, uy0=None):
     rc = lib().oracle_init(nx, ny, m.ctypes.data_as(_u8p), _d(rho0), _d(ux0), _d(uy0), _d(f))
     if rc:
         raise ValueError("oracle_init failed")
+    if bc is not None:
+        f = apply_boundaries(m, f, bc, value)
     return f
 
 
-def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0):
+def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value=None):
     """Advance a copy of f by `steps` time steps; returns the new array."""
     m = _mask(mask)
     ny, nx = m.shape
@@ -163,8 +218,10 @@ def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0):
     if f.shape != (9, ny, nx):
         raise ValueError("f must be [9, ny, nx]")
     alpha = _f64(alpha)
-    rc = lib().oracle_run(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, g[0], g[1], _d(alpha),
-                          int(steps), int(threads))
+    bc, value = _bc_args(m, bc, value)
+    rc = lib().oracle_run_bc(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, g[0], g[1], _d(alpha),
+                             None if bc is None else bc.ctypes.data_as(_u8p), _d(value),
+                             int(steps), int(threads))
     if rc:
         raise ValueError(f"oracle_run failed ({rc})")
     return f

@@ -30,7 +30,16 @@
  *     with force density F = rho*(g - alpha*u) and the half-force velocity;
  *   - a per-node Brinkman coefficient alpha adds the linear drag -rho*alpha*u,
  *     taken implicitly: u = (m/rho + g/2) / (1 + alpha/2);
- *   - with g = 0 and alpha = 0 the collision is exactly Eqs. 2-6.
+ *   - with g = 0 and alpha = 0 the collision is exactly Eqs. 2-6;
+ *   - open boundaries (Sec. 3: constant velocity and constant pressure after
+ *     Zou and He) are boundary nodes with a prescribed inward normal n along
+ *     an axis.  After every streaming phase (and on the initial state) the
+ *     three populations with v_i . n > 0, which would have come from outside
+ *     the domain, are rebuilt so that the node's Eq. 2 moments take the
+ *     prescribed values (velocity: m = rho u_b; pressure: rho = rho_b with no
+ *     tangential velocity) and the non-equilibrium part of the normal
+ *     population equals that of its opposite.  Whatever streamed into those
+ *     slots across the periodic seam is discarded.
  *
  * Precision: FP64 throughout; build with -O2 -ffp-contract=off, no fast-math;
  * sums over directions run in ascending i.
@@ -159,6 +168,99 @@ int oracle_init(int nx, int ny, const uint8_t *mask, const double *rho0, const d
     return 0;
 }
 
+/* Zou-He boundary node (Sec. 3, constant velocity / constant pressure).
+ * kind 1: prescribed velocity (a, b) = (u_x, u_y); kind 2: prescribed density
+ * a (b unused).  (nxn, nyn) is the inward unit normal, along an axis.  Reads
+ * the 9 populations of the node after streaming; writes them with the three
+ * entering ones (v_i . n > 0) replaced.  Conditions, with t the unit tangent:
+ *   sum f = rho,  sum (v.n) f = rho u_n,  sum (v.t) f = rho u_t,
+ *   f_n - f_opp(n) = (2/3) rho u_n   (equilibrium difference of the pair),
+ * which for a velocity node fix rho and for a pressure node fix u_n
+ * (u_t = 0).  Solved in closed form: with S = sum_{v.n=0} f + 2 sum_{v.n<0} f,
+ *   velocity: rho = S / (1 - u_n);  pressure: u_n = 1 - S / rho;
+ *   normal population: f_i = f_opp(i) + (2/3) rho u_n;
+ *   diagonal i, tangential part s_i = v_i . t = +-1:
+ *     f_i = f_opp(i) + (1/6) rho u_n + (s_i / 2) (rho u_t - T),
+ *   T = sum_{v.n=0} (v.t) f.  Returns 0, or -1 for a bad kind or normal. */
+int oracle_zou_he(const double *f, int kind, int nxn, int nyn, double a, double b, double *out)
+{
+    if ((kind != 1 && kind != 2) || abs(nxn) + abs(nyn) != 1)
+        return -1;
+    const int tx = -nyn, ty = nxn; /* unit tangent */
+    double par = 0.0, outgoing = 0.0, tan_sum = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        int d = CX[i] * nxn + CY[i] * nyn;
+        if (d == 0) {
+            par += f[i];
+            tan_sum += (double)(CX[i] * tx + CY[i] * ty) * f[i];
+        } else if (d < 0) {
+            outgoing += f[i];
+        }
+    }
+    const double S = par + 2.0 * outgoing;
+    double rho, un, ut;
+    if (kind == 1) {
+        un = a * nxn + b * nyn;
+        ut = a * tx + b * ty;
+        rho = S / (1.0 - un);
+    } else {
+        rho = a;
+        un = 1.0 - S / rho;
+        ut = 0.0;
+    }
+    for (int i = 0; i < Q; ++i)
+        out[i] = f[i];
+    for (int i = 0; i < Q; ++i) {
+        if (CX[i] * nxn + CY[i] * nyn <= 0)
+            continue;
+        const int j = opposite(i);
+        const int si = CX[i] * tx + CY[i] * ty;
+        if (si == 0)
+            out[i] = f[j] + (2.0 / 3.0) * rho * un;
+        else
+            out[i] = f[j] + rho * un / 6.0 + 0.5 * (double)si * (rho * ut - tan_sum);
+    }
+    return 0;
+}
+
+/* Boundary-node code: 0 none, 1..4 constant velocity with inward normal
+ * +x, -x, +y, -y, 5..8 constant pressure with the same normals. */
+static int bc_decode(uint8_t code, int *kind, int *nxn, int *nyn)
+{
+    if (code < 1 || code > 8)
+        return -1;
+    static const int NX_[4] = {1, -1, 0, 0}, NY_[4] = {0, 0, 1, -1};
+    *kind = code <= 4 ? 1 : 2;
+    *nxn = NX_[(code - 1) % 4];
+    *nyn = NY_[(code - 1) % 4];
+    return 0;
+}
+
+/* Apply the boundary conditions to the canonical state f in place:
+ * value[(k*ny + y)*nx + x], k = 0, 1 = (u_x, u_y) for velocity nodes,
+ * (rho, unused) for pressure nodes.  Codes at solid nodes are an error. */
+int oracle_apply_boundaries(int nx, int ny, const uint8_t *mask, const uint8_t *bc,
+                            const double *value, double *f)
+{
+    const size_t plane = (size_t)nx * ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            if (bc[n] == 0)
+                continue;
+            int kind, nxn, nyn;
+            if (bc_decode(bc[n], &kind, &nxn, &nyn) || mask[n] != 0)
+                return -1;
+            double fl[Q], fo[Q];
+            for (int i = 0; i < Q; ++i)
+                fl[i] = f[slot(i, x, y, nx, ny)];
+            oracle_zou_he(fl, kind, nxn, nyn, value[n], value[plane + n], fo);
+            for (int i = 0; i < Q; ++i)
+                f[slot(i, x, y, nx, ny)] = fo[i];
+        }
+    return 0;
+}
+
 /* One time step: collide every fluid node into `post`, then stream.
  * Streaming: for each fluid x and each i, the neighbour is y = x + v_i
  * (periodic).  If y is fluid, f_i(y, t+1) = fstar_i(x); otherwise the
@@ -198,9 +300,12 @@ static void one_step(int nx, int ny, const uint8_t *mask, double *f, double *pos
 }
 
 /* Run nsteps steps in place.  tau > 1/2 (Eq. 5: omega = 1/tau).  alpha may
- * be NULL (no drag).  nthreads <= 0 keeps the OpenMP default. */
-int oracle_run(int nx, int ny, const uint8_t *mask, double *f, double tau, double gx, double gy,
-               const double *alpha, long nsteps, int nthreads)
+ * be NULL (no drag).  bc / value may be NULL (no open boundaries); else the
+ * boundary conditions are applied after every streaming phase.  nthreads <= 0
+ * keeps the OpenMP default. */
+int oracle_run_bc(int nx, int ny, const uint8_t *mask, double *f, double tau, double gx,
+                  double gy, const double *alpha, const uint8_t *bc, const double *value,
+                  long nsteps, int nthreads)
 {
     if (nx < 1 || ny < 1 || !(tau > 0.5) || nsteps < 0)
         return -1;
@@ -215,10 +320,21 @@ int oracle_run(int nx, int ny, const uint8_t *mask, double *f, double tau, doubl
     double *post = (double *)calloc(total, sizeof(double));
     if (!post)
         return -2;
-    for (long s = 0; s < nsteps; ++s)
+    for (long s = 0; s < nsteps; ++s) {
         one_step(nx, ny, mask, f, post, omega, gx, gy, alpha);
+        if (bc && oracle_apply_boundaries(nx, ny, mask, bc, value, f)) {
+            free(post);
+            return -1;
+        }
+    }
     free(post);
     return 0;
+}
+
+int oracle_run(int nx, int ny, const uint8_t *mask, double *f, double tau, double gx, double gy,
+               const double *alpha, long nsteps, int nthreads)
+{
+    return oracle_run_bc(nx, ny, mask, f, tau, gx, gy, alpha, NULL, NULL, nsteps, nthreads);
 }
 
 int oracle_max_threads(void)

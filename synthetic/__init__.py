@@ -10,7 +10,15 @@ Workloads (the paper measures on synthetic geometries of its own; these stand in
     timing of Sec. 4.3, which used an all-fluid cavity: same traffic per node);
   * porous medium: random solid discs on a square domain with walls at y = 0 and
     y = ny - 1 (the sparse geometries of Sec. 4.3, built from circles of random radius);
-  * Brinkman field: a smooth random drag-coefficient field in [0, 1].
+  * Brinkman field: a smooth random drag-coefficient field in [0, 1];
+  * open channels (Sec. 4.1, chan_v / chan_p): walls at y = 0 and y = ny - 1, a constant
+    velocity or constant pressure inlet column at x = 0 and a constant pressure outlet
+    column at x = nx - 1;
+  * lid-driven cavity (Sec. 4.1): solid side and bottom walls, a constant-velocity lid.
+
+Open-boundary codes (one byte per node): 0 none, 1..4 constant velocity with inward
+normal +x, -x, +y, -y, 5..8 constant pressure with the same normals; values [2, ny, nx]
+hold (u_x, u_y) at velocity nodes and (rho, 0) at pressure nodes.
 """
 from __future__ import annotations
 
@@ -166,3 +174,48 @@ def brinkman_alpha(nx: int, ny: int, seed: int = 7, sigma: float = 8.0) -> np.nd
     s = np.real(np.fft.ifft2(np.fft.fft2(noise) * filt))
     s = (s - s.mean()) / (s.std() + 1e-300)
     return np.ascontiguousarray(0.5 * (1.0 + np.tanh(2.0 * (s - 1.0))))
+
+
+BC_VELOCITY = {(1, 0): 1, (-1, 0): 2, (0, 1): 3, (0, -1): 4}
+BC_PRESSURE = {(1, 0): 5, (-1, 0): 6, (0, 1): 7, (0, -1): 8}
+
+
+def open_channel(nx: int, ny: int, inlet: str = "velocity", u_in: float = 0.1,
+                 rho_in: float = 1.016, rho_out: float = 1.0):
+    """Channel with walls at y = 0 and ny - 1, inlet column x = 0 (constant velocity
+    (u_in, 0) or constant density rho_in) and outlet column x = nx - 1 (constant density
+    rho_out).  Returns (mask, bc, value)."""
+    if nx < 3 or ny < 3:
+        raise ValueError("open channel needs nx, ny >= 3")
+    mask = channel_mask(nx, ny)
+    bc = np.zeros((ny, nx), dtype=np.uint8)
+    value = np.zeros((2, ny, nx), dtype=np.float64)
+    if inlet == "velocity":
+        bc[1:ny - 1, 0] = BC_VELOCITY[(1, 0)]
+        value[0, 1:ny - 1, 0] = u_in
+    elif inlet == "pressure":
+        bc[1:ny - 1, 0] = BC_PRESSURE[(1, 0)]
+        value[0, 1:ny - 1, 0] = rho_in
+    else:
+        raise ValueError("inlet is 'velocity' or 'pressure'")
+    bc[1:ny - 1, nx - 1] = BC_PRESSURE[(-1, 0)]
+    value[0, 1:ny - 1, nx - 1] = rho_out
+    return mask, bc, value
+
+
+def lid_cavity(n: int, u_lid: float = 0.1, ny: int | None = None):
+    """Square cavity: solid columns x = 0 and x = n - 1 and solid row y = 0; the top row
+    y = ny - 1 (x = 1 .. n - 2) is a constant-velocity lid moving with (u_lid, 0).
+    Returns (mask, bc, value)."""
+    ny = n if ny is None else ny
+    if n < 3 or ny < 3:
+        raise ValueError("cavity needs n, ny >= 3")
+    mask = np.zeros((ny, n), dtype=np.uint8)
+    mask[:, 0] = 1
+    mask[:, n - 1] = 1
+    mask[0, :] = 1
+    bc = np.zeros((ny, n), dtype=np.uint8)
+    value = np.zeros((2, ny, n), dtype=np.float64)
+    bc[ny - 1, 1:n - 1] = BC_VELOCITY[(0, -1)]
+    value[0, ny - 1, 1:n - 1] = u_lid
+    return mask, bc, value
