@@ -50,7 +50,8 @@ def log(msg):
 
 def algorithmic_bytes_per_node(dtype, drag=False):
     """18 populations moved (read + write) plus the node-type byte (+4 B drag field)."""
-    return 18 * POP_BYTES[dtype] + 1 + (4 if drag else 0)
+    from paper_2108_13241_amd import metrics
+    return metrics.bytes_per_node(dtype, drag)
 
 
 def kernel_source_hash():
@@ -146,6 +147,41 @@ def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask):
            "bytes_moved_per_step": info["bytes_moved_per_step"]}
     if layout == "tiled16":
         out["tile_occupancy"] = nf / max(1, info["n_tiles"] * 256)
+    return out
+
+
+def measure_open_channel(lbm, inlet, dtype, layout, steps, warmup, nx=4096, ny=512):
+    """The paper's channel cases (Sec. 4.1): chan_v (inlet u = 0.1) or chan_p (inlet
+    rho = 1.016, initial 1.008), outlet rho = 1, bounce-back walls, nu = 0.25 (tau = 1.25)."""
+    import synthetic
+    m, bc, val = synthetic.open_channel(nx, ny, inlet, u_in=0.1, rho_in=1.016)
+    lat = lbm.Lattice(m, 1.25, dtype=dtype, layout=layout)
+    lat.set_boundaries(bc, val)
+    if inlet == "pressure":
+        lat.init_equilibrium(np.full((ny, nx), 1.008), None, None)
+    secs, ms = time_steps(lat, steps, warmup)
+    nf = lat.info()["n_fluid"]
+    lat.close()
+    glups = nf * steps / secs / 1e9
+    bpn = algorithmic_bytes_per_node(dtype)
+    return {"workload": f"chan_{inlet[0]} {nx}x{ny} (open inlet / outlet)", "dtype": dtype,
+            "layout": layout, "glups": glups, "ms_per_step": ms,
+            "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
+            "note": "working set partly resident in the 256 MB Infinity Cache"}
+
+
+def measure_small_channel(lbm, steps=2000):
+    """256 x 64 channel (walls at y = 0 and 63, g = 1e-6, tau = 0.8, FP64): a launch-bound
+    size; time per step with one launch per step and with steps replayed as HIP graphs."""
+    import synthetic
+    m = synthetic.channel_mask(256, 64)
+    out = {"workload": "channel 256x64 f64 dense_ab (launch-bound)", "steps": steps}
+    for name, g in (("launch_per_step", 0), ("hip_graph_32", 32)):
+        lat = lbm.Lattice(m, 0.8, force=(1e-6, 0.0), dtype="f64", layout="dense_ab")
+        lat.set_graph_steps(g)
+        secs, ms = time_steps(lat, steps, 64)
+        out[f"us_per_step_{name}"] = ms * 1e3
+        lat.close()
     return out
 
 
@@ -248,6 +284,14 @@ def main():
         c = measure_copy(lbm, 1 << 30)
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
         variants.append({"workload": "copy kernel 1 GiB", **c})
+        for inlet in ("velocity", "pressure"):
+            r = measure_open_channel(lbm, inlet, "f32", "dense_ab", args.steps, args.warmup)
+            log(f"[bench]   {r['workload']} f32: {r['glups']:.2f} GLUPS")
+            variants.append(r)
+        r = measure_small_channel(lbm)
+        log(f"[bench]   channel 256x64: {r['us_per_step_launch_per_step']:.2f} us/step, "
+            f"graphs {r['us_per_step_hip_graph_32']:.2f} us/step")
+        variants.append(r)
     if args.suite == "full":
         for nn in (1024, 2048):
             f2 = synthetic.taylor_green(nn, 0.01)

@@ -142,12 +142,39 @@ int lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *ux, cons
  * and F = rho (g - alpha u).  Errors: INVALID for values outside [0, 1]. */
 int lbm_set_porosity(lbm_ctx *ctx, const float *alpha);
 
+/* Open boundaries: constant velocity and constant pressure (Sec. 3, after Zou
+ * and He).  bc: host uint8 [ny][nx], per node 0 = none, 1..4 = constant
+ * velocity with inward normal +x, -x, +y, -y, 5..8 = constant pressure with
+ * the same normals; codes only at fluid nodes.  value: host FP64 [2][ny][nx]:
+ * (u_x, u_y) at velocity nodes (|u_x|, |u_y| < 1), (rho, unused) at pressure
+ * nodes (rho > 0).  Both are copied.  At an open node the three populations
+ * entering across the boundary (c_i . n > 0) are rebuilt, before every
+ * collision and in every view of the state, so that the node's density and
+ * momentum (Eq. 2, without the force and drag corrections) take the
+ * prescribed values (pressure nodes: no tangential velocity) and the normal
+ * population pair has equal non-equilibrium parts; whatever streamed into
+ * those slots across the periodic seam is discarded.  The canonical state is
+ * kept across the call (gathered under the old conditions, stored back under
+ * the new ones, which then apply to it).  bc = NULL removes all open
+ * boundaries.  Invalid codes
+ * or values: LBM_ERR_INVALID, nothing changed.  Contexts with open boundaries
+ * have no adjoint (LBM_ERR_UNSUPPORTED).  Synchronises the context's stream. */
+int lbm_set_boundaries(lbm_ctx *ctx, const uint8_t *bc, const double *value);
+
 /* Replace the body force (host double[2], finite). */
 int lbm_set_force(lbm_ctx *ctx, const double *force);
 
 /* Enqueue n >= 0 time steps (Algorithm 1, one fused stream-collide kernel per
  * step).  Asynchronous: returns once enqueued. */
 int lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Replay steps through HIP graphs: lbm_step then enqueues runs of `steps`
+ * consecutive steps as one captured graph (captured once, on a private stream,
+ * and replayed on the context's stream; bitwise-identical results).  -1 = auto
+ * (32 steps for lattices that move less than 128 MB per step, where host launch
+ * overhead is a visible share of a step; else off), 0 = off, or an even count in
+ * [2, 4096].  Changing the force or the drag field discards captured graphs. */
+int lbm_set_graph_steps(lbm_ctx *ctx, int32_t steps);
 
 /* Macroscopic fields (Eq. 2, with the half-force / drag velocity) of the
  * current canonical state into host FP64 [ny][nx] arrays; solid nodes get 0.
@@ -191,6 +218,12 @@ int lbm_objective_outlet_ux(lbm_ctx *ctx, int32_t x_col, double *J);
  * device buffers owned by the caller and ACCUMULATED into (+=):
  *   grad_alpha_dev [ny][nx], grad_g_dev [2]. */
 int lbm_adjoint_bytes(const lbm_ctx *ctx, size_t *bytes, int32_t *pitch);
+
+/* Copy an adjoint field to / from host FP64 [9][ny][nx] (the same indexing as the
+ * canonical populations; lambda_t(x)_i = dJ / df_i(x, t)).  Solid entries read as 0
+ * and are ignored on input.  Synchronises the stream. */
+int lbm_adjoint_get(lbm_ctx *ctx, const void *mu_dev, double *host);
+int lbm_adjoint_set(lbm_ctx *ctx, void *mu_dev, const double *host);
 
 /* lambda_T for J = dJ * mean outlet u_x over column x_col, from the current
  * canonical state, written to mu_dev; the direct dJ/dalpha and dJ/dg terms of

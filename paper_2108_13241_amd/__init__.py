@@ -150,9 +150,26 @@ class Lattice:
         self._check(self._lib.lbm_set_porosity(self._ctx,
                                                a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
 
+    def set_boundaries(self, bc, value=None):
+        """Open boundaries (constant velocity / pressure, Zou-He): bc uint8 [ny, nx] with codes
+        0 none, 1..4 velocity with inward normal +x, -x, +y, -y, 5..8 pressure with the same
+        normals; value float64 [2, ny, nx] = (u_x, u_y) or (rho, -).  bc None removes them."""
+        if bc is None:
+            self._check(self._lib.lbm_set_boundaries(self._ctx, None, None))
+            return
+        b = np.ascontiguousarray(bc, dtype=np.uint8)
+        v = np.ascontiguousarray(value, dtype=np.float64)
+        if b.shape != (self.ny, self.nx) or v.shape != (2, self.ny, self.nx):
+            raise ValueError("bc must be [ny, nx] and value [2, ny, nx]")
+        self._check(self._lib.lbm_set_boundaries(self._ctx, b.ctypes.data, v.ctypes.data))
+
     def set_force(self, g):
         arr = (ctypes.c_double * 2)(float(g[0]), float(g[1]))
         self._check(self._lib.lbm_set_force(self._ctx, arr))
+
+    def set_graph_steps(self, steps):
+        """-1 auto, 0 off, or an even number of steps per replayed HIP graph."""
+        self._check(self._lib.lbm_set_graph_steps(self._ctx, int(steps)))
 
     def step(self, n=1):
         self._check(self._lib.lbm_step(self._ctx, int(n)))
@@ -206,6 +223,16 @@ class Lattice:
         p = ctypes.c_int32()
         self._check(self._lib.lbm_adjoint_bytes(self._ctx, ctypes.byref(b), ctypes.byref(p)))
         return b.value, p.value
+
+    def adjoint_get(self, mu):
+        """Adjoint field -> host FP64 [9, ny, nx]."""
+        out = np.zeros((9, self.ny, self.nx))
+        self._check(self._lib.lbm_adjoint_get(self._ctx, _ptr(mu), _dptr(out)))
+        return out
+
+    def adjoint_set(self, mu, values):
+        v = _f64(values, (9, self.ny, self.nx))
+        self._check(self._lib.lbm_adjoint_set(self._ctx, _ptr(mu), _dptr(v)))
 
     def adjoint_seed_outlet_ux(self, x_col, dJ, mu, grad_alpha, grad_g):
         self._check(self._lib.lbm_adjoint_seed_outlet_ux(self._ctx, int(x_col), float(dJ),

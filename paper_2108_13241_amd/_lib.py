@@ -46,8 +46,10 @@ SIGNATURES = {
     "lbm_set_stream": (_c.c_int, [_vp, _vp]),
     "lbm_init_equilibrium": (_c.c_int, [_vp, _dp, _dp, _dp]),
     "lbm_set_porosity": (_c.c_int, [_vp, _c.POINTER(_c.c_float)]),
+    "lbm_set_boundaries": (_c.c_int, [_vp, _c.c_void_p, _c.c_void_p]),
     "lbm_set_force": (_c.c_int, [_vp, _dp]),
     "lbm_step": (_c.c_int, [_vp, _i64]),
+    "lbm_set_graph_steps": (_c.c_int, [_vp, _i32]),
     "lbm_macroscopic": (_c.c_int, [_vp, _dp, _dp, _dp]),
     "lbm_macroscopic_device": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_get_populations": (_c.c_int, [_vp, _dp]),
@@ -58,6 +60,8 @@ SIGNATURES = {
     "lbm_load_state": (_c.c_int, [_vp, _vp]),
     "lbm_objective_outlet_ux": (_c.c_int, [_vp, _i32, _dp]),
     "lbm_adjoint_bytes": (_c.c_int, [_vp, _c.POINTER(_sz), _c.POINTER(_i32)]),
+    "lbm_adjoint_get": (_c.c_int, [_vp, _vp, _dp]),
+    "lbm_adjoint_set": (_c.c_int, [_vp, _vp, _dp]),
     "lbm_adjoint_seed_outlet_ux": (_c.c_int, [_vp, _i32, _c.c_double, _vp, _vp, _vp]),
     "lbm_adjoint_step": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_run_checkpointed": (_c.c_int, [_vp, _i64, _i64, _vp]),

@@ -255,6 +255,32 @@ __global__ __launch_bounds__(kBlock) void k_zero(double *p, uint32_t n)
         p[i] = 0.0;
 }
 
+// Adjoint field (chunked, compute type) <-> plain FP64 planes [9][ny][nx];
+// solid and padding entries read as / are written from zero.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_adjoint_convert(R *__restrict__ mu,
+                                                            double *__restrict__ plain,
+                                                            const uint8_t *__restrict__ type,
+                                                            int nx, int ny, int pitch,
+                                                            int to_plain)
+{
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    const int y = (int)(gid / (uint32_t)pitch), x = (int)(gid - (uint32_t)y * pitch);
+    if (y >= ny)
+        return;
+    const uint32_t base = dense_base(x, y, (uint32_t)pitch / kChunk);
+    const bool fluid = x < nx && type[gid] != kSolid;
+    for (int i = 0; i < 9; ++i) {
+        if (to_plain) {
+            if (x < nx)
+                plain[((size_t)i * ny + y) * nx + x] = fluid ? (double)mu[(uint32_t)i * kChunk + base] : 0.0;
+        } else {
+            mu[(uint32_t)i * kChunk + base] =
+                fluid ? (R)plain[((size_t)i * ny + y) * nx + x] : R(0);
+        }
+    }
+}
+
 template <class ST>
 hipError_t step_typed(const DevState &s, const void *state, const void *mu_in, void *mu_out,
                       double *grad_alpha, double *partials, int accumulate)
@@ -308,6 +334,20 @@ hipError_t launch_adjoint_seed_raw(const DevState &s, const void *state, int x_c
         k_adjoint_seed<F32><<<blocks, kBlock, 0, s.stream>>>(
             (const float *)state, (float *)mu, s.type, s.nmask, s.alpha, grad_alpha, partials,
             x_col, scale, s.nx, s.ny, s.pitch, s.gx, s.gy);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_convert(const DevState &s, void *mu, double *plain, int to_plain)
+{
+    const uint32_t blocks = (uint32_t)adjoint_seed_blocks(s);
+    if (s.dtype == kF64)
+        k_adjoint_convert<double><<<blocks, kBlock, 0, s.stream>>>(
+            (double *)mu, plain, s.type, s.nx, s.ny, s.pitch, to_plain);
+    else if (s.dtype == kF32)
+        k_adjoint_convert<float><<<blocks, kBlock, 0, s.stream>>>(
+            (float *)mu, plain, s.type, s.nx, s.ny, s.pitch, to_plain);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -24,6 +24,8 @@ enum : uint8_t {
     kBoundary = 2,  // fluid node with at least one solid neighbour; its
                     // solid-neighbour bits are in the nmask array:
                     // bit i-1 set <=> node x - c_i is solid (i = 1..8)
+    kOpen = 3,      // codes 3..10: open-boundary node with boundary code
+                    // 1..8 (= code - 2, see apply_open); nmask as for kBoundary
 };
 
 // Solid-neighbour set of a node as a 9-bit mask: bit i set <=> node x - c_i is
@@ -31,7 +33,13 @@ enum : uint8_t {
 __device__ __forceinline__ unsigned solid_bits(uint8_t code, const uint8_t *__restrict__ nmask,
                                                uint32_t idx)
 {
-    return code == kBoundary ? (unsigned)nmask[idx] << 1 : 0u;
+    return code >= kBoundary ? (unsigned)nmask[idx] << 1 : 0u;
+}
+
+// Boundary code (0 = none, 1..8) of a dense or tiled node-type code.
+__device__ __forceinline__ unsigned open_code(uint8_t code)
+{
+    return code >= kOpen ? (unsigned)(code - kOpen + 1) : 0u;
 }
 
 // ---------------------------------------------------------------- storage --
@@ -44,10 +52,14 @@ __device__ __forceinline__ unsigned solid_bits(uint8_t code, const uint8_t *__re
 //                 f_i itself.
 // ld / st convert between storage and compute representation; canon / from_canon
 // convert between storage and the canonical FP64 populations f_i.
+// kExact: FP32 reciprocals are Newton-refined; the 16-bit codecs, whose storage
+// rounding (2^-11 or 2^-8 of a deviation) dwarfs a 1-ulp FP32 reciprocal error,
+// use the raw hardware reciprocal and save the refinement's instructions.
 struct F64 {
     using mem = double;
     using real = double;
     static constexpr bool kShift = false;
+    static constexpr bool kExact = true;
     static __device__ __forceinline__ real ld(mem v, int) { return v; }
     static __device__ __forceinline__ mem st(real v, int) { return v; }
     static __device__ __forceinline__ double canon(real v, int) { return v; }
@@ -58,6 +70,7 @@ struct Shifted {
     using mem = M;
     using real = float;
     static constexpr bool kShift = true;
+    static constexpr bool kExact = sizeof(M) == 4;
     static __device__ __forceinline__ real ld(mem v, int) { return (float)v; }
     static __device__ __forceinline__ mem st(real v, int)
     {
@@ -80,10 +93,26 @@ using F16S = Shifted<_Float16>;
 using BF16S = Shifted<__bf16>;
 
 // -------------------------------------------------------------- collision --
-// 1 / v: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32,
-// where the storage and arithmetic tolerance is far looser.
+// 1 / v: correctly rounded in FP64; in FP32 the hardware reciprocal refined by
+// one Newton step, r + r (1 - v r) (two FMAs instead of a full division).  The
+// raw reciprocal alone is 1 ulp off with a bias that accumulates over steps.
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
-__device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ float recip(float v)
+{
+    const float r = __builtin_amdgcn_rcpf(v);
+    return __builtin_fmaf(__builtin_fmaf(-v, r, 1.0f), r, r);
+}
+// EXACT = false: the raw FP32 hardware reciprocal (FP64 stays exact).
+template <bool EXACT>
+__device__ __forceinline__ double recip_p(double v) { return 1.0 / v; }
+template <bool EXACT>
+__device__ __forceinline__ float recip_p(float v)
+{
+    if constexpr (EXACT)
+        return recip(v);
+    else
+        return __builtin_amdgcn_rcpf(v);
+}
 
 // c . v for the first direction of the k-th opposite pair (c = (1,0), (0,1),
 // (1,1), (-1,1)), written out so no multiplication by a zero component is left.
@@ -110,33 +139,56 @@ __device__ __forceinline__ R pair_dot(int k, R vx, R vy)
 //   f^eq_{i, opp} = w (C0 + 4.5 rho (c.u)^2) +- 3 w rho (c.u),
 //   S_{i, opp}    = w (9 (c.u)(c.F) - 3 u.F) +- 3 w (c.F),
 // with C0 = rho (1 - 1.5 u.u), or sum h - 1.5 rho u.u for deviations.
-template <class R, bool DRAG, bool SHIFT, bool FORCE = true>
+// EXACT = false (16-bit storage): raw hardware reciprocals and u = m / rho
+// taken directly (see kExact of the codecs).
+template <class R, bool DRAG, bool SHIFT, bool FORCE = true, bool EXACT = true>
 __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, const R gy,
                                         const R alpha)
 {
     const R sum = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    const R rho = SHIFT ? R(1) + sum : sum;
     const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R inv_rho = recip(rho);
-    R ux = mx * inv_rho, uy = my * inv_rho;
+    // rho * v.  With deviations, rho = 1 + sum is never formed: near rho = 1 that
+    // sum would round to half an FP32 ulp of 1 (6e-8), a bias that depends on the
+    // local density and accumulates over steps; v + sum v keeps full precision.
+    auto rho_times = [&](R v) -> R {
+        if constexpr (SHIFT)
+            return v + sum * v;
+        else
+            return sum * v;
+    };
+    R ux, uy;
+    if constexpr (SHIFT && !EXACT) {
+        const R inv_rho = recip_p<false>(R(1) + sum);
+        ux = mx * inv_rho;
+        uy = my * inv_rho;
+    } else if constexpr (SHIFT) {
+        const R q = sum * recip(R(1) + sum);  // (rho - 1) / rho
+        ux = mx - mx * q;
+        uy = my - my * q;
+    } else {
+        const R inv_rho = recip(sum);
+        ux = mx * inv_rho;
+        uy = my * inv_rho;
+    }
     R Fx = R(0), Fy = R(0);
     if constexpr (FORCE) {
         ux += R(0.5) * gx;
         uy += R(0.5) * gy;
         if constexpr (DRAG) {
-            const R invD = recip(R(1) + R(0.5) * alpha);
+            const R invD = recip_p<EXACT>(R(1) + R(0.5) * alpha);
             ux *= invD;
             uy *= invD;
-            Fx = rho * (gx - alpha * ux);
-            Fy = rho * (gy - alpha * uy);
+            Fx = rho_times(gx - alpha * ux);
+            Fy = rho_times(gy - alpha * uy);
         } else {
-            Fx = rho * gx;
-            Fy = rho * gy;
+            Fx = rho_times(gx);
+            Fy = rho_times(gy);
         }
     }
     const R usq = R(1.5) * (ux * ux + uy * uy);
-    const R C0 = SHIFT ? sum - rho * usq : rho - rho * usq;
+    // C0 = rho (1 - 1.5 u.u) - (1 if SHIFT): the isotropic part of f^eq / w
+    const R C0 = SHIFT ? sum - rho_times(usq) : rho_times(R(1) - usq);
     const R keep = R(1) - omega;
     const R guo = R(1) - R(0.5) * omega;
     const R uF = ux * Fx + uy * Fy;
@@ -155,9 +207,8 @@ __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, co
         const int i = P[k], j = kOpp[i];
         const R w = R(kW[i]);
         const R cu = pair_dot(k, ux, uy);
-        const R wr = w * rho;
-        const R even = w * C0 + R(4.5) * wr * (cu * cu);
-        const R odd = R(3) * wr * cu;
+        const R even = w * (C0 + rho_times(R(4.5) * (cu * cu)));
+        const R odd = w * rho_times(R(3) * cu);
         R a = keep * f[i] + omega * (even + odd);
         R b = keep * f[j] + omega * (even - odd);
         if constexpr (FORCE) {
@@ -174,6 +225,79 @@ __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, co
 
 // Macroscopic moments of the canonical populations (Eq. 2 with the same
 // corrected velocity the collision uses), in FP64.
+// ---------------------------------------------------- open boundaries --
+// Constant-velocity / constant-pressure node (Sec. 3, after Zou and He).
+// Boundary code b = 1..8: 1..4 constant velocity with inward normal n = +x,
+// -x, +y, -y; 5..8 constant pressure with the same normals; unit tangent
+// t = (-n_y, n_x).  v = the node's two FP64 boundary values: (u_x, u_y), or
+// (rho, unused).
+// The three populations entering across the boundary (c_i . n > 0) are
+// rebuilt from the other six so that the node's density and momentum (Eq. 2)
+// take the prescribed values and the normal pair has equal non-equilibrium
+// parts.  With S = sum_{c.n=0} f + 2 sum_{c.n<0} f and T = sum_{c.n=0} (c.t) f:
+//   velocity (u prescribed): rho = S / (1 - u.n);
+//   pressure (rho prescribed, u.t = 0): rho u.n = rho - S;
+//   normal direction: f_i = f_opp(i) + (2/3) rho u.n;
+//   diagonals, s_i = c_i . t = +-1:
+//     f_i = f_opp(i) + rho u.n / 6 + (s_i / 2) (rho u.t - T).
+// Shifted storage holds h = f - w: opposite populations have equal weights and
+// the weights in S sum to 1, so in deviations S_h = S - 1, T is unchanged and
+// the rebuilt h_i use the same relations, with rho = 1 + drho carried as drho:
+//   velocity: drho = (S_h + u.n) / (1 - u.n); pressure: rho u.n = (rho - 1) - S_h.
+// Written with the normal as a runtime value and every population index a
+// compile-time constant (the roles of the directions become predicates), so
+// that the populations stay in registers.
+template <class R, bool SHIFT>
+__device__ __forceinline__ void apply_open(R (&f)[9], unsigned b, const double *__restrict__ v)
+{
+    const unsigned k = (b - 1u) & 3u;  // normal +x, -x, +y, -y
+    const int nxn = k == 0 ? 1 : (k == 1 ? -1 : 0);
+    const int nyn = k == 2 ? 1 : (k == 3 ? -1 : 0);
+    const int tx = -nyn, ty = nxn;
+    const bool velocity = b <= 4u;
+    const double v0 = v[0], v1 = v[1];
+    R par = R(0), outg = R(0), tsum = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int d = kCx[i] * nxn + kCy[i] * nyn;
+        const int si = kCx[i] * tx + kCy[i] * ty;
+        par += d == 0 ? f[i] : R(0);
+        outg += d < 0 ? f[i] : R(0);
+        tsum += d == 0 ? (si > 0 ? f[i] : (si < 0 ? -f[i] : R(0))) : R(0);
+    }
+    const R S = par + R(2) * outg;
+    R run, rut;  // rho u.n, rho u.t
+    if (velocity) {
+        const R un = (R)(v0 * nxn + v1 * nyn), ut = (R)(v0 * tx + v1 * ty);
+        if constexpr (SHIFT) {
+            const R drho = (S + un) / (R(1) - un);
+            run = un + drho * un;
+            rut = ut + drho * ut;
+        } else {
+            const R rho = S / (R(1) - un);
+            run = rho * un;
+            rut = rho * ut;
+        }
+    } else {
+        run = SHIFT ? (R)(v0 - 1.0) - S : (R)v0 - S;
+        rut = R(0);
+    }
+    const R tang = R(0.5) * (rut - tsum);
+    const R diag = run * R(1.0 / 6.0);
+    const R axis = run * R(2.0 / 3.0);
+    R g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int d = kCx[i] * nxn + kCy[i] * nyn;
+        const int si = kCx[i] * tx + kCy[i] * ty;
+        const R inc = si == 0 ? axis : (si > 0 ? diag + tang : diag - tang);
+        g[i] = d > 0 ? f[kOpp[i]] + inc : f[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = g[i];
+}
+
 __device__ __forceinline__ void moments(const double (&f)[9], double gx, double gy, double alpha,
                                         double &rho, double &ux, double &uy)
 {

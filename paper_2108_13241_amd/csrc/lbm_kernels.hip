@@ -62,13 +62,16 @@ __device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const 
 // q_{y-1} - n and q_{y+1} - n (int16 each) of the row-major ranks of (x, y-1)
 // and (x, y+1), or, for edge nodes, a row of the plain edge table.  Returns
 // the solid-neighbour bits; nb[i] = base offset of the source node x - c_i
-// (meaningless where that node is solid, which the caller never uses).
+// (meaningless where that node is solid, which the caller never uses); open =
+// the node's open-boundary code (info bits 9..12, 0 = none).
 __device__ __forceinline__ unsigned indirect_offsets(const uint32_t *__restrict__ pk,
                                                      const uint16_t *__restrict__ info,
                                                      const int32_t *__restrict__ edge,
-                                                     uint32_t n, uint32_t (&nb)[9])
+                                                     uint32_t n, uint32_t (&nb)[9],
+                                                     unsigned &open)
 {
     const unsigned inf = info[n];
+    open = (inf >> 9) & 15u;
     const unsigned sm = (inf & 0xFFu) << 1;
     const uint32_t p = pk[n];
     uint32_t src[9];
@@ -214,19 +217,21 @@ __device__ __forceinline__ void dense_pull(const typename ST::mem *__restrict__ 
 
 // ------------------------------------------------------------- step: dense --
 // Physics variant of a step kernel: plain BGK (no body force, no drag), body
-// force, or body force with a drag field.
-enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2 };
+// force, or body force with a drag field; plus kOpen when the lattice has
+// open-boundary nodes (lattices without them run kernels free of that branch).
+enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2, kOpenBC = 4 };
 
 template <class ST, int PH>
 __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
-    const uint32_t *__restrict__ seg_interior, const float *__restrict__ alpha, int nx, int ny,
-    int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
-    typename ST::real gy)
+    const uint32_t *__restrict__ seg_interior, const float *__restrict__ alpha,
+    const double *__restrict__ bc_val, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
+    typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
-    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
+                   OPEN = (PH & kOpenBC) != 0;
     int x, y;
     uint32_t L;
     if (!dense_node(bpr, nblocks, nx, x, y, L))
@@ -234,17 +239,22 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     const uint32_t n = (uint32_t)y * pitch + x;
     // Segments of interior fluid nodes need neither the node type nor the
     // neighbour bits, so their population loads issue at once.
-    unsigned sm = 0;
+    unsigned sm = 0, open = 0;
     if (!seg_interior[L]) {
         const uint8_t t = type[n];
         if (t == kSolid)
             return;
         sm = solid_bits(t, nmask, n);
+        if constexpr (OPEN)
+            open = open_code(t);
     }
     const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
     R f[9];
     dense_pull<ST>(src, a, sm, f);
-    collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+    if (OPEN && open)
+        apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
+                                                    DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dense_at(dst, a, i, 1, 1), ST::st(f[i], i));
@@ -259,11 +269,13 @@ template <class ST, int PH, bool ODD>
 __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
     const uint8_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior,
-    const float *__restrict__ alpha, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
-    typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    const float *__restrict__ alpha, const double *__restrict__ bc_val, int nx, int ny, int pitch,
+    uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy)
 {
     using R = typename ST::real;
-    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
+                   OPEN = (PH & kOpenBC) != 0;
     int x, y;
     uint32_t L;
     if (!dense_node(bpr, nblocks, nx, x, y, L))
@@ -274,12 +286,16 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     if (t == kSolid)
         return;
     const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
+    const unsigned open = OPEN ? open_code(t) : 0u;
     R f[9];
     if constexpr (!ODD) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             f[i] = ST::ld(dense_at(A, a, i, 1, 1), i);
-        collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+        if (OPEN && open)
+            apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
+                                                        DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             store_nt(&dense_at(A, a, kOpp[i], 1, 1), ST::st(f[i], i));
@@ -296,7 +312,10 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
                                                : dense_at(A, a, kOpp[i], 1 - kCy[i], 1 - kCx[i]),
                               i);
         }
-        collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+        if (OPEN && open)
+            apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
+                                                        DRAG ? (R)alpha[n] : R(0));
         // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
         if (sm == 0) {
 #pragma unroll
@@ -317,11 +336,13 @@ template <class ST, int PH>
 __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
-    const float *__restrict__ alpha, const int32_t *__restrict__ tile_nbr, uint32_t n_tiles,
-    typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    const float *__restrict__ alpha, const double *__restrict__ bc_val,
+    const int32_t *__restrict__ tile_nbr, uint32_t n_tiles, typename ST::real omega,
+    typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
-    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
+                   OPEN = (PH & kOpenBC) != 0;
     const uint32_t k = xcd_remap(blockIdx.x, n_tiles);
     const int t = (int)threadIdx.x, lx = t & 15, ly = t >> 4;
     const uint32_t n = k * kTileNodes + t;
@@ -337,7 +358,12 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     tiled_offsets(k, lx, ly, tn, nb);
     R f[9];
     pull_gather<ST>(src, kTileStride, nb, sm, f);
-    collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+    if constexpr (OPEN) {
+        if (const unsigned open = open_code(ty))
+            apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
+    }
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
+                                                    DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kTileStride + nb[0]], ST::st(f[i], i));
@@ -348,19 +374,25 @@ template <class ST, int PH>
 __global__ __launch_bounds__(kBlock) void k_step_indirect(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint32_t *__restrict__ pk, const uint16_t *__restrict__ info,
-    const int32_t *__restrict__ edge, const float *__restrict__ alpha, uint32_t n_fluid,
-    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    const int32_t *__restrict__ edge, const float *__restrict__ alpha,
+    const double *__restrict__ bc_val, uint32_t n_fluid, uint32_t nblocks,
+    typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
-    constexpr bool DRAG = PH == kDragged, FORCE = PH != kBGK;
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
+                   OPEN = (PH & kOpenBC) != 0;
     const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
     if (n >= n_fluid)
         return;
     uint32_t nb[9];
-    const unsigned sm = indirect_offsets(pk, info, edge, n, nb);
+    unsigned open;
+    const unsigned sm = indirect_offsets(pk, info, edge, n, nb, open);
     R f[9];
     pull_gather<ST>(src, kChunk, nb, sm, f);
-    collide<R, DRAG, ST::kShift, FORCE>(f, omega, gx, gy, DRAG ? (R)alpha[n] : R(0));
+    if (OPEN && open)
+        apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
+                                                    DRAG ? (R)alpha[n] : R(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kChunk + nb[0]], ST::st(f[i], i));
@@ -374,9 +406,11 @@ enum Mode : int { kPull = 0, kAAEven = 1, kAAOdd = 2 };
 // Stored-state addressing of the node handled by visit thread `gid` (dense:
 // gid = y * pitch + x; tiled: gid = tile * 256 + t; indirect: gid = n).
 // Returns false for padding and solid nodes; else the coordinates, the
-// solid-neighbour bits, the direction stride and the node base offsets.
+// solid-neighbour bits, the open-boundary code, the direction stride and the
+// node base offsets.
 __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x, int &y,
-                                        unsigned &sm, uint32_t &ds, uint32_t (&nb)[9])
+                                        unsigned &sm, unsigned &open, uint32_t &ds,
+                                        uint32_t (&nb)[9])
 {
     if (s.layout == kDenseAB || s.layout == kDenseAA) {
         y = (int)(gid / (uint32_t)s.pitch);
@@ -387,6 +421,7 @@ __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x,
         if (t == kSolid)
             return false;
         sm = solid_bits(t, s.nmask, gid);
+        open = open_code(t);
         dense_bases(x, y, s.nx, s.ny, (uint32_t)s.pitch / kChunk, nb);
         ds = kChunk;
     } else if (s.layout == kTiled16) {
@@ -398,6 +433,7 @@ __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x,
         if (ty == kSolid)
             return false;
         sm = solid_bits(ty, s.nmask, gid);
+        open = open_code(ty);
         int32_t tn[9];
         for (int d = 0; d < 9; ++d)
             tn[d] = s.tile_nbr[k * 9 + d];
@@ -408,7 +444,7 @@ __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x,
     } else {
         if (gid >= (uint32_t)s.n_fluid)
             return false;
-        sm = indirect_offsets(s.ind_pk, s.ind_info, s.ind_edge, gid, nb);
+        sm = indirect_offsets(s.ind_pk, s.ind_info, s.ind_edge, gid, nb, open);
         x = s.fluid_xy[2 * gid];
         y = s.fluid_xy[2 * gid + 1];
         ds = kChunk;
@@ -423,9 +459,9 @@ __device__ __forceinline__ bool canonical_at(const DevState &s, const typename S
                                              double (&fd)[9], double &al)
 {
     using R = typename ST::real;
-    unsigned sm = 0;
+    unsigned sm = 0, open = 0;
     uint32_t ds = 0, nb[9];
-    if (!node_at(s, gid, x, y, sm, ds, nb))
+    if (!node_at(s, gid, x, y, sm, open, ds, nb))
         return false;
     R f[9];
     if (mode == kAAEven)
@@ -434,6 +470,9 @@ __device__ __forceinline__ bool canonical_at(const DevState &s, const typename S
         aa_odd_gather<ST>(st, ds, nb, sm, f);
     else
         pull_gather<ST>(st, ds, nb, sm, f);
+    // the canonical state satisfies the open-boundary conditions
+    if (open)
+        apply_open<R, ST::kShift>(f, open, s.bc_val + 2 * (size_t)gid);
     al = s.alpha ? (double)s.alpha[gid] : 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
@@ -576,9 +615,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     int x, y;
-    unsigned sm = 0;
+    unsigned sm = 0, open = 0;
     uint32_t ds = 0, nbs[9];
-    if (!node_at(s, gid, x, y, sm, ds, nbs))
+    if (!node_at(s, gid, x, y, sm, open, ds, nbs))
         return;
     uint32_t nb[9];  // canonical (plain planes, dense pitch) offsets of z - c_i
     {
@@ -647,40 +686,50 @@ void step_launch(const DevState &s, int64_t t, int cur)
         const uint32_t nblocks = bpr * (uint32_t)s.ny;
         if (s.layout == kDenseAB) {
             k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.seg_interior, s.alpha, s.nx, s.ny, s.pitch, bpr,
-                nblocks, om, gx, gy);
+                src, dst, s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
+                s.pitch, bpr, nblocks, om, gx, gy);
         } else if (t & 1) {
             k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, 0, s.stream>>>(
-                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.nx, s.ny, s.pitch, bpr,
-                nblocks, om, gx, gy);
+                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
+                s.pitch, bpr, nblocks, om, gx, gy);
         } else {
             k_step_dense_aa<ST, PH, false><<<nblocks, kBlock, 0, s.stream>>>(
-                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.nx, s.ny, s.pitch, bpr,
-                nblocks, om, gx, gy);
+                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
+                s.pitch, bpr, nblocks, om, gx, gy);
         }
     } else if (s.layout == kTiled16) {
         const uint32_t nt = (uint32_t)s.n_tiles;
         if (nt > 0)
             k_step_tiled<ST, PH><<<nt, kTileNodes, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.tile_nbr, nt, om, gx, gy);
+                src, dst, s.type, s.nmask, s.alpha, s.bc_val, s.tile_nbr, nt, om, gx, gy);
     } else {
         const uint32_t nf = (uint32_t)s.n_fluid;
         const uint32_t nblocks = (nf + kBlock - 1) / kBlock;
         if (nf > 0)
             k_step_indirect<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
-                src, dst, s.ind_pk, s.ind_info, s.ind_edge, s.alpha, nf, nblocks, om, gx, gy);
+                src, dst, s.ind_pk, s.ind_info, s.ind_edge, s.alpha, s.bc_val, nf, nblocks, om,
+                gx, gy);
     }
+}
+
+template <class ST, int OPEN>
+void step_phys(const DevState &s, int64_t t, int cur)
+{
+    if (s.alpha)
+        step_launch<ST, kDragged | OPEN>(s, t, cur);
+    else if (s.gx != 0.0 || s.gy != 0.0)
+        step_launch<ST, kForced | OPEN>(s, t, cur);
+    else
+        step_launch<ST, kBGK | OPEN>(s, t, cur);
 }
 
 template <class ST>
 hipError_t step_typed(const DevState &s, int64_t t, int cur)
 {
-    if (s.alpha)
-        step_launch<ST, kDragged>(s, t, cur);
-    else if (s.gx != 0.0 || s.gy != 0.0)
-        step_launch<ST, kForced>(s, t, cur);
+    if (s.open)
+        step_phys<ST, kOpenBC>(s, t, cur);
     else
-        step_launch<ST, kBGK>(s, t, cur);
+        step_phys<ST, 0>(s, t, cur);
     return hipGetLastError();
 }
 

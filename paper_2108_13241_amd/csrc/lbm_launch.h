@@ -31,6 +31,9 @@ struct DevState {
     const uint32_t *ind_pk = nullptr;                       // INDIRECT: packed row offsets
     const uint16_t *ind_info = nullptr;                     // INDIRECT: solid bits + edge flag
     const int32_t *ind_edge = nullptr;                      // INDIRECT: edge-node table [][8]
+    const double *bc_val = nullptr;   // open-boundary values [node][2], same indexing as
+                                      // alpha; read only at open-boundary nodes
+    int open = 0;                     // 1 when the node types hold open-boundary codes
     int64_t n_tiles = 0, n_fluid = 0;
     double omega = 1.0, gx = 0.0, gy = 0.0;
     hipStream_t stream = nullptr;
@@ -81,6 +84,8 @@ hipError_t launch_adjoint_seed_raw(const DevState &s, const void *state, int x_c
 hipError_t launch_adjoint_step_raw(const DevState &s, const void *state, const void *mu_in,
                                    void *mu_out, double *grad_alpha, double *partials,
                                    int accumulate);
+// Adjoint field <-> device FP64 planes [9][ny][nx] (to_plain = 1: field -> planes).
+hipError_t launch_adjoint_convert(const DevState &s, void *mu, double *plain, int to_plain);
 // grad_g[0..1] += fixed-order sum of n partial pairs.
 hipError_t launch_partials_into(const double *partials, int64_t n, double *grad_g,
                                 hipStream_t stream);

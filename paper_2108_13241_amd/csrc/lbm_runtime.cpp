@@ -52,6 +52,8 @@ struct lbm_ctx {
     size_t device_bytes = 0;
     int pop_bytes = 8;
     float *alpha_buf = nullptr;
+    double *bc_buf = nullptr;  // open-boundary values [node][2]
+    int64_t n_open = 0;        // open-boundary nodes currently set
     lbm::plan::Tiles tiles;
     lbm::plan::Fluid fluid;
     int64_t n_fluid = 0;
@@ -60,6 +62,12 @@ struct lbm_ctx {
     double *adj_partials = nullptr;
     int64_t adj_capacity = 0;
     void *mu_buf[2] = {nullptr, nullptr};
+    // Step graphs (hipGraph replay of G consecutive steps), keyed by the parity
+    // the replay starts from: lattice index for A-B layouts, step parity for AA.
+    int32_t graph_steps = -1;  // -1 auto, 0 off, else an even G >= 2
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    int32_t graph_len = 0;
+    hipStream_t capture_stream = nullptr;
 };
 
 namespace {
@@ -205,11 +213,24 @@ int lbm_set_allocator(lbm_alloc_fn alloc, lbm_free_fn free_fn, void *user)
     return LBM_OK;
 }
 
+static void drop_graphs(lbm_ctx *c)
+{
+    for (auto &g : c->graph_exec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    c->graph_len = 0;
+}
+
 void lbm_destroy(lbm_ctx *c)
 {
     if (!c)
         return;
     (void)hipStreamSynchronize(c->s.stream);
+    drop_graphs(c);
+    if (c->capture_stream)
+        (void)hipStreamDestroy(c->capture_stream);
     for (auto &b : c->owned)
         raw_free(c->alloc, b.first);
     delete c;
@@ -379,6 +400,7 @@ int lbm_set_porosity(lbm_ctx *c, const float *alpha)
 {
     LBM_CHECK_CTX(c);
     lbm::DevState &s = c->s;
+    drop_graphs(c);
     if (!alpha) {
         s.alpha = nullptr;
         return LBM_OK;
@@ -417,6 +439,117 @@ int lbm_set_porosity(lbm_ctx *c, const float *alpha)
     return LBM_OK;
 }
 
+// Index of node (x, y) in the per-node arrays of the context's layout (type,
+// alpha, boundary values), or -1 when the layout holds no such node.
+static int64_t node_index(const lbm_ctx *c, int x, int y)
+{
+    const lbm::DevState &s = c->s;
+    if (s.layout == LBM_DENSE_AB || s.layout == LBM_DENSE_AA)
+        return (int64_t)y * s.pitch + x;
+    if (s.layout == LBM_TILED16) {
+        const int32_t k = c->tiles.index_of[(size_t)(y / 16) * (s.nx / 16) + x / 16];
+        return k < 0 ? -1 : (int64_t)k * lbm::kTileNodes + (y % 16) * 16 + (x % 16);
+    }
+    return c->fluid.index_of[(size_t)y * s.nx + x];
+}
+
+int lbm_set_boundaries(lbm_ctx *c, const uint8_t *bc, const double *value)
+{
+    LBM_CHECK_CTX(c);
+    lbm::DevState &s = c->s;
+    const int nx = s.nx, ny = s.ny;
+    const size_t nn = (size_t)nx * ny;
+    int64_t n_open = 0;
+    if (bc) {
+        if (!value)
+            return fail(c, LBM_ERR_INVALID, "boundary values are required with boundary codes");
+        for (size_t k = 0; k < nn; ++k) {
+            const unsigned b = bc[k];
+            if (!b)
+                continue;
+            if (b > 8)
+                return fail(c, LBM_ERR_INVALID, "boundary codes must lie in 0..8");
+            if (c->mask[k] != 0)
+                return fail(c, LBM_ERR_INVALID, "boundary codes are only allowed at fluid nodes");
+            const double v0 = value[k], v1 = value[nn + k];
+            if (b <= 4) {
+                if (!(std::isfinite(v0) && std::isfinite(v1) && std::fabs(v0) < 1.0 &&
+                      std::fabs(v1) < 1.0))
+                    return fail(c, LBM_ERR_INVALID,
+                                "boundary velocities must be finite with |u_x|, |u_y| < 1");
+            } else if (!(std::isfinite(v0) && v0 > 0.0)) {
+                return fail(c, LBM_ERR_INVALID, "boundary densities must be finite and > 0");
+            }
+            ++n_open;
+        }
+    }
+    if (n_open && !c->bc_buf) {
+        c->bc_buf = (double *)own_alloc(c, 2 * s.plane * sizeof(double));
+        if (!c->bc_buf)
+            return fail(c, LBM_ERR_NOMEM, "cannot allocate the boundary values");
+    }
+    // The canonical state is kept across the change: it is gathered with the
+    // old codes and stored back with the new ones (the new conditions then
+    // apply to it in every later view and step).
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    drop_graphs(c);
+    LBM_HIP(c, lbm::launch_fill((double *)fc.p, canonical_bytes(c) / 8, 0.0, s.stream));
+    LBM_HIP(c, lbm::launch_gather_canonical(s, c->t, c->cur, (double *)fc.p));
+    LBM_HIP(c, hipStreamSynchronize(s.stream));
+    // Node types / info words of the geometry, with the boundary codes on top.
+    std::vector<uint8_t> type, nmask;
+    std::vector<uint16_t> info;
+    if (s.layout == LBM_DENSE_AB || s.layout == LBM_DENSE_AA)
+        lbm::plan::dense_types(c->mask.data(), nx, ny, s.pitch, type, nmask);
+    else if (s.layout == LBM_TILED16)
+        lbm::plan::tiled_types(c->mask.data(), nx, ny, c->tiles, type, nmask);
+    else
+        info = lbm::plan::indirect_compact(c->fluid, c->mask.data(), nx, ny, (int64_t)s.plane).info;
+    std::vector<double> vals;
+    if (n_open)
+        vals.assign(2 * s.plane, 0.0);
+    for (int y = 0; y < ny && n_open; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t k = (size_t)y * nx + x;
+            const unsigned b = bc[k];
+            if (!b)
+                continue;
+            const int64_t i = node_index(c, x, y);
+            if (info.empty())
+                type[i] = (uint8_t)(2 + b);  // kOpen + b - 1
+            else
+                info[i] = (uint16_t)(info[i] | (b << 9));
+            vals[2 * i] = value[k];
+            vals[2 * i + 1] = value[nn + k];
+        }
+    if (!type.empty())
+        LBM_HIP(c, hipMemcpyAsync((void *)s.type, type.data(), type.size(), hipMemcpyHostToDevice,
+                                  s.stream));
+    if (!info.empty())
+        LBM_HIP(c, hipMemcpyAsync((void *)s.ind_info, info.data(), info.size() * 2,
+                                  hipMemcpyHostToDevice, s.stream));
+    std::vector<uint32_t> seg;
+    if (s.layout == LBM_DENSE_AB || s.layout == LBM_DENSE_AA) {
+        lbm::plan::dense_segment_flags(type, nx, ny, s.pitch, 256, seg);
+        LBM_HIP(c, hipMemcpyAsync((void *)s.seg_interior, seg.data(), seg.size() * 4,
+                                  hipMemcpyHostToDevice, s.stream));
+    }
+    if (n_open) {
+        LBM_HIP(c, hipMemcpyAsync(c->bc_buf, vals.data(), vals.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s.stream));
+        s.bc_val = c->bc_buf;
+    }
+    c->n_open = n_open;
+    s.open = n_open > 0;
+    int rc = scatter_from_device_canonical(c, (const double *)fc.p);
+    if (rc)
+        return rc;
+    LBM_HIP(c, hipStreamSynchronize(s.stream));
+    return LBM_OK;
+}
+
 int lbm_set_force(lbm_ctx *c, const double *force)
 {
     LBM_CHECK_CTX(c);
@@ -424,6 +557,67 @@ int lbm_set_force(lbm_ctx *c, const double *force)
         return fail(c, LBM_ERR_INVALID, "force must be two finite numbers");
     c->s.gx = force[0];
     c->s.gy = force[1];
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+// Graph length for this context: explicit setting, or (auto) 32 steps for
+// lattices small enough that host launch overhead is a visible share of a step.
+static int32_t graph_length(const lbm_ctx *c)
+{
+    if (c->graph_steps >= 0)
+        return c->graph_steps;
+    const double bytes = 18.0 * (double)c->s.plane * c->pop_bytes;
+    return bytes < 128.0 * (1 << 20) ? 32 : 0;
+}
+
+// Launch one step and advance the counters.
+static hipError_t step_once(lbm_ctx *c, hipStream_t stream)
+{
+    lbm::DevState s = c->s;
+    s.stream = stream;
+    hipError_t e = lbm::launch_step(s, c->t, c->cur);
+    if (c->s.layout != LBM_DENSE_AA)
+        c->cur ^= 1;
+    ++c->t;
+    return e;
+}
+
+// Capture G steps starting from the current parity into a graph (the counters
+// are restored afterwards: capture launches nothing).
+static int capture_graph(lbm_ctx *c, int key, int32_t G)
+{
+    if (!c->capture_stream)
+        LBM_HIP(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    const int64_t t0 = c->t;
+    const int cur0 = c->cur;
+    hipGraph_t graph = nullptr;
+    LBM_HIP(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int32_t k = 0; k < G && e == hipSuccess; ++k)
+        e = step_once(c, c->capture_stream);
+    hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
+    c->t = t0;
+    c->cur = cur0;
+    if (e != hipSuccess)
+        return fail_device(c, e, "step launch during graph capture");
+    if (e2 != hipSuccess)
+        return fail_device(c, e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->graph_exec[key], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return fail_device(c, e, "hipGraphInstantiate");
+    c->graph_len = G;
+    return LBM_OK;
+}
+
+int lbm_set_graph_steps(lbm_ctx *c, int32_t steps)
+{
+    LBM_CHECK_CTX(c);
+    if (steps < -1 || (steps > 0 && (steps % 2 != 0 || steps > 4096)))
+        return fail(c, LBM_ERR_INVALID, "graph steps must be -1 (auto), 0 (off) or even in [2, 4096]");
+    drop_graphs(c);
+    c->graph_steps = steps;
     return LBM_OK;
 }
 
@@ -432,12 +626,23 @@ int lbm_step(lbm_ctx *c, int64_t n)
     LBM_CHECK_CTX(c);
     if (n < 0)
         return fail(c, LBM_ERR_INVALID, "n must be >= 0");
-    for (int64_t k = 0; k < n; ++k) {
-        LBM_HIP(c, lbm::launch_step(c->s, c->t, c->cur));
-        if (c->s.layout != LBM_DENSE_AA)
-            c->cur ^= 1;
-        ++c->t;
+    const int32_t G = graph_length(c);
+    if (G >= 2 && c->graph_len != 0 && c->graph_len != G)
+        drop_graphs(c);
+    while (G >= 2 && n >= G) {
+        // G is even: a replay returns to the parity it started from
+        const int key = c->s.layout == LBM_DENSE_AA ? (int)(c->t & 1) : c->cur;
+        if (!c->graph_exec[key]) {
+            int rc = capture_graph(c, key, G);
+            if (rc)
+                return rc;
+        }
+        LBM_HIP(c, hipGraphLaunch(c->graph_exec[key], c->s.stream));
+        c->t += G;
+        n -= G;
     }
+    for (int64_t k = 0; k < n; ++k)
+        LBM_HIP(c, step_once(c, c->s.stream));
     return LBM_OK;
 }
 
@@ -577,6 +782,8 @@ static int adjoint_supported(lbm_ctx *c)
 {
     if (c->s.layout != LBM_DENSE_AB || (c->s.dtype != LBM_F64 && c->s.dtype != LBM_F32))
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
+    if (c->n_open)
+        return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
     return LBM_OK;
 }
 
@@ -626,9 +833,47 @@ int lbm_adjoint_bytes(const lbm_ctx *c, size_t *bytes, int32_t *pitch)
         return fail_tl(LBM_ERR_INVALID, "NULL argument");
     if (c->s.layout != LBM_DENSE_AB || (c->s.dtype != LBM_F64 && c->s.dtype != LBM_F32))
         return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
+    if (c->n_open)
+        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
     *bytes = adjoint_field_bytes(c);
     if (pitch)
         *pitch = c->s.pitch;
+    return LBM_OK;
+}
+
+int lbm_adjoint_get(lbm_ctx *c, const void *mu_dev, double *host)
+{
+    LBM_CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc)
+        return rc;
+    if (!mu_dev || !host)
+        return fail(c, LBM_ERR_INVALID, "NULL buffer");
+    const size_t bytes = (size_t)9 * c->s.nx * c->s.ny * sizeof(double);
+    Temp t(c, bytes);
+    if (!t.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the staging buffer");
+    LBM_HIP(c, lbm::launch_adjoint_convert(c->s, const_cast<void *>(mu_dev), (double *)t.p, 1));
+    LBM_HIP(c, hipMemcpyAsync(host, t.p, bytes, hipMemcpyDeviceToHost, c->s.stream));
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm_adjoint_set(lbm_ctx *c, void *mu_dev, const double *host)
+{
+    LBM_CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc)
+        return rc;
+    if (!mu_dev || !host)
+        return fail(c, LBM_ERR_INVALID, "NULL buffer");
+    const size_t bytes = (size_t)9 * c->s.nx * c->s.ny * sizeof(double);
+    Temp t(c, bytes);
+    if (!t.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the staging buffer");
+    LBM_HIP(c, hipMemcpyAsync(t.p, host, bytes, hipMemcpyHostToDevice, c->s.stream));
+    LBM_HIP(c, lbm::launch_adjoint_convert(c->s, mu_dev, (double *)t.p, 0));
+    LBM_HIP(c, hipStreamSynchronize(c->s.stream));
     return LBM_OK;
 }
 

@@ -158,3 +158,86 @@ def test_autograd_function(lbm):
     assert np.array_equal(ga64.cpu().numpy(), ga)
     assert np.allclose(gt.grad.cpu().numpy(), gg, rtol=1e-14)
     assert a.grad.dtype == torch.float32
+
+
+def test_single_step_dot_product(lbm):
+    """One adjoint step is the transpose of the step's Jacobian: for random lambda_{t+1} and
+    perturbations, <lambda_t, df> = <lambda_{t+1}, J_f df>, sum dJ/dalpha . dalpha =
+    <lambda_{t+1}, J_alpha dalpha> and dJ/dg . dg = <lambda_{t+1}, J_g dg>, with the J products
+    from central differences of the FP64 forward step, for f and alpha Richardson-extrapolated
+    from steps h and h/2 (truncation O(h^4), so the bounds are left to rounding).  alpha is quantised to
+    multiples of 2^-12 so that alpha +- 2^-10 and +- 2^-11 are exact in its FP32 storage, and
+    only nodes whose perturbed alpha stays inside [0, 1] are perturbed (a clipped, one-sided
+    difference would be first-order)."""
+    import torch
+    announce("adjoint single-step dot-product test")
+    nx, ny = 48, 24
+    m = synthetic.channel_mask(nx, ny)
+    m[8:12, 20:25] = 1
+    alpha = synthetic.brinkman_alpha(nx, ny, seed=5, sigma=3.0)
+    alpha = (np.round(alpha * 4096.0) / 4096.0).astype(np.float32)
+    g = (2e-4, 5e-5)
+    lat = lbm.Lattice(m, 0.8, force=g, dtype="f64", layout="dense_ab")
+    lat.set_porosity(alpha)
+    lat.init_equilibrium(*synthetic.random_fields(nx, ny, seed=4, rho_spread=0.02, u_amp=0.03))
+    lat.step(15)
+    state = torch.empty(lat.state_bytes(), dtype=torch.uint8, device="cuda")
+    lat.save_state(state)
+    f_t = lat.get_populations()
+    rng = np.random.default_rng(6)
+    fl = (m == 0)[None]
+    lam1 = np.where(fl, rng.standard_normal((9, ny, nx)), 0.0)
+    df = np.where(fl, rng.standard_normal((9, ny, nx)), 0.0)
+    ab, _ = lat.adjoint_bytes()
+    mu = [torch.zeros(ab, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    ga = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    gg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lat.adjoint_set(mu[0], lam1)
+    assert np.array_equal(lat.adjoint_get(mu[0]), lam1)
+    lat.adjoint_step(state, mu[0], mu[1], ga, gg)
+    lam0 = lat.adjoint_get(mu[1])
+
+    def step_from(f, a=alpha, gv=g):
+        lat.set_porosity(a)
+        lat.set_force(gv)
+        lat.set_populations(f)
+        lat.step(1)
+        return lat.get_populations()
+
+    def central(hh):
+        return (step_from(f_t + hh * df) - step_from(f_t - hh * df)) / (2 * hh)
+
+    h = 1e-4 * np.abs(f_t[:, m == 0]).max()
+    jdf = (4.0 * central(h / 2) - central(h)) / 3.0
+    lhs, rhs = float((lam0 * df).sum()), float((lam1 * jdf).sum())
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+    ha = 2.0 ** -10
+    inside = (alpha >= 2 * ha) & (alpha <= 1 - 2 * ha) & (m == 0)
+    assert inside.sum() > 100
+    e = np.where(inside, rng.choice([-1.0, 1.0], size=(ny, nx)), 0.0)
+
+    def central_alpha(hh):
+        ap = (alpha + hh * e).astype(np.float32)
+        am = (alpha - hh * e).astype(np.float32)
+        assert np.array_equal(ap.astype(np.float64) - am.astype(np.float64), 2 * hh * e)
+        return float((lam1 * (step_from(f_t, a=ap) - step_from(f_t, a=am))).sum()) / (2 * hh)
+
+    fd_a = (4.0 * central_alpha(ha / 2) - central_alpha(ha)) / 3.0
+    ad_a = float((ga.cpu().numpy() * e).sum())
+    assert abs(fd_a - ad_a) <= 1e-8 * abs(ad_a)
+
+    def central_g(b, hh):
+        gp, gm = list(g), list(g)
+        gp[b] += hh
+        gm[b] -= hh
+        return float((lam1 * (step_from(f_t, gv=gp) - step_from(f_t, gv=gm))).sum()) / (2 * hh)
+
+    # The step is a quadratic polynomial in g (u and F are linear in g; f^eq and the forcing
+    # term are quadratic in them), so a central difference in g is exact up to rounding, and a
+    # large step keeps the rounding of the differenced sums small.
+    hg = 1e-3
+    for b in range(2):
+        fd_g = central_g(b, hg)
+        assert fd_g == pytest.approx(float(gg[b]), rel=1e-8)
+    lat.close()

@@ -1,0 +1,127 @@
+"""Failure handling through the C ABI on a GPU machine: every rejected call returns its documented
+status, leaves the context usable, and no kernel is launched with bad arguments."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_13241_amd as m
+    m.load()
+    return m
+
+
+def _status(exc):
+    return exc.value.status
+
+
+def test_invalid_calls_leave_context_usable(lbm):
+    import torch
+    announce("error paths")
+    m = synthetic.channel_mask(64, 16)
+    m[:, 10] = 1  # a fully solid column
+    lat = lbm.Lattice(m, 0.8, force=(1e-5, 0.0), dtype="f64", layout="dense_ab")
+    M0 = lat.mass()
+    with pytest.raises(lbm.LbmError) as e:
+        lat.set_porosity(np.full((16, 64), 1.5, np.float32))
+    assert _status(e) == -1
+    bad = lat.get_populations()
+    bad[3, 5, 7] = np.nan
+    with pytest.raises(lbm.LbmError) as e:
+        lat.set_populations(bad)
+    assert _status(e) == -1
+    with pytest.raises(lbm.LbmError) as e:
+        lat.init_equilibrium(np.zeros((16, 64)))
+    assert _status(e) == -1
+    with pytest.raises(lbm.LbmError) as e:
+        lat.objective_outlet_ux(10)
+    assert _status(e) == -1
+    with pytest.raises(lbm.LbmError) as e:
+        lat.objective_outlet_ux(64)
+    assert _status(e) == -1
+    with pytest.raises(lbm.LbmError) as e:
+        lat.step(-1)
+    assert _status(e) == -1
+    ab, _ = lat.adjoint_bytes()
+    mu = torch.zeros(ab, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(lat.state_bytes(), dtype=torch.uint8, device="cuda")
+    gg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(lbm.LbmError) as e:
+        lat.adjoint_step(st, mu, mu, None, gg)
+    assert _status(e) == -1
+    # still usable
+    lat.step(20)
+    assert lat.mass() == pytest.approx(M0, rel=1e-13)
+    assert lat.info()["time_step"] == 20
+    lat.close()
+
+
+@pytest.mark.parametrize("layout,dtype", [("tiled16", "f64"), ("indirect", "f32"),
+                                          ("dense_ab", "f16s")])
+def test_adjoint_unsupported(lbm, layout, dtype):
+    m = synthetic.channel_mask(64, 32)
+    lat = lbm.Lattice(m, 0.8, dtype=dtype, layout=layout)
+    with pytest.raises(lbm.LbmError) as e:
+        lat.adjoint_bytes()
+    assert _status(e) == -4
+    lat.close()
+
+
+def test_allocator_failure_reports_nomem(lbm):
+    """An allocator hook that returns NULL makes lbm_create fail with LBM_ERR_NOMEM and leak
+    nothing; restoring the hooks makes creation work again."""
+    announce("allocator failure")
+    from paper_2108_13241_amd import _install_torch_allocator, _uninstall_torch_allocator
+    from paper_2108_13241_amd._lib import ALLOC_FN, FREE_FN
+    L = lbm.load()
+    calls = {"alloc": 0, "free": 0}
+
+    def alloc(n, u):
+        calls["alloc"] += 1
+        return None
+
+    def free(p, u):
+        calls["free"] += 1
+
+    a, f = ALLOC_FN(alloc), FREE_FN(free)
+    assert L.lbm_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p),
+                               None) == 0
+    try:
+        ctx = ctypes.c_void_p()
+        m = np.zeros((16, 16), np.uint8)
+        g = (ctypes.c_double * 2)(0.0, 0.0)
+        st = L.lbm_create(ctypes.byref(ctx), 16, 16,
+                          m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0.8, g, 0, 0)
+        assert st == -2
+        assert not ctx.value
+        assert calls["alloc"] >= 1
+    finally:
+        import paper_2108_13241_amd as pkg
+        pkg._alloc_cb = None
+        _install_torch_allocator()
+    lat = lbm.Lattice(np.zeros((16, 16), np.uint8), 0.8)
+    lat.step(3)
+    lat.close()
+
+
+def test_hipmalloc_path(lbm):
+    """Contexts created without the torch allocator (plain hipMalloc) work the same."""
+    m = synthetic.random_mask(48, 40, seed=9, solid_fraction=0.2)
+    a = lbm.Lattice(m, 0.7, force=(1e-4, 0.0), dtype="f64", layout="indirect", torch_memory=False)
+    a.step(30)
+    fa = a.get_populations()
+    a.close()
+    b = lbm.Lattice(m, 0.7, force=(1e-4, 0.0), dtype="f64", layout="indirect", torch_memory=True)
+    b.step(30)
+    assert np.array_equal(b.get_populations(), fa)
+    b.close()

@@ -1,0 +1,221 @@
+"""Open boundaries on the GPU (Sec. 3: constant velocity and constant pressure, after Zou and
+He) against the FP64 oracle, every layout, FP64 and FP32.
+
+Tolerances: FP64 max abs 1e-12; FP32 1e-5 relative to max(|f|, w_i) (fp_error_w): a moving
+lid drives some corner populations far below their lattice weight, where the 32-bit deviation
+storage keeps its absolute error (a CPU emulation of the FP32 path gives the same 2.8e-5
+value-relative error at a population of 1e-4 as the GPU, i.e. 1e-7 of its weight).
+
+Cases: the paper's chan_v / chan_p channels and the lid-driven cavity (Sec. 4.1) at small
+sizes, open ends combined with a body force, a drag field and random initial fields, the AA
+layout after odd and even step counts, graph replay, removal of the boundaries, a full-size
+chan_v (4096 x 512) checked on sampled nodes, and the error paths.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_util import TOL, announce, fp_error_w as fp_error
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = ["dense_ab", "dense_aa", "tiled16", "indirect"]
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_13241_amd as m
+    m.load()
+    return m
+
+
+def _gpu(lbm, mask, bc, val, tau, steps, dtype, layout, g=(0.0, 0.0), alpha=None, fields=None,
+         graph=-1):
+    lat = lbm.Lattice(mask, tau, force=g, dtype=dtype, layout=layout)
+    lat.set_graph_steps(graph)
+    lat.set_boundaries(bc, val)
+    if fields is not None:
+        lat.init_equilibrium(*fields)
+    if alpha is not None:
+        lat.set_porosity(alpha)
+    lat.step(steps)
+    f = lat.get_populations()
+    macro = lat.macroscopic()
+    lat.close()
+    return f, macro
+
+
+def _oracle(oracle_mod, mask, bc, val, tau, steps, g=(0.0, 0.0), alpha=None, fields=None):
+    f0 = oracle_mod.init(mask, *(fields or (None, None, None)), bc=bc, value=val)
+    a64 = None if alpha is None else np.asarray(alpha, np.float32).astype(np.float64)
+    return oracle_mod.run(mask, f0, tau, steps, g=g, alpha=a64, bc=bc, value=val)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("inlet", ["velocity", "pressure"])
+def test_channels_vs_oracle(lbm, oracle_mod, dtype, layout, inlet):
+    """chan_v (inlet u = 0.1) and chan_p (inlet rho = 1.016, initial rho 1.008), outlet
+    rho = 1, halfway walls; 112 x 32 nodes (7 x 2 tiles), 301 steps."""
+    announce(f"open channel {inlet} {layout} {dtype}")
+    nx, ny = 112, 32
+    m, bc, val = synthetic.open_channel(nx, ny, inlet, u_in=0.1, rho_in=1.016)
+    fields = None if inlet == "velocity" else (np.full((ny, nx), 1.008), None, None)
+    ref = _oracle(oracle_mod, m, bc, val, 0.8, 301, fields=fields)
+    got, (rho, ux, uy) = _gpu(lbm, m, bc, val, 0.8, 301, dtype, layout, fields=fields)
+    assert fp_error(got, ref, m, dtype) <= TOL[dtype]
+    inl = slice(1, ny - 1)
+    if inlet == "velocity":
+        assert np.abs(ux[inl, 0] - 0.1).max() < (1e-14 if dtype == "f64" else 1e-6)
+    else:
+        assert np.abs(rho[inl, 0] - 1.016).max() < (1e-14 if dtype == "f64" else 1e-6)
+    assert np.abs(rho[inl, nx - 1] - 1.0).max() < (1e-14 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_lid_cavity_vs_oracle(lbm, oracle_mod, dtype, layout):
+    """Lid-driven cavity 48 x 48 (lid u = 0.1, Re = 100), 400 steps."""
+    announce(f"lid cavity {layout} {dtype}")
+    n = 48
+    m, bc, val = synthetic.lid_cavity(n, 0.1)
+    tau = 3.0 * (0.1 * (n - 1) / 100.0) + 0.5
+    ref = _oracle(oracle_mod, m, bc, val, tau, 400)
+    got, _ = _gpu(lbm, m, bc, val, tau, 400, dtype, layout)
+    assert fp_error(got, ref, m, dtype) <= TOL[dtype]
+
+
+def _mixed_case(nx, ny):
+    """Open ends on all four sides of a porous box: velocity inlet with a tangential component
+    on the left, pressure outlet on the right, velocity (0, 0.02) through the bottom, pressure
+    at the top; random solid nodes inside (none on the open rows / columns)."""
+    m = synthetic.random_mask(nx, ny, seed=31, solid_fraction=0.15)
+    m[0, :] = 0
+    m[ny - 1, :] = 0
+    m[:, 0] = 0
+    m[:, nx - 1] = 0
+    bc = np.zeros((ny, nx), np.uint8)
+    val = np.zeros((2, ny, nx))
+    bc[1:ny - 1, 0] = synthetic.BC_VELOCITY[(1, 0)]
+    val[0, 1:ny - 1, 0], val[1, 1:ny - 1, 0] = 0.05, 0.01
+    bc[1:ny - 1, nx - 1] = synthetic.BC_PRESSURE[(-1, 0)]
+    val[0, 1:ny - 1, nx - 1] = 0.995
+    bc[0, :] = synthetic.BC_VELOCITY[(0, 1)]
+    val[1, 0, :] = 0.02
+    bc[ny - 1, :] = synthetic.BC_PRESSURE[(0, -1)]
+    val[0, ny - 1, :] = 1.003
+    return m, bc, val
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_mixed_open_sides_force_drag(lbm, oracle_mod, dtype, layout):
+    """All four normals and both kinds at once, corners included, with a body force, a drag
+    field and random initial fields; 96 x 48, 150 steps."""
+    announce(f"mixed open sides {layout} {dtype}")
+    nx, ny = 96, 48
+    m, bc, val = _mixed_case(nx, ny)
+    alpha = synthetic.brinkman_alpha(nx, ny) * 0.2
+    fields = synthetic.random_fields(nx, ny, seed=5, rho_spread=0.02, u_amp=0.03)
+    g = (2e-5, -1e-5)
+    ref = _oracle(oracle_mod, m, bc, val, 0.75, 150, g=g, alpha=alpha, fields=fields)
+    got, _ = _gpu(lbm, m, bc, val, 0.75, 150, dtype, layout, g=g, alpha=alpha, fields=fields)
+    assert fp_error(got, ref, m, dtype) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("steps", [1, 2, 7, 8])
+def test_aa_views_odd_and_even(lbm, oracle_mod, steps):
+    """The AA layout's canonical view after odd and even step counts applies the boundary
+    conditions like the A-B view does."""
+    announce(f"open AA view after {steps} steps")
+    m, bc, val = synthetic.open_channel(70, 20, "velocity", u_in=0.08)
+    ref = _oracle(oracle_mod, m, bc, val, 0.9, steps)
+    got, _ = _gpu(lbm, m, bc, val, 0.9, steps, "f64", "dense_aa")
+    assert fp_error(got, ref, m, "f64") <= 1e-12
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_graph_replay_with_open_boundaries(lbm, layout):
+    announce(f"open boundaries graph replay {layout}")
+    m, bc, val = synthetic.lid_cavity(48, 0.1)
+    a, _ = _gpu(lbm, m, bc, val, 0.7, 77, "f64", layout, graph=0)
+    b, _ = _gpu(lbm, m, bc, val, 0.7, 77, "f64", layout, graph=8)
+    assert np.array_equal(a, b)
+
+
+def test_remove_boundaries(lbm, oracle_mod):
+    """Setting, then removing the boundaries: the run equals the oracle with boundaries for the
+    first steps and without them for the rest."""
+    announce("open boundaries removed mid-run")
+    m, bc, val = synthetic.open_channel(64, 16, "velocity", u_in=0.05)
+    lat = lbm.Lattice(m, 0.8, dtype="f64", layout="dense_ab")
+    lat.set_boundaries(bc, val)
+    lat.step(40)
+    lat.set_boundaries(None)
+    lat.step(30)
+    got = lat.get_populations()
+    lat.close()
+    f = _oracle(oracle_mod, m, bc, val, 0.8, 40)
+    ref = oracle_mod.run(m, f, 0.8, 30)
+    assert fp_error(got, ref, m, "f64") <= 1e-12
+
+
+def test_open_boundary_errors(lbm):
+    announce("open boundary error paths")
+    import torch
+    m, bc, val = synthetic.open_channel(64, 16, "velocity", u_in=0.05)
+    lat = lbm.Lattice(m, 0.8, dtype="f64", layout="dense_ab")
+    lat.step(3)
+    f0 = lat.get_populations()
+    for mutate in (lambda b, v: b.__setitem__((0, 5), 1),            # code at a solid node
+                   lambda b, v: b.__setitem__((3, 5), 9),            # unknown code
+                   lambda b, v: v.__setitem__((0, 3, 0), 1.0),       # |u| = 1
+                   lambda b, v: v.__setitem__((1, 3, 0), np.nan),    # non-finite velocity
+                   lambda b, v: (b.__setitem__((3, 9), 5), v.__setitem__((0, 3, 9), 0.0))):
+        b, v = bc.copy(), val.copy()
+        mutate(b, v)
+        with pytest.raises(lbm.LbmError) as e:
+            lat.set_boundaries(b, v)
+        assert e.value.status == -1
+    assert np.array_equal(lat.get_populations(), f0)  # nothing changed
+    lat.set_boundaries(bc, val)
+    ab_err = None
+    try:
+        lat.adjoint_bytes()
+    except lbm.LbmError as e:
+        ab_err = e.status
+    assert ab_err == -4
+    lat.step(5)
+    lat.close()
+
+
+def test_chan_v_4096x512_sampled(lbm, oracle_mod):
+    """The paper's chan_v size (4096 x 512, FP32, dense A-B): after 10 steps, 16 sampled nodes
+    (half of them on or next to the inlet / outlet columns) against the oracle run on a
+    periodic 48 x 48 window around each (exact for 10 steps: the window's own wrap-around
+    error travels one node per step and stays 14 nodes away)."""
+    announce("chan_v 4096x512 f32 sampled")
+    nx, ny, steps, half = 4096, 512, 10, 24
+    m, bc, val = synthetic.open_channel(nx, ny, "velocity", u_in=0.1)
+    lat = lbm.Lattice(m, 0.8, dtype="f32", layout="dense_ab")
+    lat.set_boundaries(bc, val)
+    lat.step(steps)
+    f = lat.get_populations()
+    lat.close()
+    rng = np.random.default_rng(3)
+    ys = rng.integers(1, ny - 1, 16)
+    xs = np.concatenate([rng.integers(0, nx, 8), [0, 1, 2, nx - 1, nx - 2, nx - 3, 0, nx - 1]])
+    worst = 0.0
+    for y, x in zip(ys, xs):
+        yy = np.arange(y - half, y + half) % ny
+        xx = np.arange(x - half, x + half) % nx
+        mw = np.ascontiguousarray(m[yy[:, None], xx[None, :]])
+        bw = np.ascontiguousarray(bc[yy[:, None], xx[None, :]])
+        vw = np.ascontiguousarray(val[:, yy[:, None], xx[None, :]])
+        ref = _oracle(oracle_mod, mw, bw, vw, 0.8, steps)[:, half, half]
+        got = f[:, y, x]
+        worst = max(worst, float((np.abs(got - ref) / np.abs(ref)).max()))
+    assert worst <= TOL["f32"]
