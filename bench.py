@@ -185,8 +185,14 @@ def measure_small_channel(lbm, steps=2000):
     return out
 
 
-def measure_adjoint(lbm, steps=200):
-    """Adjoint kernel time per step vs forward step time (1024 x 256 channel, FP32)."""
+def measure_adjoint(lbm, steps=200, T=2000):
+    """Adjoint cost on the 1024 x 256 channel with a drag field, FP32.
+
+    adjoint_over_forward: one adjoint step (adjoint kernel + its dJ/dg partial reduction) per
+    host call against one forward step per host call (graph replay off, so both pay the same
+    launch path).  checkpointed_*: the drivers as a user runs them, T steps with checkpoints
+    every K = ceil(sqrt(T)) (forward with checkpoint copies; backward = segment recompute +
+    adjoint), whole-run wall time on the device."""
     import torch
 
     import synthetic
@@ -195,7 +201,10 @@ def measure_adjoint(lbm, steps=200):
     alpha = synthetic.brinkman_alpha(nx, ny, seed=7, sigma=8.0).astype(np.float32)
     lat = lbm.Lattice(m, 0.8, force=(1e-5, 0.0), dtype="f32", layout="dense_ab")
     lat.set_porosity(alpha)
+    lat.set_graph_steps(0)
     fwd_s, fwd_ms = time_steps(lat, steps, 20)
+    lat.set_graph_steps(-1)
+    _, fwd_graph_ms = time_steps(lat, steps, 20)
     sb = lat.state_bytes()
     state = torch.empty(sb, dtype=torch.uint8, device="cuda")
     lat.save_state(state)
@@ -214,10 +223,33 @@ def measure_adjoint(lbm, steps=200):
     e1.record()
     torch.cuda.synchronize()
     adj_ms = e0.elapsed_time(e1) / steps
+    # checkpointed drivers
+    K = int(math.ceil(math.sqrt(T)))
+    ckpt = torch.empty(((T + K - 1) // K) * sb, dtype=torch.uint8, device="cuda")
+    seg = torch.empty(K * sb, dtype=torch.uint8, device="cuda")
+    lat.init_equilibrium(None, None, None)
+    torch.cuda.synchronize()
+    e0.record()
+    lat.run_checkpointed(T, K, ckpt)
+    e1.record()
+    torch.cuda.synchronize()
+    run_ms = e0.elapsed_time(e1)
+    ga.zero_()
+    gg.zero_()
+    torch.cuda.synchronize()
+    e0.record()
+    lat.adjoint_checkpointed(T, K, ckpt, seg, nx - 1, 1.0, ga, gg)
+    e1.record()
+    torch.cuda.synchronize()
+    back_ms = e0.elapsed_time(e1)
     lat.close()
+    del ckpt, seg
     return {"workload": "channel 1024x256 with drag field, f32", "forward_ms_per_step": fwd_ms,
+            "forward_graph_replay_ms_per_step": fwd_graph_ms,
             "adjoint_ms_per_step": adj_ms, "adjoint_over_forward": adj_ms / fwd_ms,
-            "amortised_with_recompute": (adj_ms + fwd_ms) / fwd_ms}
+            "checkpointed_T": T, "checkpointed_K": K,
+            "checkpointed_forward_ms": run_ms, "checkpointed_backward_ms": back_ms,
+            "checkpointed_backward_over_forward": back_ms / run_ms}
 
 
 def cpu_baseline(n, fields, budget_s=12.0):
@@ -311,7 +343,8 @@ def main():
                         f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid")
                     variants.append(r)
         a = measure_adjoint(lbm)
-        log(f"[bench]   adjoint/forward = {a['adjoint_over_forward']:.2f}")
+        log(f"[bench]   adjoint/forward = {a['adjoint_over_forward']:.2f} per step; "
+            f"checkpointed backward/forward = {a['checkpointed_backward_over_forward']:.2f}")
         variants.append(a)
 
     bpn = algorithmic_bytes_per_node("f64")
