@@ -215,6 +215,64 @@ __device__ __forceinline__ void dense_pull(const typename ST::mem *__restrict__ 
                       i);
 }
 
+// Wave-wide shift by one lane (DPP wave_shr:1 / wave_shl:1) of a full
+// wavefront.  UP: lane l receives lane l - 1's value, else lane l + 1's; the
+// end lane without a source (lane 0, resp. lane 63) keeps `edge` (the DPP
+// "old" operand with bound_ctrl off), so no select or branch is needed.
+template <bool UP>
+__device__ __forceinline__ uint32_t lane_shift_u32(uint32_t v, uint32_t edge)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, UP ? 0x138 : 0x130, 0xf, 0xf,
+                                                 false);
+}
+template <bool UP>
+__device__ __forceinline__ float lane_shift(float v, float edge)
+{
+    return __builtin_bit_cast(float, lane_shift_u32<UP>(__builtin_bit_cast(uint32_t, v),
+                                                        __builtin_bit_cast(uint32_t, edge)));
+}
+template <bool UP>
+__device__ __forceinline__ double lane_shift(double v, double edge)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v), e = __builtin_bit_cast(uint64_t, edge);
+    const uint32_t lo = lane_shift_u32<UP>((uint32_t)b, (uint32_t)e);
+    const uint32_t hi = lane_shift_u32<UP>((uint32_t)(b >> 32), (uint32_t)(e >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Pull gather of a full wavefront (64 consecutive columns x0 .. x0 + 63, all
+// interior fluid nodes) with aligned loads only: every lane loads column x of
+// each direction's source row, and the values from columns x - 1 and x + 1
+// come from the neighbouring lanes by one lane shift; lane 0 (sources at
+// x - 1) and lane 63 (sources at x + 1) take theirs from one wave-uniform load
+// in the neighbouring chunk, with the periodic wrap at x = 0 and nx - 1.  Same
+// values as dense_pull with no solid neighbours.  Callers guarantee that all
+// 64 lanes are active.
+template <class ST>
+__device__ __forceinline__ void dense_pull_aligned(const typename ST::mem *__restrict__ s,
+                                                   const DenseRC &a, int x0, int nx,
+                                                   typename ST::real (&f)[9])
+{
+    using M = typename ST::mem;
+    using R = typename ST::real;
+    M *sp = const_cast<M *>(s);
+    const uint32_t cl = col_off(x0 == 0 ? nx - 1 : x0 - 1);
+    const uint32_t cr = col_off(x0 + 64 < nx ? x0 + 64 : 0);
+    R v[9], e[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        v[i] = ST::ld(dense_at(sp, a, i, 1 - kCy[i], 1), i);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (kCx[i] != 0)
+            e[i] = ST::ld(sp[(uint32_t)i * kChunk + a.r[1 - kCy[i]] + (kCx[i] > 0 ? cl : cr)], i);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = kCx[i] == 0 ? v[i]
+               : kCx[i] > 0 ? lane_shift<true>(v[i], e[i])
+                            : lane_shift<false>(v[i], e[i]);
+}
+
 // ------------------------------------------------------------- step: dense --
 // Physics variant of a step kernel: plain BGK (no body force, no drag), body
 // force, or body force with a drag field; plus kOpen when the lattice has
@@ -238,9 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
         return;
     const uint32_t n = (uint32_t)y * pitch + x;
     // Segments of interior fluid nodes need neither the node type nor the
-    // neighbour bits, so their population loads issue at once.
+    // neighbour bits, so their population loads issue at once, all aligned.
     unsigned sm = 0, open = 0;
-    if (!seg_interior[L]) {
+    const bool interior = seg_interior[L] != 0;
+    if (!interior) {
         const uint8_t t = type[n];
         if (t == kSolid)
             return;
@@ -249,8 +308,13 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
             open = open_code(t);
     }
     const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
+    // first column of this wavefront (wave-uniform)
+    const int x0 = __builtin_amdgcn_readfirstlane(x - (int)(threadIdx.x & 63u));
     R f[9];
-    dense_pull<ST>(src, a, sm, f);
+    if (interior && x0 + 64 <= nx)
+        dense_pull_aligned<ST>(src, a, x0, nx, f);
+    else
+        dense_pull<ST>(src, a, sm, f);
     if (OPEN && open)
         apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
     collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
