@@ -15,7 +15,11 @@ paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on st
   variants  = the same measurement for the other storage types and the AA layout
               (and, with --suite full, the porous / sparse layouts and the adjoint).
 
-Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 100] [--suite default|full]
+  --suite sparse: the paper's sparse-geometry study (Sec. 4.3, Fig. 8): sparse efficiency
+              eta_P (Eq. 9) over porosity for regular and random circle obstacles, per layout.
+
+Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 100]
+                       [--suite default|full|headline|sparse]
 """
 from __future__ import annotations
 
@@ -80,10 +84,12 @@ def measured_traffic(kernel_key):
 
 
 def time_steps(lat, steps, warmup):
-    """(seconds for `steps` steps, per-step ms) with HIP events on the lattice's stream."""
+    """(seconds for `steps` steps, per-step ms) with HIP events on the lattice's stream.
+    The warm-up is at least 64 steps, so that a lattice replaying its steps as HIP graphs
+    has captured them (a one-time cost of a few ms) before the timed region."""
     import torch
     stream = torch.cuda.current_stream()
-    lat.step(warmup)
+    lat.step(max(warmup, 64))
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -185,6 +191,56 @@ def measure_small_channel(lbm, steps=2000):
     return out
 
 
+def measure_sparse_geometry(lbm, geom, dtype, layout, steps, warmup):
+    """One of the paper's sparse geometries (Sec. 4.3): pressure inlet / outlet, walls,
+    nu = 0.5 (tau = 2); GLUPS counting non-solid nodes only (Eq. 8)."""
+    m, bc, val, info = geom
+    lat = lbm.Lattice(m, 2.0, dtype=dtype, layout=layout)
+    lat.set_boundaries(bc, val)
+    secs, ms = time_steps(lat, steps, warmup)
+    li = lat.info()
+    lat.close()
+    nf = li["n_fluid"]
+    return {"kind": info["kind"], "phi": info.get("phi_target", 1.0),
+            "phi_achieved": info["phi_achieved"], "dtype": dtype, "layout": layout,
+            "glups_per_fluid_node": nf * steps / secs / 1e9, "ms_per_step": ms,
+            "n_tiles": li["n_tiles"] if layout.startswith("tiled16") else None}
+
+
+def sparse_study(lbm, n, steps, warmup):
+    """eta_P (Eq. 9) over porosity for the regular 8 x 8 circle array (phi >= 0.3) and
+    random circles r in [8, 256] (Sec. 4.3, Fig. 8), per layout and dtype, against the same
+    channel without obstacles (the dense geometry) in the same layout."""
+    import synthetic
+    from paper_2108_13241_amd import metrics
+    layouts = ("dense_ab", "tiled16", "tiled16_all", "indirect")
+    dtypes = ("f32", "f64")
+    rows = []
+    dense = synthetic.open_box(n)
+    ref = {}
+    for dt in dtypes:
+        for lay in layouts:
+            r = measure_sparse_geometry(lbm, dense, dt, lay, steps, warmup)
+            ref[(dt, lay)] = r["glups_per_fluid_node"]
+            r["eta_P"] = 1.0
+            rows.append(r)
+    log(f"[bench]   dense reference: " + ", ".join(f"{k[0]} {k[1]} {v:.1f}" for k, v in ref.items()))
+    geoms = [("regular", phi) for phi in (0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3)] + \
+            [("random", phi) for phi in (0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1)]
+    for kind, phi in geoms:
+        geom = synthetic.circle_array(n, phi) if kind == "regular" else \
+            synthetic.random_circles(n, phi)
+        line = []
+        for dt in dtypes:
+            for lay in layouts:
+                r = measure_sparse_geometry(lbm, geom, dt, lay, steps, warmup)
+                r["eta_P"] = metrics.sparse_efficiency(r["glups_per_fluid_node"], ref[(dt, lay)])
+                rows.append(r)
+                line.append(f"{dt} {lay} {r['eta_P']:.2f}")
+        log(f"[bench]   {kind} phi={phi}: eta_P " + ", ".join(line))
+    return rows
+
+
 def measure_adjoint(lbm, steps=200, T=2000):
     """Adjoint cost on the 1024 x 256 channel with a drag field, FP32.
 
@@ -278,7 +334,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--suite", default="default", choices=["default", "full", "headline"])
+    ap.add_argument("--suite", default="default",
+                    choices=["default", "full", "headline", "sparse"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-reps", type=int, default=20)
     args = ap.parse_args()
@@ -303,6 +360,8 @@ def main():
     head = measure_dense(lbm, n, "f64", "dense_ab", args.steps, args.warmup, fields)
     log(f"[bench]   {head['glups']:.2f} GLUPS, {head['hbm_gbps']:.0f} GB/s")
     variants = []
+    if args.suite == "sparse":
+        variants.extend(sparse_study(lbm, n, max(args.steps // 5, 20), max(args.warmup // 5, 5)))
     if args.suite == "headline":
         c = measure_copy(lbm, 1 << 30, reps=args.copy_reps)
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")

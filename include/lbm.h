@@ -70,12 +70,18 @@ typedef enum {
  *             Sec. 4.3).  Requires nx and ny to be multiples of 16.
  *  INDIRECT : two lattices holding only fluid nodes (row-major compaction) and
  *             a per-node neighbour table (the fluid-index-array approach of
- *             Sec. 1). */
+ *             Sec. 1).
+ *  TILED16_ALL: the "tile" layout of Sec. 4.3: a dense array of all 16 x 16
+ *             tiles, empty ones included, in row-major tile order, run by the
+ *             TILED16 kernels (memory and launch cover every tile).  Reported
+ *             as TILED16_ALL by lbm_get_info.  Requires nx and ny to be
+ *             multiples of 16. */
 typedef enum {
     LBM_DENSE_AB = 0,
     LBM_DENSE_AA = 1,
     LBM_TILED16 = 2,
-    LBM_INDIRECT = 3
+    LBM_INDIRECT = 3,
+    LBM_TILED16_ALL = 4
 } lbm_layout;
 
 typedef enum {
@@ -173,7 +179,9 @@ int lbm_step(lbm_ctx *ctx, int64_t n);
  * and replayed on the context's stream; bitwise-identical results).  -1 = auto
  * (32 steps for lattices that move less than 128 MB per step, where host launch
  * overhead is a visible share of a step; else off), 0 = off, or an even count in
- * [2, 4096].  Changing the force or the drag field discards captured graphs. */
+ * [2, 4096].  The first replay from each parity captures and instantiates its
+ * graph (a one-time cost of a few ms).  Changing the force, the drag field or
+ * the open boundaries discards captured graphs. */
 int lbm_set_graph_steps(lbm_ctx *ctx, int32_t steps);
 
 /* Macroscopic fields (Eq. 2, with the half-force / drag velocity) of the

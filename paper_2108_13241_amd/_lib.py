@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
 
 DTYPES = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 POP_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
-LAYOUTS = {"dense_ab": 0, "dense_aa": 1, "tiled16": 2, "indirect": 3}
+LAYOUTS = {"dense_ab": 0, "dense_aa": 1, "tiled16": 2, "indirect": 3, "tiled16_all": 4}
 STATUS = {0: "LBM_OK", -1: "LBM_ERR_INVALID", -2: "LBM_ERR_NOMEM", -3: "LBM_ERR_DEVICE",
           -4: "LBM_ERR_UNSUPPORTED", -5: "LBM_ERR_STATE"}
 

@@ -55,11 +55,16 @@ __device__ __forceinline__ unsigned open_code(uint8_t code)
 // kExact: FP32 reciprocals are Newton-refined; the 16-bit codecs, whose storage
 // rounding (2^-11 or 2^-8 of a deviation) dwarfs a 1-ulp FP32 reciprocal error,
 // use the raw hardware reciprocal and save the refinement's instructions.
+// kAligned: interior dense segments gather with aligned loads and lane shifts
+// (dense_pull_aligned).  It pays off for the 2-byte formats, whose shifted
+// 128-byte wavefront loads would touch two cache lines instead of one; for FP32
+// and FP64 the plain shifted loads are as fast and move slightly fewer bytes.
 struct F64 {
     using mem = double;
     using real = double;
     static constexpr bool kShift = false;
     static constexpr bool kExact = true;
+    static constexpr bool kAligned = false;
     static __device__ __forceinline__ real ld(mem v, int) { return v; }
     static __device__ __forceinline__ mem st(real v, int) { return v; }
     static __device__ __forceinline__ double canon(real v, int) { return v; }
@@ -71,6 +76,7 @@ struct Shifted {
     using real = float;
     static constexpr bool kShift = true;
     static constexpr bool kExact = sizeof(M) == 4;
+    static constexpr bool kAligned = sizeof(M) == 2;
     static __device__ __forceinline__ real ld(mem v, int) { return (float)v; }
     static __device__ __forceinline__ mem st(real v, int)
     {

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     // first column of this wavefront (wave-uniform)
     const int x0 = __builtin_amdgcn_readfirstlane(x - (int)(threadIdx.x & 63u));
     R f[9];
-    if (interior && x0 + 64 <= nx)
+    if (ST::kAligned && interior && x0 + 64 <= nx)
         dense_pull_aligned<ST>(src, a, x0, nx, f);
     else
         dense_pull<ST>(src, a, sm, f);

@@ -55,14 +55,14 @@ void dense_segment_flags(const std::vector<uint8_t> &type, int nx, int ny, int p
         }
 }
 
-Tiles tiles16(const uint8_t *mask, int nx, int ny)
+Tiles tiles16(const uint8_t *mask, int nx, int ny, bool keep_all)
 {
     Tiles t;
     const int tx_n = nx / 16, ty_n = ny / 16;
     t.index_of.assign((size_t)tx_n * ty_n, -1);
     for (int ty = 0; ty < ty_n; ++ty)
         for (int tx = 0; tx < tx_n; ++tx) {
-            bool any = false;
+            bool any = keep_all;
             for (int ly = 0; ly < 16 && !any; ++ly)
                 for (int lx = 0; lx < 16; ++lx)
                     if (mask[(size_t)(ty * 16 + ly) * nx + tx * 16 + lx] == 0) {

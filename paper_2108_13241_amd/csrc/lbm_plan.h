@@ -36,8 +36,8 @@ struct Tiles {
     std::vector<int32_t> nbr;  // [n_tiles][9]; entry d: tile at (tx, ty) + c_d, -1 if empty
     std::vector<int32_t> index_of;  // [tiles_y][tiles_x] -> kept index or -1
 };
-// nx, ny must be multiples of 16.
-Tiles tiles16(const uint8_t *mask, int nx, int ny);
+// nx, ny must be multiples of 16.  keep_all: keep empty (all-solid) tiles too.
+Tiles tiles16(const uint8_t *mask, int nx, int ny, bool keep_all = false);
 // Tile-layout type codes / nmask / node lists ([n_tiles][256]).
 void tiled_types(const uint8_t *mask, int nx, int ny, const Tiles &t, std::vector<uint8_t> &type,
                  std::vector<uint8_t> &nmask);

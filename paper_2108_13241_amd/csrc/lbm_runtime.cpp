@@ -54,6 +54,7 @@ struct lbm_ctx {
     float *alpha_buf = nullptr;
     double *bc_buf = nullptr;  // open-boundary values [node][2]
     int64_t n_open = 0;        // open-boundary nodes currently set
+    int abi_layout = 0;        // layout as requested (TILED16_ALL runs as TILED16)
     lbm::plan::Tiles tiles;
     lbm::plan::Fluid fluid;
     int64_t n_fluid = 0;
@@ -252,14 +253,20 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
         return fail_tl(LBM_ERR_INVALID, "force must be finite");
     if ((int)dtype < 0 || (int)dtype > 3)
         return fail_tl(LBM_ERR_INVALID, "unknown dtype");
-    if ((int)layout < 0 || (int)layout > 3)
+    if ((int)layout < 0 || (int)layout > 4)
         return fail_tl(LBM_ERR_INVALID, "unknown layout");
+    // the "tile" layout runs the TILED16 path over a tile list that keeps every tile
+    const lbm_layout abi_layout = layout;
+    const bool all_tiles = layout == LBM_TILED16_ALL;
+    if (all_tiles)
+        layout = LBM_TILED16;
     const size_t nn = (size_t)nx * ny;
     for (size_t k = 0; k < nn; ++k)
         if (node_type[k] > 1)
             return fail_tl(LBM_ERR_INVALID, "node_type values must be 0 (fluid) or 1 (solid)");
     if (layout == LBM_TILED16 && (nx % 16 != 0 || ny % 16 != 0))
-        return fail_tl(LBM_ERR_UNSUPPORTED, "TILED16 needs nx and ny to be multiples of 16");
+        return fail_tl(LBM_ERR_UNSUPPORTED,
+                       "TILED16 / TILED16_ALL need nx and ny to be multiples of 16");
     const int64_t pitch = round_up(nx, 64);
     if ((int64_t)9 * ny * pitch >= (int64_t(1) << 32))
         return fail_tl(LBM_ERR_UNSUPPORTED, "mesh too large for 32-bit lattice offsets");
@@ -278,6 +285,7 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
     lbm::DevState &s = c->s;
     s.dtype = dtype;
     s.layout = layout;
+    c->abi_layout = abi_layout;
     s.nx = nx;
     s.ny = ny;
     s.pitch = (int)pitch;
@@ -316,7 +324,7 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
             return fail_create(rc, "cannot upload the segment flags");
         s.seg_interior = (const uint32_t *)p;
     } else if (layout == LBM_TILED16) {
-        c->tiles = lbm::plan::tiles16(node_type, nx, ny);
+        c->tiles = lbm::plan::tiles16(node_type, nx, ny, all_tiles);
         lbm::plan::tiled_types(node_type, nx, ny, c->tiles, type, nmask);
         s.n_tiles = c->tiles.n_tiles;
         s.plane = (size_t)std::max<int64_t>(s.n_tiles, 1) * lbm::kTileNodes;
@@ -1002,7 +1010,7 @@ int lbm_get_info(const lbm_ctx *c, lbm_info_t *info)
     info->nx = s.nx;
     info->ny = s.ny;
     info->dtype = s.dtype;
-    info->layout = s.layout;
+    info->layout = c->abi_layout;
     info->n_nodes = (int64_t)s.nx * s.ny;
     info->n_fluid = c->n_fluid;
     info->n_tiles = s.n_tiles;

@@ -35,3 +35,14 @@ def bandwidth_gbps(glups_value: float, node_bytes: float) -> float:
 def utilisation(gbps: float, peak_gbps: float) -> float:
     """U_B = P_B / B_peak."""
     return gbps / peak_gbps
+
+
+def porosity(n_non_solid: int, n_all: int) -> float:
+    """phi of Eq. 8: the fraction of non-solid nodes."""
+    return n_non_solid / n_all
+
+
+def sparse_efficiency(p_sparse: float, p_dense: float) -> float:
+    """eta_P of Eq. 9: performance on a sparse geometry over performance on the dense one,
+    same data layout and geometry size (performance counts non-solid nodes only)."""
+    return p_sparse / p_dense

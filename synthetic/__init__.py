@@ -219,3 +219,110 @@ def lid_cavity(n: int, u_lid: float = 0.1, ny: int | None = None):
     bc[ny - 1, 1:n - 1] = BC_VELOCITY[(0, -1)]
     value[0, ny - 1, 1:n - 1] = u_lid
     return mask, bc, value
+
+
+# ---------------------------------------------------------------- sparse study --
+# The paper's sparse geometries (Sec. 4.3, Fig. 7 and 8): square n x n domains filled with
+# solid circles, bounce-back walls at y = 0 and y = n - 1, constant-pressure inlet (left,
+# rho = 1.016) and outlet (right, rho = 1.0).  Porosity phi (Eq. 8) counts every non-solid
+# node over all nodes.
+
+def _paint_circle(m, cx, cy, r):
+    """Mark the nodes with (x - cx)^2 + (y - cy)^2 <= r^2 solid (clipped to the domain, no
+    wrap); returns the number of nodes that became solid."""
+    ny, nx = m.shape
+    y0, y1 = max(int(math.floor(cy - r)), 0), min(int(math.ceil(cy + r)), ny - 1)
+    x0, x1 = max(int(math.floor(cx - r)), 0), min(int(math.ceil(cx + r)), nx - 1)
+    if y0 > y1 or x0 > x1:
+        return 0
+    ys = np.arange(y0, y1 + 1, dtype=np.float64)[:, None]
+    xs = np.arange(x0, x1 + 1, dtype=np.float64)[None, :]
+    inside = (xs - cx) ** 2 + (ys - cy) ** 2 <= r * r
+    block = m[y0:y1 + 1, x0:x1 + 1]
+    new = int((inside & (block == 0)).sum())
+    block[inside] = 1
+    return new
+
+
+def _open_ends(m, rho_in=1.016, rho_out=1.0):
+    """Pressure inlet on the fluid nodes of column 0, outlet on those of column n - 1."""
+    ny, nx = m.shape
+    bc = np.zeros((ny, nx), dtype=np.uint8)
+    value = np.zeros((2, ny, nx), dtype=np.float64)
+    rows = np.arange(1, ny - 1)
+    inl = rows[m[rows, 0] == 0]
+    out = rows[m[rows, nx - 1] == 0]
+    bc[inl, 0] = BC_PRESSURE[(1, 0)]
+    value[0, inl, 0] = rho_in
+    bc[out, nx - 1] = BC_PRESSURE[(-1, 0)]
+    value[0, out, nx - 1] = rho_out
+    return bc, value
+
+
+def _walls(n):
+    m = np.zeros((n, n), dtype=np.uint8)
+    m[0, :] = 1
+    m[n - 1, :] = 1
+    return m
+
+
+def circle_array(n: int, phi: float, k: int = 8):
+    """Regular arrangement (Sec. 4.3): a k x k array of equal solid circles centred at
+    ((i + 1/2) n / k, (j + 1/2) n / k); the radius is the largest (to 1e-6 node) whose
+    porosity is still >= phi.  phi < 0.3 is refused: the circles then overlap and close
+    the domain walls (why the paper stops there).  Returns (mask, bc, value, info)."""
+    if phi < 0.3 or phi > 1.0:
+        raise ValueError("the regular circle array is defined for 0.3 <= phi <= 1")
+    centres = [((i + 0.5) * n / k, (j + 0.5) * n / k) for j in range(k) for i in range(k)]
+
+    def build(r):
+        m = _walls(n)
+        for cx, cy in centres:
+            _paint_circle(m, cx, cy, r)
+        return m
+
+    def porosity(m):
+        return float((m == 0).sum()) / (n * n)
+
+    lo, hi = 0.0, n / (2.0 * k) * math.sqrt(2.0) + 1.0
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        if porosity(build(mid)) >= phi:
+            lo = mid
+        else:
+            hi = mid
+    m = build(lo)
+    bc, value = _open_ends(m)
+    return m, bc, value, {"kind": "regular", "phi_target": phi, "phi_achieved": porosity(m),
+                          "radius": lo, "circles": k * k}
+
+
+def random_circles(n: int, phi: float, seed: int | None = None, rmin: int = 8, rmax: int = 256):
+    """Random arrangement (Sec. 4.3): circles with integer radii uniform in [rmin, rmax] and
+    centres uniform over the domain (overlap allowed, clipped at the domain edges) are added
+    until the porosity falls to phi or below.  Seeded by 2000 + round(100 phi) by default.
+    Returns (mask, bc, value, info)."""
+    if seed is None:
+        seed = 2000 + int(round(100 * phi))
+    rng = np.random.default_rng(seed)
+    m = _walls(n)
+    solid = int(m.sum())
+    target = int(math.ceil((1.0 - phi) * n * n))
+    count = 0
+    while solid < target:
+        r = int(rng.integers(rmin, rmax + 1))
+        cx, cy = int(rng.integers(0, n)), int(rng.integers(0, n))
+        solid += _paint_circle(m, cx, cy, r)
+        count += 1
+    bc, value = _open_ends(m)
+    return m, bc, value, {"kind": "random", "phi_target": phi,
+                          "phi_achieved": float((m == 0).sum()) / (n * n), "circles": count,
+                          "seed": seed}
+
+
+def open_box(n: int):
+    """The dense counterpart of the sparse geometries: walls, pressure inlet and outlet, no
+    obstacles (the reference geometry of the sparse efficiency, Eq. 9)."""
+    m = _walls(n)
+    bc, value = _open_ends(m)
+    return m, bc, value, {"kind": "dense", "phi_achieved": float((m == 0).sum()) / (n * n)}

@@ -52,7 +52,8 @@ def _create(lib, nx, ny, mask, tau=0.8, force=(0.0, 0.0), dtype=0, layout=0):
 
 @pytest.mark.parametrize("kw,status", [
     ({"tau": 0.5}, -1), ({"tau": float("nan")}, -1), ({"force": (float("inf"), 0.0)}, -1),
-    ({"dtype": 7}, -1), ({"layout": 9}, -1), ({"layout": 2}, -4)])
+    ({"dtype": 7}, -1), ({"layout": 9}, -1), ({"layout": 5}, -1), ({"layout": 2}, -4),
+    ({"layout": 4}, -4)])
 def test_create_validation(lib, kw, status):
     m = np.zeros((10, 20), np.uint8)
     st, ctx = _create(lib, 20, 10, m, **kw)

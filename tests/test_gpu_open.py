@@ -19,7 +19,7 @@ from gpu_util import TOL, announce, fp_error_w as fp_error
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = ["dense_ab", "dense_aa", "tiled16", "indirect"]
+LAYOUTS = ["dense_ab", "dense_aa", "tiled16", "indirect", "tiled16_all"]
 
 
 @pytest.fixture(scope="module")

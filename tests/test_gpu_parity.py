@@ -12,7 +12,7 @@ from gpu_util import TOL, announce, fp_error
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = ["dense_ab", "dense_aa", "tiled16", "indirect"]
+LAYOUTS = ["dense_ab", "dense_aa", "tiled16", "indirect", "tiled16_all"]
 
 
 @pytest.fixture(scope="module")
@@ -127,7 +127,7 @@ def test_exact_rational_4x4(lbm, layout, case):
     ex = exact.run(mask, rho, ux, uy, Fr(4, 5), 3, g=g, alpha=alpha)
     tofl = lambda a: np.array([[float(v) for v in row] for row in a])
     m = np.array(mask, dtype=np.uint8)
-    rep = 4 if layout == "tiled16" else 1
+    rep = 4 if layout.startswith("tiled16") else 1
     M = np.tile(m, (rep, rep))
     F = [np.tile(tofl(a), (rep, rep)) for a in (rho, ux, uy)]
     got = run_gpu(lbm, M, 0.8, 3, "f64", layout, g=(float(g[0]), float(g[1])), fields=F)
@@ -176,7 +176,7 @@ def test_layouts_bitwise_equal(lbm, dtype):
     for steps in (40, 41):
         ref = run_gpu(lbm, m, 0.75, steps, dtype, "dense_ab", g=(1e-5, 0.0), alpha=alpha,
                       fields=fields)
-        for layout in ("dense_aa", "tiled16", "indirect"):
+        for layout in ("dense_aa", "tiled16", "indirect", "tiled16_all"):
             got = run_gpu(lbm, m, 0.75, steps, dtype, layout, g=(1e-5, 0.0), alpha=alpha,
                           fields=fields)
             assert np.array_equal(got, ref), (layout, steps)
@@ -255,7 +255,7 @@ def test_objective_matches_oracle(lbm, oracle_mod):
     lat.close()
 
 
-@pytest.mark.parametrize("layout", ["dense_ab", "dense_aa", "tiled16", "indirect"])
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_graph_replay_bitwise(lbm, layout):
     """Steps replayed through captured HIP graphs give bitwise the same populations as steps
     launched one by one, across odd step counts, a force change and a drag change mid-run."""

@@ -45,7 +45,7 @@ DRIVER = textwrap.dedent(r"""
                 for (int x = nx; x < pitch; ++x)
                     if (type[(size_t)y * pitch + x] != 1) return 3;
         } else {
-            lbm::plan::Tiles t = lbm::plan::tiles16(mask.data(), nx, ny);
+            lbm::plan::Tiles t = lbm::plan::tiles16(mask.data(), nx, ny, tiled == 3);
             lbm::plan::tiled_types(mask.data(), nx, ny, t, type, nmask);
             for (long k = 0; k < t.n_tiles; ++k)
                 for (int l = 0; l < 256; ++l)
@@ -108,6 +108,19 @@ def test_tiled_types(planner):
     m[:, 16:32] = 1
     rows = _run(planner, m, 0, True)
     for x, y, t, b in rows:
+        assert (t, b) == _expected(m, x, y), (x, y)
+
+
+def test_tiled_types_keep_all(planner):
+    """The "tile" layout keeps every tile, the all-solid ones (solid codes throughout) too."""
+    m = synthetic.random_mask(48, 32, seed=4, solid_fraction=0.3)
+    m[:, 16:32] = 1
+    compact = _run(planner, m, 0, True)
+    full = _run(planner, m, 0, 3)
+    assert len(compact) == 4 * 256 and len(full) == 6 * 256
+    seen = {(x, y) for x, y, _, _ in full}
+    assert len(seen) == 48 * 32
+    for x, y, t, b in full:
         assert (t, b) == _expected(m, x, y), (x, y)
 
 
