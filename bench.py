@@ -191,6 +191,60 @@ def measure_small_channel(lbm, steps=2000):
     return out
 
 
+def measure_setup(lbm, mask, dtype="f64"):
+    """Geometry preprocessing on the host plus device set-up (lbm_create: planning, uploads,
+    allocation, equilibrium initial state) and a re-initialisation alone, per layout."""
+    import torch
+    out = []
+    for layout in ("dense_ab", "dense_aa", "tiled16", "tiled16_all", "indirect"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat = lbm.Lattice(mask, 0.6, dtype=dtype, layout=layout)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.init_equilibrium(None, None, None)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out.append({"layout": layout, "dtype": dtype, "create_s": t1 - t0,
+                    "init_equilibrium_s": t2 - t1, "n_fluid": lat.info()["n_fluid"]})
+        lat.close()
+    return out
+
+
+def measure_views(lbm, n, fields, reps=20):
+    """Macroscopic fields (Eq. 2; device FP64 rho, u_x, u_y) and the FP64 mass reduction on
+    the 4096^2 FP64 dense lattice, against their algorithmic bytes: every population read
+    once (+ the node type), 24 B written per node for the fields."""
+    import torch
+    import synthetic
+    m = synthetic.all_fluid(n, n)
+    lat = lbm.Lattice(m, 0.6, dtype="f64", layout="dense_ab")
+    lat.init_equilibrium(*fields)
+    out = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(3)]
+    lat.macroscopic_device(*out)
+    lat.mass()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lat.macroscopic_device(*out)
+    e1.record()
+    torch.cuda.synchronize()
+    macro_s = e0.elapsed_time(e1) / 1e3 / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lat.mass()  # includes the device-to-host copy of the result and a stream sync
+    mass_s = (time.perf_counter() - t0) / reps
+    lat.close()
+    nodes = n * n
+    macro_b = nodes * (9 * 8 + 1 + 24)
+    mass_b = nodes * (9 * 8 + 1)
+    return {"workload": f"views taylor-green {n}^2 f64 dense_ab",
+            "macroscopic_ms": macro_s * 1e3, "macroscopic_gbps": macro_b / macro_s / 1e9,
+            "macroscopic_frac_of_peak": macro_b / macro_s / 1e9 / HBM_PEAK_GBPS,
+            "mass_ms_with_sync": mass_s * 1e3, "mass_gbps": mass_b / mass_s / 1e9}
+
+
 def measure_sparse_geometry(lbm, geom, dtype, layout, steps, warmup):
     """One of the paper's sparse geometries (Sec. 4.3): pressure inlet / outlet, walls,
     nu = 0.5 (tau = 2); GLUPS counting non-solid nodes only (Eq. 8)."""
@@ -401,6 +455,15 @@ def main():
                     log(f"[bench]   phi={phi} {dtype} {layout}: "
                         f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid")
                     variants.append(r)
+        mask_p, _ = synthetic.porous_discs(n, 0.5)
+        for r in measure_setup(lbm, mask_p):
+            log(f"[bench]   create {r['layout']} porous {n}^2: {r['create_s']:.2f} s, "
+                f"re-init {r['init_equilibrium_s'] * 1e3:.1f} ms")
+            variants.append({"workload": f"setup porous discs {n}^2 phi=0.5", **r})
+        v = measure_views(lbm, n, fields)
+        log(f"[bench]   macroscopic {v['macroscopic_ms']:.3f} ms ({v['macroscopic_frac_of_peak']:.3f}), "
+            f"mass {v['mass_ms_with_sync']:.3f} ms")
+        variants.append(v)
         a = measure_adjoint(lbm)
         log(f"[bench]   adjoint/forward = {a['adjoint_over_forward']:.2f} per step; "
             f"checkpointed backward/forward = {a['checkpointed_backward_over_forward']:.2f}")

@@ -942,13 +942,12 @@ int lbm_run_checkpointed(lbm_ctx *c, int64_t T, int64_t K, void *ckpt_dev)
         return fail(c, LBM_ERR_INVALID, "need T >= 0, K >= 1 and a checkpoint buffer");
     size_t sb = 0;
     lbm_state_bytes(c, &sb);
-    for (int64_t s = 0; s < T; ++s) {
-        if (s % K == 0) {
-            int rc = lbm_save_state(c, (char *)ckpt_dev + (size_t)(s / K) * sb);
-            if (rc)
-                return rc;
-        }
-        int rc = lbm_step(c, 1);
+    // one checkpoint, then the segment's steps in one call (graph replay applies)
+    for (int64_t s = 0; s < T; s += K) {
+        int rc = lbm_save_state(c, (char *)ckpt_dev + (size_t)(s / K) * sb);
+        if (rc)
+            return rc;
+        rc = lbm_step(c, std::min<int64_t>(K, T - s));
         if (rc)
             return rc;
     }
