@@ -362,6 +362,46 @@ def measure_adjoint(lbm, steps=200, T=2000):
             "checkpointed_backward_over_forward": back_ms / run_ms}
 
 
+def measure_adjoint_large(lbm, n=4096, steps=50):
+    """Adjoint kernel against the forward step at a size where both are HBM-bound: n x n
+    channel with a drag field, FP32 state.  Algorithmic bytes per fluid node: forward 77
+    (18 x 4 + type + alpha), adjoint 129 (state 36 + lambda in 36 + lambda out 36 + alpha 4 +
+    type 1 + FP64 gradient read-modify-write 16)."""
+    import torch
+
+    import synthetic
+    m = synthetic.channel_mask(n, n)
+    alpha = synthetic.brinkman_alpha(n, n, seed=7, sigma=8.0).astype(np.float32)
+    lat = lbm.Lattice(m, 0.8, force=(1e-5, 0.0), dtype="f32", layout="dense_ab")
+    lat.set_porosity(alpha)
+    fwd_s, fwd_ms = time_steps(lat, steps, 10)
+    state = torch.empty(lat.state_bytes(), dtype=torch.uint8, device="cuda")
+    lat.save_state(state)
+    ab, _ = lat.adjoint_bytes()
+    mu = [torch.zeros(ab, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    ga = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    gg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lat.adjoint_seed_outlet_ux(n - 1, 1.0, mu[0], ga, gg)
+    for k in range(5):
+        lat.adjoint_step(state, mu[k % 2], mu[1 - k % 2], ga, gg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        lat.adjoint_step(state, mu[k % 2], mu[1 - k % 2], ga, gg)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / steps
+    nf = lat.info()["n_fluid"]
+    lat.close()
+    del state, mu, ga
+    return {"workload": f"adjoint channel {n}x{n} with drag field, f32",
+            "forward_ms_per_step": fwd_ms, "adjoint_ms_per_step": adj_ms,
+            "adjoint_over_forward": adj_ms / fwd_ms,
+            "forward_frac_of_peak": nf * 77 / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "adjoint_frac_of_peak": nf * 129 / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+
+
 def cpu_baseline(n, fields, budget_s=12.0):
     """The FP64 oracle (as it is) on the host cores, a bounded number of steps."""
     import oracle
@@ -464,6 +504,11 @@ def main():
         log(f"[bench]   macroscopic {v['macroscopic_ms']:.3f} ms ({v['macroscopic_frac_of_peak']:.3f}), "
             f"mass {v['mass_ms_with_sync']:.3f} ms")
         variants.append(v)
+        al = measure_adjoint_large(lbm, n)
+        log(f"[bench]   adjoint {n}^2: {al['adjoint_ms_per_step'] * 1e3:.1f} us "
+            f"({al['adjoint_frac_of_peak']:.3f}) vs forward {al['forward_ms_per_step'] * 1e3:.1f} us "
+            f"({al['forward_frac_of_peak']:.3f}): {al['adjoint_over_forward']:.2f}x")
+        variants.append(al)
         a = measure_adjoint(lbm)
         log(f"[bench]   adjoint/forward = {a['adjoint_over_forward']:.2f} per step; "
             f"checkpointed backward/forward = {a['checkpointed_backward_over_forward']:.2f}")

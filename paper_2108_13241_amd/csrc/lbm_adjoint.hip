@@ -22,7 +22,13 @@ constexpr int kBlock = 256;
 
 // Reverse of collide<R, DRAG, SHIFT>: given the pre-collision f and the adjoint nu of
 // the post-collision populations, return fb = (dC/df)^T nu, ab = nu . dC/dalpha
-// and (gbx, gby) = nu . dC/dg.
+// and (gbx, gby) = nu . dC/dg.  Opposite directions i, j = opp(i) are taken as a
+// pair, as in the forward collision: c_j = -c_i flips the sign of c.u and c.F,
+// so with e = omega w nu and s = (1 - omega/2) w nu the pair contributes
+//   to rho:    (e_i + e_j)(1 + 4.5 (c.u)^2 - 1.5 u.u) + 3 (c.u)(e_i - e_j),
+//   to u:      c_i [rho (3 (e_i - e_j) + 9 (c.u)(e_i + e_j)) + 9 (c.F)(s_i + s_j)],
+//   to F:      c_i [3 (s_i - s_j) + 9 (c.u)(s_i + s_j)],
+// and -rho e, -3 s to the adjoints of 1.5 u.u and u.F for every direction.
 template <class R, bool DRAG, bool SHIFT>
 __device__ __forceinline__ void collide_vjp(const R (&f)[9], const R (&nu)[9], const R omega,
                                             const R gx, const R gy, const R alpha, R (&fb)[9],
@@ -34,12 +40,12 @@ __device__ __forceinline__ void collide_vjp(const R (&f)[9], const R (&nu)[9], c
     const R rho = SHIFT ? R(1) + sum : sum;
     const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R inv_rho = R(1) / rho;
+    const R inv_rho = recip(rho);
     const R ux0 = mx * inv_rho + R(0.5) * gx;
     const R uy0 = my * inv_rho + R(0.5) * gy;
     R ux = ux0, uy = uy0, invD = R(1);
     if constexpr (DRAG) {
-        invD = R(1) / (R(1) + R(0.5) * alpha);
+        invD = recip(R(1) + R(0.5) * alpha);
         ux = ux0 * invD;
         uy = uy0 * invD;
     }
@@ -48,25 +54,39 @@ __device__ __forceinline__ void collide_vjp(const R (&f)[9], const R (&nu)[9], c
     const R usq = R(1.5) * (ux * ux + uy * uy);
     const R guo = R(1) - R(0.5) * omega;
 
-    // reverse sweep
-    R rhob = 0, ubx = 0, uby = 0, Fbx = 0, Fby = 0, usqb = 0, uFb = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const R cx = R(kCx[i]), cy = R(kCy[i]), w = R(kW[i]);
-        const R cu = cx * ux + cy * uy;
-        const R cF = cx * Fx + cy * Fy;
-        const R e = omega * nu[i] * w;  // (adjoint of f^eq_i) * w_i
-        const R sb = guo * nu[i] * w;   // (adjoint of S_i) * w_i
-        rhob += e * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
-        usqb -= e * rho;
-        const R cub = e * rho * (R(3) + R(9) * cu) + sb * R(9) * cF;
-        const R cFb = sb * (R(3) + R(9) * cu);
-        uFb -= R(3) * sb;
-        ubx += cub * cx;
-        uby += cub * cy;
-        Fbx += cFb * cx;
-        Fby += cFb * cy;
+    // reverse sweep: rest population, then the four opposite pairs
+    R rhob, esum, ssum, ubx = R(0), uby = R(0), Fbx = R(0), Fby = R(0);
+    {
+        const R t = nu[0] * R(kW[0]);
+        const R e = omega * t;
+        rhob = e * (R(1) - usq);
+        esum = e;
+        ssum = guo * t;
     }
+    constexpr int P[4] = {1, 2, 5, 6};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = P[k], j = kOpp[i];
+        const R w = R(kW[i]);
+        const R tp = (nu[i] + nu[j]) * w, tm = (nu[i] - nu[j]) * w;
+        const R ep = omega * tp, em = omega * tm, sp = guo * tp, sm = guo * tm;
+        const R cu = pair_dot(k, ux, uy), cF = pair_dot(k, Fx, Fy);
+        rhob += ep * (R(1) + R(4.5) * cu * cu - usq) + R(3) * cu * em;
+        esum += ep;
+        ssum += sp;
+        const R du = rho * (R(3) * em + R(9) * cu * ep) + R(9) * cF * sp;
+        const R dF = R(3) * sm + R(9) * cu * sp;
+        // along c_i = (1,0), (0,1), (1,1), (-1,1)
+        if (k != 1) {
+            ubx += k == 3 ? -du : du;
+            Fbx += k == 3 ? -dF : dF;
+        }
+        if (k != 0) {
+            uby += du;
+            Fby += dF;
+        }
+    }
+    const R usqb = -rho * esum, uFb = R(-3) * ssum;
     // uF = u . F and usq = 1.5 u . u
     ubx += uFb * Fx + R(3) * usqb * ux;
     uby += uFb * Fy + R(3) * usqb * uy;
@@ -74,8 +94,10 @@ __device__ __forceinline__ void collide_vjp(const R (&f)[9], const R (&nu)[9], c
     Fby += uFb * uy;
     // F = rho (g - alpha u)
     rhob += Fbx * (gx - a * ux) + Fby * (gy - a * uy);
-    ubx -= rho * a * Fbx;
-    uby -= rho * a * Fby;
+    if constexpr (DRAG) {
+        ubx -= rho * a * Fbx;
+        uby -= rho * a * Fby;
+    }
     gbx = rho * Fbx;
     gby = rho * Fby;
     ab = -rho * (Fbx * ux + Fby * uy);
@@ -94,9 +116,30 @@ __device__ __forceinline__ void collide_vjp(const R (&f)[9], const R (&nu)[9], c
     gby += R(0.5) * u0by;
     rhob -= inv_rhob * inv_rho * inv_rho;
     // rho = sum f, m = sum c f; plus the direct (1 - omega) f_i term
+    const R keep = R(1) - omega;
 #pragma unroll
-    for (int j = 0; j < 9; ++j)
-        fb[j] = (R(1) - omega) * nu[j] + rhob + R(kCx[j]) * mbx + R(kCy[j]) * mby;
+    for (int j = 0; j < 9; ++j) {
+        R acc = keep * nu[j] + rhob;
+        if (kCx[j] > 0)
+            acc += mbx;
+        else if (kCx[j] < 0)
+            acc -= mbx;
+        if (kCy[j] > 0)
+            acc += mby;
+        else if (kCy[j] < 0)
+            acc -= mby;
+        fb[j] = acc;
+    }
+}
+
+// Sum of two values over one wavefront (valid in lane 0); no barrier.
+__device__ __forceinline__ void wave_sum2(double &a, double &b)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
 }
 
 __device__ __forceinline__ void block_sum2(double &a, double &b)
@@ -128,55 +171,73 @@ template <class ST, bool DRAG>
 __global__ __launch_bounds__(kBlock) void k_adjoint_step(
     const typename ST::mem *__restrict__ state, const typename ST::real *__restrict__ mu_in,
     typename ST::real *__restrict__ mu_out, const uint8_t *__restrict__ type,
-    const uint8_t *__restrict__ nmask, const float *__restrict__ alpha,
-    double *__restrict__ grad_alpha, double *__restrict__ partials, int accumulate, int nx, int ny,
-    int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
-    typename ST::real gy)
+    const uint8_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior,
+    const float *__restrict__ alpha, double *__restrict__ grad_alpha,
+    double *__restrict__ partials, int accumulate, int nx, int ny, int pitch, uint32_t bpr,
+    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy)
 {
     using R = typename ST::real;
+    using M = typename ST::mem;
     const uint32_t L = xcd_remap(blockIdx.x, nblocks);
     const int y = (int)(L / bpr);
     const int x = (int)(L - (uint32_t)y * bpr) * kBlock + (int)threadIdx.x;
     double gxs = 0.0, gys = 0.0;
     if (x < nx) {
         const uint32_t own = (uint32_t)y * pitch + x;
-        const uint8_t t = type[own];
-        if (t != kSolid) {
-            const unsigned sm = solid_bits(t, nmask, own);
-            uint32_t nb[9];
-            dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
+        // all-interior row segments read neither the node type nor the neighbour bits
+        unsigned sm = 0;
+        bool fluid = true;
+        if (!seg_interior[L]) {
+            const uint8_t t = type[own];
+            fluid = t != kSolid;
+            sm = solid_bits(t, nmask, own);
+        }
+        if (fluid) {
+            const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
+            M *sp = const_cast<M *>(state);
+            R *mp = const_cast<R *>(mu_in);
             R f[9], nu[9];
+            if (sm == 0) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                // forward pull: f_i(x) = s_i(x - c_i) or s_opp(i)(x)
-                const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
-                                                    : (uint32_t)i * kChunk + nb[i];
-                f[i] = ST::ld(state[o], i);
-                // reverse pull: x + c_i is node x - c_opp(i)
-                const uint32_t q = ((sm >> kOpp[i]) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
-                                                          : (uint32_t)i * kChunk + nb[kOpp[i]];
-                nu[i] = mu_in[q];
+                for (int i = 0; i < 9; ++i) {
+                    // forward pull f_i(x) = s_i(x - c_i); reverse pull nu_i = mu_i(x + c_i)
+                    f[i] = ST::ld(dense_at(sp, a, i, 1 - kCy[i], 1 - kCx[i]), i);
+                    nu[i] = dense_at(mp, a, i, 1 + kCy[i], 1 + kCx[i]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    // x - c_i solid: bounce-back slot s_opp(i)(x); x + c_i is node
+                    // x - c_opp(i), solid: the adjoint of that bounce-back, mu_opp(i)(x)
+                    f[i] = ST::ld(((sm >> i) & 1u) ? dense_at(sp, a, kOpp[i], 1, 1)
+                                                   : dense_at(sp, a, i, 1 - kCy[i], 1 - kCx[i]),
+                                  i);
+                    nu[i] = ((sm >> kOpp[i]) & 1u) ? dense_at(mp, a, kOpp[i], 1, 1)
+                                                   : dense_at(mp, a, i, 1 + kCy[i], 1 + kCx[i]);
+                }
             }
             const R al = DRAG ? (R)alpha[own] : R(0);
             R fb[9], ab, gbx, gby;
             collide_vjp<R, DRAG, ST::kShift>(f, nu, omega, gx, gy, al, fb, ab, gbx, gby);
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                store_nt(&mu_out[(uint32_t)i * kChunk + nb[0]], fb[i]);
+                store_nt(&dense_at(mu_out, a, i, 1, 1), fb[i]);
             if (DRAG)
                 grad_alpha[(size_t)y * nx + x] += (double)ab;
             gxs = (double)gbx;
             gys = (double)gby;
         }
     }
-    block_sum2(gxs, gys);
-    if (threadIdx.x == 0) {
+    // one dJ/dg partial pair per wavefront (no workgroup barrier)
+    wave_sum2(gxs, gys);
+    if ((threadIdx.x & 63u) == 0) {
+        const uint32_t p = 2u * (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
         if (accumulate) {
-            partials[2 * blockIdx.x] += gxs;
-            partials[2 * blockIdx.x + 1] += gys;
+            partials[p] += gxs;
+            partials[p + 1] += gys;
         } else {
-            partials[2 * blockIdx.x] = gxs;
-            partials[2 * blockIdx.x + 1] = gys;
+            partials[p] = gxs;
+            partials[p + 1] = gys;
         }
     }
 }
@@ -234,6 +295,27 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(
 }
 
 // grad_g += fixed-order sum of n partial pairs (one block).
+// Two-stage fixed-order sum of n interleaved (dJ/dg_x, dJ/dg_y) partial pairs:
+// block b of the first stage adds pairs [b * kSumPer, (b + 1) * kSumPer).
+constexpr uint32_t kSumPer = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_pairs_stage(const double *__restrict__ in, uint32_t n,
+                                                        double *__restrict__ out)
+{
+    const uint32_t lo = blockIdx.x * kSumPer;
+    const uint32_t hi = lo + kSumPer < n ? lo + kSumPer : n;
+    double a = 0.0, b = 0.0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        a += in[2 * i];
+        b += in[2 * i + 1];
+    }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = a;
+        out[2 * blockIdx.x + 1] = b;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_partials_into(const double *__restrict__ partials,
                                                           uint32_t n, double *grad_g)
 {
@@ -292,13 +374,13 @@ hipError_t step_typed(const DevState &s, const void *state, const void *mu_in, v
     if (s.alpha)
         k_adjoint_step<ST, true><<<nblocks, kBlock, 0, s.stream>>>(
             (const typename ST::mem *)state, (const R *)mu_in, (R *)mu_out, s.type, s.nmask,
-            s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
-            gy);
+            s.seg_interior, s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, bpr,
+            nblocks, om, gx, gy);
     else
         k_adjoint_step<ST, false><<<nblocks, kBlock, 0, s.stream>>>(
             (const typename ST::mem *)state, (const R *)mu_in, (R *)mu_out, s.type, s.nmask,
-            s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, bpr, nblocks, om, gx,
-            gy);
+            s.seg_interior, s.alpha, grad_alpha, partials, accumulate, s.nx, s.ny, s.pitch, bpr,
+            nblocks, om, gx, gy);
     return hipGetLastError();
 }
 
@@ -307,6 +389,14 @@ hipError_t step_typed(const DevState &s, const void *state, const void *mu_in, v
 int64_t adjoint_blocks(const DevState &s)
 {
     return (int64_t)((s.nx + kBlock - 1) / kBlock) * s.ny;
+}
+
+int64_t adjoint_step_partials(const DevState &s) { return adjoint_blocks(s) * (kBlock / 64); }
+
+int64_t adjoint_scratch_pairs(const DevState &s)
+{
+    const int64_t n = std::max(adjoint_step_partials(s), adjoint_seed_blocks(s));
+    return n + (n + kSumPer - 1) / kSumPer + 1;
 }
 
 int64_t adjoint_seed_blocks(const DevState &s) { return ((int64_t)s.ny * s.pitch + kBlock - 1) / kBlock; }
@@ -353,10 +443,16 @@ hipError_t launch_adjoint_convert(const DevState &s, void *mu, double *plain, in
     return hipGetLastError();
 }
 
-hipError_t launch_partials_into(const double *partials, int64_t n, double *grad_g,
+hipError_t launch_partials_into(double *partials, int64_t n, double *grad_g,
                                 hipStream_t stream)
 {
-    k_partials_into<<<1, kBlock, 0, stream>>>(partials, (uint32_t)n, grad_g);
+    if (n <= 0)
+        return hipSuccess;
+    // stage results go right after the n pairs (see adjoint_scratch_pairs)
+    const int64_t nst = (n + kSumPer - 1) / kSumPer;
+    double *stage = partials + 2 * n;
+    k_pairs_stage<<<(uint32_t)nst, kBlock, 0, stream>>>(partials, (uint32_t)n, stage);
+    k_partials_into<<<1, kBlock, 0, stream>>>(stage, (uint32_t)nst, grad_g);
     return hipGetLastError();
 }
 

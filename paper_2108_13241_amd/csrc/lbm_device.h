@@ -377,6 +377,43 @@ __device__ __forceinline__ void dense_bases(int x, int y, int nx, int ny, uint32
 
 // Streaming stores: the lattice written by a step is not read again until the
 // next step, so the stores bypass the caches' retention (nontemporal).
+// Dense addressing split into row and column parts: node (x, y) has base
+// offset row_off(y) + col_off(x).  A step workgroup is one row segment, so the
+// three row offsets (rows y-1, y, y+1) are uniform (scalar registers) and each
+// lane keeps three column offsets (columns x-1, x, x+1), which stay below 2^28
+// so that loads use a scalar base plus a 32-bit lane offset.
+struct DenseRC {
+    uint32_t r[3];  // rows y-1, y, y+1
+    uint32_t c[3];  // columns x-1, x, x+1
+};
+
+__device__ __forceinline__ uint32_t col_off(int x)
+{
+    return ((((uint32_t)x >> 6) * (9u * kChunk)) | ((uint32_t)x & 63u)) & 0x0FFFFFFFu;
+}
+
+__device__ __forceinline__ DenseRC dense_rc(int x, int y, int nx, int ny, uint32_t cpr)
+{
+    DenseRC a;
+    const uint32_t row = cpr * (9u * kChunk);
+    a.r[0] = (uint32_t)wrap_dec(y, ny) * row;
+    a.r[1] = (uint32_t)y * row;
+    a.r[2] = (uint32_t)wrap_inc(y, ny) * row;
+    a.c[0] = col_off(wrap_dec(x, nx));
+    a.c[1] = col_off(x);
+    a.c[2] = col_off(wrap_inc(x, nx));
+    return a;
+}
+
+// Element of population plane `i` at row slot `ri`, column slot `ci` of a
+// dense lattice: scalar part i * 64 + r[ri], lane part c[ci].
+template <class M>
+__device__ __forceinline__ M &dense_at(M *__restrict__ s, const DenseRC &a, int i, int ri, int ci)
+{
+    M *p = s + ((uint32_t)i * kChunk + a.r[ri]);
+    return p[a.c[ci]];
+}
+
 template <class T>
 __device__ __forceinline__ void store_nt(T *p, T v)
 {

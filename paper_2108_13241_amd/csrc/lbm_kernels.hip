@@ -156,43 +156,6 @@ __device__ __forceinline__ bool dense_node(uint32_t bpr, uint32_t nblocks, int n
     return x < nx;
 }
 
-// Dense addressing split into row and column parts: node (x, y) has base
-// offset row_off(y) + col_off(x).  A step workgroup is one row segment, so the
-// three row offsets (rows y-1, y, y+1) are uniform (scalar registers) and each
-// lane keeps three column offsets (columns x-1, x, x+1), which stay below 2^28
-// so that loads use a scalar base plus a 32-bit lane offset.
-struct DenseRC {
-    uint32_t r[3];  // rows y-1, y, y+1
-    uint32_t c[3];  // columns x-1, x, x+1
-};
-
-__device__ __forceinline__ uint32_t col_off(int x)
-{
-    return ((((uint32_t)x >> 6) * (9u * kChunk)) | ((uint32_t)x & 63u)) & 0x0FFFFFFFu;
-}
-
-__device__ __forceinline__ DenseRC dense_rc(int x, int y, int nx, int ny, uint32_t cpr)
-{
-    DenseRC a;
-    const uint32_t row = cpr * (9u * kChunk);
-    a.r[0] = (uint32_t)wrap_dec(y, ny) * row;
-    a.r[1] = (uint32_t)y * row;
-    a.r[2] = (uint32_t)wrap_inc(y, ny) * row;
-    a.c[0] = col_off(wrap_dec(x, nx));
-    a.c[1] = col_off(x);
-    a.c[2] = col_off(wrap_inc(x, nx));
-    return a;
-}
-
-// Element of population plane `i` at row slot `ri`, column slot `ci` of a
-// dense lattice: scalar part i * 64 + r[ri], lane part c[ci].
-template <class M>
-__device__ __forceinline__ M &dense_at(M *__restrict__ s, const DenseRC &a, int i, int ri, int ci)
-{
-    M *p = s + ((uint32_t)i * kChunk + a.r[ri]);
-    return p[a.c[ci]];
-}
-
 // Pull gather of the dense layout (same values as pull_gather with dense_bases):
 // the source of f_i is node x - c_i, i.e. row slot 1 - c_i.y, column slot 1 - c_i.x.
 template <class ST>
@@ -634,6 +597,24 @@ __global__ __launch_bounds__(kBlock) void k_visit(DevState s, const typename ST:
     }
 }
 
+// Fixed-order sums of block partials run in two stages: block b of the first
+// adds entries [b * kSumPer, (b + 1) * kSumPer) (many blocks, all in flight),
+// then one block adds the stage results; the order is fixed either way.
+constexpr uint32_t kSumPer = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_sum_stage(const double *__restrict__ in, uint32_t n,
+                                                      double *__restrict__ out)
+{
+    const uint32_t lo = blockIdx.x * kSumPer;
+    const uint32_t hi = lo + kSumPer < n ? lo + kSumPer : n;
+    double s = 0.0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock)
+        s += in[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = s;
+}
+
 // Fixed-order sum of the block partials (one block).
 __global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restrict__ partials,
                                                          uint32_t n, double *out)
@@ -837,14 +818,17 @@ template <class Op>
 hipError_t reduce(const DevState &s, int64_t t, int cur, const Op &op, double *out)
 {
     const int64_t nb = visit_blocks(s);
-    if (nb > s.red_capacity)
+    const int64_t nst = (nb + kSumPer - 1) / kSumPer;
+    if (nb + nst > s.red_capacity)
         return hipErrorInvalidValue;
     if (nb == 0)
         return launch_fill(out, 1, 0.0, s.stream);
     hipError_t e = visit(s, t, cur, op, s.red_partials);
     if (e != hipSuccess)
         return e;
-    k_sum_partials<<<1, kBlock, 0, s.stream>>>(s.red_partials, (uint32_t)nb, out);
+    double *stage = s.red_partials + nb;
+    k_sum_stage<<<(uint32_t)nst, kBlock, 0, s.stream>>>(s.red_partials, (uint32_t)nb, stage);
+    k_sum_partials<<<1, kBlock, 0, s.stream>>>(stage, (uint32_t)nst, out);
     return hipGetLastError();
 }
 
@@ -861,6 +845,12 @@ hipError_t scatter_typed(const DevState &s, int64_t t, int cur, const double *fc
 }
 
 }  // namespace
+
+int64_t reduction_capacity(const DevState &s)
+{
+    const int64_t nb = visit_blocks(s);
+    return nb + (nb + kSumPer - 1) / kSumPer + 1;
+}
 
 int64_t visit_blocks(const DevState &s)
 {

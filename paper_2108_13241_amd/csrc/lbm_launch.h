@@ -44,6 +44,9 @@ struct DevState {
 
 // Number of thread blocks the visit / reduction kernels use for this layout.
 int64_t visit_blocks(const DevState &s);
+// Doubles of reduction scratch (red_partials) a reduction needs: one partial per
+// visit block plus the first-stage sums.
+int64_t reduction_capacity(const DevState &s);
 
 // One time step from lattice `cur` (A-B layouts write lattice 1 - cur).  For
 // DENSE_AA, t is the number of steps already taken (its parity picks the
@@ -72,6 +75,10 @@ hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t s
 // Adjoint fields are dense [9][ny][pitch] in the compute type.  dJ/dg block
 // partials are pairs (x, y) per block.
 int64_t adjoint_blocks(const DevState &s);       // blocks of one adjoint step
+int64_t adjoint_step_partials(const DevState &s);  // dJ/dg partial pairs of one adjoint step
+// Pairs of adjoint scratch needed: the partials of a step or seed plus the
+// first-stage sums of launch_partials_into (written right after the partials).
+int64_t adjoint_scratch_pairs(const DevState &s);
 int64_t adjoint_seed_blocks(const DevState &s);  // blocks of the seed kernel
 // lambda_T of J = scale * sum of u_x over the fluid nodes of column x_col, read
 // from the stored lattice `state`; direct dJ/dalpha terms into grad_alpha (if
@@ -87,7 +94,7 @@ hipError_t launch_adjoint_step_raw(const DevState &s, const void *state, const v
 // Adjoint field <-> device FP64 planes [9][ny][nx] (to_plain = 1: field -> planes).
 hipError_t launch_adjoint_convert(const DevState &s, void *mu, double *plain, int to_plain);
 // grad_g[0..1] += fixed-order sum of n partial pairs.
-hipError_t launch_partials_into(const double *partials, int64_t n, double *grad_g,
+hipError_t launch_partials_into(double *partials, int64_t n, double *grad_g,
                                 hipStream_t stream);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
 

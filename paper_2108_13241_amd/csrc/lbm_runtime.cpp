@@ -370,7 +370,7 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
         if (!s.f[k])
             return fail_create(LBM_ERR_NOMEM, "cannot allocate the lattice");
     }
-    s.red_capacity = std::max<int64_t>(lbm::visit_blocks(s), 1);
+    s.red_capacity = lbm::reduction_capacity(s);
     s.red_partials = (double *)own_alloc(c, (size_t)s.red_capacity * sizeof(double));
     c->red_out = (double *)own_alloc(c, 8 * sizeof(double));
     if (!s.red_partials || !c->red_out)
@@ -803,7 +803,7 @@ static size_t adjoint_field_bytes(const lbm_ctx *c)
 // Per-block dJ/dg partial pairs for the seed and step kernels.
 static int ensure_adjoint_scratch(lbm_ctx *c)
 {
-    const int64_t need = 2 * std::max(lbm::adjoint_blocks(c->s), lbm::adjoint_seed_blocks(c->s));
+    const int64_t need = 2 * lbm::adjoint_scratch_pairs(c->s);
     if (c->adj_capacity >= need)
         return LBM_OK;
     c->adj_partials = (double *)own_alloc(c, (size_t)need * sizeof(double));
@@ -930,8 +930,8 @@ int lbm_adjoint_step(lbm_ctx *c, const void *state_t_dev, const void *mu_in_dev,
         return rc;
     LBM_HIP(c, lbm::launch_adjoint_step_raw(c->s, state_t_dev, mu_in_dev, mu_out_dev,
                                             grad_alpha_dev, c->adj_partials, 0));
-    LBM_HIP(c, lbm::launch_partials_into(c->adj_partials, lbm::adjoint_blocks(c->s), grad_g_dev,
-                                         c->s.stream));
+    LBM_HIP(c, lbm::launch_partials_into(c->adj_partials, lbm::adjoint_step_partials(c->s),
+                                         grad_g_dev, c->s.stream));
     return LBM_OK;
 }
 
@@ -972,7 +972,7 @@ int lbm_adjoint_checkpointed(lbm_ctx *c, int64_t T, int64_t K, const void *ckpt_
     lbm_state_bytes(c, &sb);
     if ((rc = seed_impl(c, state_lattice(c), x_col, dJ, c->mu_buf[0], grad_alpha_dev, grad_g_dev)))
         return rc;
-    const int64_t nb = lbm::adjoint_blocks(c->s);
+    const int64_t nb = lbm::adjoint_step_partials(c->s);
     LBM_HIP(c, lbm::launch_zero(c->adj_partials, 2 * nb, c->s.stream));
     int mu = 0;
     // Replay state: a copy of the device description whose lattices point into
