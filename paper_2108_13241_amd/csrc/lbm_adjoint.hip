@@ -448,6 +448,10 @@ hipError_t launch_partials_into(double *partials, int64_t n, double *grad_g,
 {
     if (n <= 0)
         return hipSuccess;
+    if (n <= 4 * (int64_t)kSumPer) {  // few partials: one block, one launch
+        k_partials_into<<<1, kBlock, 0, stream>>>(partials, (uint32_t)n, grad_g);
+        return hipGetLastError();
+    }
     // stage results go right after the n pairs (see adjoint_scratch_pairs)
     const int64_t nst = (n + kSumPer - 1) / kSumPer;
     double *stage = partials + 2 * n;

@@ -98,6 +98,38 @@ __device__ __forceinline__ unsigned indirect_offsets(const uint32_t *__restrict_
     return sm;
 }
 
+// ------------------------------------------------------------ lane moves --
+// DPP move with control word CTRL; a lane whose source lane is outside its row
+// or wavefront keeps `edge` (the DPP "old" operand with bound_ctrl off), so the
+// end lanes need no select or branch.  Source lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v, uint32_t edge)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v, float edge)
+{
+    return __builtin_bit_cast(float, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v),
+                                                   __builtin_bit_cast(uint32_t, edge)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v, double edge)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v), e = __builtin_bit_cast(uint64_t, edge);
+    const uint32_t lo = dpp_u32<CTRL>((uint32_t)b, (uint32_t)e);
+    const uint32_t hi = dpp_u32<CTRL>((uint32_t)(b >> 32), (uint32_t)(e >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+constexpr int kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+// Wave-wide shift by one lane of a full wavefront: UP, lane l receives lane
+// l - 1's value (lane 0 keeps edge), else lane l + 1's (lane 63 keeps edge).
+template <bool UP, class R>
+__device__ __forceinline__ R lane_shift(R v, R edge)
+{
+    return dpp_move<UP ? kWaveShr1 : kWaveShl1>(v, edge);
+}
+
 // ---------------------------------------------------------------- gathers --
 // Pull gather of Algorithm 1: f_i(x) = s_i(x - c_i), or, when x - c_i is solid
 // (bit i of sm), the halfway bounce-back value s_opp(i)(x).  ds = direction
@@ -178,30 +210,6 @@ __device__ __forceinline__ void dense_pull(const typename ST::mem *__restrict__ 
                       i);
 }
 
-// Wave-wide shift by one lane (DPP wave_shr:1 / wave_shl:1) of a full
-// wavefront.  UP: lane l receives lane l - 1's value, else lane l + 1's; the
-// end lane without a source (lane 0, resp. lane 63) keeps `edge` (the DPP
-// "old" operand with bound_ctrl off), so no select or branch is needed.
-template <bool UP>
-__device__ __forceinline__ uint32_t lane_shift_u32(uint32_t v, uint32_t edge)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, UP ? 0x138 : 0x130, 0xf, 0xf,
-                                                 false);
-}
-template <bool UP>
-__device__ __forceinline__ float lane_shift(float v, float edge)
-{
-    return __builtin_bit_cast(float, lane_shift_u32<UP>(__builtin_bit_cast(uint32_t, v),
-                                                        __builtin_bit_cast(uint32_t, edge)));
-}
-template <bool UP>
-__device__ __forceinline__ double lane_shift(double v, double edge)
-{
-    const uint64_t b = __builtin_bit_cast(uint64_t, v), e = __builtin_bit_cast(uint64_t, edge);
-    const uint32_t lo = lane_shift_u32<UP>((uint32_t)b, (uint32_t)e);
-    const uint32_t hi = lane_shift_u32<UP>((uint32_t)(b >> 32), (uint32_t)(e >> 32));
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
 
 // Pull gather of a full wavefront (64 consecutive columns x0 .. x0 + 63, all
 // interior fluid nodes) with aligned loads only: every lane loads column x of
@@ -826,6 +834,10 @@ hipError_t reduce(const DevState &s, int64_t t, int cur, const Op &op, double *o
     hipError_t e = visit(s, t, cur, op, s.red_partials);
     if (e != hipSuccess)
         return e;
+    if (nb <= 4 * (int64_t)kSumPer) {  // few partials: one block, one launch
+        k_sum_partials<<<1, kBlock, 0, s.stream>>>(s.red_partials, (uint32_t)nb, out);
+        return hipGetLastError();
+    }
     double *stage = s.red_partials + nb;
     k_sum_stage<<<(uint32_t)nst, kBlock, 0, s.stream>>>(s.red_partials, (uint32_t)nb, stage);
     k_sum_partials<<<1, kBlock, 0, s.stream>>>(stage, (uint32_t)nst, out);
