@@ -93,6 +93,11 @@ def lib():
                                     ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp,
                                     ctypes.c_long, ctypes.c_int]
         L.oracle_run_bc.restype = ctypes.c_int
+        L.oracle_collide_trt.argtypes = [_dp] + [ctypes.c_double] * 5 + [_dp]
+        L.oracle_run_trt.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p,
+                                     _dp, ctypes.c_long, ctypes.c_int]
+        L.oracle_run_trt.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -146,6 +151,19 @@ def collide(f, omega, alpha=0.0, g=(0.0, 0.0)):
     out = np.zeros(9)
     lib().oracle_collide(_d(f), alpha, g[0], g[1], omega, _d(out))
     return out
+
+
+def collide_trt(f, omega_p, omega_m, alpha=0.0, g=(0.0, 0.0)):
+    """Two-relaxation-time collision (omega_m = omega_p is BGK)."""
+    f = _f64(f)
+    out = np.zeros(9)
+    lib().oracle_collide_trt(_d(f), alpha, g[0], g[1], omega_p, omega_m, _d(out))
+    return out
+
+
+def trt_tau_minus(tau, magic):
+    """Antisymmetric relaxation time for the parameter Lambda = (tau - 1/2)(tau_m - 1/2)."""
+    return 0.5 + magic / (tau - 0.5)
 
 
 def collide_jacobian(f, omega, alpha=0.0, g=(0.0, 0.0)):
@@ -210,8 +228,10 @@ def init(mask, rho0=None, ux0=None, uy0=None, bc=None, value=None):
     return f
 
 
-def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value=None):
-    """Advance a copy of f by `steps` time steps; returns the new array."""
+def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value=None,
+        tau_minus=None):
+    """Advance a copy of f by `steps` time steps; returns the new array.  tau_minus: the
+    antisymmetric relaxation time of the two-relaxation-time collision (None: BGK)."""
     m = _mask(mask)
     ny, nx = m.shape
     f = np.array(f, dtype=np.float64, order="C", copy=True)
@@ -219,9 +239,10 @@ def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value
         raise ValueError("f must be [9, ny, nx]")
     alpha = _f64(alpha)
     bc, value = _bc_args(m, bc, value)
-    rc = lib().oracle_run_bc(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, g[0], g[1], _d(alpha),
-                             None if bc is None else bc.ctypes.data_as(_u8p), _d(value),
-                             int(steps), int(threads))
+    tm = float(tau) if tau_minus is None else float(tau_minus)
+    rc = lib().oracle_run_trt(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
+                              _d(alpha), None if bc is None else bc.ctypes.data_as(_u8p),
+                              _d(value), int(steps), int(threads))
     if rc:
         raise ValueError(f"oracle_run failed ({rc})")
     return f

@@ -148,6 +148,37 @@ void oracle_collide(const double *f, double alpha, double gx, double gy, double 
         fstar[i] = f[i] - omega * (f[i] - feq[i]) + (1.0 - 0.5 * omega) * S[i];
 }
 
+/* Two-relaxation-time collision (a collision model other than the paper's
+ * BGK, named as the paper's future work): every population pair (i, opp(i))
+ * is split into its symmetric and antisymmetric parts,
+ *   f^+_i = (f_i + f_opp(i)) / 2,  f^-_i = (f_i - f_opp(i)) / 2,
+ * and likewise f^eq and the forcing term S; the symmetric parts relax with
+ * omega+ (which sets the viscosity as omega does in Eq. 5), the antisymmetric
+ * parts with omega-:
+ *   fstar_i = f_i - omega+ (f^+_i - f^eq+_i) - omega- (f^-_i - f^eq-_i)
+ *             + (1 - omega+/2) S^+_i + (1 - omega-/2) S^-_i.
+ * omega- = omega+ is the BGK collision above. */
+void oracle_collide_trt(const double *f, double alpha, double gx, double gy, double omega_p,
+                        double omega_m, double *fstar)
+{
+    double m[3];
+    oracle_node_velocity(f, alpha, gx, gy, m);
+    double rho = m[0], ux = m[1], uy = m[2];
+    double Fx = rho * (gx - alpha * ux);
+    double Fy = rho * (gy - alpha * uy);
+    double feq[Q], S[Q];
+    oracle_equilibrium(rho, ux, uy, feq);
+    oracle_guo_source(ux, uy, Fx, Fy, S);
+    for (int i = 0; i < Q; ++i) {
+        int j = opposite(i);
+        double fp = 0.5 * (f[i] + f[j]), fm = 0.5 * (f[i] - f[j]);
+        double ep = 0.5 * (feq[i] + feq[j]), em = 0.5 * (feq[i] - feq[j]);
+        double sp = 0.5 * (S[i] + S[j]), sm = 0.5 * (S[i] - S[j]);
+        fstar[i] = f[i] - omega_p * (fp - ep) - omega_m * (fm - em) + (1.0 - 0.5 * omega_p) * sp +
+                   (1.0 - 0.5 * omega_m) * sm;
+    }
+}
+
 /* Initialisation (Algorithm 1, first loop): f_i = f^eq_i(rho0, u0) at every
  * fluid node.  NULL fields mean rho0 = 1, u0 = 0.  Solid slots are zeroed. */
 int oracle_init(int nx, int ny, const uint8_t *mask, const double *rho0, const double *ux0,
@@ -267,7 +298,7 @@ int oracle_apply_boundaries(int nx, int ny, const uint8_t *mask, const uint8_t *
  * population bounces back halfway: f_opp(i)(x, t+1) = fstar_i(x).  This is a
  * bijection on fluid slots. */
 static void one_step(int nx, int ny, const uint8_t *mask, double *f, double *post, double omega,
-                     double gx, double gy, const double *alpha)
+                     double omega_m, double gx, double gy, const double *alpha)
 {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
@@ -278,7 +309,10 @@ static void one_step(int nx, int ny, const uint8_t *mask, double *f, double *pos
             double fl[Q], fs[Q];
             for (int i = 0; i < Q; ++i)
                 fl[i] = f[slot(i, x, y, nx, ny)];
-            oracle_collide(fl, alpha ? alpha[n] : 0.0, gx, gy, omega, fs);
+            if (omega_m == omega)
+                oracle_collide(fl, alpha ? alpha[n] : 0.0, gx, gy, omega, fs);
+            else
+                oracle_collide_trt(fl, alpha ? alpha[n] : 0.0, gx, gy, omega, omega_m, fs);
             for (int i = 0; i < Q; ++i)
                 post[slot(i, x, y, nx, ny)] = fs[i];
         }
@@ -299,15 +333,16 @@ static void one_step(int nx, int ny, const uint8_t *mask, double *f, double *pos
         }
 }
 
-/* Run nsteps steps in place.  tau > 1/2 (Eq. 5: omega = 1/tau).  alpha may
- * be NULL (no drag).  bc / value may be NULL (no open boundaries); else the
- * boundary conditions are applied after every streaming phase.  nthreads <= 0
- * keeps the OpenMP default. */
-int oracle_run_bc(int nx, int ny, const uint8_t *mask, double *f, double tau, double gx,
-                  double gy, const double *alpha, const uint8_t *bc, const double *value,
-                  long nsteps, int nthreads)
+/* Run nsteps steps in place.  tau > 1/2 (Eq. 5: omega = 1/tau); tau_m > 1/2
+ * is the antisymmetric relaxation time of the two-relaxation-time collision
+ * (tau_m = tau: BGK).  alpha may be NULL (no drag).  bc / value may be NULL
+ * (no open boundaries); else the boundary conditions are applied after every
+ * streaming phase.  nthreads <= 0 keeps the OpenMP default. */
+int oracle_run_trt(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
+                   double gx, double gy, const double *alpha, const uint8_t *bc,
+                   const double *value, long nsteps, int nthreads)
 {
-    if (nx < 1 || ny < 1 || !(tau > 0.5) || nsteps < 0)
+    if (nx < 1 || ny < 1 || !(tau > 0.5) || !(tau_m > 0.5) || nsteps < 0)
         return -1;
 #ifdef _OPENMP
     if (nthreads > 0)
@@ -315,13 +350,13 @@ int oracle_run_bc(int nx, int ny, const uint8_t *mask, double *f, double tau, do
 #else
     (void)nthreads;
 #endif
-    double omega = 1.0 / tau;
+    double omega = 1.0 / tau, omega_m = tau_m == tau ? omega : 1.0 / tau_m;
     size_t total = (size_t)Q * nx * ny;
     double *post = (double *)calloc(total, sizeof(double));
     if (!post)
         return -2;
     for (long s = 0; s < nsteps; ++s) {
-        one_step(nx, ny, mask, f, post, omega, gx, gy, alpha);
+        one_step(nx, ny, mask, f, post, omega, omega_m, gx, gy, alpha);
         if (bc && oracle_apply_boundaries(nx, ny, mask, bc, value, f)) {
             free(post);
             return -1;
@@ -329,6 +364,13 @@ int oracle_run_bc(int nx, int ny, const uint8_t *mask, double *f, double tau, do
     }
     free(post);
     return 0;
+}
+
+int oracle_run_bc(int nx, int ny, const uint8_t *mask, double *f, double tau, double gx,
+                  double gy, const double *alpha, const uint8_t *bc, const double *value,
+                  long nsteps, int nthreads)
+{
+    return oracle_run_trt(nx, ny, mask, f, tau, tau, gx, gy, alpha, bc, value, nsteps, nthreads);
 }
 
 int oracle_run(int nx, int ny, const uint8_t *mask, double *f, double tau, double gx, double gy,
@@ -499,7 +541,7 @@ int oracle_outlet_ux_gradient(int nx, int ny, const uint8_t *mask, const double 
     for (long t = 0; t < T; ++t) {
         memcpy(states + (size_t)(t + 1) * total, states + (size_t)t * total,
                total * sizeof(double));
-        one_step(nx, ny, mask, states + (size_t)(t + 1) * total, post, omega, gx, gy, alpha);
+        one_step(nx, ny, mask, states + (size_t)(t + 1) * total, post, omega, omega, gx, gy, alpha);
     }
     const double *fT = states + (size_t)T * total;
     if (oracle_objective_outlet_ux(nx, ny, mask, fT, gx, gy, alpha, x_out, J) != 0) {
