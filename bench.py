@@ -101,10 +101,11 @@ def time_steps(lat, steps, warmup):
     return ms / 1e3, ms / max(steps, 1)
 
 
-def measure_dense(lbm, n, dtype, layout, steps, warmup, fields):
+def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0):
     import synthetic
     m = synthetic.all_fluid(n, n)
     lat = lbm.Lattice(m, 0.6, dtype=dtype, layout=layout)
+    lat.set_trt(trt)
     lat.init_equilibrium(*fields)
     secs, ms = time_steps(lat, steps, warmup)
     info = lat.info()
@@ -113,7 +114,8 @@ def measure_dense(lbm, n, dtype, layout, steps, warmup, fields):
     nf = info["n_fluid"]
     glups = nf * steps / secs / 1e9
     bpn = algorithmic_bytes_per_node(dtype)
-    return {"workload": f"taylor-green {n}^2", "dtype": dtype, "layout": layout,
+    return {"workload": f"taylor-green {n}^2" + (f" TRT magic={trt:g}" if trt else ""),
+            "dtype": dtype, "layout": layout,
             "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
             "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
             "paper_U_B_bytes": 18 * POP_BYTES[dtype], "bytes_per_node": bpn,
@@ -465,6 +467,11 @@ def main():
                               ("f16s", "dense_ab"), ("bf16s", "dense_ab")]:
             r = measure_dense(lbm, n, dtype, layout, args.steps, args.warmup, fields)
             log(f"[bench]   {dtype} {layout}: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
+            variants.append(r)
+        for dtype in ("f64", "f32"):
+            r = measure_dense(lbm, n, dtype, "dense_ab", args.steps, args.warmup, fields,
+                              trt=3.0 / 16.0)
+            log(f"[bench]   {dtype} dense_ab TRT: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
             variants.append(r)
         c = measure_copy(lbm, 1 << 30)
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")

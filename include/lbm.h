@@ -167,6 +167,19 @@ int lbm_set_porosity(lbm_ctx *ctx, const float *alpha);
  * have no adjoint (LBM_ERR_UNSUPPORTED).  Synchronises the context's stream. */
 int lbm_set_boundaries(lbm_ctx *ctx, const uint8_t *bc, const double *value);
 
+/* Collision model.  magic = 0: BGK (Eqs. 3-6, the default).  magic > 0: the
+ * two-relaxation-time collision (a collision model beyond the paper's BGK,
+ * which the paper names as future work): each population pair (i, opp(i)) is
+ * split into its symmetric and antisymmetric parts; the symmetric parts relax
+ * with omega = 1 / tau (so tau sets the viscosity, Eq. 5), the antisymmetric
+ * parts with omega_m = 1 / tau_m, tau_m = 1/2 + magic / (tau - 1/2), i.e.
+ * magic = (tau - 1/2)(tau_m - 1/2); the forcing term is split the same way.
+ * With halfway bounce-back walls, magic = 3/16 puts the walls of a steady
+ * channel flow exactly halfway between nodes.  Invalid (negative or not
+ * finite): LBM_ERR_INVALID.  Contexts using TRT have no adjoint
+ * (LBM_ERR_UNSUPPORTED).  Discards captured step graphs. */
+int lbm_set_trt(lbm_ctx *ctx, double magic);
+
 /* Replace the body force (host double[2], finite). */
 int lbm_set_force(lbm_ctx *ctx, const double *force);
 

@@ -163,6 +163,10 @@ class Lattice:
             raise ValueError("bc must be [ny, nx] and value [2, ny, nx]")
         self._check(self._lib.lbm_set_boundaries(self._ctx, b.ctypes.data, v.ctypes.data))
 
+    def set_trt(self, magic):
+        """Two-relaxation-time collision with parameter Lambda = magic (0 = BGK)."""
+        self._check(self._lib.lbm_set_trt(self._ctx, float(magic)))
+
     def set_force(self, g):
         arr = (ctypes.c_double * 2)(float(g[0]), float(g[1]))
         self._check(self._lib.lbm_set_force(self._ctx, arr))

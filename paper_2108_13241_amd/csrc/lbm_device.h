@@ -147,9 +147,17 @@ __device__ __forceinline__ R pair_dot(int k, R vx, R vy)
 // with C0 = rho (1 - 1.5 u.u), or sum h - 1.5 rho u.u for deviations.
 // EXACT = false (16-bit storage): raw hardware reciprocals and u = m / rho
 // taken directly (see kExact of the codecs).
-template <class R, bool DRAG, bool SHIFT, bool FORCE = true, bool EXACT = true>
+// TRT: two-relaxation-time collision (a collision model beyond the paper's
+// BGK): the symmetric part of each pair, fp = (f_i + f_opp(i)) / 2, relaxes
+// with omega (and sets the viscosity), the antisymmetric part fm with
+// omega_m; the forcing term is split the same way.  Per pair
+//   P = (1 - omega) fp + omega even  [+ (1 - omega/2) S_even],
+//   M = (1 - omega_m) fm + omega_m odd  [+ (1 - omega_m/2) S_odd],
+//   f_i <- P + M,  f_opp(i) <- P - M,
+// with even / odd the parts of f^eq; omega_m = omega is BGK.
+template <class R, bool DRAG, bool SHIFT, bool FORCE = true, bool EXACT = true, bool TRT = false>
 __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, const R gy,
-                                        const R alpha)
+                                        const R alpha, const R omega_m = R(0))
 {
     const R sum = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
     const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -215,6 +223,19 @@ __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, co
         const R cu = pair_dot(k, ux, uy);
         const R even = w * (C0 + rho_times(R(4.5) * (cu * cu)));
         const R odd = w * rho_times(R(3) * cu);
+        if constexpr (TRT) {
+            const R fp = R(0.5) * (f[i] + f[j]), fm = R(0.5) * (f[i] - f[j]);
+            R P = keep * fp + omega * even;
+            R M = (R(1) - omega_m) * fm + omega_m * odd;
+            if constexpr (FORCE) {
+                const R cF = pair_dot(k, Fx, Fy);
+                P += guo * (w * (R(9) * cu * cF - R(3) * uF));
+                M += (R(1) - R(0.5) * omega_m) * (R(3) * w * cF);
+            }
+            f[i] = P + M;
+            f[j] = P - M;
+            continue;
+        }
         R a = keep * f[i] + omega * (even + odd);
         R b = keep * f[j] + omega * (even - odd);
         if constexpr (FORCE) {

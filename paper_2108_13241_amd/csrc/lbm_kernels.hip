@@ -247,8 +247,9 @@ __device__ __forceinline__ void dense_pull_aligned(const typename ST::mem *__res
 // ------------------------------------------------------------- step: dense --
 // Physics variant of a step kernel: plain BGK (no body force, no drag), body
 // force, or body force with a drag field; plus kOpen when the lattice has
-// open-boundary nodes (lattices without them run kernels free of that branch).
-enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2, kOpenBC = 4 };
+// open-boundary nodes (lattices without them run kernels free of that branch);
+// plus kTRT for the two-relaxation-time collision.
+enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2, kOpenBC = 4, kTRT = 8 };
 
 template <class ST, int PH>
 __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
@@ -256,11 +257,12 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
     const uint32_t *__restrict__ seg_interior, const float *__restrict__ alpha,
     const double *__restrict__ bc_val, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
-    typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    typename ST::real omega, typename ST::real gx, typename ST::real gy,
+    typename ST::real omega_m)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0;
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
     int x, y;
     uint32_t L;
     if (!dense_node(bpr, nblocks, nx, x, y, L))
@@ -288,8 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
         dense_pull<ST>(src, a, sm, f);
     if (OPEN && open)
         apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-    collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
-                                                    DRAG ? (R)alpha[n] : R(0));
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
+                                                         DRAG ? (R)alpha[n] : R(0), omega_m);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dense_at(dst, a, i, 1, 1), ST::st(f[i], i));
@@ -306,11 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     const uint8_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior,
     const float *__restrict__ alpha, const double *__restrict__ bc_val, int nx, int ny, int pitch,
     uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
-    typename ST::real gy)
+    typename ST::real gy, typename ST::real omega_m)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0;
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
     int x, y;
     uint32_t L;
     if (!dense_node(bpr, nblocks, nx, x, y, L))
@@ -329,8 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
             f[i] = ST::ld(dense_at(A, a, i, 1, 1), i);
         if (OPEN && open)
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-        collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
-                                                        DRAG ? (R)alpha[n] : R(0));
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
+                                                             DRAG ? (R)alpha[n] : R(0), omega_m);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             store_nt(&dense_at(A, a, kOpp[i], 1, 1), ST::st(f[i], i));
@@ -349,8 +351,8 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
         }
         if (OPEN && open)
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-        collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
-                                                        DRAG ? (R)alpha[n] : R(0));
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
+                                                             DRAG ? (R)alpha[n] : R(0), omega_m);
         // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
         if (sm == 0) {
 #pragma unroll
@@ -373,11 +375,11 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
     const float *__restrict__ alpha, const double *__restrict__ bc_val,
     const int32_t *__restrict__ tile_nbr, uint32_t n_tiles, typename ST::real omega,
-    typename ST::real gx, typename ST::real gy)
+    typename ST::real gx, typename ST::real gy, typename ST::real omega_m)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0;
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
     const uint32_t k = xcd_remap(blockIdx.x, n_tiles);
     const int t = (int)threadIdx.x, lx = t & 15, ly = t >> 4;
     const uint32_t n = k * kTileNodes + t;
@@ -397,8 +399,8 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
         if (const unsigned open = open_code(ty))
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
     }
-    collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
-                                                    DRAG ? (R)alpha[n] : R(0));
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
+                                                         DRAG ? (R)alpha[n] : R(0), omega_m);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kTileStride + nb[0]], ST::st(f[i], i));
@@ -411,11 +413,12 @@ __global__ __launch_bounds__(kBlock) void k_step_indirect(
     const uint32_t *__restrict__ pk, const uint16_t *__restrict__ info,
     const int32_t *__restrict__ edge, const float *__restrict__ alpha,
     const double *__restrict__ bc_val, uint32_t n_fluid, uint32_t nblocks,
-    typename ST::real omega, typename ST::real gx, typename ST::real gy)
+    typename ST::real omega, typename ST::real gx, typename ST::real gy,
+    typename ST::real omega_m)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0;
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
     const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
     if (n >= n_fluid)
         return;
@@ -426,8 +429,8 @@ __global__ __launch_bounds__(kBlock) void k_step_indirect(
     pull_gather<ST>(src, kChunk, nb, sm, f);
     if (OPEN && open)
         apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-    collide<R, DRAG, ST::kShift, FORCE, ST::kExact>(f, omega, gx, gy,
-                                                    DRAG ? (R)alpha[n] : R(0));
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
+                                                         DRAG ? (R)alpha[n] : R(0), omega_m);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kChunk + nb[0]], ST::st(f[i], i));
@@ -731,7 +734,7 @@ void step_launch(const DevState &s, int64_t t, int cur)
 {
     using M = typename ST::mem;
     using R = typename ST::real;
-    const R om = (R)s.omega, gx = (R)s.gx, gy = (R)s.gy;
+    const R om = (R)s.omega, gx = (R)s.gx, gy = (R)s.gy, omm = (R)s.omega_m;
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
     if (s.layout == kDenseAB || s.layout == kDenseAA) {
@@ -740,28 +743,28 @@ void step_launch(const DevState &s, int64_t t, int cur)
         if (s.layout == kDenseAB) {
             k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
                 src, dst, s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
-                s.pitch, bpr, nblocks, om, gx, gy);
+                s.pitch, bpr, nblocks, om, gx, gy, omm);
         } else if (t & 1) {
             k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, 0, s.stream>>>(
                 (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
-                s.pitch, bpr, nblocks, om, gx, gy);
+                s.pitch, bpr, nblocks, om, gx, gy, omm);
         } else {
             k_step_dense_aa<ST, PH, false><<<nblocks, kBlock, 0, s.stream>>>(
                 (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
-                s.pitch, bpr, nblocks, om, gx, gy);
+                s.pitch, bpr, nblocks, om, gx, gy, omm);
         }
     } else if (s.layout == kTiled16) {
         const uint32_t nt = (uint32_t)s.n_tiles;
         if (nt > 0)
             k_step_tiled<ST, PH><<<nt, kTileNodes, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.bc_val, s.tile_nbr, nt, om, gx, gy);
+                src, dst, s.type, s.nmask, s.alpha, s.bc_val, s.tile_nbr, nt, om, gx, gy, omm);
     } else {
         const uint32_t nf = (uint32_t)s.n_fluid;
         const uint32_t nblocks = (nf + kBlock - 1) / kBlock;
         if (nf > 0)
             k_step_indirect<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
                 src, dst, s.ind_pk, s.ind_info, s.ind_edge, s.alpha, s.bc_val, nf, nblocks, om,
-                gx, gy);
+                gx, gy, omm);
     }
 }
 
@@ -779,10 +782,16 @@ void step_phys(const DevState &s, int64_t t, int cur)
 template <class ST>
 hipError_t step_typed(const DevState &s, int64_t t, int cur)
 {
-    if (s.open)
+    if (s.trt) {
+        if (s.open)
+            step_phys<ST, kOpenBC | kTRT>(s, t, cur);
+        else
+            step_phys<ST, kTRT>(s, t, cur);
+    } else if (s.open) {
         step_phys<ST, kOpenBC>(s, t, cur);
-    else
+    } else {
         step_phys<ST, 0>(s, t, cur);
+    }
     return hipGetLastError();
 }
 

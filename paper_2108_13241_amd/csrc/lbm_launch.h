@@ -34,6 +34,8 @@ struct DevState {
     const double *bc_val = nullptr;   // open-boundary values [node][2], same indexing as
                                       // alpha; read only at open-boundary nodes
     int open = 0;                     // 1 when the node types hold open-boundary codes
+    int trt = 0;                      // 1: two-relaxation-time collision (omega_m below)
+    double omega_m = 1.0;             // antisymmetric relaxation rate (TRT)
     int64_t n_tiles = 0, n_fluid = 0;
     double omega = 1.0, gx = 0.0, gy = 0.0;
     hipStream_t stream = nullptr;

@@ -290,6 +290,7 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
     s.ny = ny;
     s.pitch = (int)pitch;
     s.omega = 1.0 / tau;
+    s.omega_m = s.omega;
     s.gx = force ? force[0] : 0.0;
     s.gy = force ? force[1] : 0.0;
     s.stream = nullptr;
@@ -558,6 +559,25 @@ int lbm_set_boundaries(lbm_ctx *c, const uint8_t *bc, const double *value)
     return LBM_OK;
 }
 
+int lbm_set_trt(lbm_ctx *c, double magic)
+{
+    LBM_CHECK_CTX(c);
+    if (!(std::isfinite(magic) && magic >= 0.0))
+        return fail(c, LBM_ERR_INVALID, "the TRT parameter must be finite and >= 0 (0 = BGK)");
+    drop_graphs(c);
+    lbm::DevState &s = c->s;
+    if (magic == 0.0) {
+        s.trt = 0;
+        s.omega_m = s.omega;
+        return LBM_OK;
+    }
+    const double tau = 1.0 / s.omega;
+    const double tau_m = 0.5 + magic / (tau - 0.5);
+    s.trt = 1;
+    s.omega_m = 1.0 / tau_m;
+    return LBM_OK;
+}
+
 int lbm_set_force(lbm_ctx *c, const double *force)
 {
     LBM_CHECK_CTX(c);
@@ -792,6 +812,8 @@ static int adjoint_supported(lbm_ctx *c)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
     if (c->n_open)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
+    if (c->s.trt)
+        return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
     return LBM_OK;
 }
 
@@ -843,6 +865,8 @@ int lbm_adjoint_bytes(const lbm_ctx *c, size_t *bytes, int32_t *pitch)
         return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
     if (c->n_open)
         return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
+    if (c->s.trt)
+        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
     *bytes = adjoint_field_bytes(c);
     if (pitch)
         *pitch = c->s.pitch;
