@@ -34,6 +34,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRC3 = os.path.join(_HERE, "lbm_oracle_d3q19.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -46,7 +47,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared", "-o", tmp, _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -94,6 +95,19 @@ def lib():
                                     ctypes.c_long, ctypes.c_int]
         L.oracle_run_bc.restype = ctypes.c_int
         L.oracle_collide_trt.argtypes = [_dp] + [ctypes.c_double] * 5 + [_dp]
+        L.oracle3_constants.argtypes = [_ip, _ip, _ip, _dp, _ip]
+        L.oracle3_equilibrium.argtypes = [ctypes.c_double] * 4 + [_dp]
+        L.oracle3_guo_source.argtypes = [ctypes.c_double] * 6 + [_dp]
+        L.oracle3_node_velocity.argtypes = [_dp] + [ctypes.c_double] * 3 + [_dp]
+        L.oracle3_collide.argtypes = [_dp] + [ctypes.c_double] * 4 + [_dp]
+        L.oracle3_init.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp, _dp, _dp, _dp, _dp]
+        L.oracle3_init.restype = ctypes.c_int
+        L.oracle3_run.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp] + [ctypes.c_double] * 4 + \
+            [ctypes.c_long, ctypes.c_int]
+        L.oracle3_run.restype = ctypes.c_int
+        L.oracle3_macroscopic.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp] + \
+            [ctypes.c_double] * 3 + [_dp] * 4
+        L.oracle3_macroscopic.restype = ctypes.c_int
         L.oracle_run_trt.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p,
                                      _dp, ctypes.c_long, ctypes.c_int]
@@ -289,3 +303,81 @@ def outlet_ux_gradient(mask, f0, tau, steps, x_out, g=(0.0, 0.0), alpha=None):
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+# ------------------------------------------------------------------- D3Q19 --
+# Arrays: mask uint8 [nz, ny, nx]; f float64 [19, nz, ny, nx]; g = (g_x, g_y, g_z).
+
+def constants3():
+    """(cx, cy, cz, w, opp) of the D3Q19 oracle."""
+    c = [(ctypes.c_int * 19)() for _ in range(3)]
+    w = (ctypes.c_double * 19)()
+    opp = (ctypes.c_int * 19)()
+    lib().oracle3_constants(c[0], c[1], c[2], w, opp)
+    return tuple(np.array(a[:]) for a in c) + (np.array(w[:]), np.array(opp[:]))
+
+
+def equilibrium3(rho, ux, uy, uz):
+    out = np.zeros(19)
+    lib().oracle3_equilibrium(rho, ux, uy, uz, _d(out))
+    return out
+
+
+def guo_source3(u, F):
+    out = np.zeros(19)
+    lib().oracle3_guo_source(u[0], u[1], u[2], F[0], F[1], F[2], _d(out))
+    return out
+
+
+def node_velocity3(f, g=(0.0, 0.0, 0.0)):
+    f = _f64(f)
+    out = np.zeros(4)
+    lib().oracle3_node_velocity(_d(f), g[0], g[1], g[2], _d(out))
+    return out
+
+
+def collide3(f, omega, g=(0.0, 0.0, 0.0)):
+    f = _f64(f)
+    out = np.zeros(19)
+    lib().oracle3_collide(_d(f), g[0], g[1], g[2], omega, _d(out))
+    return out
+
+
+def _mask3(m):
+    m = np.ascontiguousarray(m, dtype=np.uint8)
+    if m.ndim != 3:
+        raise ValueError("mask must be [nz, ny, nx]")
+    return m
+
+
+def init3(mask, rho0=None, ux0=None, uy0=None, uz0=None):
+    m = _mask3(mask)
+    nz, ny, nx = m.shape
+    f = np.zeros((19, nz, ny, nx))
+    fl = [_f64(a) for a in (rho0, ux0, uy0, uz0)]
+    if lib().oracle3_init(nx, ny, nz, m.ctypes.data_as(_u8p), *[_d(a) for a in fl], _d(f)):
+        raise ValueError("oracle3_init failed")
+    return f
+
+
+def run3(mask, f, tau, steps, g=(0.0, 0.0, 0.0), threads=0):
+    m = _mask3(mask)
+    nz, ny, nx = m.shape
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    if f.shape != (19, nz, ny, nx):
+        raise ValueError("f must be [19, nz, ny, nx]")
+    rc = lib().oracle3_run(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), tau, g[0], g[1], g[2],
+                           int(steps), int(threads))
+    if rc:
+        raise ValueError(f"oracle3_run failed ({rc})")
+    return f
+
+
+def macroscopic3(mask, f, g=(0.0, 0.0, 0.0)):
+    m = _mask3(mask)
+    nz, ny, nx = m.shape
+    f = _f64(f)
+    out = [np.zeros((nz, ny, nx)) for _ in range(4)]
+    lib().oracle3_macroscopic(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), g[0], g[1], g[2],
+                              *[_d(a) for a in out])
+    return tuple(out)

@@ -1,0 +1,227 @@
+/*
+ * Plain FP64 CPU oracle of the D3Q19 BGK lattice-Boltzmann time step with
+ * halfway bounce-back walls and Guo body forcing: the three-dimensional
+ * lattice that the paper names as its future work, with the same update as
+ * the two-dimensional oracle (Sec. 2.2, Eq. 3 as collision then streaming;
+ * Eq. 4 BGK; Eq. 6 equilibrium, which holds unchanged in 3D with the D3Q19
+ * weights; Eq. 5 viscosity).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The GPU library never links, calls, includes or
+ * shares anything with this file; only the test-suite and the benchmark's
+ * CPU-baseline leg load it.
+ *
+ * State: f[((i*nz + z)*ny + y)*nx + x] holds the canonical pre-collision
+ * populations at fluid nodes; solid slots hold 0.  mask[(z*ny + y)*nx + x]:
+ * 0 fluid, 1 solid.  All three axes wrap periodically; walls come only from
+ * the mask.  Build with -O2 -ffp-contract=off, no fast-math.
+ *
+ * Velocities (the paper numbers only D2Q9): 0 rest; 1..6 the axis directions
+ * +x, -x, +y, -y, +z, -z; 7..18 the twelve edge directions as opposite pairs
+ * (+x+y, -x-y), (+x-y, -x+y), (+x+z, -x-z), (+x-z, -x+z), (+y+z, -y-z),
+ * (+y-z, -y+z).  Weights: 1/3 at rest, 1/18 on the axes, 1/36 on the edges.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define Q3 19
+
+static const int CX3[Q3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int CY3[Q3] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int CZ3[Q3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+static double weight3(int i)
+{
+    int s = abs(CX3[i]) + abs(CY3[i]) + abs(CZ3[i]);
+    return s == 0 ? 1.0 / 3.0 : (s == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+static int opposite3(int i)
+{
+    for (int j = 0; j < Q3; ++j)
+        if (CX3[j] == -CX3[i] && CY3[j] == -CY3[i] && CZ3[j] == -CZ3[i])
+            return j;
+    return -1;
+}
+
+static int wrap3(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+static size_t slot3(int i, int x, int y, int z, int nx, int ny, int nz)
+{
+    return (((size_t)i * nz + z) * ny + y) * nx + x;
+}
+
+void oracle3_constants(int *cx, int *cy, int *cz, double *w, int *opp)
+{
+    for (int i = 0; i < Q3; ++i) {
+        cx[i] = CX3[i];
+        cy[i] = CY3[i];
+        cz[i] = CZ3[i];
+        w[i] = weight3(i);
+        opp[i] = opposite3(i);
+    }
+}
+
+/* Eq. 6 with the D3Q19 weights. */
+void oracle3_equilibrium(double rho, double ux, double uy, double uz, double *feq)
+{
+    double usq = ux * ux + uy * uy + uz * uz;
+    for (int i = 0; i < Q3; ++i) {
+        double cu = CX3[i] * ux + CY3[i] * uy + CZ3[i] * uz;
+        feq[i] = weight3(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    }
+}
+
+/* Guo forcing term: S_i = w_i [3 (c_i - u) . F + 9 (c_i . u)(c_i . F)]. */
+void oracle3_guo_source(double ux, double uy, double uz, double Fx, double Fy, double Fz,
+                        double *S)
+{
+    for (int i = 0; i < Q3; ++i) {
+        double cu = CX3[i] * ux + CY3[i] * uy + CZ3[i] * uz;
+        double cF = CX3[i] * Fx + CY3[i] * Fy + CZ3[i] * Fz;
+        double uF = ux * Fx + uy * Fy + uz * Fz;
+        S[i] = weight3(i) * (3.0 * (cF - uF) + 9.0 * cu * cF);
+    }
+}
+
+/* rho, and the velocity with the half-force correction u = m/rho + g/2. */
+void oracle3_node_velocity(const double *f, double gx, double gy, double gz, double *out)
+{
+    double rho = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    for (int i = 0; i < Q3; ++i) {
+        rho += f[i];
+        mx += CX3[i] * f[i];
+        my += CY3[i] * f[i];
+        mz += CZ3[i] * f[i];
+    }
+    out[0] = rho;
+    out[1] = mx / rho + 0.5 * gx;
+    out[2] = my / rho + 0.5 * gy;
+    out[3] = mz / rho + 0.5 * gz;
+}
+
+/* BGK collision with forcing F = rho g:
+ *   fstar_i = f_i - omega (f_i - f^eq_i) + (1 - omega/2) S_i. */
+void oracle3_collide(const double *f, double gx, double gy, double gz, double omega,
+                     double *fstar)
+{
+    double m[4];
+    oracle3_node_velocity(f, gx, gy, gz, m);
+    double feq[Q3], S[Q3];
+    oracle3_equilibrium(m[0], m[1], m[2], m[3], feq);
+    oracle3_guo_source(m[1], m[2], m[3], m[0] * gx, m[0] * gy, m[0] * gz, S);
+    for (int i = 0; i < Q3; ++i)
+        fstar[i] = f[i] - omega * (f[i] - feq[i]) + (1.0 - 0.5 * omega) * S[i];
+}
+
+/* f_i = f^eq_i(rho0, u0) at fluid nodes; NULL fields mean rho0 = 1, u0 = 0. */
+int oracle3_init(int nx, int ny, int nz, const uint8_t *mask, const double *rho0,
+                 const double *ux0, const double *uy0, const double *uz0, double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1)
+        return -1;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = ((size_t)z * ny + y) * nx + x;
+                double feq[Q3] = {0};
+                if (mask[n] == 0)
+                    oracle3_equilibrium(rho0 ? rho0[n] : 1.0, ux0 ? ux0[n] : 0.0,
+                                        uy0 ? uy0[n] : 0.0, uz0 ? uz0[n] : 0.0, feq);
+                for (int i = 0; i < Q3; ++i)
+                    f[slot3(i, x, y, z, nx, ny, nz)] = feq[i];
+            }
+    return 0;
+}
+
+/* One step: collide every fluid node, then push every post-collision
+ * population to x + c_i, or back to its origin reversed when x + c_i is
+ * solid (halfway bounce-back). */
+static void one_step3(int nx, int ny, int nz, const uint8_t *mask, double *f, double *post,
+                      double omega, double gx, double gy, double gz)
+{
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = ((size_t)z * ny + y) * nx + x;
+                if (mask[n] != 0)
+                    continue;
+                double fl[Q3], fs[Q3];
+                for (int i = 0; i < Q3; ++i)
+                    fl[i] = f[slot3(i, x, y, z, nx, ny, nz)];
+                oracle3_collide(fl, gx, gy, gz, omega, fs);
+                for (int i = 0; i < Q3; ++i)
+                    post[slot3(i, x, y, z, nx, ny, nz)] = fs[i];
+            }
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = ((size_t)z * ny + y) * nx + x;
+                if (mask[n] != 0)
+                    continue;
+                for (int i = 0; i < Q3; ++i) {
+                    int xn = wrap3(x + CX3[i], nx), yn = wrap3(y + CY3[i], ny),
+                        zn = wrap3(z + CZ3[i], nz);
+                    double v = post[slot3(i, x, y, z, nx, ny, nz)];
+                    if (mask[((size_t)zn * ny + yn) * nx + xn] == 0)
+                        f[slot3(i, xn, yn, zn, nx, ny, nz)] = v;
+                    else
+                        f[slot3(opposite3(i), x, y, z, nx, ny, nz)] = v;
+                }
+            }
+}
+
+int oracle3_run(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau, double gx,
+                double gy, double gz, long nsteps, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !(tau > 0.5) || nsteps < 0)
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    size_t total = (size_t)Q3 * nx * ny * nz;
+    double *post = (double *)calloc(total, sizeof(double));
+    if (!post)
+        return -2;
+    for (long s = 0; s < nsteps; ++s)
+        one_step3(nx, ny, nz, mask, f, post, 1.0 / tau, gx, gy, gz);
+    free(post);
+    return 0;
+}
+
+/* rho and the corrected velocity of the canonical state; solid nodes 0. */
+int oracle3_macroscopic(int nx, int ny, int nz, const uint8_t *mask, const double *f, double gx,
+                        double gy, double gz, double *rho, double *ux, double *uy, double *uz)
+{
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = ((size_t)z * ny + y) * nx + x;
+                if (mask[n] != 0) {
+                    rho[n] = ux[n] = uy[n] = uz[n] = 0.0;
+                    continue;
+                }
+                double fl[Q3], m[4];
+                for (int i = 0; i < Q3; ++i)
+                    fl[i] = f[slot3(i, x, y, z, nx, ny, nz)];
+                oracle3_node_velocity(fl, gx, gy, gz, m);
+                rho[n] = m[0];
+                ux[n] = m[1];
+                uy[n] = m[2];
+                uz[n] = m[3];
+            }
+    return 0;
+}
