@@ -1,0 +1,117 @@
+/*
+ * lbm3d.h - C ABI of the D3Q19 lattice of the MI355X (gfx950) lattice-Boltzmann
+ * library.
+ *
+ * The paper (Tomczak, arXiv 2108.13241) names the three-dimensional lattice as
+ * its future work (Sec. 6).  This interface runs the same update as lbm.h in 3D:
+ * the fused pull stream-and-collide step of Algorithm 1 with halfway bounce-back
+ * walls (Sec. 3), the BGK operator of Eqs. 3-5 and the equilibrium of Eq. 6 with
+ * the D3Q19 weights, plus a body force through Guo's forcing term.  One layout:
+ * two dense lattices swapped every step (the A-B scheme of lbm.h's DENSE_AB).
+ *
+ * Conventions (as in lbm.h, whose status codes, dtype enum and allocator hook
+ * this interface shares)
+ *  - Every call returns an lbm_status (0 = LBM_OK); nothing aborts or throws.
+ *    On LBM_ERR_INVALID / LBM_ERR_UNSUPPORTED nothing changed.  A device
+ *    failure returns LBM_ERR_DEVICE and marks the context broken (later calls
+ *    return LBM_ERR_STATE).  lbm3d_last_error() explains the failure.
+ *  - Host arrays are owned by the caller and only read (or written) during the
+ *    call.  3-D fields are row-major [nz][ny][nx] (x fastest), no padding.
+ *  - Node types: 0 = fluid, 1 = solid.  All three axes are periodic; walls come
+ *    only from solid nodes.  A population that would stream into a solid node
+ *    returns to its origin node reversed in the same step (halfway bounce-back).
+ *  - Velocities: 0 rest; 1..6 the axis directions +x, -x, +y, -y, +z, -z;
+ *    7..18 the edge directions in opposite pairs (+x+y, -x-y), (+x-y, -x+y),
+ *    (+x+z, -x-z), (+x-z, -x+z), (+y+z, -y-z), (+y-z, -y+z).  Weights 1/3 (rest),
+ *    1/18 (axes), 1/36 (edges).
+ *  - "Canonical" populations are the pre-collision values f_i(x, t) as FP64
+ *    [19][nz][ny][nx]; solid slots = 0.
+ *  - dtype: LBM_F64 stores and computes in FP64; LBM_F32, LBM_F16_SHIFTED and
+ *    LBM_BF16_SHIFTED store the deviation f_i - w_i in 32 or 16 bits and compute
+ *    in FP32 on the deviations.
+ *  - A context is not thread-safe; work is enqueued on its stream, and calls
+ *    that return host data synchronise that stream.
+ */
+#ifndef LBM3D_H
+#define LBM3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm3d_ctx lbm3d_ctx; /* opaque; owned by the library until lbm3d_destroy */
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t dtype;
+    int64_t n_nodes;             /* nx * ny * nz */
+    int64_t n_fluid;             /* fluid nodes: the ones counted for LUPS (Eq. 8) */
+    int64_t time_step;           /* steps since the last (re)initialisation */
+    int32_t pop_bytes;           /* bytes per stored population: 8, 4 or 2 */
+    double bytes_per_fluid_node; /* algorithmic bytes per fluid node per step:
+                                    38 * pop_bytes + 1 (node type) */
+    size_t device_bytes;         /* device memory held by the context */
+} lbm3d_info_t;
+
+/* Create a D3Q19 lattice (Eq. 5: omega = 1 / tau), at rest (rho = 1, u = 0),
+ * on the current HIP device and its default stream.
+ *  nx, ny, nz  mesh size, >= 1 each; 19 * nz * ny * (nx rounded up to 64) must
+ *              stay below 2^32 (about 226 M nodes, e.g. 576^3).
+ *  node_type   host uint8 [nz][ny][nx], 0 fluid / 1 solid; copied.
+ *  tau         relaxation time > 1/2 (nu = (tau - 1/2) / 3).
+ *  force       host double[3] body-force acceleration (g_x, g_y, g_z); NULL = 0.
+ *              Force density F = rho g through Guo's forcing term.
+ *  dtype       storage type (see above).
+ * Errors: INVALID (sizes, tau, force, mask values, dtype), UNSUPPORTED (too
+ * large for 32-bit offsets), NOMEM, DEVICE. */
+int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint8_t *node_type,
+                 double tau, const double *force, lbm_dtype dtype);
+
+/* Enqueue later work on `hip_stream` (NULL = default stream), after waiting for
+ * the work already enqueued. */
+int lbm3d_set_stream(lbm3d_ctx *ctx, void *hip_stream);
+
+/* Reset to the equilibrium (Eq. 6) of host FP64 [nz][ny][nx] fields; any field
+ * may be NULL (rho = 1, u = 0).  rho > 0 and finite values at fluid nodes. */
+int lbm3d_init_equilibrium(lbm3d_ctx *ctx, const double *rho, const double *ux,
+                           const double *uy, const double *uz);
+
+/* Change the body-force acceleration (host double[3], finite). */
+int lbm3d_set_force(lbm3d_ctx *ctx, const double *force);
+
+/* Enqueue n >= 0 time steps (one kernel launch each). */
+int lbm3d_step(lbm3d_ctx *ctx, int64_t n);
+
+/* rho and u = m / rho + g / 2 (Eq. 2 with the half-force correction) into host
+ * FP64 [nz][ny][nx] arrays (any may be NULL); solid nodes get 0.  Synchronises. */
+int lbm3d_macroscopic(lbm3d_ctx *ctx, double *rho, double *ux, double *uy, double *uz);
+
+/* Canonical populations to / from host FP64 [19][nz][ny][nx].  set requires
+ * finite values at fluid nodes (solid slots are ignored) and rounds to the
+ * storage type.  Both synchronise. */
+int lbm3d_get_populations(lbm3d_ctx *ctx, double *f);
+int lbm3d_set_populations(lbm3d_ctx *ctx, const double *f);
+
+/* Total mass (sum of rho over fluid nodes) in a fixed summation order on the
+ * device.  Synchronises. */
+int lbm3d_mass(lbm3d_ctx *ctx, double *mass);
+
+int lbm3d_get_info(const lbm3d_ctx *ctx, lbm3d_info_t *info);
+
+/* Message of the last failure on ctx; with ctx == NULL, the calling thread's
+ * last failure outside a context (e.g. lbm3d_create).  Never NULL. */
+const char *lbm3d_last_error(const lbm3d_ctx *ctx);
+
+/* Release the context and its device buffers (NULL is a no-op). */
+void lbm3d_destroy(lbm3d_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM3D_H */

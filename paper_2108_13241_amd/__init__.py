@@ -1,4 +1,5 @@
-"""MI355X-native D2Q9 lattice-Boltzmann library: Python binding of include/lbm.h.
+"""MI355X-native D2Q9 / D3Q19 lattice-Boltzmann library: Python binding of include/lbm.h and
+include/lbm3d.h.
 
 Every step of the method runs in the HIP kernels of ``liblbm_hip.so``; this module only
 marshals arguments.  PyTorch supplies device memory (its caching allocator is
@@ -15,9 +16,9 @@ import ctypes
 
 import numpy as np
 
-from ._lib import DTYPES, LAYOUTS, POP_BYTES, LbmError, LbmInfo, check, load
+from ._lib import DTYPES, LAYOUTS, POP_BYTES, Lbm3dInfo, LbmError, LbmInfo, check, check3, load
 
-__all__ = ["Lattice", "LbmError", "DTYPES", "LAYOUTS", "plan_tiles", "plan_indirect",
+__all__ = ["Lattice", "Lattice3D", "LbmError", "DTYPES", "LAYOUTS", "plan_tiles", "plan_indirect",
            "copy_kernel", "ChannelObjective", "load"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -257,6 +258,89 @@ class Lattice:
 
 
 # ------------------------------------------------------------ host planning --
+class Lattice3D:
+    """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B
+    layout, BGK with Guo forcing, halfway bounce-back.  Arrays are [nz, ny, nx]; canonical
+    populations [19, nz, ny, nx] in the velocity order of include/lbm3d.h."""
+
+    def __init__(self, mask, tau, force=(0.0, 0.0, 0.0), dtype="f64", stream=None,
+                 torch_memory=True):
+        import torch
+
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.ndim != 3:
+            raise ValueError("mask must be [nz, ny, nx]")
+        self.nz, self.ny, self.nx = mask.shape
+        self.shape = mask.shape
+        self.mask = mask
+        self.dtype = dtype
+        self._lib = load()
+        if torch_memory:
+            _install_torch_allocator()
+        else:
+            _uninstall_torch_allocator()
+        self._ctx = ctypes.c_void_p()
+        g = (ctypes.c_double * 3)(*(float(v) for v in force))
+        check3(self._lib.lbm3d_create(ctypes.byref(self._ctx), self.nx, self.ny, self.nz,
+                                      mask.ctypes.data_as(_u8p), float(tau), g, DTYPES[dtype]),
+               None)
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream())
+
+    def _check(self, status):
+        check3(status, self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm3d_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def set_stream(self, stream):
+        raw = getattr(stream, "cuda_stream", stream)
+        self.stream = stream
+        self._check(self._lib.lbm3d_set_stream(self._ctx, ctypes.c_void_p(int(raw or 0))))
+
+    def init_equilibrium(self, rho=None, ux=None, uy=None, uz=None):
+        f = [_f64(a, self.shape) for a in (rho, ux, uy, uz)]
+        self._check(self._lib.lbm3d_init_equilibrium(self._ctx, *[_dptr(a) for a in f]))
+
+    def set_force(self, g):
+        arr = (ctypes.c_double * 3)(*(float(v) for v in g))
+        self._check(self._lib.lbm3d_set_force(self._ctx, arr))
+
+    def step(self, n=1):
+        self._check(self._lib.lbm3d_step(self._ctx, int(n)))
+
+    def macroscopic(self):
+        out = [np.zeros(self.shape) for _ in range(4)]
+        self._check(self._lib.lbm3d_macroscopic(self._ctx, *[_dptr(o) for o in out]))
+        return tuple(out)
+
+    def get_populations(self):
+        f = np.zeros((19,) + self.shape)
+        self._check(self._lib.lbm3d_get_populations(self._ctx, _dptr(f)))
+        return f
+
+    def set_populations(self, f):
+        f = _f64(f, (19,) + self.shape)
+        self._check(self._lib.lbm3d_set_populations(self._ctx, _dptr(f)))
+
+    def mass(self):
+        m = ctypes.c_double()
+        self._check(self._lib.lbm3d_mass(self._ctx, ctypes.byref(m)))
+        return m.value
+
+    def info(self):
+        i = Lbm3dInfo()
+        self._check(self._lib.lbm3d_get_info(self._ctx, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in Lbm3dInfo._fields_}
+
+
 def plan_tiles(mask):
     """(tile_xy [n, 2], tile_nbr [n, 9]) of the compacted 16x16 tile list."""
     m = np.ascontiguousarray(mask, dtype=np.uint8)

@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/lbm.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/lbm.h and include/lbm3d.h (argument
+marshalling only).
 
 The HIP library must have been built (``python -m paper_2108_13241_amd.build``); there
 is no fallback: loading fails loudly when it is missing.
@@ -33,10 +34,18 @@ class LbmInfo(ctypes.Structure):
                 ("bytes_moved_per_step", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
 
 
+class Lbm3dInfo(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
+                ("n_fluid", ctypes.c_int64), ("time_step", ctypes.c_int64),
+                ("pop_bytes", ctypes.c_int32), ("bytes_per_fluid_node", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
-# Every function declared in include/lbm.h: name -> (restype, argtypes).
+# Every function declared in include/*.h: name -> (restype, argtypes).
 _c = ctypes
 _vp, _dp, _i32, _i64, _sz = _c.c_void_p, _c.POINTER(_c.c_double), _c.c_int32, _c.c_int64, _c.c_size_t
 SIGNATURES = {
@@ -77,6 +86,20 @@ SIGNATURES = {
     "lbm_error_string": (_c.c_char_p, [_c.c_int]),
     "lbm_last_error": (_c.c_char_p, [_vp]),
     "lbm_destroy": (None, [_vp]),
+    # include/lbm3d.h
+    "lbm3d_create": (_c.c_int, [_c.POINTER(_vp), _i32, _i32, _i32, _c.POINTER(_c.c_uint8),
+                                _c.c_double, _dp, _c.c_int]),
+    "lbm3d_set_stream": (_c.c_int, [_vp, _vp]),
+    "lbm3d_init_equilibrium": (_c.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "lbm3d_set_force": (_c.c_int, [_vp, _dp]),
+    "lbm3d_step": (_c.c_int, [_vp, _i64]),
+    "lbm3d_macroscopic": (_c.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "lbm3d_get_populations": (_c.c_int, [_vp, _dp]),
+    "lbm3d_set_populations": (_c.c_int, [_vp, _dp]),
+    "lbm3d_mass": (_c.c_int, [_vp, _dp]),
+    "lbm3d_get_info": (_c.c_int, [_vp, _c.POINTER(Lbm3dInfo)]),
+    "lbm3d_last_error": (_c.c_char_p, [_vp]),
+    "lbm3d_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -101,4 +124,10 @@ def load():
 def check(status: int, ctx=None):
     if status != 0:
         msg = load().lbm_last_error(ctx)
+        raise LbmError(status, msg.decode() if msg else "")
+
+
+def check3(status: int, ctx=None):
+    if status != 0:
+        msg = load().lbm3d_last_error(ctx)
         raise LbmError(status, msg.decode() if msg else "")

@@ -1,0 +1,543 @@
+// HIP kernels of the D3Q19 lattice (the three-dimensional lattice the paper
+// names as future work): the fused pull stream-and-collide step of
+// Algorithm 1 with halfway bounce-back walls, BGK collision (Eqs. 3-6 with the
+// D3Q19 weights) and Guo body forcing, on a dense two-lattice (A-B) layout,
+// plus initialisation, canonical views and FP64 reductions.
+//
+// Layout: [nz][ny][pitch/64][19][64] (chunks of 64 nodes along x, each holding
+// its 19 populations as runs of 64); node types and solid-neighbour bits per
+// node [nz][ny][pitch]; one "all interior" flag per 256-node row segment.
+#include "lbm3d_launch.h"
+#include "lbm_device.h"
+
+namespace lbm3 {
+namespace {
+
+using lbm::kChunk;
+using lbm::store_nt;
+using lbm::xcd_remap;
+using lbm::wrap_dec;
+using lbm::wrap_inc;
+constexpr int kBlock = 256;
+constexpr int Q = 19;
+
+// Velocities: rest; axes +x, -x, +y, -y, +z, -z; edges as opposite pairs
+// (+x+y, -x-y), (+x-y, -x+y), (+x+z, -x-z), (+x-z, -x+z), (+y+z, -y-z),
+// (+y-z, -y+z).  opp(i) = i + 1 for odd i, i - 1 for even i > 0.
+__device__ constexpr int kCx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int kCy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int kCz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__device__ constexpr int kOpp[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+// Weights of Eq. 6 for D3Q19: 1/3 at rest, 1/18 on the axes, 1/36 on the edges.
+__device__ constexpr double kW[Q] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                                     1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+enum : uint8_t { kFluid = 0, kSolid = 1, kBoundary = 2 };
+
+// Storage codecs: FP64 stores f_i; the narrow formats store the deviation
+// h_i = f_i - w_i (rho0 = 1) and the collision works on h_i (FP32 arithmetic).
+struct F64 {
+    using mem = double;
+    using real = double;
+    static constexpr bool kShift = false;
+    static __device__ __forceinline__ real ld(mem v, int) { return v; }
+    static __device__ __forceinline__ mem st(real v, int) { return v; }
+    static __device__ __forceinline__ double canon(real v, int) { return v; }
+    static __device__ __forceinline__ mem from_canon(double f, int) { return f; }
+};
+template <class M>
+struct Shifted {
+    using mem = M;
+    using real = float;
+    static constexpr bool kShift = true;
+    static __device__ __forceinline__ real ld(mem v, int) { return (float)v; }
+    static __device__ __forceinline__ mem st(real v, int)
+    {
+        if constexpr (sizeof(M) == 2)
+            asm volatile("" : "+v"(v));  // round to FP32 first, identically everywhere
+        return (mem)v;
+    }
+    static __device__ __forceinline__ double canon(real v, int i) { return (double)v + kW[i]; }
+    static __device__ __forceinline__ mem from_canon(double f, int i)
+    {
+        return (mem)(float)(f - kW[i]);
+    }
+};
+
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+__device__ __forceinline__ float recip(float v)
+{
+    const float r = __builtin_amdgcn_rcpf(v);
+    return __builtin_fmaf(__builtin_fmaf(-v, r, 1.0f), r, r);
+}
+
+// c . v for the first direction of pair k: (1,0,0), (0,1,0), (0,0,1), (1,1,0),
+// (1,-1,0), (1,0,1), (1,0,-1), (0,1,1), (0,1,-1), without multiplications.
+template <class R>
+__device__ __forceinline__ R pair_dot(int k, R vx, R vy, R vz)
+{
+    switch (k) {
+    case 0: return vx;
+    case 1: return vy;
+    case 2: return vz;
+    case 3: return vx + vy;
+    case 4: return vx - vy;
+    case 5: return vx + vz;
+    case 6: return vx - vz;
+    case 7: return vy + vz;
+    default: return vy - vz;
+    }
+}
+
+// BGK collision with Guo forcing (F = rho g) at one node, in place:
+//   f_i <- f_i - omega (f_i - f^eq_i) + (1 - omega/2) S_i,
+// u = m / rho + g / 2, f^eq of Eq. 6 with the D3Q19 weights,
+// S_i = w_i [3 (c_i - u) . F + 9 (c_i . u)(c_i . F)].  Opposite directions
+// share everything but the terms odd in c, so they are updated as a pair; with
+// SHIFT, f holds deviations and rho = 1 + sum is never rounded (rho v = v + sum v).
+template <class R, bool SHIFT, bool FORCE>
+__device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz)
+{
+    R sum = f[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        sum += f[i];
+    R mx = R(0), my = R(0), mz = R(0);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const R d = f[i] - f[i + 1];
+        if (kCx[i] > 0) mx += d; else if (kCx[i] < 0) mx -= d;
+        if (kCy[i] > 0) my += d; else if (kCy[i] < 0) my -= d;
+        if (kCz[i] > 0) mz += d; else if (kCz[i] < 0) mz -= d;
+    }
+    auto rho_times = [&](R v) -> R {
+        if constexpr (SHIFT)
+            return v + sum * v;
+        else
+            return sum * v;
+    };
+    R ux, uy, uz;
+    if constexpr (SHIFT) {
+        const R q = sum * recip(R(1) + sum);
+        ux = mx - mx * q;
+        uy = my - my * q;
+        uz = mz - mz * q;
+    } else {
+        const R inv = recip(sum);
+        ux = mx * inv;
+        uy = my * inv;
+        uz = mz * inv;
+    }
+    R Fx = R(0), Fy = R(0), Fz = R(0);
+    if constexpr (FORCE) {
+        ux += R(0.5) * gx;
+        uy += R(0.5) * gy;
+        uz += R(0.5) * gz;
+        Fx = rho_times(gx);
+        Fy = rho_times(gy);
+        Fz = rho_times(gz);
+    }
+    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    const R C0 = SHIFT ? sum - rho_times(usq) : rho_times(R(1) - usq);
+    const R keep = R(1) - omega, guo = R(1) - R(0.5) * omega;
+    const R uF = ux * Fx + uy * Fy + uz * Fz;
+    {
+        R s = keep * f[0] + omega * (R(kW[0]) * C0);
+        if constexpr (FORCE)
+            s += guo * (R(kW[0]) * (R(-3) * uF));
+        f[0] = s;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1, j = i + 1;
+        const R w = R(kW[i]);
+        const R cu = pair_dot(k, ux, uy, uz);
+        const R even = w * (C0 + rho_times(R(4.5) * (cu * cu)));
+        const R odd = w * rho_times(R(3) * cu);
+        R a = keep * f[i] + omega * (even + odd);
+        R b = keep * f[j] + omega * (even - odd);
+        if constexpr (FORCE) {
+            const R cF = pair_dot(k, Fx, Fy, Fz);
+            const R se = w * (R(9) * cu * cF - R(3) * uF);
+            const R so = R(3) * w * cF;
+            a += guo * (se + so);
+            b += guo * (se - so);
+        }
+        f[i] = a;
+        f[j] = b;
+    }
+}
+
+// Row offsets of rows (y + dy, z + dz), dy, dz in {-1, 0, 1} (periodic), and
+// column offsets of columns x - 1, x, x + 1: node (x, y, z), direction i has
+// element i * 64 + row[dz + 1][dy + 1] + col[dx + 1].
+struct Addr {
+    uint32_t row[3][3];
+    uint32_t col[3];
+};
+
+__device__ __forceinline__ uint32_t col_off(int x)
+{
+    return (((uint32_t)x >> 6) * (uint32_t)(Q * kChunk)) + ((uint32_t)x & 63u);
+}
+
+__device__ __forceinline__ Addr addr_of(int x, int y, int z, int nx, int ny, int nz, uint32_t cpr)
+{
+    Addr a;
+    const int ys[3] = {wrap_dec(y, ny), y, wrap_inc(y, ny)};
+    const int zs[3] = {wrap_dec(z, nz), z, wrap_inc(z, nz)};
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+            a.row[dz][dy] = ((uint32_t)zs[dz] * (uint32_t)ny + (uint32_t)ys[dy]) * cpr *
+                            (uint32_t)(Q * kChunk);
+    a.col[0] = col_off(wrap_dec(x, nx));
+    a.col[1] = col_off(x);
+    a.col[2] = col_off(wrap_inc(x, nx));
+    return a;
+}
+
+// Pull gather: f_i(x) = s_i(x - c_i), or s_opp(i)(x) when x - c_i is solid
+// (bit i of sm).
+template <class ST>
+__device__ __forceinline__ void pull3(const typename ST::mem *__restrict__ s, const Addr &a,
+                                      uint32_t sm, typename ST::real (&f)[Q])
+{
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const uint32_t o = ((sm >> i) & 1u)
+                               ? (uint32_t)kOpp[i] * kChunk + a.row[1][1] + a.col[1]
+                               : (uint32_t)i * kChunk + a.row[1 - kCz[i]][1 - kCy[i]] +
+                                     a.col[1 - kCx[i]];
+        f[i] = ST::ld(s[o], i);
+    }
+}
+
+__device__ __forceinline__ uint32_t solid_bits3(uint8_t t, const uint32_t *__restrict__ nmask,
+                                                uint32_t n)
+{
+    return t == kBoundary ? nmask[n] << 1 : 0u;
+}
+
+template <class ST, bool FORCE>
+__global__ __launch_bounds__(kBlock) void k_step3(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
+    const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask,
+    const uint32_t *__restrict__ seg_interior, int nx, int ny, int nz, int pitch, uint32_t bpr,
+    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy,
+    typename ST::real gz)
+{
+    using R = typename ST::real;
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t r = L / bpr;  // row index z * ny + y
+    const int x = (int)(L - r * bpr) * kBlock + (int)threadIdx.x;
+    if (x >= nx)
+        return;
+    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
+    const uint32_t n = r * (uint32_t)pitch + (uint32_t)x;
+    uint32_t sm = 0;
+    if (!seg_interior[L]) {
+        const uint8_t t = type[n];
+        if (t == kSolid)
+            return;
+        sm = solid_bits3(t, nmask, n);
+    }
+    const Addr a = addr_of(x, y, z, nx, ny, nz, (uint32_t)pitch / kChunk);
+    R f[Q];
+    pull3<ST>(src, a, sm, f);
+    collide3<R, ST::kShift, FORCE>(f, omega, gx, gy, gz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        store_nt(&dst[(uint32_t)i * kChunk + a.row[1][1] + a.col[1]], ST::st(f[i], i));
+}
+
+// ------------------------------------------------------------ canonical views --
+// Canonical FP64 buffers are [19][nz][ny][pitch].
+
+// Thread gid = node (z * ny + y) * pitch + x: the canonical (pull-gathered)
+// populations of a fluid node; false for padding and solid nodes.
+template <class ST>
+__device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST::mem *st,
+                                             uint32_t gid, int &x, int &y, int &z,
+                                             double (&fd)[Q])
+{
+    const uint32_t r = gid / (uint32_t)s.pitch;
+    x = (int)(gid - r * (uint32_t)s.pitch);
+    if (x >= s.nx || r >= (uint32_t)(s.ny * s.nz))
+        return false;
+    y = (int)(r % (uint32_t)s.ny);
+    z = (int)(r / (uint32_t)s.ny);
+    const uint8_t t = s.type[gid];
+    if (t == kSolid)
+        return false;
+    const Addr a = addr_of(x, y, z, s.nx, s.ny, s.nz, (uint32_t)s.pitch / kChunk);
+    typename ST::real f[Q];
+    pull3<ST>(st, a, solid_bits3(t, s.nmask, gid), f);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        fd[i] = ST::canon(f[i], i);
+    return true;
+}
+
+template <class ST>
+__global__ __launch_bounds__(kBlock) void k_gather3(State3 s, const typename ST::mem *st,
+                                                    double *__restrict__ fc)
+{
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    int x, y, z;
+    double f[Q];
+    if (!canonical_at<ST>(s, st, gid, x, y, z, f))
+        return;
+    const uint32_t plane = (uint32_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        fc[(uint32_t)i * plane + gid] = f[i];
+}
+
+// Macroscopic fields (Eq. 2 with the half-force velocity) into [nz][ny][nx]
+// buffers, and per-block partial sums of rho (for the mass).
+template <class ST>
+__global__ __launch_bounds__(kBlock) void k_macro3(State3 s, const typename ST::mem *st,
+                                                   double *rho, double *ux, double *uy,
+                                                   double *uz, double *partials)
+{
+    __shared__ double ws[kBlock / 64];
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    int x, y, z;
+    double f[Q];
+    double r = 0.0;
+    if (canonical_at<ST>(s, st, gid, x, y, z, f)) {
+        double mx = 0.0, my = 0.0, mz = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            r += f[i];
+            mx += kCx[i] * f[i];
+            my += kCy[i] * f[i];
+            mz += kCz[i] * f[i];
+        }
+        if (rho) {
+            const size_t o = ((size_t)z * s.ny + y) * s.nx + x;
+            rho[o] = r;
+            ux[o] = mx / r + 0.5 * s.gx;
+            uy[o] = my / r + 0.5 * s.gy;
+            uz[o] = mz / r + 0.5 * s.gz;
+        }
+    }
+    if (partials) {
+        for (int o = 32; o > 0; o >>= 1)
+            r += __shfl_down(r, o, 64);
+        if ((threadIdx.x & 63) == 0)
+            ws[threadIdx.x >> 6] = r;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < kBlock / 64; ++i)
+                t += ws[i];
+            partials[blockIdx.x] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum3(const double *__restrict__ in, uint32_t n,
+                                                 uint32_t per, double *__restrict__ out)
+{
+    __shared__ double ws[kBlock / 64];
+    const uint32_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    double t = 0.0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock)
+        t += in[i];
+    for (int o = 32; o > 0; o >>= 1)
+        t += __shfl_down(t, o, 64);
+    if ((threadIdx.x & 63) == 0)
+        ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double u = 0.0;
+        for (int i = 0; i < kBlock / 64; ++i)
+            u += ws[i];
+        out[blockIdx.x] = u;
+    }
+}
+
+// Equilibrium (Eq. 6, D3Q19 weights) into a canonical buffer; NULL fields:
+// rho = 1, u = 0.
+__global__ __launch_bounds__(kBlock) void k_equilibrium3(State3 s, const double *__restrict__ rho,
+                                                         const double *__restrict__ ux,
+                                                         const double *__restrict__ uy,
+                                                         const double *__restrict__ uz,
+                                                         double *__restrict__ fc)
+{
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t r = gid / (uint32_t)s.pitch;
+    const int x = (int)(gid - r * (uint32_t)s.pitch);
+    if (x >= s.nx || r >= (uint32_t)(s.ny * s.nz))
+        return;
+    const size_t o = (size_t)r * s.nx + x;
+    const double d = rho ? rho[o] : 1.0, u = ux ? ux[o] : 0.0, v = uy ? uy[o] : 0.0,
+                 w = uz ? uz[o] : 0.0;
+    const double usq = u * u + v * v + w * w;
+    const uint32_t plane = (uint32_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+    for (int i = 0; i < Q; ++i) {
+        const double cu = kCx[i] * u + kCy[i] * v + kCz[i] * w;
+        fc[(uint32_t)i * plane + gid] = kW[i] * d * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    }
+}
+
+// Canonical -> stored A-B state: slot s_j(q) streams into f_j(q + c_j), or,
+// when q + c_j is solid, into f_opp(j)(q) (the inverse of the pull gather).
+template <class ST>
+__global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem *st,
+                                                     const double *__restrict__ fc)
+{
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t r = gid / (uint32_t)s.pitch;
+    const int x = (int)(gid - r * (uint32_t)s.pitch);
+    if (x >= s.nx || r >= (uint32_t)(s.ny * s.nz))
+        return;
+    const uint8_t t = s.type[gid];
+    if (t == kSolid)
+        return;
+    const int y = (int)(r % (uint32_t)s.ny), z = (int)(r / (uint32_t)s.ny);
+    const uint32_t sm = solid_bits3(t, s.nmask, gid);
+    const uint32_t plane = (uint32_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+    const Addr a = addr_of(x, y, z, s.nx, s.ny, s.nz, (uint32_t)s.pitch / kChunk);
+    for (int j = 0; j < Q; ++j) {
+        double v;
+        // q + c_j is node q - c_opp(j): solid iff bit opp(j) is set
+        if ((sm >> kOpp[j]) & 1u) {
+            v = fc[(uint32_t)kOpp[j] * plane + gid];
+        } else {
+            const int xs = x + kCx[j] < 0 ? s.nx - 1 : (x + kCx[j] >= s.nx ? 0 : x + kCx[j]);
+            const int ys = y + kCy[j] < 0 ? s.ny - 1 : (y + kCy[j] >= s.ny ? 0 : y + kCy[j]);
+            const int zs = z + kCz[j] < 0 ? s.nz - 1 : (z + kCz[j] >= s.nz ? 0 : z + kCz[j]);
+            v = fc[(uint32_t)j * plane + ((uint32_t)zs * s.ny + ys) * (uint32_t)s.pitch + xs];
+        }
+        st[(uint32_t)j * kChunk + a.row[1][1] + a.col[1]] = ST::from_canon(v, j);
+    }
+}
+
+template <class ST>
+hipError_t step_typed(const State3 &s, int cur)
+{
+    using M = typename ST::mem;
+    using R = typename ST::real;
+    const uint32_t bpr = (uint32_t)((s.nx + kBlock - 1) / kBlock);
+    const uint32_t nb = bpr * (uint32_t)s.ny * (uint32_t)s.nz;
+    const M *src = (const M *)s.f[cur];
+    M *dst = (M *)s.f[1 - cur];
+    if (s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0)
+        k_step3<ST, true><<<nb, kBlock, 0, s.stream>>>(
+            src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
+            (R)s.omega, (R)s.gx, (R)s.gy, (R)s.gz);
+    else
+        k_step3<ST, false><<<nb, kBlock, 0, s.stream>>>(
+            src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
+            (R)s.omega, R(0), R(0), R(0));
+    return hipGetLastError();
+}
+
+uint32_t node_blocks(const State3 &s)
+{
+    return (uint32_t)(((int64_t)s.nz * s.ny * s.pitch + kBlock - 1) / kBlock);
+}
+
+}  // namespace
+
+hipError_t launch_step3(const State3 &s, int cur)
+{
+    switch (s.dtype) {
+    case 0: return step_typed<F64>(s, cur);
+    case 1: return step_typed<Shifted<float>>(s, cur);
+    case 2: return step_typed<Shifted<_Float16>>(s, cur);
+    case 3: return step_typed<Shifted<__bf16>>(s, cur);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_equilibrium3(const State3 &s, const double *rho, const double *ux,
+                               const double *uy, const double *uz, double *fc)
+{
+    k_equilibrium3<<<node_blocks(s), kBlock, 0, s.stream>>>(s, rho, ux, uy, uz, fc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter3(const State3 &s, int cur, const double *fc)
+{
+    void *dst = s.f[cur];
+    const uint32_t nb = node_blocks(s);
+    switch (s.dtype) {
+    case 0: k_scatter3<F64><<<nb, kBlock, 0, s.stream>>>(s, (double *)dst, fc); break;
+    case 1: k_scatter3<Shifted<float>><<<nb, kBlock, 0, s.stream>>>(s, (float *)dst, fc); break;
+    case 2:
+        k_scatter3<Shifted<_Float16>><<<nb, kBlock, 0, s.stream>>>(s, (_Float16 *)dst, fc);
+        break;
+    case 3:
+        k_scatter3<Shifted<__bf16>><<<nb, kBlock, 0, s.stream>>>(s, (__bf16 *)dst, fc);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather3(const State3 &s, int cur, double *fc)
+{
+    const void *src = s.f[cur];
+    const uint32_t nb = node_blocks(s);
+    switch (s.dtype) {
+    case 0: k_gather3<F64><<<nb, kBlock, 0, s.stream>>>(s, (const double *)src, fc); break;
+    case 1:
+        k_gather3<Shifted<float>><<<nb, kBlock, 0, s.stream>>>(s, (const float *)src, fc);
+        break;
+    case 2:
+        k_gather3<Shifted<_Float16>><<<nb, kBlock, 0, s.stream>>>(s, (const _Float16 *)src, fc);
+        break;
+    case 3:
+        k_gather3<Shifted<__bf16>><<<nb, kBlock, 0, s.stream>>>(s, (const __bf16 *)src, fc);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int64_t reduction_capacity3(const State3 &s)
+{
+    const int64_t nb = node_blocks(s);
+    return nb + (nb + 2047) / 2048 + 1;
+}
+
+hipError_t launch_macro3(const State3 &s, int cur, double *rho, double *ux, double *uy, double *uz,
+                         double *mass)
+{
+    const void *src = s.f[cur];
+    const uint32_t nb = node_blocks(s);
+    double *part = mass ? s.red : nullptr;
+    switch (s.dtype) {
+    case 0:
+        k_macro3<F64><<<nb, kBlock, 0, s.stream>>>(s, (const double *)src, rho, ux, uy, uz, part);
+        break;
+    case 1:
+        k_macro3<Shifted<float>><<<nb, kBlock, 0, s.stream>>>(s, (const float *)src, rho, ux, uy,
+                                                              uz, part);
+        break;
+    case 2:
+        k_macro3<Shifted<_Float16>><<<nb, kBlock, 0, s.stream>>>(s, (const _Float16 *)src, rho,
+                                                                 ux, uy, uz, part);
+        break;
+    case 3:
+        k_macro3<Shifted<__bf16>><<<nb, kBlock, 0, s.stream>>>(s, (const __bf16 *)src, rho, ux, uy,
+                                                               uz, part);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    if (mass) {
+        // fixed-order sums: blocks of 2048 partials, then one block
+        const uint32_t nst = (nb + 2047) / 2048;
+        k_sum3<<<nst, kBlock, 0, s.stream>>>(s.red, nb, 2048, s.red + nb);
+        k_sum3<<<1, kBlock, 0, s.stream>>>(s.red + nb, nst, nst, mass);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm3

@@ -1,0 +1,52 @@
+// Internal interface between the D3Q19 host runtime (lbm3d_runtime.cpp) and
+// its HIP kernels (lbm3d_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+// The process-wide device allocator registered with lbm_set_allocator (both
+// NULL: hipMalloc / hipFree).
+void current_allocator(lbm_alloc_fn *alloc, lbm_free_fn *free_fn, void **user);
+}  // namespace lbm
+
+namespace lbm3 {
+
+// Device state of a D3Q19 context.  Populations: [nz][ny][pitch/64][19][64]
+// (chunks of 64 nodes along x, 19 runs of 64 each); types, neighbour bits and
+// canonical planes use the padded node index (z * ny + y) * pitch + x.
+struct State3 {
+    int dtype = 0;
+    int nx = 0, ny = 0, nz = 0;
+    int pitch = 0;                           // nx rounded up to a multiple of 64
+    void *f[2] = {nullptr, nullptr};         // the two lattices (A-B)
+    const uint8_t *type = nullptr;           // 0 fluid, 1 solid, 2 fluid next to a solid
+    const uint32_t *nmask = nullptr;         // bit i-1 set <=> node x - c_i is solid
+    const uint32_t *seg_interior = nullptr;  // per 256-node row segment: 1 = all type 0
+    double omega = 1.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    hipStream_t stream = nullptr;
+    double *red = nullptr;                   // reduction scratch (reduction_capacity3 doubles)
+};
+
+// One step from lattice cur into lattice 1 - cur.
+hipError_t launch_step3(const State3 &s, int cur);
+// Equilibrium of device FP64 [nz][ny][nx] fields (NULL: rho = 1, u = 0) into the
+// canonical buffer fc (FP64 [19][nz][ny][pitch]).
+hipError_t launch_equilibrium3(const State3 &s, const double *rho, const double *ux,
+                               const double *uy, const double *uz, double *fc);
+// Canonical fc -> stored lattice cur.
+hipError_t launch_scatter3(const State3 &s, int cur, const double *fc);
+// Stored lattice cur -> canonical fc at fluid nodes (other slots untouched).
+hipError_t launch_gather3(const State3 &s, int cur, double *fc);
+// Macroscopic fields of fluid nodes into FP64 [nz][ny][nx] buffers (rho may be
+// NULL to skip them; other entries untouched) and, when mass is non-NULL, the
+// total mass into *mass (device) through fixed-order sums in s.red.
+hipError_t launch_macro3(const State3 &s, int cur, double *rho, double *ux, double *uy, double *uz,
+                         double *mass);
+int64_t reduction_capacity3(const State3 &s);
+
+}  // namespace lbm3

@@ -1,0 +1,444 @@
+// C ABI of the D3Q19 lattice: argument checks, geometry preprocessing (node
+// types, solid-neighbour bits, interior-segment flags), device buffers and
+// kernel sequencing.  All arithmetic of the method runs in the HIP kernels.
+#include "lbm3d.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm3d_launch.h"
+#include "lbm_launch.h"
+
+namespace {
+
+thread_local std::string t_last_error3 = "no error";
+
+int fail_tl(int status, const std::string &msg)
+{
+    t_last_error3 = msg;
+    return status;
+}
+
+constexpr int Q = 19;
+// Velocities in the order of the public header.
+constexpr int kCx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kCy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kCz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+bool finite3(const double *v)
+{
+    return !v || (std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]));
+}
+
+}  // namespace
+
+struct lbm3d_ctx {
+    lbm3::State3 s;
+    lbm_alloc_fn alloc = nullptr;
+    lbm_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    int64_t t = 0;
+    int cur = 0;
+    bool broken = false;
+    std::string last_error = "no error";
+    std::vector<uint8_t> mask;  // host copy [nz][ny][nx]
+    std::vector<void *> owned;
+    size_t device_bytes = 0;
+    int pop_bytes = 8;
+    int64_t n_fluid = 0;
+    double *red_out = nullptr;
+};
+
+namespace {
+
+int fail(lbm3d_ctx *c, int status, const std::string &msg)
+{
+    c->last_error = msg;
+    return status;
+}
+
+int fail_device(lbm3d_ctx *c, hipError_t e, const char *what)
+{
+    c->broken = true;
+    c->last_error = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+    return LBM_ERR_DEVICE;
+}
+
+#define LBM3_HIP(c, expr)                             \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess)                         \
+            return fail_device((c), e_, #expr);       \
+    } while (0)
+
+#define LBM3_CHECK_CTX(c)                                                                    \
+    do {                                                                                     \
+        if (!(c))                                                                            \
+            return fail_tl(LBM_ERR_INVALID, "context is NULL");                              \
+        if ((c)->broken)                                                                     \
+            return fail((c), LBM_ERR_STATE,                                                  \
+                        "context broken by an earlier error: " + (c)->last_error);           \
+    } while (0)
+
+void *raw_alloc(const lbm3d_ctx *c, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 256;
+    if (c->alloc)
+        return c->alloc(bytes, c->user);
+    void *p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void raw_free(const lbm3d_ctx *c, void *p)
+{
+    if (!p)
+        return;
+    if (c->free_fn)
+        c->free_fn(p, c->user);
+    else
+        (void)hipFree(p);
+}
+
+void *own_alloc(lbm3d_ctx *c, size_t bytes)
+{
+    void *p = raw_alloc(c, bytes);
+    if (p) {
+        c->owned.push_back(p);
+        c->device_bytes += bytes;
+    }
+    return p;
+}
+
+struct Temp {
+    lbm3d_ctx *c;
+    void *p = nullptr;
+    Temp(lbm3d_ctx *c_, size_t bytes) : c(c_) { p = raw_alloc(c, bytes); }
+    ~Temp()
+    {
+        if (p) {
+            (void)hipStreamSynchronize(c->s.stream);
+            raw_free(c, p);
+        }
+    }
+    Temp(const Temp &) = delete;
+    Temp &operator=(const Temp &) = delete;
+};
+
+size_t padded_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s.pitch; }
+size_t canonical_bytes(const lbm3d_ctx *c) { return (size_t)Q * padded_nodes(c) * sizeof(double); }
+size_t field_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s.nx; }
+
+// Node types, solid-neighbour bits and interior-segment flags of a mask:
+// type 0 = fluid with no solid neighbour, 1 = solid, 2 = fluid with one; bit
+// i-1 of nbits = node x - c_i is solid; a 256-node row segment is interior when
+// all its nodes inside the mesh have type 0.  Padding columns are solid.
+void plan_types(const uint8_t *mask, int nx, int ny, int nz, int pitch, std::vector<uint8_t> &type,
+                std::vector<uint32_t> &nbits, std::vector<uint32_t> &seg)
+{
+    const size_t np = (size_t)nz * ny * pitch;
+    type.assign(np, 1);
+    nbits.assign(np, 0);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t n = ((size_t)z * ny + y) * nx + x;
+                const size_t p = ((size_t)z * ny + y) * pitch + x;
+                if (mask[n]) {
+                    type[p] = 1;
+                    continue;
+                }
+                uint32_t b = 0;
+                for (int i = 1; i < Q; ++i) {
+                    const int xs = wrap(x - kCx[i], nx), ys = wrap(y - kCy[i], ny),
+                              zs = wrap(z - kCz[i], nz);
+                    if (mask[((size_t)zs * ny + ys) * nx + xs])
+                        b |= 1u << (i - 1);
+                }
+                nbits[p] = b;
+                type[p] = b ? 2 : 0;
+            }
+    const int bpr = (nx + 255) / 256;
+    seg.assign((size_t)nz * ny * bpr, 1);
+    for (int r = 0; r < nz * ny; ++r)
+        for (int x = 0; x < nx; ++x)
+            if (type[(size_t)r * pitch + x] != 0)
+                seg[(size_t)r * bpr + x / 256] = 0;
+}
+
+int init_state(lbm3d_ctx *c, const double *rho, const double *ux, const double *uy,
+               const double *uz)
+{
+    const size_t field = field_nodes(c) * sizeof(double);
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    const double *h[4] = {rho, ux, uy, uz};
+    Temp d0(c, rho ? field : 0), d1(c, ux ? field : 0), d2(c, uy ? field : 0),
+        d3(c, uz ? field : 0);
+    Temp *d[4] = {&d0, &d1, &d2, &d3};
+    const double *dp[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4; ++k)
+        if (h[k]) {
+            if (!d[k]->p)
+                return fail(c, LBM_ERR_NOMEM, "cannot allocate the field staging buffer");
+            LBM3_HIP(c, hipMemcpyAsync(d[k]->p, h[k], field, hipMemcpyHostToDevice, c->s.stream));
+            dp[k] = (const double *)d[k]->p;
+        }
+    c->t = 0;
+    c->cur = 0;
+    LBM3_HIP(c, lbm3::launch_equilibrium3(c->s, dp[0], dp[1], dp[2], dp[3], (double *)fc.p));
+    LBM3_HIP(c, lbm3::launch_scatter3(c->s, c->cur, (const double *)fc.p));
+    LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm3d_destroy(lbm3d_ctx *c)
+{
+    if (!c)
+        return;
+    (void)hipStreamSynchronize(c->s.stream);
+    for (void *p : c->owned)
+        raw_free(c, p);
+    delete c;
+}
+
+int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint8_t *node_type,
+                 double tau, const double *force, lbm_dtype dtype)
+{
+    if (!out)
+        return fail_tl(LBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1)
+        return fail_tl(LBM_ERR_INVALID, "nx, ny and nz must be >= 1");
+    if (!node_type)
+        return fail_tl(LBM_ERR_INVALID, "node_type is NULL");
+    if (!std::isfinite(tau) || !(tau > 0.5))
+        return fail_tl(LBM_ERR_INVALID, "tau must be finite and > 1/2");
+    if (!finite3(force))
+        return fail_tl(LBM_ERR_INVALID, "force must be finite");
+    if ((int)dtype < 0 || (int)dtype > 3)
+        return fail_tl(LBM_ERR_INVALID, "unknown dtype");
+    const int64_t pitch = ((int64_t)nx + 63) / 64 * 64;
+    if ((int64_t)Q * nz * ny * pitch >= (int64_t(1) << 32))
+        return fail_tl(LBM_ERR_UNSUPPORTED, "mesh too large for 32-bit lattice offsets");
+    const size_t nn = (size_t)nx * ny * nz;
+    for (size_t k = 0; k < nn; ++k)
+        if (node_type[k] > 1)
+            return fail_tl(LBM_ERR_INVALID, "node_type values must be 0 (fluid) or 1 (solid)");
+
+    lbm3d_ctx *c = new (std::nothrow) lbm3d_ctx();
+    if (!c)
+        return fail_tl(LBM_ERR_NOMEM, "cannot allocate the context");
+    lbm::current_allocator(&c->alloc, &c->free_fn, &c->user);
+    lbm3::State3 &s = c->s;
+    s.dtype = dtype;
+    s.nx = nx;
+    s.ny = ny;
+    s.nz = nz;
+    s.pitch = (int)pitch;
+    s.omega = 1.0 / tau;
+    s.gx = force ? force[0] : 0.0;
+    s.gy = force ? force[1] : 0.0;
+    s.gz = force ? force[2] : 0.0;
+    c->pop_bytes = dtype == LBM_F64 ? 8 : dtype == LBM_F32 ? 4 : 2;
+    c->mask.assign(node_type, node_type + nn);
+    for (size_t k = 0; k < nn; ++k)
+        c->n_fluid += node_type[k] == 0;
+
+    auto fail_create = [&](int st, const std::string &m) {
+        t_last_error3 = m;
+        lbm3d_destroy(c);
+        return st;
+    };
+    auto upload = [&](const void *h, size_t bytes, void **dst) -> int {
+        *dst = own_alloc(c, bytes);
+        if (!*dst)
+            return LBM_ERR_NOMEM;
+        if (bytes && hipMemcpy(*dst, h, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return LBM_ERR_DEVICE;
+        return LBM_OK;
+    };
+    std::vector<uint8_t> type;
+    std::vector<uint32_t> nbits, seg;
+    plan_types(node_type, nx, ny, nz, (int)pitch, type, nbits, seg);
+    void *p = nullptr;
+    int rc;
+    if ((rc = upload(type.data(), type.size(), &p)))
+        return fail_create(rc, "cannot upload the node types");
+    s.type = (const uint8_t *)p;
+    if ((rc = upload(nbits.data(), nbits.size() * 4, &p)))
+        return fail_create(rc, "cannot upload the neighbour bits");
+    s.nmask = (const uint32_t *)p;
+    if ((rc = upload(seg.data(), seg.size() * 4, &p)))
+        return fail_create(rc, "cannot upload the segment flags");
+    s.seg_interior = (const uint32_t *)p;
+    const size_t lattice = (size_t)Q * padded_nodes(c) * c->pop_bytes;
+    for (int k = 0; k < 2; ++k) {
+        s.f[k] = own_alloc(c, lattice);
+        if (!s.f[k])
+            return fail_create(LBM_ERR_NOMEM, "cannot allocate the lattice");
+    }
+    s.red = (double *)own_alloc(c, (size_t)lbm3::reduction_capacity3(s) * sizeof(double));
+    c->red_out = (double *)own_alloc(c, sizeof(double));
+    if (!s.red || !c->red_out)
+        return fail_create(LBM_ERR_NOMEM, "cannot allocate reduction scratch");
+    rc = init_state(c, nullptr, nullptr, nullptr, nullptr);
+    if (rc)
+        return fail_create(rc, c->last_error);
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm3d_set_stream(lbm3d_ctx *c, void *hip_stream)
+{
+    LBM3_CHECK_CTX(c);
+    LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+    c->s.stream = (hipStream_t)hip_stream;
+    return LBM_OK;
+}
+
+int lbm3d_init_equilibrium(lbm3d_ctx *c, const double *rho, const double *ux, const double *uy,
+                           const double *uz)
+{
+    LBM3_CHECK_CTX(c);
+    const size_t nn = field_nodes(c);
+    for (size_t k = 0; k < nn; ++k) {
+        if (c->mask[k] != 0)
+            continue;
+        if ((rho && !(std::isfinite(rho[k]) && rho[k] > 0)) || (ux && !std::isfinite(ux[k])) ||
+            (uy && !std::isfinite(uy[k])) || (uz && !std::isfinite(uz[k])))
+            return fail(c, LBM_ERR_INVALID, "initial fields must be finite with rho > 0");
+    }
+    return init_state(c, rho, ux, uy, uz);
+}
+
+int lbm3d_set_force(lbm3d_ctx *c, const double *force)
+{
+    LBM3_CHECK_CTX(c);
+    if (!force || !finite3(force))
+        return fail(c, LBM_ERR_INVALID, "force must be three finite numbers");
+    c->s.gx = force[0];
+    c->s.gy = force[1];
+    c->s.gz = force[2];
+    return LBM_OK;
+}
+
+int lbm3d_step(lbm3d_ctx *c, int64_t n)
+{
+    LBM3_CHECK_CTX(c);
+    if (n < 0)
+        return fail(c, LBM_ERR_INVALID, "n must be >= 0");
+    for (int64_t k = 0; k < n; ++k) {
+        LBM3_HIP(c, lbm3::launch_step3(c->s, c->cur));
+        c->cur ^= 1;
+        ++c->t;
+    }
+    return LBM_OK;
+}
+
+int lbm3d_macroscopic(lbm3d_ctx *c, double *rho, double *ux, double *uy, double *uz)
+{
+    LBM3_CHECK_CTX(c);
+    const size_t nn = field_nodes(c), bytes = nn * sizeof(double);
+    Temp d(c, 4 * bytes);
+    if (!d.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the output staging buffer");
+    double *b = (double *)d.p;
+    LBM3_HIP(c, lbm::launch_fill(b, 4 * nn, 0.0, c->s.stream));
+    LBM3_HIP(c, lbm3::launch_macro3(c->s, c->cur, b, b + nn, b + 2 * nn, b + 3 * nn, nullptr));
+    double *h[4] = {rho, ux, uy, uz};
+    for (int k = 0; k < 4; ++k)
+        if (h[k])
+            LBM3_HIP(c, hipMemcpyAsync(h[k], b + k * nn, bytes, hipMemcpyDeviceToHost,
+                                       c->s.stream));
+    LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm3d_get_populations(lbm3d_ctx *c, double *f)
+{
+    LBM3_CHECK_CTX(c);
+    if (!f)
+        return fail(c, LBM_ERR_INVALID, "f is NULL");
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    LBM3_HIP(c, lbm::launch_fill((double *)fc.p, canonical_bytes(c) / 8, 0.0, c->s.stream));
+    LBM3_HIP(c, lbm3::launch_gather3(c->s, c->cur, (double *)fc.p));
+    const size_t w = (size_t)c->s.nx * sizeof(double);
+    LBM3_HIP(c, hipMemcpy2DAsync(f, w, fc.p, (size_t)c->s.pitch * sizeof(double), w,
+                                 (size_t)Q * c->s.nz * c->s.ny, hipMemcpyDeviceToHost,
+                                 c->s.stream));
+    LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm3d_set_populations(lbm3d_ctx *c, const double *f)
+{
+    LBM3_CHECK_CTX(c);
+    if (!f)
+        return fail(c, LBM_ERR_INVALID, "f is NULL");
+    const size_t nn = field_nodes(c);
+    for (int i = 0; i < Q; ++i)
+        for (size_t k = 0; k < nn; ++k)
+            if (c->mask[k] == 0 && !std::isfinite(f[i * nn + k]))
+                return fail(c, LBM_ERR_INVALID, "populations must be finite at fluid nodes");
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    const size_t w = (size_t)c->s.nx * sizeof(double);
+    LBM3_HIP(c, hipMemcpy2DAsync(fc.p, (size_t)c->s.pitch * sizeof(double), f, w, w,
+                                 (size_t)Q * c->s.nz * c->s.ny, hipMemcpyHostToDevice,
+                                 c->s.stream));
+    LBM3_HIP(c, lbm3::launch_scatter3(c->s, c->cur, (const double *)fc.p));
+    LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm3d_mass(lbm3d_ctx *c, double *mass)
+{
+    LBM3_CHECK_CTX(c);
+    if (!mass)
+        return fail(c, LBM_ERR_INVALID, "mass is NULL");
+    LBM3_HIP(c, lbm3::launch_macro3(c->s, c->cur, nullptr, nullptr, nullptr, nullptr, c->red_out));
+    LBM3_HIP(c, hipMemcpyAsync(mass, c->red_out, sizeof(double), hipMemcpyDeviceToHost,
+                               c->s.stream));
+    LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
+int lbm3d_get_info(const lbm3d_ctx *c, lbm3d_info_t *info)
+{
+    if (!c || !info)
+        return fail_tl(LBM_ERR_INVALID, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->nx = c->s.nx;
+    info->ny = c->s.ny;
+    info->nz = c->s.nz;
+    info->dtype = c->s.dtype;
+    info->n_nodes = (int64_t)c->s.nx * c->s.ny * c->s.nz;
+    info->n_fluid = c->n_fluid;
+    info->time_step = c->t;
+    info->pop_bytes = c->pop_bytes;
+    info->bytes_per_fluid_node = 2.0 * Q * c->pop_bytes + 1.0;
+    info->device_bytes = c->device_bytes;
+    return LBM_OK;
+}
+
+const char *lbm3d_last_error(const lbm3d_ctx *c)
+{
+    return c ? c->last_error.c_str() : t_last_error3.c_str();
+}
+
+}  // extern "C"

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "lbm3d_launch.h"
 #include "lbm_launch.h"
 #include "lbm_plan.h"
 
@@ -38,6 +39,14 @@ int fail_tl(int status, const std::string &msg)
 int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
 }  // namespace
+
+void lbm::current_allocator(lbm_alloc_fn *alloc, lbm_free_fn *free_fn, void **user)
+{
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    *alloc = g_alloc.alloc;
+    *free_fn = g_alloc.free;
+    *user = g_alloc.user;
+}
 
 struct lbm_ctx {
     lbm::DevState s;

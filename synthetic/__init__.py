@@ -14,7 +14,10 @@ Workloads (the paper measures on synthetic geometries of its own; these stand in
   * open channels (Sec. 4.1, chan_v / chan_p): walls at y = 0 and y = ny - 1, a constant
     velocity or constant pressure inlet column at x = 0 and a constant pressure outlet
     column at x = nx - 1;
-  * lid-driven cavity (Sec. 4.1): solid side and bottom walls, a constant-velocity lid.
+  * lid-driven cavity (Sec. 4.1): solid side and bottom walls, a constant-velocity lid;
+  * 3-D (D3Q19) inputs, arrays [nz, ny, nx]: the three-dimensional Taylor-Green vortex
+    (all fluid, periodic), random solids with optional walls at z = 0 and z = nz - 1,
+    random fields, and random populations scaled per direction.
 
 Open-boundary codes (one byte per node): 0 none, 1..4 constant velocity with inward
 normal +x, -x, +y, -y, 5..8 constant pressure with the same normals; values [2, ny, nx]
@@ -326,3 +329,53 @@ def open_box(n: int):
     m = _walls(n)
     bc, value = _open_ends(m)
     return m, bc, value, {"kind": "dense", "phi_achieved": float((m == 0).sum()) / (n * n)}
+
+
+# ------------------------------------------------------------------ 3-D inputs --
+def taylor_green3(n: int, u0: float = 0.01):
+    """Three-dimensional Taylor-Green vortex on a periodic n^3 lattice, k = 2 pi / n:
+    u_x = u0 sin(kx) cos(ky) cos(kz), u_y = -u0 cos(kx) sin(ky) cos(kz), u_z = 0,
+    p - p0 = (u0^2 / 16) (cos 2kx + cos 2ky)(cos 2kz + 2) with rho = 1 + 3 (p - p0).
+    Returns (rho, ux, uy, uz) as float64 [n, n, n] (index [z, y, x])."""
+    k = 2.0 * math.pi / n
+    c = np.arange(n, dtype=np.float64) * k
+    x, y, z = c[None, None, :], c[None, :, None], c[:, None, None]
+    ux = u0 * np.sin(x) * np.cos(y) * np.cos(z)
+    uy = -u0 * np.cos(x) * np.sin(y) * np.cos(z)
+    uz = np.zeros((n, n, n))
+    rho = 1.0 + 3.0 * (u0 * u0 / 16.0) * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
+    return tuple(np.ascontiguousarray(np.broadcast_to(a, (n, n, n))) for a in (rho, ux, uy, uz))
+
+
+def random_mask3(nx: int, ny: int, nz: int, seed: int, solid_fraction: float = 0.15,
+                 walls: bool = False) -> np.ndarray:
+    """Independent random solid nodes [nz, ny, nx]; walls: solid planes z = 0 and nz - 1."""
+    rng = np.random.default_rng(seed)
+    m = (rng.random((nz, ny, nx)) < solid_fraction).astype(np.uint8)
+    if walls:
+        m[0] = 1
+        m[nz - 1] = 1
+    if not (m == 0).any():
+        m[nz // 2, ny // 2, nx // 2] = 0
+    return m
+
+
+def random_fields3(nx: int, ny: int, nz: int, seed: int, rho_spread: float = 0.03,
+                   u_amp: float = 0.03):
+    """rho in [1 - spread, 1 + spread], each velocity component in [-u_amp, u_amp]."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + rho_spread * (2.0 * rng.random((nz, ny, nx)) - 1.0)
+    u = [u_amp * (2.0 * rng.random((nz, ny, nx)) - 1.0) for _ in range(3)]
+    return (rho, *u)
+
+
+def random_populations(scale, shape, seed: int, amp: float = 0.05) -> np.ndarray:
+    """Populations scale[i] * (1 + amp * U(-1, 1)) of shape [len(scale), *shape] (float64):
+    a state away from equilibrium, so that the collision's relaxation is exercised."""
+    rng = np.random.default_rng(seed)
+    scale = np.asarray(scale, np.float64).reshape((-1,) + (1,) * len(shape))
+    f = rng.random((scale.shape[0],) + tuple(shape))
+    f *= 2.0 * amp
+    f += 1.0 - amp
+    f *= scale
+    return f

@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads and exports every
-function include/lbm.h declares, argument validation fails with the documented status
+function include/*.h declares, argument validation fails with the documented status
 before touching the device, and the geometry planners agree with brute force."""
+import glob
 import os
 import re
 
@@ -13,10 +14,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    hdr = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(lbm_\w+)\s*\(", hdr,
-                                 flags=re.M)))
+    names = set()
+    for path in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        hdr = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names |= set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(lbm\w*_\w+)\s*\(",
+                                hdr, flags=re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +30,8 @@ def lib():
 
 def test_all_declared_symbols_exported(lib):
     names = declared_functions()
-    assert len(names) >= 28
+    assert len(names) >= 40
+    assert "lbm3d_step" in names and "lbm_step" in names
     from paper_2108_13241_amd._lib import SIGNATURES
     for n in names:
         assert hasattr(lib, n), n
@@ -75,6 +79,48 @@ def test_null_context(lib):
     assert lib.lbm_step(None, 1) == -1
     assert lib.lbm_mass(None, ctypes.byref(ctypes.c_double())) == -1
     lib.lbm_destroy(None)
+
+
+def _create3(lib, nx, ny, nz, m, tau=0.8, force=None, dtype=0):
+    import ctypes
+    ctx = ctypes.c_void_p(1)
+    g = (ctypes.c_double * 3)(*force) if force is not None else None
+    st = lib.lbm3d_create(ctypes.byref(ctx), nx, ny, nz,
+                          m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tau, g, dtype)
+    return st, ctx
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(nx=0), -1), (dict(nz=0), -1), (dict(tau=0.5), -1), (dict(tau=float("nan")), -1),
+    (dict(force=(0.0, float("inf"), 0.0)), -1), (dict(dtype=4), -1), (dict(dtype=-1), -1),
+    # 19 * nz * ny * pitch >= 2^32 is refused before any allocation
+    (dict(nx=1024, ny=1024, nz=256), -4),
+])
+def test_create3d_validation(lib, args, status):
+    kw = dict(nx=12, ny=10, nz=6)
+    kw.update(args)
+    nx, ny, nz = kw.pop("nx"), kw.pop("ny"), kw.pop("nz")
+    m = np.zeros(max(nx * ny * nz, 1) if status != -4 else 1, np.uint8)
+    st, ctx = _create3(lib, nx, ny, nz, m, **kw)
+    assert st == status
+    assert not ctx.value
+    assert lib.lbm3d_last_error(None)
+
+
+def test_create3d_rejects_bad_mask(lib):
+    m = np.zeros((4, 5, 6), np.uint8)
+    m[1, 2, 3] = 7
+    st, _ = _create3(lib, 6, 5, 4, m)
+    assert st == -1
+    assert b"node_type" in lib.lbm3d_last_error(None)
+
+
+def test_null_context3d(lib):
+    import ctypes
+    assert lib.lbm3d_step(None, 1) == -1
+    assert lib.lbm3d_mass(None, ctypes.byref(ctypes.c_double())) == -1
+    assert lib.lbm3d_get_info(None, None) == -1
+    lib.lbm3d_destroy(None)
 
 
 def test_allocator_pairing(lib):

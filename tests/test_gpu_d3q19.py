@@ -1,0 +1,218 @@
+"""GPU parity of the D3Q19 lattice (include/lbm3d.h) against the FP64 D3Q19 oracle.
+
+Tolerances (written here, applied to canonical populations at fluid slots):
+  FP64: max |f_gpu - f_oracle| <= 1e-12;   FP32: max |f_gpu - f_oracle| / |f_oracle| <= 1e-5.
+16-bit storage is an approximation of the FP64 result: its velocity error is printed and
+only loosely bounded (parity unpinned for those two formats, as for D2Q9).
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_util import TOL, announce, fp_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_13241_amd as m
+    m.load()
+    return m
+
+
+def run_gpu(lbm, mask, tau, steps, dtype, g=(0.0, 0.0, 0.0), fields=None, f0=None):
+    lat = lbm.Lattice3D(mask, tau, force=g, dtype=dtype)
+    if fields is not None:
+        lat.init_equilibrium(*fields)
+    if f0 is not None:
+        lat.set_populations(f0)
+    lat.step(steps)
+    f = lat.get_populations()
+    lat.close()
+    return f
+
+
+def run_oracle(oracle_mod, mask, tau, steps, g=(0.0, 0.0, 0.0), fields=None, f0=None):
+    if f0 is None:
+        f0 = oracle_mod.init3(mask, *(fields or (None, None, None, None)))
+    return oracle_mod.run3(mask, f0, tau, steps, g=g)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(70, 24, 20), (300, 5, 7)])
+def test_random_solids_vs_oracle(lbm, oracle_mod, dtype, shape):
+    """Random solids (12 %) and walls at z = 0, nz - 1, a body force along all three axes,
+    random initial fields, 41 steps; nx not a multiple of 64 (ragged last chunk) and, for
+    nx = 300, a second 256-node row segment."""
+    nx, ny, nz = shape
+    announce(f"d3q19 random solids {nx}x{ny}x{nz} {dtype}")
+    m = synthetic.random_mask3(nx, ny, nz, seed=4, solid_fraction=0.12, walls=True)
+    fields = synthetic.random_fields3(nx, ny, nz, seed=9)
+    g = (2e-5, -1e-5, 1e-5)
+    ref = run_oracle(oracle_mod, m, 0.7, 41, g=g, fields=fields)
+    got = run_gpu(lbm, m, 0.7, 41, dtype, g=g, fields=fields)
+    assert fp_error(got, ref, m, dtype) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_plane_channel_interior_segments(lbm, oracle_mod, dtype):
+    """Walls at z = 0 and z = 11 only: rows with 2 <= z <= 9 are all-interior segments (the
+    fast path that skips the node-type read), rows next to the walls are not."""
+    announce(f"d3q19 plane channel {dtype}")
+    nx, ny, nz = 512, 6, 12
+    m = np.zeros((nz, ny, nx), np.uint8)
+    m[0] = 1
+    m[nz - 1] = 1
+    fields = synthetic.random_fields3(nx, ny, nz, seed=2, rho_spread=0.01, u_amp=0.01)
+    ref = run_oracle(oracle_mod, m, 0.8, 100, g=(1e-5, 0.0, 0.0), fields=fields)
+    got = run_gpu(lbm, m, 0.8, 100, dtype, g=(1e-5, 0.0, 0.0), fields=fields)
+    assert fp_error(got, ref, m, dtype) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_taylor_green3_vs_oracle(lbm, oracle_mod, dtype):
+    """All-fluid periodic 64^3 Taylor-Green vortex, 60 steps."""
+    announce(f"d3q19 taylor-green 64^3 {dtype}")
+    n = 64
+    m = np.zeros((n, n, n), np.uint8)
+    fields = synthetic.taylor_green3(n, 0.02)
+    ref = run_oracle(oracle_mod, m, 0.6, 60, fields=fields)
+    got = run_gpu(lbm, m, 0.6, 60, dtype, fields=fields)
+    assert fp_error(got, ref, m, dtype) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 5), (3, 1, 1), (2, 3, 1), (65, 2, 3),
+                                   (64, 1, 2)])
+def test_degenerate_shapes(lbm, oracle_mod, dtype, shape):
+    """One-node and one-wide lattices (a node is its own periodic neighbour), and a lattice
+    exactly one chunk wide, with random solids."""
+    nx, ny, nz = shape
+    announce(f"d3q19 degenerate {nx}x{ny}x{nz} {dtype}")
+    m = synthetic.random_mask3(nx, ny, nz, seed=nx * 100 + ny * 10 + nz, solid_fraction=0.25)
+    f0 = synthetic.random_populations(oracle_mod.constants3()[3], (nz, ny, nx), seed=3,
+                                      amp=0.1) * (m == 0)
+    ref = run_oracle(oracle_mod, m, 0.9, 17, g=(1e-4, 2e-4, -1e-4), f0=f0)
+    got = run_gpu(lbm, m, 0.9, 17, dtype, g=(1e-4, 2e-4, -1e-4), f0=f0)
+    assert fp_error(got, ref, m, dtype) <= TOL[dtype]
+
+
+def test_set_force_midway(lbm, oracle_mod):
+    """Changing the force between steps equals two oracle runs with the two forces."""
+    announce("d3q19 set_force midway")
+    nx, ny, nz = 40, 12, 10
+    m = synthetic.random_mask3(nx, ny, nz, seed=5, solid_fraction=0.1, walls=True)
+    ref = oracle_mod.run3(m, oracle_mod.init3(m), 0.75, 20, g=(1e-4, 0.0, 0.0))
+    ref = oracle_mod.run3(m, ref, 0.75, 15, g=(0.0, -2e-4, 5e-5))
+    lat = lbm.Lattice3D(m, 0.75, force=(1e-4, 0.0, 0.0), dtype="f64")
+    lat.step(20)
+    lat.set_force((0.0, -2e-4, 5e-5))
+    lat.step(15)
+    got = lat.get_populations()
+    assert lat.info()["time_step"] == 35
+    lat.close()
+    assert fp_error(got, ref, m, "f64") <= TOL["f64"]
+
+
+def test_populations_roundtrip(lbm, oracle_mod):
+    """set then get returns the canonical state exactly (FP64), from either lattice."""
+    announce("d3q19 roundtrip")
+    nx, ny, nz = 33, 9, 7
+    m = synthetic.random_mask3(nx, ny, nz, seed=6, solid_fraction=0.2)
+    f = synthetic.random_populations(oracle_mod.constants3()[3], (nz, ny, nx), seed=4) * (m == 0)
+    lat = lbm.Lattice3D(m, 0.8, dtype="f64")
+    for steps in (0, 3):
+        lat.step(steps)
+        lat.set_populations(f)
+        assert np.array_equal(lat.get_populations(), f)
+    lat.close()
+
+
+def test_macroscopic_and_mass(lbm, oracle_mod):
+    """rho and u (Eq. 2 with the half-force velocity) against the oracle; mass is the sum of
+    the oracle's populations (1e-12 relative) and stays constant with walls and a force."""
+    announce("d3q19 macroscopic and mass")
+    nx, ny, nz = 48, 20, 16
+    m = synthetic.random_mask3(nx, ny, nz, seed=7, solid_fraction=0.15, walls=True)
+    fields = synthetic.random_fields3(nx, ny, nz, seed=3)
+    g = (3e-5, 1e-5, -2e-5)
+    ref = run_oracle(oracle_mod, m, 0.7, 30, g=g, fields=fields)
+    lat = lbm.Lattice3D(m, 0.7, force=g, dtype="f64")
+    lat.init_equilibrium(*fields)
+    M0 = lat.mass()
+    lat.step(30)
+    M1 = lat.mass()
+    out = lat.macroscopic()
+    lat.close()
+    exp = oracle_mod.macroscopic3(m, ref, g=g)
+    for a, b in zip(out, exp):
+        assert np.abs(a - b).max() <= 1e-12
+    total = float(ref.sum())
+    assert abs(M1 - total) <= 1e-12 * total
+    assert abs(M1 - M0) <= 1e-12 * total
+
+
+@pytest.mark.parametrize("dtype,bound", [("f16s", 2e-2), ("bf16s", 1e-1), ("f32", 1e-4)])
+def test_reduced_storage_velocity_error(lbm, dtype, bound):
+    """16-bit deviation storage: velocity L2 error against the FP64 GPU path (pinned above),
+    printed; Taylor-Green 64^3, 300 steps."""
+    announce(f"d3q19 reduced storage {dtype}")
+    n = 64
+    m = np.zeros((n, n, n), np.uint8)
+    fields = synthetic.taylor_green3(n, 0.02)
+    out = {}
+    for dt in ("f64", dtype):
+        lat = lbm.Lattice3D(m, 0.6, dtype=dt)
+        lat.init_equilibrium(*fields)
+        lat.step(300)
+        out[dt] = lat.macroscopic()
+        lat.close()
+    u64 = np.stack(out["f64"][1:])
+    u = np.stack(out[dtype][1:])
+    err = float(np.sqrt(((u - u64) ** 2).sum() / (u64 ** 2).sum()))
+    print(f"\n[reduced] d3q19 taylor-green 64^3 300 steps {dtype}: velocity L2 rel err {err:.3e}")
+    assert np.isfinite(err) and err < bound
+
+
+# ------------------------------------------------------------ full size --
+@pytest.fixture(scope="module")
+def full_case(oracle_mod):
+    """256^3 (the benchmark size): 5 % random solids, random non-equilibrium populations."""
+    n = 256
+    m = synthetic.random_mask3(n, n, n, seed=11, solid_fraction=0.05)
+    f0 = synthetic.random_populations(oracle_mod.constants3()[3], (n, n, n), seed=12, amp=0.05)
+    f0 *= (m == 0)
+    return m, f0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_sampled(lbm, oracle_mod, full_case, dtype):
+    """One step of the 256^3 lattice in the benchmark's launch configuration; 300 sampled
+    fluid nodes are checked one by one: the oracle steps the node's periodic 3 x 3 x 3
+    neighbourhood, whose centre then holds exactly the full lattice's new populations (a
+    node pulls only from its direct neighbours)."""
+    m, f0 = full_case
+    n = m.shape[0]
+    announce(f"d3q19 full size {n}^3 sampled {dtype}")
+    g = (1e-5, -2e-5, 3e-5)
+    got = run_gpu(lbm, m, 0.8, 1, dtype, g=g, f0=f0)
+    rng = np.random.default_rng(13)
+    worst = 0.0
+    checked = 0
+    while checked < 300:
+        z, y, x = (int(v) for v in rng.integers(0, n, 3))
+        if m[z, y, x]:
+            continue
+        idx = [np.arange(a - 1, a + 2) % n for a in (z, y, x)]
+        pm = m[np.ix_(*idx)]
+        pf = f0[(slice(None),) + np.ix_(*idx)]
+        exp = oracle_mod.run3(pm, pf, 0.8, 1, g=g)[:, 1, 1, 1]
+        val = got[:, z, y, x]
+        err = np.abs(val - exp) if dtype == "f64" else np.abs(val - exp) / np.abs(exp)
+        worst = max(worst, float(err.max()))
+        checked += 1
+    assert worst <= TOL[dtype]
