@@ -112,6 +112,10 @@ def lib():
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p,
                                      _dp, ctypes.c_long, ctypes.c_int]
         L.oracle_run_trt.restype = ctypes.c_int
+        L.oracle_run_walls.argtypes = L.oracle_run_trt.argtypes + [ctypes.c_int]
+        L.oracle_run_walls.restype = ctypes.c_int
+        L.oracle_fullway_fill.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp]
+        L.oracle_fullway_fill.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -243,9 +247,11 @@ def init(mask, rho0=None, ux0=None, uy0=None, bc=None, value=None):
 
 
 def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value=None,
-        tau_minus=None):
+        tau_minus=None, fullway=False):
     """Advance a copy of f by `steps` time steps; returns the new array.  tau_minus: the
-    antisymmetric relaxation time of the two-relaxation-time collision (None: BGK)."""
+    antisymmetric relaxation time of the two-relaxation-time collision (None: BGK).
+    fullway: full-way bounce-back (f then includes the wall slots of solid nodes next to
+    fluid)."""
     m = _mask(mask)
     ny, nx = m.shape
     f = np.array(f, dtype=np.float64, order="C", copy=True)
@@ -254,11 +260,24 @@ def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value
     alpha = _f64(alpha)
     bc, value = _bc_args(m, bc, value)
     tm = float(tau) if tau_minus is None else float(tau_minus)
-    rc = lib().oracle_run_trt(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
-                              _d(alpha), None if bc is None else bc.ctypes.data_as(_u8p),
-                              _d(value), int(steps), int(threads))
+    rc = lib().oracle_run_walls(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
+                                _d(alpha), None if bc is None else bc.ctypes.data_as(_u8p),
+                                _d(value), int(steps), int(threads), int(bool(fullway)))
     if rc:
         raise ValueError(f"oracle_run failed ({rc})")
+    return f
+
+
+def fullway_fill(mask, f):
+    """Copy of f whose wall slots (solid nodes next to fluid) hold the full-way initial
+    values: slot i of wall node w = f_i of the fluid node w - c_i, else 0."""
+    m = _mask(mask)
+    ny, nx = m.shape
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    if f.shape != (9, ny, nx):
+        raise ValueError("f must be [9, ny, nx]")
+    if lib().oracle_fullway_fill(nx, ny, m.ctypes.data_as(_u8p), _d(f)):
+        raise ValueError("oracle_fullway_fill failed")
     return f
 
 

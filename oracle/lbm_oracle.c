@@ -39,7 +39,16 @@
  *     prescribed values (velocity: m = rho u_b; pressure: rho = rho_b with no
  *     tangential velocity) and the non-equilibrium part of the normal
  *     population equals that of its opposite.  Whatever streamed into those
- *     slots across the periodic seam is discarded.
+ *     slots across the periodic seam is discarded;
+ *   - full-way bounce-back (the alternative wall rule, selected per run): the
+ *     paper's bounce-back boundary nodes hold and move populations without
+ *     computing anything (Sec. 4.3).  Solid nodes with at least one fluid
+ *     neighbour ("wall nodes") then store populations: in a step they do not
+ *     collide but reverse what they hold (post_i = f_opp(i)), and they take
+ *     part in streaming.  Only wall slots fed by a fluid node carry values
+ *     (the others hold 0).  A population sent into a wall returns to its
+ *     origin two steps later instead of one; steady states equal those of
+ *     the halfway rule.
  *
  * Precision: FP64 throughout; build with -O2 -ffp-contract=off, no fast-math;
  * sums over directions run in ascending i.
@@ -292,20 +301,23 @@ int oracle_apply_boundaries(int nx, int ny, const uint8_t *mask, const uint8_t *
     return 0;
 }
 
-/* One time step: collide every fluid node into `post`, then stream.
- * Streaming: for each fluid x and each i, the neighbour is y = x + v_i
- * (periodic).  If y is fluid, f_i(y, t+1) = fstar_i(x); otherwise the
- * population bounces back halfway: f_opp(i)(x, t+1) = fstar_i(x).  This is a
- * bijection on fluid slots. */
-static void one_step(int nx, int ny, const uint8_t *mask, double *f, double *post, double omega,
-                     double omega_m, double gx, double gy, const double *alpha)
+/* Collision phase: every fluid node collides into `post`; with `wall`
+ * non-NULL (full-way rule) every wall node reverses its populations into
+ * `post`. */
+static void collide_phase(int nx, int ny, const uint8_t *mask, const uint8_t *wall,
+                          const double *f, double *post, double omega, double omega_m,
+                          double gx, double gy, const double *alpha)
 {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t n = (size_t)y * nx + x;
-            if (mask[n] != 0)
+            if (mask[n] != 0) {
+                if (wall && wall[n])
+                    for (int i = 0; i < Q; ++i)
+                        post[slot(i, x, y, nx, ny)] = f[slot(opposite(i), x, y, nx, ny)];
                 continue;
+            }
             double fl[Q], fs[Q];
             for (int i = 0; i < Q; ++i)
                 fl[i] = f[slot(i, x, y, nx, ny)];
@@ -316,7 +328,14 @@ static void one_step(int nx, int ny, const uint8_t *mask, double *f, double *pos
             for (int i = 0; i < Q; ++i)
                 post[slot(i, x, y, nx, ny)] = fs[i];
         }
+}
 
+/* Halfway streaming: for each fluid x and each i, the neighbour is
+ * y = x + v_i (periodic).  If y is fluid, f_i(y, t+1) = fstar_i(x); otherwise
+ * the population bounces back halfway: f_opp(i)(x, t+1) = fstar_i(x).  This
+ * is a bijection on fluid slots. */
+static void stream_halfway(int nx, int ny, const uint8_t *mask, double *f, const double *post)
+{
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -333,14 +352,84 @@ static void one_step(int nx, int ny, const uint8_t *mask, double *f, double *pos
         }
 }
 
+/* Full-way streaming: every post-collision population of a fluid or wall node
+ * moves to x + v_i.  A fluid target takes it from either kind of source (a
+ * fluid node's neighbours are all fluid or wall); a wall target only from a
+ * fluid source, and its other slots are cleared. */
+static void stream_fullway(int nx, int ny, const uint8_t *mask, const uint8_t *wall, double *f,
+                           const double *post)
+{
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            if (wall[(size_t)y * nx + x])
+                for (int i = 0; i < Q; ++i)
+                    f[slot(i, x, y, nx, ny)] = 0.0;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            if (mask[n] != 0 && !wall[n])
+                continue;
+            for (int i = 0; i < Q; ++i) {
+                int xn = wrap(x + CX[i], nx), yn = wrap(y + CY[i], ny);
+                size_t t = (size_t)yn * nx + xn;
+                if (mask[t] == 0 || (wall[t] && mask[n] == 0))
+                    f[slot(i, xn, yn, nx, ny)] = post[slot(i, x, y, nx, ny)];
+            }
+        }
+}
+
+/* Wall nodes of a mask: solid nodes with at least one fluid neighbour. */
+static void find_walls(int nx, int ny, const uint8_t *mask, uint8_t *wall)
+{
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            wall[n] = 0;
+            if (mask[n] == 0)
+                continue;
+            for (int i = 1; i < Q; ++i)
+                if (mask[(size_t)wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)] == 0)
+                    wall[n] = 1;
+        }
+}
+
+/* Full-way initial wall slots: slot i of a wall node w takes f_i of the fluid
+ * node w - v_i (its value had that node been at rest in the step before: an
+ * equilibrium state maps to itself under a force-free collision), 0 where
+ * w - v_i is not fluid.  Fluid slots are unchanged. */
+int oracle_fullway_fill(int nx, int ny, const uint8_t *mask, double *f)
+{
+    if (nx < 1 || ny < 1)
+        return -1;
+    uint8_t *wall = (uint8_t *)malloc((size_t)nx * ny);
+    if (!wall)
+        return -2;
+    find_walls(nx, ny, mask, wall);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (!wall[(size_t)y * nx + x])
+                continue;
+            for (int i = 0; i < Q; ++i) {
+                int xs = wrap(x - CX[i], nx), ys = wrap(y - CY[i], ny);
+                f[slot(i, x, y, nx, ny)] =
+                    mask[(size_t)ys * nx + xs] == 0 ? f[slot(i, xs, ys, nx, ny)] : 0.0;
+            }
+        }
+    free(wall);
+    return 0;
+}
+
 /* Run nsteps steps in place.  tau > 1/2 (Eq. 5: omega = 1/tau); tau_m > 1/2
  * is the antisymmetric relaxation time of the two-relaxation-time collision
  * (tau_m = tau: BGK).  alpha may be NULL (no drag).  bc / value may be NULL
  * (no open boundaries); else the boundary conditions are applied after every
- * streaming phase.  nthreads <= 0 keeps the OpenMP default. */
-int oracle_run_trt(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
-                   double gx, double gy, const double *alpha, const uint8_t *bc,
-                   const double *value, long nsteps, int nthreads)
+ * streaming phase.  fullway selects the full-way wall rule (the state then
+ * includes the wall slots).  nthreads <= 0 keeps the OpenMP default. */
+int oracle_run_walls(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
+                     double gx, double gy, const double *alpha, const uint8_t *bc,
+                     const double *value, long nsteps, int nthreads, int fullway)
 {
     if (nx < 1 || ny < 1 || !(tau > 0.5) || !(tau_m > 0.5) || nsteps < 0)
         return -1;
@@ -353,17 +442,35 @@ int oracle_run_trt(int nx, int ny, const uint8_t *mask, double *f, double tau, d
     double omega = 1.0 / tau, omega_m = tau_m == tau ? omega : 1.0 / tau_m;
     size_t total = (size_t)Q * nx * ny;
     double *post = (double *)calloc(total, sizeof(double));
-    if (!post)
+    uint8_t *wall = fullway ? (uint8_t *)malloc((size_t)nx * ny) : NULL;
+    if (!post || (fullway && !wall)) {
+        free(post);
+        free(wall);
         return -2;
-    for (long s = 0; s < nsteps; ++s) {
-        one_step(nx, ny, mask, f, post, omega, omega_m, gx, gy, alpha);
-        if (bc && oracle_apply_boundaries(nx, ny, mask, bc, value, f)) {
-            free(post);
-            return -1;
-        }
+    }
+    if (wall)
+        find_walls(nx, ny, mask, wall);
+    int rc = 0;
+    for (long s = 0; s < nsteps && rc == 0; ++s) {
+        collide_phase(nx, ny, mask, wall, f, post, omega, omega_m, gx, gy, alpha);
+        if (wall)
+            stream_fullway(nx, ny, mask, wall, f, post);
+        else
+            stream_halfway(nx, ny, mask, f, post);
+        if (bc && oracle_apply_boundaries(nx, ny, mask, bc, value, f))
+            rc = -1;
     }
     free(post);
-    return 0;
+    free(wall);
+    return rc;
+}
+
+int oracle_run_trt(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
+                   double gx, double gy, const double *alpha, const uint8_t *bc,
+                   const double *value, long nsteps, int nthreads)
+{
+    return oracle_run_walls(nx, ny, mask, f, tau, tau_m, gx, gy, alpha, bc, value, nsteps,
+                            nthreads, 0);
 }
 
 int oracle_run_bc(int nx, int ny, const uint8_t *mask, double *f, double tau, double gx,
@@ -541,7 +648,9 @@ int oracle_outlet_ux_gradient(int nx, int ny, const uint8_t *mask, const double 
     for (long t = 0; t < T; ++t) {
         memcpy(states + (size_t)(t + 1) * total, states + (size_t)t * total,
                total * sizeof(double));
-        one_step(nx, ny, mask, states + (size_t)(t + 1) * total, post, omega, omega, gx, gy, alpha);
+        double *ft = states + (size_t)(t + 1) * total;
+        collide_phase(nx, ny, mask, NULL, ft, post, omega, omega, gx, gy, alpha);
+        stream_halfway(nx, ny, mask, ft, post);
     }
     const double *fT = states + (size_t)T * total;
     if (oracle_objective_outlet_ux(nx, ny, mask, fT, gx, gy, alpha, x_out, J) != 0) {
