@@ -180,6 +180,27 @@ int lbm_set_boundaries(lbm_ctx *ctx, const uint8_t *bc, const double *value);
  * (LBM_ERR_UNSUPPORTED).  Discards captured step graphs. */
 int lbm_set_trt(lbm_ctx *ctx, double magic);
 
+/* Wall rule.  mode 0: halfway bounce-back (the default; see the conventions
+ * above).  mode 1: full-way bounce-back, the boundary nodes of Sec. 4.3 that
+ * hold and move populations without computing: a solid node with a fluid
+ * neighbour (a "wall node") receives the populations streamed into it,
+ * reverses them in the next step instead of colliding, and streams them back,
+ * so a population returns to its node two steps after leaving it instead of
+ * one (same steady states, different transients).  Under mode 1:
+ *  - the canonical state also holds the wall slots: population j of wall node
+ *    w, for every j whose source w - c_j is fluid (other solid slots stay 0);
+ *    lbm_get_populations returns them, lbm_set_populations reads them (they
+ *    must be finite), lbm_mass counts them;
+ *  - lbm_init_equilibrium, and switching from mode 0, set wall slot j of w to
+ *    population j of the fluid node w - c_j (its value had that node been at
+ *    equilibrium in the step before); switching back drops them;
+ *  - no extra memory: both lattices of the A-B pair hold state, so DENSE_AA,
+ *    raw state checkpoints (lbm_save_state / lbm_load_state and the
+ *    checkpointed drivers) and the adjoint return LBM_ERR_UNSUPPORTED.
+ * The fluid populations are kept across a switch.  Invalid mode:
+ * LBM_ERR_INVALID.  Discards captured step graphs; synchronises the stream. */
+int lbm_set_bounce_back(lbm_ctx *ctx, int32_t mode);
+
 /* Replace the body force (host double[2], finite). */
 int lbm_set_force(lbm_ctx *ctx, const double *force);
 
@@ -237,7 +258,9 @@ int lbm_objective_outlet_ux(lbm_ctx *ctx, int32_t x_col, double *J);
  * lbm_adjoint_bytes bytes (which also reports the row pitch).
  * lambda_t = dJ / df(t) with f the canonical populations.  Gradients are FP64
  * device buffers owned by the caller and ACCUMULATED into (+=):
- *   grad_alpha_dev [ny][nx], grad_g_dev [2]. */
+ *   grad_alpha_dev [ny][nx], grad_g_dev [2].
+ * Every adjoint entry point returns LBM_ERR_UNSUPPORTED for other layouts and
+ * types, open boundaries, the TRT collision and the full-way wall rule. */
 int lbm_adjoint_bytes(const lbm_ctx *ctx, size_t *bytes, int32_t *pitch);
 
 /* Copy an adjoint field to / from host FP64 [9][ny][nx] (the same indexing as the

@@ -168,6 +168,12 @@ class Lattice:
         """Two-relaxation-time collision with parameter Lambda = magic (0 = BGK)."""
         self._check(self._lib.lbm_set_trt(self._ctx, float(magic)))
 
+    def set_bounce_back(self, mode):
+        """"halfway" (default) or "fullway" wall rule (0 / 1); under full-way the canonical
+        populations include the wall slots of solid nodes next to fluid."""
+        m = {"halfway": 0, "fullway": 1}.get(mode, mode)
+        self._check(self._lib.lbm_set_bounce_back(self._ctx, int(m)))
+
     def set_force(self, g):
         arr = (ctypes.c_double * 2)(float(g[0]), float(g[1]))
         self._check(self._lib.lbm_set_force(self._ctx, arr))

@@ -132,10 +132,14 @@ __device__ __forceinline__ R lane_shift(R v, R edge)
 
 // ---------------------------------------------------------------- gathers --
 // Pull gather of Algorithm 1: f_i(x) = s_i(x - c_i), or, when x - c_i is solid
-// (bit i of sm), the halfway bounce-back value s_opp(i)(x).  ds = direction
-// stride of the layout, nb = node base offsets.
+// (bit i of sm), the bounce-back value bb_opp(i)(x): bb = s for the halfway
+// rule; for the full-way rule bb is the other lattice of an A-B pair, which
+// still holds the node's post-collision values of two steps back (a population
+// sent into a wall node returns two steps later).  ds = direction stride of
+// the layout, nb = node base offsets.
 template <class ST>
-__device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__ s, uint32_t ds,
+__device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__ s,
+                                            const typename ST::mem *bb, uint32_t ds,
                                             const uint32_t (&nb)[9], unsigned sm,
                                             typename ST::real (&f)[9])
 {
@@ -146,11 +150,10 @@ __device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__
         return;
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * ds + nb[0]
-                                            : (uint32_t)i * ds + nb[i];
-        f[i] = ST::ld(s[o], i);
-    }
+    for (int i = 0; i < 9; ++i)
+        f[i] = ST::ld(((sm >> i) & 1u) ? bb[(uint32_t)kOpp[i] * ds + nb[0]]
+                                       : s[(uint32_t)i * ds + nb[i]],
+                      i);
 }
 
 // AA pattern, odd step read (and the canonical view after an odd number of
@@ -189,14 +192,16 @@ __device__ __forceinline__ bool dense_node(uint32_t bpr, uint32_t nblocks, int n
 }
 
 // Pull gather of the dense layout (same values as pull_gather with dense_bases):
-// the source of f_i is node x - c_i, i.e. row slot 1 - c_i.y, column slot 1 - c_i.x.
+// the source of f_i is node x - c_i, i.e. row slot 1 - c_i.y, column slot 1 - c_i.x;
+// bounce-back values come from bb (see pull_gather).
 template <class ST>
 __device__ __forceinline__ void dense_pull(const typename ST::mem *__restrict__ s,
-                                           const DenseRC &a, unsigned sm,
-                                           typename ST::real (&f)[9])
+                                           const typename ST::mem *bb, const DenseRC &a,
+                                           unsigned sm, typename ST::real (&f)[9])
 {
     using M = typename ST::mem;
     M *sp = const_cast<M *>(s);
+    M *bp = const_cast<M *>(bb);
     if (sm == 0) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
@@ -205,7 +210,7 @@ __device__ __forceinline__ void dense_pull(const typename ST::mem *__restrict__ 
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        f[i] = ST::ld(((sm >> i) & 1u) ? dense_at(sp, a, kOpp[i], 1, 1)
+        f[i] = ST::ld(((sm >> i) & 1u) ? dense_at(bp, a, kOpp[i], 1, 1)
                                        : dense_at(sp, a, i, 1 - kCy[i], 1 - kCx[i]),
                       i);
 }
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     const uint32_t *__restrict__ seg_interior, const float *__restrict__ alpha,
     const double *__restrict__ bc_val, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
     typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real omega_m)
+    typename ST::real omega_m, int fullway)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     if (ST::kAligned && interior && x0 + 64 <= nx)
         dense_pull_aligned<ST>(src, a, x0, nx, f);
     else
-        dense_pull<ST>(src, a, sm, f);
+        dense_pull<ST>(src, fullway ? dst : src, a, sm, f);
     if (OPEN && open)
         apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
     collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
     const float *__restrict__ alpha, const double *__restrict__ bc_val,
     const int32_t *__restrict__ tile_nbr, uint32_t n_tiles, typename ST::real omega,
-    typename ST::real gx, typename ST::real gy, typename ST::real omega_m)
+    typename ST::real gx, typename ST::real gy, typename ST::real omega_m, int fullway)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
@@ -394,7 +399,7 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     uint32_t nb[9];
     tiled_offsets(k, lx, ly, tn, nb);
     R f[9];
-    pull_gather<ST>(src, kTileStride, nb, sm, f);
+    pull_gather<ST>(src, fullway ? dst : src, kTileStride, nb, sm, f);
     if constexpr (OPEN) {
         if (const unsigned open = open_code(ty))
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
@@ -414,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_step_indirect(
     const int32_t *__restrict__ edge, const float *__restrict__ alpha,
     const double *__restrict__ bc_val, uint32_t n_fluid, uint32_t nblocks,
     typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real omega_m)
+    typename ST::real omega_m, int fullway)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_step_indirect(
     unsigned open;
     const unsigned sm = indirect_offsets(pk, info, edge, n, nb, open);
     R f[9];
-    pull_gather<ST>(src, kChunk, nb, sm, f);
+    pull_gather<ST>(src, fullway ? dst : src, kChunk, nb, sm, f);
     if (OPEN && open)
         apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
     collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
@@ -491,14 +496,20 @@ __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x,
 }
 
 // Canonical populations (FP64) of the fluid node handled by thread `gid`.
+// bb: the bounce-back source of pull_gather.  With the full-way rule (bb not
+// st) the node also reports its wall slots: bit j of wl set <=> node x + c_j is
+// solid; the population in flight there, f_j(x + c_j), is the node's stored
+// slot j (wv[j]).
 template <class ST>
 __device__ __forceinline__ bool canonical_at(const DevState &s, const typename ST::mem *st,
-                                             int mode, uint32_t gid, int &x, int &y,
-                                             double (&fd)[9], double &al)
+                                             const typename ST::mem *bb, int mode, uint32_t gid,
+                                             int &x, int &y, double (&fd)[9], double &al,
+                                             unsigned &wl, double (&wv)[9])
 {
     using R = typename ST::real;
     unsigned sm = 0, open = 0;
     uint32_t ds = 0, nb[9];
+    wl = 0;
     if (!node_at(s, gid, x, y, sm, open, ds, nb))
         return false;
     R f[9];
@@ -507,7 +518,14 @@ __device__ __forceinline__ bool canonical_at(const DevState &s, const typename S
     else if (mode == kAAOdd)
         aa_odd_gather<ST>(st, ds, nb, sm, f);
     else
-        pull_gather<ST>(st, ds, nb, sm, f);
+        pull_gather<ST>(st, bb, ds, nb, sm, f);
+    if (bb != st) {
+        for (int j = 1; j < 9; ++j)
+            if ((sm >> kOpp[j]) & 1u) {  // x + c_j is x - c_opp(j)
+                wl |= 1u << j;
+                wv[j] = ST::canon(ST::ld(st[(uint32_t)j * ds + nb[0]], j), j);
+            }
+    }
     // the canonical state satisfies the open-boundary conditions
     if (open)
         apply_open<R, ST::kShift>(f, open, s.bc_val + 2 * (size_t)gid);
@@ -538,13 +556,21 @@ __device__ __forceinline__ double block_sum(double v)
 struct OpCanonical {
     double *fc;
     uint32_t plane_c;
-    int pitch;
+    int pitch, nx, ny;
     static constexpr bool kReduce = false;
-    __device__ double operator()(int x, int y, const double (&f)[9], double) const
+    __device__ double operator()(int x, int y, const double (&f)[9], double, unsigned wl,
+                                 const double (&wv)[9]) const
     {
         const uint32_t o = (uint32_t)y * pitch + x;
         for (int i = 0; i < 9; ++i)
             fc[(uint32_t)i * plane_c + o] = f[i];
+        // wall slots (full-way rule): each has exactly one fluid source node
+        for (int j = 1; j < 9; ++j)
+            if ((wl >> j) & 1u) {
+                const int xw = x + kCx[j] < 0 ? nx - 1 : (x + kCx[j] >= nx ? 0 : x + kCx[j]);
+                const int yw = y + kCy[j] < 0 ? ny - 1 : (y + kCy[j] >= ny ? 0 : y + kCy[j]);
+                fc[(uint32_t)j * plane_c + (uint32_t)yw * pitch + xw] = wv[j];
+            }
         return 0.0;
     }
 };
@@ -554,7 +580,8 @@ struct OpMacro {
     int opitch;
     double gx, gy;
     static constexpr bool kReduce = false;
-    __device__ double operator()(int x, int y, const double (&f)[9], double al) const
+    __device__ double operator()(int x, int y, const double (&f)[9], double al, unsigned,
+                                 const double (&)[9]) const
     {
         double r, u, v;
         moments(f, gx, gy, al, r, u, v);
@@ -569,11 +596,18 @@ struct OpMacro {
     }
 };
 
+// Mass of a node: its populations plus (full-way rule) those in flight in the
+// wall slots it feeds, so that the total counts every population once.
 struct OpMass {
     static constexpr bool kReduce = true;
-    __device__ double operator()(int, int, const double (&f)[9], double) const
+    __device__ double operator()(int, int, const double (&f)[9], double, unsigned wl,
+                                 const double (&wv)[9]) const
     {
-        return f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        double m = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        for (int j = 1; j < 9; ++j)
+            if ((wl >> j) & 1u)
+                m += wv[j];
+        return m;
     }
 };
 
@@ -581,7 +615,8 @@ struct OpColumnUx {
     int x_col;
     double gx, gy;
     static constexpr bool kReduce = true;
-    __device__ double operator()(int x, int, const double (&f)[9], double al) const
+    __device__ double operator()(int x, int, const double (&f)[9], double al, unsigned,
+                                 const double (&)[9]) const
     {
         if (x != x_col)
             return 0.0;
@@ -592,15 +627,17 @@ struct OpColumnUx {
 };
 
 template <class ST, class Op>
-__global__ __launch_bounds__(kBlock) void k_visit(DevState s, const typename ST::mem *st, int mode,
-                                                  Op op, double *partials)
+__global__ __launch_bounds__(kBlock) void k_visit(DevState s, const typename ST::mem *st,
+                                                  const typename ST::mem *bb, int mode, Op op,
+                                                  double *partials)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     int x = 0, y = 0;
-    double f[9], al = 0.0;
+    double f[9], al = 0.0, wv[9];
+    unsigned wl;
     double c = 0.0;
-    if (canonical_at<ST>(s, st, mode, gid, x, y, f, al))
-        c = op(x, y, f, al);
+    if (canonical_at<ST>(s, st, bb, mode, gid, x, y, f, al, wl, wv))
+        c = op(x, y, f, al, wl, wv);
     if constexpr (Op::kReduce) {
         const double b = block_sum(c);
         if (threadIdx.x == 0)
@@ -665,8 +702,13 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(int nx, int ny, int pitc
 // must stream into f_j: s_j(z) = f_j(z + c_j) if z + c_j is fluid, else
 // f_opp(j)(z) (the inverse of the pull gather).  AA even: s_j(z) = f_j(z).
 // AA odd: s_j(z) = f_opp(j)(z - c_j) if z - c_j is fluid, else f_j(z).
+// Full-way rule (walls = 1 or 2, A-B only): s_j(z) = f_j(z + c_j) also when
+// z + c_j is a wall node (its wall slot; walls = 2: the node's own f_j, the
+// initial wall-slot rule), and the other lattice's slot opp(i) of z holds
+// f_i(z) for every bounce-back link i (it returns from the wall at this step).
 template <class ST>
-__global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem *st, int mode,
+__global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem *st,
+                                                    typename ST::mem *other, int mode, int walls,
                                                     const double *__restrict__ fc)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
@@ -699,13 +741,18 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem
         } else if (mode == kAAOdd) {
             v = ((sm >> j) & 1u) ? fc[(uint32_t)j * pc + nb[0]]
                                  : fc[(uint32_t)kOpp[j] * pc + nb[j]];
+        } else if (((sm >> kOpp[j]) & 1u) == 0 || walls == 1) {
+            v = fc[(uint32_t)j * pc + nb[kOpp[j]]];  // z + c_j is node z - c_opp(j)
         } else {
-            // z + c_j is node z - c_opp(j)
-            v = ((sm >> kOpp[j]) & 1u) ? fc[(uint32_t)kOpp[j] * pc + nb[0]]
-                                       : fc[(uint32_t)j * pc + nb[kOpp[j]]];
+            v = fc[(uint32_t)(walls == 2 ? j : kOpp[j]) * pc + nb[0]];
         }
         st[(uint32_t)j * ds + nbs[0]] = ST::from_canon(v, j);
     }
+    if (walls != 0 && mode == kPull)
+        for (int i = 1; i < 9; ++i)
+            if ((sm >> i) & 1u)
+                other[(uint32_t)kOpp[i] * ds + nbs[0]] =
+                    ST::from_canon(fc[(uint32_t)i * pc + nb[0]], kOpp[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(double *p, size_t n, double v)
@@ -743,7 +790,7 @@ void step_launch(const DevState &s, int64_t t, int cur)
         if (s.layout == kDenseAB) {
             k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
                 src, dst, s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
-                s.pitch, bpr, nblocks, om, gx, gy, omm);
+                s.pitch, bpr, nblocks, om, gx, gy, omm, s.fullway);
         } else if (t & 1) {
             k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, 0, s.stream>>>(
                 (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
@@ -757,14 +804,15 @@ void step_launch(const DevState &s, int64_t t, int cur)
         const uint32_t nt = (uint32_t)s.n_tiles;
         if (nt > 0)
             k_step_tiled<ST, PH><<<nt, kTileNodes, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.bc_val, s.tile_nbr, nt, om, gx, gy, omm);
+                src, dst, s.type, s.nmask, s.alpha, s.bc_val, s.tile_nbr, nt, om, gx, gy, omm,
+                s.fullway);
     } else {
         const uint32_t nf = (uint32_t)s.n_fluid;
         const uint32_t nblocks = (nf + kBlock - 1) / kBlock;
         if (nf > 0)
             k_step_indirect<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
                 src, dst, s.ind_pk, s.ind_info, s.ind_edge, s.alpha, s.bc_val, nf, nblocks, om,
-                gx, gy, omm);
+                gx, gy, omm, s.fullway);
     }
 }
 
@@ -814,8 +862,11 @@ hipError_t visit_typed(const DevState &s, int64_t t, int cur, const Op &op, doub
     const int64_t nb = visit_blocks(s);
     if (nb == 0)
         return hipSuccess;
-    k_visit<ST, Op><<<(uint32_t)nb, kBlock, 0, s.stream>>>(
-        s, (const typename ST::mem *)view_lattice(s, cur), mode_of(s, t), op, partials);
+    using M = typename ST::mem;
+    const M *st = (const M *)view_lattice(s, cur);
+    const M *bb = s.fullway && s.layout != kDenseAA ? (const M *)s.f[1 - cur] : st;
+    k_visit<ST, Op><<<(uint32_t)nb, kBlock, 0, s.stream>>>(s, st, bb, mode_of(s, t), op,
+                                                          partials);
     return hipGetLastError();
 }
 
@@ -854,14 +905,17 @@ hipError_t reduce(const DevState &s, int64_t t, int cur, const Op &op, double *o
 }
 
 template <class ST>
-hipError_t scatter_typed(const DevState &s, int64_t t, int cur, const double *fc)
+hipError_t scatter_typed(const DevState &s, int64_t t, int cur, const double *fc, int fill)
 {
+    using M = typename ST::mem;
     const int64_t nb = visit_blocks(s);
     if (nb == 0)
         return hipSuccess;
-    void *dst = s.layout == kDenseAA ? s.f[0] : s.f[cur];
-    k_scatter<ST><<<(uint32_t)nb, kBlock, 0, s.stream>>>(s, (typename ST::mem *)dst,
-                                                         mode_of(s, t), fc);
+    const bool ab = s.layout != kDenseAA;
+    M *dst = (M *)(ab ? s.f[cur] : s.f[0]);
+    M *other = ab ? (M *)s.f[1 - cur] : nullptr;
+    const int walls = s.fullway && ab ? (fill ? 2 : 1) : 0;
+    k_scatter<ST><<<(uint32_t)nb, kBlock, 0, s.stream>>>(s, dst, other, mode_of(s, t), walls, fc);
     return hipGetLastError();
 }
 
@@ -893,13 +947,14 @@ hipError_t launch_step(const DevState &s, int64_t t, int cur)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const double *fc)
+hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const double *fc,
+                                    int fill_walls)
 {
     switch (s.dtype) {
-    case kF64: return scatter_typed<F64>(s, t, cur, fc);
-    case kF32: return scatter_typed<F32>(s, t, cur, fc);
-    case kF16S: return scatter_typed<F16S>(s, t, cur, fc);
-    case kBF16S: return scatter_typed<BF16S>(s, t, cur, fc);
+    case kF64: return scatter_typed<F64>(s, t, cur, fc, fill_walls);
+    case kF32: return scatter_typed<F32>(s, t, cur, fc, fill_walls);
+    case kF16S: return scatter_typed<F16S>(s, t, cur, fc, fill_walls);
+    case kBF16S: return scatter_typed<BF16S>(s, t, cur, fc, fill_walls);
     }
     return hipErrorInvalidValue;
 }
@@ -915,7 +970,7 @@ hipError_t launch_equilibrium(const DevState &s, const double *rho, const double
 
 hipError_t launch_gather_canonical(const DevState &s, int64_t t, int cur, double *fc)
 {
-    OpCanonical op{fc, (uint32_t)s.ny * (uint32_t)s.pitch, s.pitch};
+    OpCanonical op{fc, (uint32_t)s.ny * (uint32_t)s.pitch, s.pitch, s.nx, s.ny};
     return visit(s, t, cur, op, nullptr);
 }
 

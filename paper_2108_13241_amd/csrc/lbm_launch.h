@@ -35,6 +35,7 @@ struct DevState {
                                       // alpha; read only at open-boundary nodes
     int open = 0;                     // 1 when the node types hold open-boundary codes
     int trt = 0;                      // 1: two-relaxation-time collision (omega_m below)
+    int fullway = 0;                  // 1: full-way bounce-back (A-B layouts)
     double omega_m = 1.0;             // antisymmetric relaxation rate (TRT)
     int64_t n_tiles = 0, n_fluid = 0;
     double omega = 1.0, gx = 0.0, gy = 0.0;
@@ -55,8 +56,12 @@ int64_t reduction_capacity(const DevState &s);
 // even or odd kernel).
 hipError_t launch_step(const DevState &s, int64_t t, int cur);
 
-// Canonical populations fc (device FP64 [9][ny][nx]) -> stored state at step t.
-hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const double *fc);
+// Canonical populations fc (device FP64 [9][ny][pitch]) -> stored state at step t.
+// Full-way rule: fc's wall slots become the populations in flight; with
+// fill_walls they are taken instead from the fluid node each slot is fed by
+// (slot j of wall node w <- f_j(w - c_j)).
+hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const double *fc,
+                                    int fill_walls);
 // Equilibrium (Eq. 6) from device FP64 [ny][nx] fields (null = rest) -> fc.
 hipError_t launch_equilibrium(const DevState &s, const double *rho, const double *ux,
                               const double *uy, double *fc);

@@ -173,9 +173,11 @@ int canonical_to_host(lbm_ctx *c, const double *fc_dev, double *host)
     return LBM_OK;
 }
 
-int scatter_from_device_canonical(lbm_ctx *c, const double *fc_dev)
+// fill_walls: under the full-way rule, initialise the wall slots from the fluid
+// nodes that feed them instead of reading them from fc.
+int scatter_from_device_canonical(lbm_ctx *c, const double *fc_dev, int fill_walls = 0)
 {
-    LBM_HIP(c, lbm::launch_scatter_canonical(c->s, c->t, c->cur, fc_dev));
+    LBM_HIP(c, lbm::launch_scatter_canonical(c->s, c->t, c->cur, fc_dev, fill_walls));
     return LBM_OK;
 }
 
@@ -199,7 +201,7 @@ int init_state(lbm_ctx *c, const double *rho, const double *ux, const double *uy
     c->t = 0;
     c->cur = 0;
     LBM_HIP(c, lbm::launch_equilibrium(c->s, dp[0], dp[1], dp[2], (double *)fc.p));
-    int rc = scatter_from_device_canonical(c, (const double *)fc.p);
+    int rc = scatter_from_device_canonical(c, (const double *)fc.p, 1);
     if (rc)
         return rc;
     LBM_HIP(c, hipStreamSynchronize(c->s.stream));
@@ -587,6 +589,33 @@ int lbm_set_trt(lbm_ctx *c, double magic)
     return LBM_OK;
 }
 
+int lbm_set_bounce_back(lbm_ctx *c, int32_t mode)
+{
+    LBM_CHECK_CTX(c);
+    lbm::DevState &s = c->s;
+    if (mode != 0 && mode != 1)
+        return fail(c, LBM_ERR_INVALID, "bounce-back mode must be 0 (halfway) or 1 (full-way)");
+    if (mode == s.fullway)
+        return LBM_OK;
+    if (mode == 1 && s.layout == LBM_DENSE_AA)
+        return fail(c, LBM_ERR_UNSUPPORTED,
+                    "full-way bounce-back needs a two-lattice layout (not DENSE_AA)");
+    // Keep the fluid populations: gather under the old rule, store under the
+    // new one (switching to full-way fills the wall slots from their sources).
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    drop_graphs(c);
+    LBM_HIP(c, lbm::launch_fill((double *)fc.p, canonical_bytes(c) / 8, 0.0, s.stream));
+    LBM_HIP(c, lbm::launch_gather_canonical(s, c->t, c->cur, (double *)fc.p));
+    s.fullway = mode;
+    int rc = scatter_from_device_canonical(c, (const double *)fc.p, mode);
+    if (rc)
+        return rc;
+    LBM_HIP(c, hipStreamSynchronize(s.stream));
+    return LBM_OK;
+}
+
 int lbm_set_force(lbm_ctx *c, const double *force)
 {
     LBM_CHECK_CTX(c);
@@ -739,6 +768,24 @@ int lbm_set_populations(lbm_ctx *c, const double *f)
         for (size_t k = 0; k < nn; ++k)
             if (c->mask[k] == 0 && !std::isfinite(f[i * nn + k]))
                 return fail(c, LBM_ERR_INVALID, "populations must be finite at fluid nodes");
+    if (c->s.fullway) {
+        // wall slot j of solid node w is read when w - c_j is fluid
+        static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+        static const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        const int nx = c->s.nx, ny = c->s.ny;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t k = (size_t)y * nx + x;
+                if (c->mask[k] == 0)
+                    continue;
+                for (int j = 1; j < 9; ++j) {
+                    const int xs = (x - cx[j] + nx) % nx, ys = (y - cy[j] + ny) % ny;
+                    if (c->mask[(size_t)ys * nx + xs] == 0 && !std::isfinite(f[j * nn + k]))
+                        return fail(c, LBM_ERR_INVALID,
+                                    "populations must be finite in the wall slots");
+                }
+            }
+    }
     Temp fc(c, canonical_bytes(c));
     if (!fc.p)
         return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
@@ -779,6 +826,9 @@ int lbm_save_state(lbm_ctx *c, void *dev_dst)
     LBM_CHECK_CTX(c);
     if (!dev_dst)
         return fail(c, LBM_ERR_INVALID, "destination is NULL");
+    if (c->s.fullway)
+        return fail(c, LBM_ERR_UNSUPPORTED,
+                    "raw state checkpoints hold one lattice; the full-way rule keeps state in both");
     size_t b = 0;
     lbm_state_bytes(c, &b);
     LBM_HIP(c, hipMemcpyAsync(dev_dst, state_lattice(c), b, hipMemcpyDeviceToDevice, c->s.stream));
@@ -790,6 +840,9 @@ int lbm_load_state(lbm_ctx *c, const void *dev_src)
     LBM_CHECK_CTX(c);
     if (!dev_src)
         return fail(c, LBM_ERR_INVALID, "source is NULL");
+    if (c->s.fullway)
+        return fail(c, LBM_ERR_UNSUPPORTED,
+                    "raw state checkpoints hold one lattice; the full-way rule keeps state in both");
     size_t b = 0;
     lbm_state_bytes(c, &b);
     LBM_HIP(c, hipMemcpyAsync(state_lattice(c), dev_src, b, hipMemcpyDeviceToDevice, c->s.stream));
@@ -823,6 +876,8 @@ static int adjoint_supported(lbm_ctx *c)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
     if (c->s.trt)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
+    if (c->s.fullway)
+        return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports halfway bounce-back only");
     return LBM_OK;
 }
 
@@ -876,6 +931,8 @@ int lbm_adjoint_bytes(const lbm_ctx *c, size_t *bytes, int32_t *pitch)
         return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
     if (c->s.trt)
         return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
+    if (c->s.fullway)
+        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports halfway bounce-back only");
     *bytes = adjoint_field_bytes(c);
     if (pitch)
         *pitch = c->s.pitch;
