@@ -12,8 +12,10 @@ paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on st
               on, against the MI355X HBM peak (8 TB/s);
   cpu_baseline = the FP64 CPU oracle on the host cores, a bounded number of steps of
               the same 4096^2 workload;
-  variants  = the same measurement for the other storage types and the AA layout
-              (and, with --suite full, the porous / sparse layouts and the adjoint).
+  variants  = the same measurement for the other storage types and the AA layout, the
+              open-boundary channels and the D3Q19 lattice (256^3 three-dimensional
+              Taylor-Green vortex), and, with --suite full, the porous / sparse layouts
+              and the adjoint.
 
   --suite sparse: the paper's sparse-geometry study (Sec. 4.3, Fig. 8): sparse efficiency
               eta_P (Eq. 9) over porosity for regular and random circle obstacles, per layout.
@@ -122,6 +124,22 @@ def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0):
             "mass_check": mass_ok}
 
 
+def measure_d3q19(lbm, n, dtype, steps, warmup):
+    """D3Q19 dense A-B step on the periodic n^3 three-dimensional Taylor-Green vortex."""
+    import synthetic
+    m = np.zeros((n, n, n), np.uint8)
+    lat = lbm.Lattice3D(m, 0.6, dtype=dtype)
+    lat.init_equilibrium(*synthetic.taylor_green3(n, 0.01))
+    secs, ms = time_steps(lat, steps, warmup)
+    nf = lat.info()["n_fluid"]
+    lat.close()
+    glups = nf * steps / secs / 1e9
+    bpn = 38 * POP_BYTES[dtype] + 1
+    return {"workload": f"d3q19 taylor-green {n}^3", "dtype": dtype, "layout": "dense_ab",
+            "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
+            "frac_of_peak": glups * bpn / HBM_PEAK_GBPS, "bytes_per_node": bpn}
+
+
 def measure_copy(lbm, nbytes, reps=20):
     """Achievable read+write bandwidth of a plain 16-byte copy kernel (a10)."""
     import torch
@@ -141,15 +159,18 @@ def measure_copy(lbm, nbytes, reps=20):
     return {"bytes": nbytes, "gbps": 2 * nbytes / s / 1e9, "frac_of_peak": 2 * nbytes / s / 1e9 / HBM_PEAK_GBPS}
 
 
-def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask):
+def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask, wall="halfway"):
     lat = lbm.Lattice(mask, 0.6, force=(1e-6, 0.0), dtype=dtype, layout=layout)
+    lat.set_bounce_back(wall)
     secs, ms = time_steps(lat, steps, warmup)
     info = lat.info()
     lat.close()
     nf = info["n_fluid"]
     glups = nf * steps / secs / 1e9
     bpn = algorithmic_bytes_per_node(dtype)
-    out = {"workload": f"porous discs {n}^2 phi={phi}", "dtype": dtype, "layout": layout,
+    out = {"workload": f"porous discs {n}^2 phi={phi}"
+                       + (" full-way bounce-back" if wall == "fullway" else ""),
+           "dtype": dtype, "layout": layout,
            "n_fluid": nf, "glups_per_fluid_node": glups, "ms_per_step": ms,
            "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
            "bytes_moved_per_step": info["bytes_moved_per_step"]}
@@ -484,6 +505,10 @@ def main():
         log(f"[bench]   channel 256x64: {r['us_per_step_launch_per_step']:.2f} us/step, "
             f"graphs {r['us_per_step_hip_graph_32']:.2f} us/step")
         variants.append(r)
+        for dtype in ("f64", "f32", "f16s"):
+            r = measure_d3q19(lbm, 256, dtype, args.steps // 2, args.warmup)
+            log(f"[bench]   d3q19 256^3 {dtype}: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
+            variants.append(r)
     if args.suite == "full":
         for nn in (1024, 2048):
             f2 = synthetic.taylor_green(nn, 0.01)
@@ -503,6 +528,13 @@ def main():
                         f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid")
                     variants.append(r)
         mask_p, _ = synthetic.porous_discs(n, 0.5)
+        for dtype in ("f32", "f64"):
+            for layout in ("dense_ab", "indirect"):
+                r = measure_porous(lbm, n, 0.5, dtype, layout, args.steps // 2, args.warmup // 2,
+                                   mask_p, wall="fullway")
+                log(f"[bench]   phi=0.5 full-way {dtype} {layout}: "
+                    f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid")
+                variants.append(r)
         for r in measure_setup(lbm, mask_p):
             log(f"[bench]   create {r['layout']} porous {n}^2: {r['create_s']:.2f} s, "
                 f"re-init {r['init_equilibrium_s'] * 1e3:.1f} ms")
