@@ -60,12 +60,16 @@ def algorithmic_bytes_per_node(dtype, drag=False):
     return metrics.bytes_per_node(dtype, drag)
 
 
-def kernel_source_hash():
+HEADLINE_SOURCES = ("lbm_device.h", "lbm_kernels.hip", "lbm_launch.h")
+D3Q19_SOURCES = ("lbm3d_kernels.hip", "lbm3d_launch.h", "lbm_device.h")
+
+
+def kernel_source_hash(names=HEADLINE_SOURCES):
+    """Hash of the sources a kernel is built from (default: the D2Q9 step kernels)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2108_13241_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in sorted(names):
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -435,7 +439,7 @@ def cpu_baseline(n, fields, budget_s=12.0):
     t0 = time.perf_counter()
     f = oracle.run(m, f, 0.6, 1, threads=threads)
     one = time.perf_counter() - t0
-    steps = int(max(1, min(50, budget_s / max(one, 1e-3))))
+    steps = int(max(1, min(400, budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     oracle.run(m, f, 0.6, steps, threads=threads)
     secs = time.perf_counter() - t0
