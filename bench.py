@@ -429,8 +429,19 @@ def measure_adjoint_large(lbm, n=4096, steps=50):
             "adjoint_frac_of_peak": nf * 129 / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n, fields, budget_s=12.0):
-    """The FP64 oracle (as it is) on the host cores, a bounded number of steps."""
+    """The FP64 oracle (as it is) on the host cores, a bounded number of steps; plus one
+    step on a single thread."""
     import oracle
     import synthetic
     m = synthetic.all_fluid(n, n)
@@ -441,12 +452,16 @@ def cpu_baseline(n, fields, budget_s=12.0):
     one = time.perf_counter() - t0
     steps = int(max(1, min(400, budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
-    oracle.run(m, f, 0.6, steps, threads=threads)
+    f = oracle.run(m, f, 0.6, steps, threads=threads)
     secs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.run(m, f, 0.6, 1, threads=1)
+    secs1 = time.perf_counter() - t0
     return {"value": n * n * steps / secs / 1e9, "unit": "GLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} steps of the taylor-green {n}^2 FP64 workload "
-                      f"({secs:.1f} s, OpenMP over rows)"}
+                      f"({secs:.1f} s, OpenMP over rows)",
+            "value_1thread": n * n / secs1 / 1e9, "cpu_model": _cpu_model()}
 
 
 def main():

@@ -172,7 +172,9 @@ __device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz)
 
 // Row offsets of rows (y + dy, z + dz), dy, dz in {-1, 0, 1} (periodic), and
 // column offsets of columns x - 1, x, x + 1: node (x, y, z), direction i has
-// element i * 64 + row[dz + 1][dy + 1] + col[dx + 1].
+// element i * 64 + row[dz + 1][dy + 1] + col[dx + 1].  In a step the rows are
+// wave-uniform (one row segment per workgroup), so an element is addressed as a
+// uniform pointer plus a 32-bit lane offset; column offsets stay below 2^28.
 struct Addr {
     uint32_t row[3][3];
     uint32_t col[3];
@@ -180,7 +182,15 @@ struct Addr {
 
 __device__ __forceinline__ uint32_t col_off(int x)
 {
-    return (((uint32_t)x >> 6) * (uint32_t)(Q * kChunk)) + ((uint32_t)x & 63u);
+    return ((((uint32_t)x >> 6) * (uint32_t)(Q * kChunk)) | ((uint32_t)x & 63u)) & 0x0FFFFFFFu;
+}
+
+// Element of direction i at row slot (dz, dy) and column slot dx.
+template <class M>
+__device__ __forceinline__ M &elem(M *s, const Addr &a, int i, int dz, int dy, int dx)
+{
+    M *p = s + ((uint32_t)i * kChunk + a.row[dz][dy]);
+    return p[a.col[dx]];
 }
 
 __device__ __forceinline__ Addr addr_of(int x, int y, int z, int nx, int ny, int nz, uint32_t cpr)
@@ -206,14 +216,19 @@ template <class ST>
 __device__ __forceinline__ void pull3(const typename ST::mem *__restrict__ s, const Addr &a,
                                       uint32_t sm, typename ST::real (&f)[Q])
 {
+    using M = typename ST::mem;
+    M *sp = const_cast<M *>(s);
+    if (sm == 0) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const uint32_t o = ((sm >> i) & 1u)
-                               ? (uint32_t)kOpp[i] * kChunk + a.row[1][1] + a.col[1]
-                               : (uint32_t)i * kChunk + a.row[1 - kCz[i]][1 - kCy[i]] +
-                                     a.col[1 - kCx[i]];
-        f[i] = ST::ld(s[o], i);
+        for (int i = 0; i < Q; ++i)
+            f[i] = ST::ld(elem(sp, a, i, 1 - kCz[i], 1 - kCy[i], 1 - kCx[i]), i);
+        return;
     }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        f[i] = ST::ld(((sm >> i) & 1u) ? elem(sp, a, kOpp[i], 1, 1, 1)
+                                       : elem(sp, a, i, 1 - kCz[i], 1 - kCy[i], 1 - kCx[i]),
+                      i);
 }
 
 __device__ __forceinline__ uint32_t solid_bits3(uint8_t t, const uint32_t *__restrict__ nmask,
@@ -251,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_step3(
     collide3<R, ST::kShift, FORCE>(f, omega, gx, gy, gz);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        store_nt(&dst[(uint32_t)i * kChunk + a.row[1][1] + a.col[1]], ST::st(f[i], i));
+        store_nt(&elem(dst, a, i, 1, 1, 1), ST::st(f[i], i));
 }
 
 // ------------------------------------------------------------ canonical views --
@@ -414,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
             const int zs = z + kCz[j] < 0 ? s.nz - 1 : (z + kCz[j] >= s.nz ? 0 : z + kCz[j]);
             v = fc[(uint32_t)j * plane + ((uint32_t)zs * s.ny + ys) * (uint32_t)s.pitch + xs];
         }
-        st[(uint32_t)j * kChunk + a.row[1][1] + a.col[1]] = ST::from_canon(v, j);
+        elem(st, a, j, 1, 1, 1) = ST::from_canon(v, j);
     }
 }
 

@@ -216,3 +216,30 @@ def test_full_size_sampled(lbm, oracle_mod, full_case, dtype):
         worst = max(worst, float(err.max()))
         checked += 1
     assert worst <= TOL[dtype]
+
+
+def test_error_paths_and_info(lbm, oracle_mod):
+    """Invalid arguments are refused with LBM_ERR_INVALID and change nothing; info() reports
+    the sizes and algorithmic bytes."""
+    announce("d3q19 error paths")
+    nx, ny, nz = 20, 9, 7
+    m = synthetic.random_mask3(nx, ny, nz, seed=2, solid_fraction=0.2)
+    lat = lbm.Lattice3D(m, 0.8, force=(1e-4, 0.0, 0.0), dtype="f32")
+    lat.step(5)
+    before = lat.get_populations()
+    bad = before.copy()
+    z, y, x = (int(v[0]) for v in np.nonzero(m == 0))
+    bad[3, z, y, x] = np.nan
+    for call in (lambda: lat.set_populations(bad),
+                 lambda: lat.init_equilibrium(np.zeros(m.shape)),
+                 lambda: lat.set_force((0.0, float("inf"), 0.0))):
+        with pytest.raises(lbm.LbmError) as e:
+            call()
+        assert e.value.status == -1
+    assert np.array_equal(lat.get_populations(), before)
+    info = lat.info()
+    assert (info["nx"], info["ny"], info["nz"]) == (nx, ny, nz)
+    assert info["n_fluid"] == int((m == 0).sum()) and info["n_nodes"] == m.size
+    assert info["pop_bytes"] == 4 and info["bytes_per_fluid_node"] == 38 * 4 + 1
+    assert info["time_step"] == 5 and info["device_bytes"] > 0
+    lat.close()
