@@ -224,29 +224,53 @@ __device__ __forceinline__ void dense_pull(const typename ST::mem *__restrict__ 
 // in the neighbouring chunk, with the periodic wrap at x = 0 and nx - 1.  Same
 // values as dense_pull with no solid neighbours.  Callers guarantee that all
 // 64 lanes are active.
+// Split into the loads (aligned_load, raw stored values) and the lane shifts
+// (aligned_finish), so that a thread can issue the loads of two rows before
+// it computes either.
+template <class M>
+struct AlignedRaw {
+    M v[9], e[9];  // own column of each source row; edge values (c_x != 0 only)
+};
+
+template <class ST>
+__device__ __forceinline__ void aligned_load(const typename ST::mem *__restrict__ s,
+                                             const DenseRC &a, int x0, int nx,
+                                             AlignedRaw<typename ST::mem> &r)
+{
+    using M = typename ST::mem;
+    M *sp = const_cast<M *>(s);
+    const uint32_t cl = col_off(x0 == 0 ? nx - 1 : x0 - 1);
+    const uint32_t cr = col_off(x0 + 64 < nx ? x0 + 64 : 0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        r.v[i] = dense_at(sp, a, i, 1 - kCy[i], 1);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (kCx[i] != 0)
+            r.e[i] = sp[(uint32_t)i * kChunk + a.r[1 - kCy[i]] + (kCx[i] > 0 ? cl : cr)];
+}
+
+template <class ST>
+__device__ __forceinline__ void aligned_finish(const AlignedRaw<typename ST::mem> &r,
+                                               typename ST::real (&f)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const typename ST::real v = ST::ld(r.v[i], i);
+        f[i] = kCx[i] == 0 ? v
+               : kCx[i] > 0 ? lane_shift<true>(v, ST::ld(r.e[i], i))
+                            : lane_shift<false>(v, ST::ld(r.e[i], i));
+    }
+}
+
 template <class ST>
 __device__ __forceinline__ void dense_pull_aligned(const typename ST::mem *__restrict__ s,
                                                    const DenseRC &a, int x0, int nx,
                                                    typename ST::real (&f)[9])
 {
-    using M = typename ST::mem;
-    using R = typename ST::real;
-    M *sp = const_cast<M *>(s);
-    const uint32_t cl = col_off(x0 == 0 ? nx - 1 : x0 - 1);
-    const uint32_t cr = col_off(x0 + 64 < nx ? x0 + 64 : 0);
-    R v[9], e[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        v[i] = ST::ld(dense_at(sp, a, i, 1 - kCy[i], 1), i);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        if (kCx[i] != 0)
-            e[i] = ST::ld(sp[(uint32_t)i * kChunk + a.r[1 - kCy[i]] + (kCx[i] > 0 ? cl : cr)], i);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        f[i] = kCx[i] == 0 ? v[i]
-               : kCx[i] > 0 ? lane_shift<true>(v[i], e[i])
-                            : lane_shift<false>(v[i], e[i]);
+    AlignedRaw<typename ST::mem> r;
+    aligned_load<ST>(s, a, x0, nx, r);
+    aligned_finish<ST>(r, f);
 }
 
 // ------------------------------------------------------------- step: dense --
@@ -256,27 +280,53 @@ __device__ __forceinline__ void dense_pull_aligned(const typename ST::mem *__res
 // plus kTRT for the two-relaxation-time collision.
 enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2, kOpenBC = 4, kTRT = 8 };
 
+// Arguments shared by the dense A-B step kernels.
+template <class ST>
+struct DenseArgs {
+    const typename ST::mem *__restrict__ src;
+    typename ST::mem *__restrict__ dst;
+    const uint8_t *__restrict__ type;
+    const uint8_t *__restrict__ nmask;
+    const uint32_t *__restrict__ seg_interior;
+    const float *__restrict__ alpha;
+    const double *__restrict__ bc_val;
+    int nx, ny, pitch;
+    uint32_t bpr, nblocks;
+    typename ST::real omega, gx, gy, omega_m;
+    int fullway;
+};
+
+// Collision and streaming stores of one dense node (post-collision values to
+// the node's own slots of dst).
 template <class ST, int PH>
-__global__ __launch_bounds__(kBlock) void k_step_dense_ab(
-    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
-    const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
-    const uint32_t *__restrict__ seg_interior, const float *__restrict__ alpha,
-    const double *__restrict__ bc_val, int nx, int ny, int pitch, uint32_t bpr, uint32_t nblocks,
-    typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real omega_m, int fullway)
+__device__ __forceinline__ void dense_collide_store(const DenseArgs<ST> &k, const DenseRC &a,
+                                                    uint32_t n, typename ST::real (&f)[9])
 {
     using R = typename ST::real;
-    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
-    int x, y;
-    uint32_t L;
-    if (!dense_node(bpr, nblocks, nx, x, y, L))
-        return;
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK, TRT = (PH & kTRT) != 0;
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, k.omega, k.gx, k.gy,
+                                                         DRAG ? (R)k.alpha[n] : R(0), k.omega_m);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        store_nt(&dense_at(k.dst, a, i, 1, 1), ST::st(f[i], i));
+}
+
+// One node (x, y) of row segment L of the A-B step.
+template <class ST, int PH>
+__device__ __forceinline__ void dense_ab_node(const DenseArgs<ST> &k, int x, int y, uint32_t L)
+{
+    using R = typename ST::real;
+    constexpr bool OPEN = (PH & kOpenBC) != 0;
+    const typename ST::mem *__restrict__ src = k.src;
+    typename ST::mem *__restrict__ dst = k.dst;
+    const uint8_t *__restrict__ type = k.type;
+    const uint8_t *__restrict__ nmask = k.nmask;
+    const int nx = k.nx, ny = k.ny, pitch = k.pitch;
     const uint32_t n = (uint32_t)y * pitch + x;
     // Segments of interior fluid nodes need neither the node type nor the
     // neighbour bits, so their population loads issue at once, all aligned.
     unsigned sm = 0, open = 0;
-    const bool interior = seg_interior[L] != 0;
+    const bool interior = k.seg_interior[L] != 0;
     if (!interior) {
         const uint8_t t = type[n];
         if (t == kSolid)
@@ -292,14 +342,58 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(
     if (ST::kAligned && interior && x0 + 64 <= nx)
         dense_pull_aligned<ST>(src, a, x0, nx, f);
     else
-        dense_pull<ST>(src, fullway ? dst : src, a, sm, f);
+        dense_pull<ST>(src, k.fullway ? dst : src, a, sm, f);
     if (OPEN && open)
-        apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
-                                                         DRAG ? (R)alpha[n] : R(0), omega_m);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        store_nt(&dense_at(dst, a, i, 1, 1), ST::st(f[i], i));
+        apply_open<R, ST::kShift>(f, open, k.bc_val + 2 * (size_t)n);
+    dense_collide_store<ST, PH>(k, a, n, f);
+}
+
+template <class ST, int PH>
+__global__ __launch_bounds__(kBlock) void k_step_dense_ab(const DenseArgs<ST> k)
+{
+    int x, y;
+    uint32_t L;
+    if (!dense_node(k.bpr, k.nblocks, k.nx, x, y, L))
+        return;
+    dense_ab_node<ST, PH>(k, x, y, L);
+}
+
+// Two rows per workgroup (rows y0 = 2 p and y0 + 1 of one 256-column segment),
+// for the 16-bit storages: when both segments are all-interior and the wave is
+// full, the thread issues the loads of both rows before it computes either, so
+// each wave keeps twice the bytes in flight (these kernels are bound by memory
+// latency rather than by bandwidth or arithmetic).  Otherwise the two rows run
+// one after the other as in k_step_dense_ab.  k.nblocks = bpr * ceil(ny / 2).
+template <class ST, int PH>
+__global__ __launch_bounds__(kBlock) void k_step_dense_ab2(const DenseArgs<ST> k)
+{
+    using R = typename ST::real;
+    const uint32_t B = xcd_remap(blockIdx.x, k.nblocks);
+    const uint32_t p = B / k.bpr, sx = B - p * k.bpr;
+    const int x = (int)sx * kBlock + (int)threadIdx.x;
+    if (x >= k.nx)
+        return;
+    const int y0 = 2 * (int)p, y1 = y0 + 1;
+    const uint32_t L0 = (uint32_t)y0 * k.bpr + sx, L1 = L0 + k.bpr;
+    const int x0 = __builtin_amdgcn_readfirstlane(x - (int)(threadIdx.x & 63u));
+    const bool fast = y1 < k.ny && x0 + 64 <= k.nx && k.seg_interior[L0] != 0 &&
+                      k.seg_interior[L1] != 0;
+    if (fast) {
+        const uint32_t cpr = (uint32_t)k.pitch / kChunk;
+        const DenseRC a0 = dense_rc(x, y0, k.nx, k.ny, cpr), a1 = dense_rc(x, y1, k.nx, k.ny, cpr);
+        AlignedRaw<typename ST::mem> r0, r1;
+        aligned_load<ST>(k.src, a0, x0, k.nx, r0);
+        aligned_load<ST>(k.src, a1, x0, k.nx, r1);
+        R f[9];
+        aligned_finish<ST>(r0, f);
+        dense_collide_store<ST, PH>(k, a0, (uint32_t)y0 * k.pitch + x, f);
+        aligned_finish<ST>(r1, f);
+        dense_collide_store<ST, PH>(k, a1, (uint32_t)y1 * k.pitch + x, f);
+        return;
+    }
+    dense_ab_node<ST, PH>(k, x, y0, L0);
+    if (y1 < k.ny)
+        dense_ab_node<ST, PH>(k, x, y1, L1);
 }
 
 // AA pattern (single lattice A).  Even step: read A_i(x), write the
@@ -788,9 +882,15 @@ void step_launch(const DevState &s, int64_t t, int cur)
         const uint32_t bpr = (uint32_t)((s.nx + kBlock - 1) / kBlock);
         const uint32_t nblocks = bpr * (uint32_t)s.ny;
         if (s.layout == kDenseAB) {
-            k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
-                s.pitch, bpr, nblocks, om, gx, gy, omm, s.fullway);
+            DenseArgs<ST> k{src,   dst,  s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val,
+                            s.nx,  s.ny, s.pitch, bpr,   nblocks,        om,      gx,
+                            gy,    omm,  s.fullway};
+            if constexpr (ST::kAligned) {
+                k.nblocks = bpr * (uint32_t)((s.ny + 1) / 2);
+                k_step_dense_ab2<ST, PH><<<k.nblocks, kBlock, 0, s.stream>>>(k);
+            } else {
+                k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(k);
+            }
         } else if (t & 1) {
             k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, 0, s.stream>>>(
                 (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,

@@ -277,3 +277,39 @@ def test_graph_replay_bitwise(lbm, layout):
         lat.close()
     assert np.array_equal(runs[0], runs[1])
     assert np.array_equal(runs[0], runs[2])
+
+
+@pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
+@pytest.mark.parametrize("case", ["plain", "force_drag", "trt_open"])
+def test_dense_row_pairs_16bit(lbm, dtype, case):
+    """The 16-bit dense A-B step runs two rows per workgroup (both rows' loads issued before
+    either is computed when both segments are all-interior and the wave is full, else the two
+    rows one after the other).  Bitwise equal to the indirect layout's kernel on a 600 x 77
+    lattice (odd row count, a ragged last wave) whose solids fill only x < 200, so that
+    all-interior segments and segments with solids alternate between row pairs."""
+    announce(f"dense row pairs {dtype} {case}")
+    nx, ny = 600, 77
+    rng = np.random.default_rng(21)
+    m = np.zeros((ny, nx), np.uint8)
+    m[:, :200] = (rng.random((ny, 200)) < 0.15).astype(np.uint8)
+    m[::5, 250] = 1  # a few rows whose second segment is not all-interior
+    fields = synthetic.random_fields(nx, ny, seed=4, rho_spread=0.02, u_amp=0.02)
+    out = []
+    for layout in ("dense_ab", "indirect"):
+        g = (1e-5, -2e-6) if case != "plain" else (0.0, 0.0)
+        lat = lbm.Lattice(m, 0.7, force=g, dtype=dtype, layout=layout)
+        if case == "force_drag":
+            lat.set_porosity(synthetic.brinkman_alpha(nx, ny, seed=2, sigma=4.0))
+        if case == "trt_open":
+            lat.set_trt(3.0 / 16.0)
+            bc = np.zeros((ny, nx), np.uint8)
+            val = np.zeros((2, ny, nx))
+            col = (m[:, nx - 1] == 0)
+            bc[col, nx - 1] = synthetic.BC_PRESSURE[(-1, 0)]
+            val[0, col, nx - 1] = 1.0
+            lat.set_boundaries(bc, val)
+        lat.init_equilibrium(*fields)
+        lat.step(23)
+        out.append(lat.get_populations())
+        lat.close()
+    assert np.array_equal(out[0], out[1])
