@@ -119,7 +119,7 @@ void *own_alloc(lbm3d_ctx *c, size_t bytes)
 struct Temp {
     lbm3d_ctx *c;
     void *p = nullptr;
-    Temp(lbm3d_ctx *c_, size_t bytes) : c(c_) { p = raw_alloc(c, bytes); }
+    Temp(lbm3d_ctx *c_, size_t bytes) : c(c_) { p = bytes ? raw_alloc(c, bytes) : nullptr; }
     ~Temp()
     {
         if (p) {

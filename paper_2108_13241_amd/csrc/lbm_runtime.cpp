@@ -147,7 +147,7 @@ void *own_alloc(lbm_ctx *c, size_t bytes)
 struct Temp {
     lbm_ctx *c;
     void *p = nullptr;
-    Temp(lbm_ctx *c_, size_t bytes) : c(c_) { p = raw_alloc(c->alloc, bytes); }
+    Temp(lbm_ctx *c_, size_t bytes) : c(c_) { p = bytes ? raw_alloc(c->alloc, bytes) : nullptr; }
     ~Temp()
     {
         if (p) {
