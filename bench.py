@@ -447,10 +447,15 @@ def cpu_baseline(n, fields, budget_s=12.0):
     m = synthetic.all_fluid(n, n)
     f = oracle.init(m, *fields)
     threads = oracle.max_threads()
+    f = oracle.run(m, f, 0.6, 1, threads=threads)  # first touch of the buffers
+    # per-step cost without the per-call copy and allocation: 4 steps minus 1 step
     t0 = time.perf_counter()
     f = oracle.run(m, f, 0.6, 1, threads=threads)
-    one = time.perf_counter() - t0
-    steps = int(max(1, min(400, budget_s / max(one, 1e-3))))
+    t1 = time.perf_counter()
+    f = oracle.run(m, f, 0.6, 4, threads=threads)
+    t4 = time.perf_counter() - t1
+    one = max((t4 - (t1 - t0)) / 3.0, 1e-4)
+    steps = int(max(1, min(400, budget_s / one)))
     t0 = time.perf_counter()
     f = oracle.run(m, f, 0.6, steps, threads=threads)
     secs = time.perf_counter() - t0
