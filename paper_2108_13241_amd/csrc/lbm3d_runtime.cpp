@@ -1,6 +1,7 @@
 // C ABI of the D3Q19 lattice: argument checks, geometry preprocessing (node
-// types, solid-neighbour bits, interior-segment flags), device buffers and
-// kernel sequencing.  All arithmetic of the method runs in the HIP kernels.
+// types, solid-neighbour bits, interior-segment flags; lbm_plan.cpp), device
+// buffers and kernel sequencing.  All arithmetic of the method runs in the HIP
+// kernels.
 #include "lbm3d.h"
 
 #include <hip/hip_runtime.h>
@@ -12,6 +13,7 @@
 
 #include "lbm3d_launch.h"
 #include "lbm_launch.h"
+#include "lbm_plan.h"
 
 namespace {
 
@@ -24,12 +26,6 @@ int fail_tl(int status, const std::string &msg)
 }
 
 constexpr int Q = 19;
-// Velocities in the order of the public header.
-constexpr int kCx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int kCy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int kCz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-
-int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 bool finite3(const double *v)
 {
@@ -135,43 +131,6 @@ size_t padded_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->
 size_t canonical_bytes(const lbm3d_ctx *c) { return (size_t)Q * padded_nodes(c) * sizeof(double); }
 size_t field_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s.nx; }
 
-// Node types, solid-neighbour bits and interior-segment flags of a mask:
-// type 0 = fluid with no solid neighbour, 1 = solid, 2 = fluid with one; bit
-// i-1 of nbits = node x - c_i is solid; a 256-node row segment is interior when
-// all its nodes inside the mesh have type 0.  Padding columns are solid.
-void plan_types(const uint8_t *mask, int nx, int ny, int nz, int pitch, std::vector<uint8_t> &type,
-                std::vector<uint32_t> &nbits, std::vector<uint32_t> &seg)
-{
-    const size_t np = (size_t)nz * ny * pitch;
-    type.assign(np, 1);
-    nbits.assign(np, 0);
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y)
-            for (int x = 0; x < nx; ++x) {
-                const size_t n = ((size_t)z * ny + y) * nx + x;
-                const size_t p = ((size_t)z * ny + y) * pitch + x;
-                if (mask[n]) {
-                    type[p] = 1;
-                    continue;
-                }
-                uint32_t b = 0;
-                for (int i = 1; i < Q; ++i) {
-                    const int xs = wrap(x - kCx[i], nx), ys = wrap(y - kCy[i], ny),
-                              zs = wrap(z - kCz[i], nz);
-                    if (mask[((size_t)zs * ny + ys) * nx + xs])
-                        b |= 1u << (i - 1);
-                }
-                nbits[p] = b;
-                type[p] = b ? 2 : 0;
-            }
-    const int bpr = (nx + 255) / 256;
-    seg.assign((size_t)nz * ny * bpr, 1);
-    for (int r = 0; r < nz * ny; ++r)
-        for (int x = 0; x < nx; ++x)
-            if (type[(size_t)r * pitch + x] != 0)
-                seg[(size_t)r * bpr + x / 256] = 0;
-}
-
 int init_state(lbm3d_ctx *c, const double *rho, const double *ux, const double *uy,
                const double *uz)
 {
@@ -271,7 +230,7 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
     };
     std::vector<uint8_t> type;
     std::vector<uint32_t> nbits, seg;
-    plan_types(node_type, nx, ny, nz, (int)pitch, type, nbits, seg);
+    lbm::plan::dense_types3(node_type, nx, ny, nz, (int)pitch, type, nbits, seg);
     void *p = nullptr;
     int rc;
     if ((rc = upload(type.data(), type.size(), &p)))

@@ -168,5 +168,42 @@ IndirectCompact indirect_compact(const Fluid &fl, const uint8_t *mask, int nx, i
     return out;
 }
 
+// D3Q19 velocities (host copy for planning), in the order of include/lbm3d.h.
+static const int kHostCx3[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int kHostCy3[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int kHostCz3[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+void dense_types3(const uint8_t *mask, int nx, int ny, int nz, int pitch,
+                  std::vector<uint8_t> &type, std::vector<uint32_t> &nbits,
+                  std::vector<uint32_t> &seg)
+{
+    const size_t np = (size_t)nz * ny * pitch;
+    type.assign(np, 1);
+    nbits.assign(np, 0);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t n = ((size_t)z * ny + y) * nx + x;
+                const size_t p = ((size_t)z * ny + y) * pitch + x;
+                if (mask[n])
+                    continue;
+                uint32_t b = 0;
+                for (int i = 1; i < 19; ++i) {
+                    const int xs = wrapi(x - kHostCx3[i], nx), ys = wrapi(y - kHostCy3[i], ny),
+                              zs = wrapi(z - kHostCz3[i], nz);
+                    if (mask[((size_t)zs * ny + ys) * nx + xs])
+                        b |= 1u << (i - 1);
+                }
+                nbits[p] = b;
+                type[p] = b ? 2 : 0;
+            }
+    const int bpr = (nx + 255) / 256;
+    seg.assign((size_t)nz * ny * bpr, 1);
+    for (size_t r = 0; r < (size_t)nz * ny; ++r)
+        for (int x = 0; x < nx; ++x)
+            if (type[r * pitch + x] != 0)
+                seg[r * bpr + x / 256] = 0;
+}
+
 }  // namespace plan
 }  // namespace lbm

@@ -73,5 +73,14 @@ struct IndirectCompact {
 IndirectCompact indirect_compact(const Fluid &fl, const uint8_t *mask, int nx, int ny,
                                  int64_t plane);
 
+// D3Q19 dense planning ([nz][ny][pitch] padded node index, mask [nz][ny][nx]):
+// type 1 solid (and padding), 0 fluid with only fluid neighbours, 2 fluid with
+// a solid neighbour; nbits[p] bit i-1 set iff node x - c_i (periodic) is solid,
+// i = 1..18 in the velocity order of include/lbm3d.h; seg[(z ny + y) bpr + s]
+// = 1 iff every node of 256-node row segment s has type 0 (bpr = ceil(nx / 256)).
+void dense_types3(const uint8_t *mask, int nx, int ny, int nz, int pitch,
+                  std::vector<uint8_t> &type, std::vector<uint32_t> &nbits,
+                  std::vector<uint32_t> &seg);
+
 }  // namespace plan
 }  // namespace lbm

@@ -1,6 +1,6 @@
-"""The native geometry planner (lbm_plan.cpp, plain C++) compiled with g++ on the host:
-node-type codes and solid-neighbour bits of the dense and tiled layouts against a
-brute-force recomputation (no GPU needed)."""
+"""The native geometry planner (lbm_plan.cpp, plain C++) compiled with g++ on the host under
+AddressSanitizer and UBSan: node-type codes and solid-neighbour bits of the dense and tiled
+layouts against a brute-force recomputation (no GPU needed)."""
 import os
 import subprocess
 import textwrap
@@ -64,7 +64,10 @@ def planner(tmp_path_factory):
     src = d / "drv.cpp"
     src.write_text(DRIVER)
     exe = d / "drv"
-    subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC, str(src),
+    # host-only build under AddressSanitizer and UBSan: any out-of-bounds access or
+    # undefined behaviour in the planner aborts the driver and fails the test
+    subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-I", CSRC, str(src),
                     os.path.join(CSRC, "lbm_plan.cpp"), "-o", str(exe)], check=True)
     return str(exe)
 
@@ -167,3 +170,74 @@ def test_indirect_compact(planner, shape, frac):
         assert d == list(nbr[:, n]), n
     # interior nodes use the compact form
     assert sum(1 for r in rows if not r[2] & 0x100) > 0
+
+
+DRIVER3 = textwrap.dedent(r"""
+    #include <cstdio>
+    #include <vector>
+    #include "lbm_plan.h"
+    int main() {
+        int nx, ny, nz, pitch;
+        if (std::scanf("%d %d %d %d", &nx, &ny, &nz, &pitch) != 4) return 2;
+        std::vector<uint8_t> mask((size_t)nx * ny * nz);
+        for (auto &m : mask) { int v; if (std::scanf("%d", &v) != 1) return 2; m = (uint8_t)v; }
+        std::vector<uint8_t> type;
+        std::vector<uint32_t> nbits, seg;
+        lbm::plan::dense_types3(mask.data(), nx, ny, nz, pitch, type, nbits, seg);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < pitch; ++x) {
+                    const size_t p = ((size_t)z * ny + y) * pitch + x;
+                    std::printf("%d %u\n", type[p], nbits[p]);
+                }
+        for (uint32_t f : seg) std::printf("%u\n", f);
+        return 0;
+    }
+""")
+
+
+@pytest.fixture(scope="module")
+def planner3(tmp_path_factory):
+    d = tmp_path_factory.mktemp("plan3")
+    src = d / "drv3.cpp"
+    src.write_text(DRIVER3)
+    exe = d / "drv3"
+    subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-I", CSRC, str(src),
+                    os.path.join(CSRC, "lbm_plan.cpp"), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+@pytest.mark.parametrize("shape", [(70, 9, 7), (300, 3, 2), (1, 1, 1), (1, 1, 5), (64, 2, 3)])
+def test_dense_types3_brute_force(planner3, oracle_mod, shape):
+    """D3Q19 node types, solid-neighbour bits (velocities from the pinned D3Q19 oracle) and
+    256-node interior-segment flags, padding columns solid."""
+    nx, ny, nz = shape
+    pitch = (nx + 63) // 64 * 64
+    m = synthetic.random_mask3(nx, ny, nz, seed=nx + 7 * ny + 13 * nz, solid_fraction=0.1)
+    inp = f"{nx} {ny} {nz} {pitch}\n" + " ".join(str(int(v)) for v in m.ravel())
+    r = subprocess.run([planner3], input=inp, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    rows = [list(map(int, ln.split())) for ln in r.stdout.split("\n") if ln.strip()]
+    n_pad = nz * ny * pitch
+    cells = np.array(rows[:n_pad]).reshape(nz, ny, pitch, 2)
+    seg = np.array([v[0] for v in rows[n_pad:]])
+    cx, cy, cz, _, _ = oracle_mod.constants3()
+    bpr = (nx + 255) // 256
+    exp_seg = np.ones(nz * ny * bpr, int)
+    for z in range(nz):
+        for y in range(ny):
+            assert (cells[z, y, nx:, 0] == 1).all()
+            for x in range(nx):
+                t, b = cells[z, y, x]
+                if m[z, y, x]:
+                    assert t == 1
+                else:
+                    bits = 0
+                    for i in range(1, 19):
+                        if m[(z - cz[i]) % nz, (y - cy[i]) % ny, (x - cx[i]) % nx]:
+                            bits |= 1 << (i - 1)
+                    assert (t, b) == ((2 if bits else 0), bits)
+                if t != 0:
+                    exp_seg[(z * ny + y) * bpr + x // 256] = 0
+    assert np.array_equal(seg, exp_seg)
