@@ -264,6 +264,13 @@ class Lattice:
 
 
 # ------------------------------------------------------------ host planning --
+def _force3(g):
+    g = [float(v) for v in g]
+    if len(g) != 3:
+        raise ValueError("a D3Q19 force has three components (g_x, g_y, g_z)")
+    return (ctypes.c_double * 3)(*g)
+
+
 class Lattice3D:
     """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B
     layout, BGK with Guo forcing, halfway bounce-back.  Arrays are [nz, ny, nx]; canonical
@@ -286,7 +293,7 @@ class Lattice3D:
         else:
             _uninstall_torch_allocator()
         self._ctx = ctypes.c_void_p()
-        g = (ctypes.c_double * 3)(*(float(v) for v in force))
+        g = _force3(force)
         check3(self._lib.lbm3d_create(ctypes.byref(self._ctx), self.nx, self.ny, self.nz,
                                       mask.ctypes.data_as(_u8p), float(tau), g, DTYPES[dtype]),
                None)
@@ -316,8 +323,7 @@ class Lattice3D:
         self._check(self._lib.lbm3d_init_equilibrium(self._ctx, *[_dptr(a) for a in f]))
 
     def set_force(self, g):
-        arr = (ctypes.c_double * 3)(*(float(v) for v in g))
-        self._check(self._lib.lbm3d_set_force(self._ctx, arr))
+        self._check(self._lib.lbm3d_set_force(self._ctx, _force3(g)))
 
     def step(self, n=1):
         self._check(self._lib.lbm3d_step(self._ctx, int(n)))
