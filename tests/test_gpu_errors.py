@@ -105,6 +105,16 @@ def test_allocator_failure_reports_nomem(lbm):
         assert st == -2
         assert not ctx.value
         assert calls["alloc"] >= 1
+        # D3Q19 contexts take their memory from the same hook
+        n0 = calls["alloc"]
+        m3 = np.zeros((4, 8, 8), np.uint8)
+        g3 = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+        st = L.lbm3d_create(ctypes.byref(ctx), 8, 8, 4,
+                            m3.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0.8, g3, 0)
+        assert st == -2
+        assert not ctx.value
+        assert calls["alloc"] > n0
+        assert L.lbm3d_last_error(None)
     finally:
         import paper_2108_13241_amd as pkg
         pkg._alloc_cb = None
@@ -125,3 +135,27 @@ def test_hipmalloc_path(lbm):
     b.step(30)
     assert np.array_equal(b.get_populations(), fa)
     b.close()
+
+
+def test_d3q19_memory_paths(lbm):
+    """A D3Q19 context created while torch's allocator is registered takes its lattices from
+    torch (torch.cuda.memory_allocated grows by at least the two lattices); one created with
+    plain hipMalloc gives bitwise the same populations."""
+    import torch
+    announce("d3q19 memory paths")
+    m = synthetic.random_mask3(40, 12, 10, seed=3, solid_fraction=0.1)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    a = lbm.Lattice3D(m, 0.7, force=(1e-4, 0.0, 0.0), dtype="f64", torch_memory=True)
+    grown = torch.cuda.memory_allocated() - before
+    assert grown >= 2 * 19 * 10 * 12 * 64 * 8
+    assert a.info()["device_bytes"] <= grown + (1 << 20)
+    a.step(12)
+    fa = a.get_populations()
+    a.close()
+    b = lbm.Lattice3D(m, 0.7, force=(1e-4, 0.0, 0.0), dtype="f64", torch_memory=False)
+    b.step(12)
+    assert np.array_equal(b.get_populations(), fa)
+    b.close()
+    from paper_2108_13241_amd import _install_torch_allocator
+    _install_torch_allocator()
