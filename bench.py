@@ -144,6 +144,33 @@ def measure_d3q19(lbm, n, dtype, steps, warmup):
             "frac_of_peak": glups * bpn / HBM_PEAK_GBPS, "bytes_per_node": bpn}
 
 
+def measure_end_to_end(lbm, n, fields, steps):
+    """The headline workload including its host transfers: re-initialisation from host FP64
+    fields (rho, ux, uy uploaded), `steps` steps, and the macroscopic fields read back into
+    host arrays.  Reported beside the headline, never as its value."""
+    import torch
+
+    import synthetic
+    lat = lbm.Lattice(synthetic.all_fluid(n, n), 0.6, dtype="f64", layout="dense_ab")
+    lat.init_equilibrium(*fields)
+    lat.step(64)
+    lat.macroscopic()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.init_equilibrium(*fields)
+    t1 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lat.macroscopic()
+    t3 = time.perf_counter()
+    lat.close()
+    return {"workload": f"taylor-green {n}^2 f64 dense_ab, host fields in and out",
+            "steps": steps, "upload_init_s": t1 - t0, "steps_s": t2 - t1,
+            "download_macroscopic_s": t3 - t2,
+            "glups_incl_host_transfers": n * n * steps / (t3 - t0) / 1e9}
+
+
 def measure_copy(lbm, nbytes, reps=20):
     """Achievable read+write bandwidth of a plain 16-byte copy kernel (a10)."""
     import torch
@@ -528,6 +555,11 @@ def main():
         r = measure_small_channel(lbm)
         log(f"[bench]   channel 256x64: {r['us_per_step_launch_per_step']:.2f} us/step, "
             f"graphs {r['us_per_step_hip_graph_32']:.2f} us/step")
+        variants.append(r)
+        r = measure_end_to_end(lbm, n, fields, args.steps)
+        log(f"[bench]   end to end with host transfers: {r['glups_incl_host_transfers']:.2f} GLUPS "
+            f"(upload + init {r['upload_init_s'] * 1e3:.0f} ms, read-back "
+            f"{r['download_macroscopic_s'] * 1e3:.0f} ms)")
         variants.append(r)
         for dtype in ("f64", "f32", "f16s"):
             r = measure_d3q19(lbm, 256, dtype, args.steps // 2, args.warmup)
