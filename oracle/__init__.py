@@ -105,6 +105,10 @@ def lib():
         L.oracle3_run.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp] + [ctypes.c_double] * 4 + \
             [ctypes.c_long, ctypes.c_int]
         L.oracle3_run.restype = ctypes.c_int
+        L.oracle3_run_trt.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp] + [ctypes.c_double] * 5 + \
+            [ctypes.c_long, ctypes.c_int]
+        L.oracle3_run_trt.restype = ctypes.c_int
+        L.oracle3_collide_trt.argtypes = [_dp] + [ctypes.c_double] * 5 + [_dp]
         L.oracle3_macroscopic.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp] + \
             [ctypes.c_double] * 3 + [_dp] * 4
         L.oracle3_macroscopic.restype = ctypes.c_int
@@ -362,6 +366,14 @@ def collide3(f, omega, g=(0.0, 0.0, 0.0)):
     return out
 
 
+def collide3_trt(f, omega_p, omega_m, g=(0.0, 0.0, 0.0)):
+    """D3Q19 two-relaxation-time collision (omega_m = omega_p is BGK)."""
+    f = _f64(f)
+    out = np.zeros(19)
+    lib().oracle3_collide_trt(_d(f), g[0], g[1], g[2], omega_p, omega_m, _d(out))
+    return out
+
+
 def _mask3(m):
     m = np.ascontiguousarray(m, dtype=np.uint8)
     if m.ndim != 3:
@@ -379,14 +391,17 @@ def init3(mask, rho0=None, ux0=None, uy0=None, uz0=None):
     return f
 
 
-def run3(mask, f, tau, steps, g=(0.0, 0.0, 0.0), threads=0):
+def run3(mask, f, tau, steps, g=(0.0, 0.0, 0.0), threads=0, tau_minus=None):
+    """Advance a copy of the D3Q19 state f by `steps` steps.  tau_minus: antisymmetric
+    relaxation time of the two-relaxation-time collision (None: BGK)."""
     m = _mask3(mask)
     nz, ny, nx = m.shape
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     if f.shape != (19, nz, ny, nx):
         raise ValueError("f must be [19, nz, ny, nx]")
-    rc = lib().oracle3_run(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), tau, g[0], g[1], g[2],
-                           int(steps), int(threads))
+    tm = float(tau) if tau_minus is None else float(tau_minus)
+    rc = lib().oracle3_run_trt(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
+                               g[2], int(steps), int(threads))
     if rc:
         raise ValueError(f"oracle3_run failed ({rc})")
     return f

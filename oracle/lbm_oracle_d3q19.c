@@ -4,7 +4,9 @@
  * lattice that the paper names as its future work, with the same update as
  * the two-dimensional oracle (Sec. 2.2, Eq. 3 as collision then streaming;
  * Eq. 4 BGK; Eq. 6 equilibrium, which holds unchanged in 3D with the D3Q19
- * weights; Eq. 5 viscosity).
+ * weights; Eq. 5 viscosity), and the two-relaxation-time collision of the
+ * two-dimensional oracle (each population pair split into its symmetric and
+ * antisymmetric parts, relaxed at omega_p and omega_m).
  *
  * TEST INFRASTRUCTURE ONLY.  The GPU library never links, calls, includes or
  * shares anything with this file; only the test-suite and the benchmark's
@@ -122,6 +124,29 @@ void oracle3_collide(const double *f, double gx, double gy, double gz, double om
         fstar[i] = f[i] - omega * (f[i] - feq[i]) + (1.0 - 0.5 * omega) * S[i];
 }
 
+/* Two-relaxation-time collision with forcing F = rho g: for each pair
+ * (i, opp(i)) the symmetric parts (f_i + f_opp)/2 relax with omega_p and the
+ * antisymmetric parts (f_i - f_opp)/2 with omega_m, towards the same parts of
+ * f^eq; the forcing term is split alike, with factors (1 - omega/2) of its own
+ * rate.  omega_m = omega_p is the BGK collision. */
+void oracle3_collide_trt(const double *f, double gx, double gy, double gz, double omega_p,
+                         double omega_m, double *fstar)
+{
+    double m[4];
+    oracle3_node_velocity(f, gx, gy, gz, m);
+    double feq[Q3], S[Q3];
+    oracle3_equilibrium(m[0], m[1], m[2], m[3], feq);
+    oracle3_guo_source(m[1], m[2], m[3], m[0] * gx, m[0] * gy, m[0] * gz, S);
+    for (int i = 0; i < Q3; ++i) {
+        int j = opposite3(i);
+        double fp = 0.5 * (f[i] + f[j]), fm = 0.5 * (f[i] - f[j]);
+        double ep = 0.5 * (feq[i] + feq[j]), em = 0.5 * (feq[i] - feq[j]);
+        double sp = 0.5 * (S[i] + S[j]), sm = 0.5 * (S[i] - S[j]);
+        fstar[i] = f[i] - omega_p * (fp - ep) - omega_m * (fm - em) + (1.0 - 0.5 * omega_p) * sp +
+                   (1.0 - 0.5 * omega_m) * sm;
+    }
+}
+
 /* f_i = f^eq_i(rho0, u0) at fluid nodes; NULL fields mean rho0 = 1, u0 = 0. */
 int oracle3_init(int nx, int ny, int nz, const uint8_t *mask, const double *rho0,
                  const double *ux0, const double *uy0, const double *uz0, double *f)
@@ -146,7 +171,7 @@ int oracle3_init(int nx, int ny, int nz, const uint8_t *mask, const double *rho0
  * population to x + c_i, or back to its origin reversed when x + c_i is
  * solid (halfway bounce-back). */
 static void one_step3(int nx, int ny, int nz, const uint8_t *mask, double *f, double *post,
-                      double omega, double gx, double gy, double gz)
+                      double omega, double omega_m, double gx, double gy, double gz)
 {
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
@@ -158,7 +183,10 @@ static void one_step3(int nx, int ny, int nz, const uint8_t *mask, double *f, do
                 double fl[Q3], fs[Q3];
                 for (int i = 0; i < Q3; ++i)
                     fl[i] = f[slot3(i, x, y, z, nx, ny, nz)];
-                oracle3_collide(fl, gx, gy, gz, omega, fs);
+                if (omega_m == omega)
+                    oracle3_collide(fl, gx, gy, gz, omega, fs);
+                else
+                    oracle3_collide_trt(fl, gx, gy, gz, omega, omega_m, fs);
                 for (int i = 0; i < Q3; ++i)
                     post[slot3(i, x, y, z, nx, ny, nz)] = fs[i];
             }
@@ -181,10 +209,12 @@ static void one_step3(int nx, int ny, int nz, const uint8_t *mask, double *f, do
             }
 }
 
-int oracle3_run(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau, double gx,
-                double gy, double gz, long nsteps, int nthreads)
+/* nsteps steps in place; tau_m is the antisymmetric relaxation time of the
+ * two-relaxation-time collision (tau_m = tau: BGK). */
+int oracle3_run_trt(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
+                    double tau_m, double gx, double gy, double gz, long nsteps, int nthreads)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || !(tau > 0.5) || nsteps < 0)
+    if (nx < 1 || ny < 1 || nz < 1 || !(tau > 0.5) || !(tau_m > 0.5) || nsteps < 0)
         return -1;
 #ifdef _OPENMP
     if (nthreads > 0)
@@ -196,10 +226,17 @@ int oracle3_run(int nx, int ny, int nz, const uint8_t *mask, double *f, double t
     double *post = (double *)calloc(total, sizeof(double));
     if (!post)
         return -2;
+    double omega = 1.0 / tau, omega_m = tau_m == tau ? omega : 1.0 / tau_m;
     for (long s = 0; s < nsteps; ++s)
-        one_step3(nx, ny, nz, mask, f, post, 1.0 / tau, gx, gy, gz);
+        one_step3(nx, ny, nz, mask, f, post, omega, omega_m, gx, gy, gz);
     free(post);
     return 0;
+}
+
+int oracle3_run(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau, double gx,
+                double gy, double gz, long nsteps, int nthreads)
+{
+    return oracle3_run_trt(nx, ny, nz, mask, f, tau, tau, gx, gy, gz, nsteps, nthreads);
 }
 
 /* rho and the corrected velocity of the canonical state; solid nodes 0. */

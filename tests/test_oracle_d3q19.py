@@ -149,3 +149,91 @@ def test_mass_and_momentum(oracle_mod, lat3):
     P0 = np.einsum("ai,izyx->a", c, fp)
     P1 = np.einsum("ai,izyx->a", c, oracle_mod.run3(mp, fp, 0.9, T, g=tuple(g)))
     assert np.abs(P1 - P0 - T * g * fp.sum()).max() < 1e-12 * fp.sum()
+
+
+# ------------------------------------------------------- two-relaxation-time --
+def _random_f3(oracle_mod, rng):
+    return oracle_mod.equilibrium3(1.0, 0.03, -0.02, 0.01) * (1 + 0.03 * rng.standard_normal(19))
+
+
+def test_trt3_reduces_to_bgk(oracle_mod):
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        f = _random_f3(oracle_mod, rng)
+        om = 1.0 / (0.5 + rng.random())
+        g = tuple(1e-3 * rng.standard_normal(3))
+        assert np.abs(oracle_mod.collide3_trt(f, om, om, g) - oracle_mod.collide3(f, om, g)).max() < 1e-16
+
+
+def test_trt3_conservation_and_force(oracle_mod, lat3):
+    c, _, _ = lat3
+    rng = np.random.default_rng(12)
+    g = np.array([2e-3, -1e-3, 5e-4])
+    for _ in range(10):
+        f = _random_f3(oracle_mod, rng)
+        op, om = 1.0 / (0.5 + rng.random()), 1.0 / (0.5 + rng.random())
+        out = oracle_mod.collide3_trt(f, op, om, tuple(g))
+        rho = f.sum()
+        assert abs(out.sum() - rho) < 1e-15
+        assert np.abs(c @ out - c @ f - rho * g).max() < 1e-16
+
+
+@pytest.mark.parametrize("tau_m", [0.55, 0.8, 1.7])
+def test_trt3_viscosity_from_tau_plus(oracle_mod, tau_m):
+    """Shear wave u_x = u0 sin(k z): decay exp(-nu k^2 t), nu = (tau+ - 1/2)/3, any tau-, up
+    to the O(k^2) dispersion term, whose coefficient depends on Lambda (2-D pin: same k)."""
+    nx, ny, nz, tau, u0 = 2, 2, 64, 0.8, 1e-4
+    k = 2 * math.pi / nz
+    m = np.zeros((nz, ny, nx), np.uint8)
+    z = np.arange(nz)[:, None, None] * np.ones((1, ny, nx))
+    f = oracle_mod.init3(m, None, u0 * np.sin(k * z), None, None)
+    amp = []
+    for t in (200, 1200):
+        ft = oracle_mod.run3(m, f, tau, t, tau_minus=tau_m)
+        _, ux, _, _ = oracle_mod.macroscopic3(m, ft)
+        amp.append((ux[:, 0, 0] * np.sin(k * np.arange(nz))).sum() * 2 / nz)
+    rate = -math.log(amp[1] / amp[0]) / 1000.0
+    nu = (tau - 0.5) / 3.0
+    assert abs(rate / (nu * k * k) - 1.0) < 2e-3
+
+
+@pytest.mark.parametrize("magic", [3.0 / 16.0, 0.25, 1.0 / 12.0])
+def test_trt3_steady_channel_closed_form(oracle_mod, magic):
+    """Walls at z = 0 and nz - 1, force along x: the exact TRT halfway-bounce-back profile
+    u(z) = (g/2nu)(z - 1/2)(H + 1/2 - z) + (g/nu)(16 Lambda - 3)/24, H = nz - 2."""
+    nx, ny, nz, tau, g = 2, 2, 14, 0.9, 1e-5
+    H = nz - 2
+    m = np.zeros((nz, ny, nx), np.uint8)
+    m[0] = 1
+    m[nz - 1] = 1
+    tau_m = oracle_mod.trt_tau_minus(tau, magic)
+    f = oracle_mod.run3(m, oracle_mod.init3(m), tau, 30000, g=(g, 0.0, 0.0), tau_minus=tau_m)
+    _, ux, uy, uz = oracle_mod.macroscopic3(m, f, g=(g, 0.0, 0.0))
+    nu = (tau - 0.5) / 3.0
+    zz = np.arange(1, nz - 1)
+    exact = g / (2 * nu) * (zz - 0.5) * (H + 0.5 - zz) + g / nu * (16 * magic - 3) / 24
+    assert np.abs(ux[1:nz - 1, 0, 0] - exact).max() < 1e-10 * exact.max()
+    assert max(np.abs(uy[1:nz - 1]).max(), np.abs(uz[1:nz - 1]).max()) < 1e-12 * exact.max()
+
+
+def test_trt3_z_invariant_projection_is_d2q9(oracle_mod, lat3):
+    """As the BGK projection pin, with the two-relaxation-time collision on both sides."""
+    c, _, _ = lat3
+    nx, ny, nz = 20, 14, 3
+    m2 = synthetic.random_mask(nx, ny, seed=9, solid_fraction=0.15)
+    m2[0, :] = 1
+    m2[ny - 1, :] = 1
+    rho, ux, uy = synthetic.random_fields(nx, ny, seed=4, rho_spread=0.03, u_amp=0.03)
+    g = (2e-4, -1e-4)
+    tm = 1.3
+    f2 = oracle_mod.run(m2, oracle_mod.init(m2, rho, ux, uy), 0.7, 40, g=g, tau_minus=tm)
+    rep = lambda a: np.repeat(a[None], nz, axis=0)
+    m3 = rep(m2)
+    f3 = oracle_mod.init3(m3, rep(rho), rep(ux), rep(uy), None)
+    f3 = oracle_mod.run3(m3, f3, 0.7, 40, g=(g[0], g[1], 0.0), tau_minus=tm)
+    cx2, cy2, _, _ = oracle_mod.constants()
+    for k in range(9):
+        group = [i for i in range(19) if c[0, i] == cx2[k] and c[1, i] == cy2[k]]
+        proj = f3[group].sum(axis=0)
+        for z in range(nz):
+            assert np.abs(proj[z] - f2[k]).max() < 1e-14
