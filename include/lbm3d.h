@@ -6,7 +6,8 @@
  * its future work (Sec. 6).  This interface runs the same update as lbm.h in 3D:
  * the fused pull stream-and-collide step of Algorithm 1 with halfway bounce-back
  * walls (Sec. 3), the BGK operator of Eqs. 3-5 and the equilibrium of Eq. 6 with
- * the D3Q19 weights, plus a body force through Guo's forcing term.  One layout:
+ * the D3Q19 weights, plus a body force through Guo's forcing term and, as an
+ * option, the two-relaxation-time collision.  One layout:
  * two dense lattices swapped every step (the A-B scheme of lbm.h's DENSE_AB).
  *
  * Conventions (as in lbm.h, whose status codes, dtype enum and allocator hook
@@ -83,6 +84,13 @@ int lbm3d_init_equilibrium(lbm3d_ctx *ctx, const double *rho, const double *ux,
 
 /* Change the body-force acceleration (host double[3], finite). */
 int lbm3d_set_force(lbm3d_ctx *ctx, const double *force);
+
+/* Collision model, as lbm_set_trt: magic = 0 BGK (the default); magic > 0 the
+ * two-relaxation-time collision, whose pair-wise symmetric parts relax with
+ * omega = 1 / tau and antisymmetric parts with omega_m = 1 / tau_m,
+ * tau_m = 1/2 + magic / (tau - 1/2) (forcing split alike).  Invalid (negative
+ * or not finite): LBM_ERR_INVALID. */
+int lbm3d_set_trt(lbm3d_ctx *ctx, double magic);
 
 /* Enqueue n >= 0 time steps (one kernel launch each). */
 int lbm3d_step(lbm3d_ctx *ctx, int64_t n);

@@ -325,6 +325,10 @@ class Lattice3D:
     def set_force(self, g):
         self._check(self._lib.lbm3d_set_force(self._ctx, _force3(g)))
 
+    def set_trt(self, magic):
+        """Two-relaxation-time collision with parameter Lambda = magic (0 = BGK)."""
+        self._check(self._lib.lbm3d_set_trt(self._ctx, float(magic)))
+
     def step(self, n=1):
         self._check(self._lib.lbm3d_step(self._ctx, int(n)))
 

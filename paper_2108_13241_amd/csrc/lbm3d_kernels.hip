@@ -97,8 +97,11 @@ __device__ __forceinline__ R pair_dot(int k, R vx, R vy, R vz)
 // S_i = w_i [3 (c_i - u) . F + 9 (c_i . u)(c_i . F)].  Opposite directions
 // share everything but the terms odd in c, so they are updated as a pair; with
 // SHIFT, f holds deviations and rho = 1 + sum is never rounded (rho v = v + sum v).
-template <class R, bool SHIFT, bool FORCE>
-__device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz)
+// TRT: the pair's symmetric part P = (f_i + f_opp)/2 relaxes with omega and its
+// antisymmetric part M = (f_i - f_opp)/2 with omega_m (forcing split alike);
+// f_i = P + M, f_opp = P - M.
+template <class R, bool SHIFT, bool FORCE, bool TRT = false>
+__device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz, R omega_m = R(0))
 {
     R sum = f[0];
 #pragma unroll
@@ -156,17 +159,29 @@ __device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz)
         const R cu = pair_dot(k, ux, uy, uz);
         const R even = w * (C0 + rho_times(R(4.5) * (cu * cu)));
         const R odd = w * rho_times(R(3) * cu);
-        R a = keep * f[i] + omega * (even + odd);
-        R b = keep * f[j] + omega * (even - odd);
-        if constexpr (FORCE) {
-            const R cF = pair_dot(k, Fx, Fy, Fz);
-            const R se = w * (R(9) * cu * cF - R(3) * uF);
-            const R so = R(3) * w * cF;
-            a += guo * (se + so);
-            b += guo * (se - so);
+        if constexpr (TRT) {
+            R P = keep * (R(0.5) * (f[i] + f[j])) + omega * even;
+            R M = (R(1) - omega_m) * (R(0.5) * (f[i] - f[j])) + omega_m * odd;
+            if constexpr (FORCE) {
+                const R cF = pair_dot(k, Fx, Fy, Fz);
+                P += guo * (w * (R(9) * cu * cF - R(3) * uF));
+                M += (R(1) - R(0.5) * omega_m) * (R(3) * w * cF);
+            }
+            f[i] = P + M;
+            f[j] = P - M;
+        } else {
+            R a = keep * f[i] + omega * (even + odd);
+            R b = keep * f[j] + omega * (even - odd);
+            if constexpr (FORCE) {
+                const R cF = pair_dot(k, Fx, Fy, Fz);
+                const R se = w * (R(9) * cu * cF - R(3) * uF);
+                const R so = R(3) * w * cF;
+                a += guo * (se + so);
+                b += guo * (se - so);
+            }
+            f[i] = a;
+            f[j] = b;
         }
-        f[i] = a;
-        f[j] = b;
     }
 }
 
@@ -237,13 +252,13 @@ __device__ __forceinline__ uint32_t solid_bits3(uint8_t t, const uint32_t *__res
     return t == kBoundary ? nmask[n] << 1 : 0u;
 }
 
-template <class ST, bool FORCE>
+template <class ST, bool FORCE, bool TRT>
 __global__ __launch_bounds__(kBlock) void k_step3(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask,
     const uint32_t *__restrict__ seg_interior, int nx, int ny, int nz, int pitch, uint32_t bpr,
     uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real gz)
+    typename ST::real gz, typename ST::real omega_m)
 {
     using R = typename ST::real;
     const uint32_t L = xcd_remap(blockIdx.x, nblocks);
@@ -263,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_step3(
     const Addr a = addr_of(x, y, z, nx, ny, nz, (uint32_t)pitch / kChunk);
     R f[Q];
     pull3<ST>(src, a, sm, f);
-    collide3<R, ST::kShift, FORCE>(f, omega, gx, gy, gz);
+    collide3<R, ST::kShift, FORCE, TRT>(f, omega, gx, gy, gz, omega_m);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         store_nt(&elem(dst, a, i, 1, 1, 1), ST::st(f[i], i));
@@ -433,8 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
     }
 }
 
-template <class ST>
-hipError_t step_typed(const State3 &s, int cur)
+template <class ST, bool TRT>
+void step_launch3(const State3 &s, int cur)
 {
     using M = typename ST::mem;
     using R = typename ST::real;
@@ -443,13 +458,22 @@ hipError_t step_typed(const State3 &s, int cur)
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
     if (s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0)
-        k_step3<ST, true><<<nb, kBlock, 0, s.stream>>>(
+        k_step3<ST, true, TRT><<<nb, kBlock, 0, s.stream>>>(
             src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
-            (R)s.omega, (R)s.gx, (R)s.gy, (R)s.gz);
+            (R)s.omega, (R)s.gx, (R)s.gy, (R)s.gz, (R)s.omega_m);
     else
-        k_step3<ST, false><<<nb, kBlock, 0, s.stream>>>(
+        k_step3<ST, false, TRT><<<nb, kBlock, 0, s.stream>>>(
             src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
-            (R)s.omega, R(0), R(0), R(0));
+            (R)s.omega, R(0), R(0), R(0), (R)s.omega_m);
+}
+
+template <class ST>
+hipError_t step_typed(const State3 &s, int cur)
+{
+    if (s.trt)
+        step_launch3<ST, true>(s, cur);
+    else
+        step_launch3<ST, false>(s, cur);
     return hipGetLastError();
 }
 

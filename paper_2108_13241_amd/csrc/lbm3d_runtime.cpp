@@ -207,6 +207,7 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
     s.nz = nz;
     s.pitch = (int)pitch;
     s.omega = 1.0 / tau;
+    s.omega_m = s.omega;
     s.gx = force ? force[0] : 0.0;
     s.gy = force ? force[1] : 0.0;
     s.gz = force ? force[2] : 0.0;
@@ -290,6 +291,23 @@ int lbm3d_set_force(lbm3d_ctx *c, const double *force)
     c->s.gx = force[0];
     c->s.gy = force[1];
     c->s.gz = force[2];
+    return LBM_OK;
+}
+
+int lbm3d_set_trt(lbm3d_ctx *c, double magic)
+{
+    LBM3_CHECK_CTX(c);
+    if (!(std::isfinite(magic) && magic >= 0.0))
+        return fail(c, LBM_ERR_INVALID, "the TRT parameter must be finite and >= 0 (0 = BGK)");
+    lbm3::State3 &s = c->s;
+    if (magic == 0.0) {
+        s.trt = 0;
+        s.omega_m = s.omega;
+        return LBM_OK;
+    }
+    const double tau = 1.0 / s.omega;
+    s.trt = 1;
+    s.omega_m = 1.0 / (0.5 + magic / (tau - 0.5));
     return LBM_OK;
 }
 

@@ -243,3 +243,29 @@ def test_error_paths_and_info(lbm, oracle_mod):
     assert info["pop_bytes"] == 4 and info["bytes_per_fluid_node"] == 38 * 4 + 1
     assert info["time_step"] == 5 and info["device_bytes"] > 0
     lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_trt_vs_oracle(lbm, oracle_mod, dtype):
+    """Two-relaxation-time collision (Lambda = 1/4, tau = 0.7 -> tau- = 1.75) with random
+    solids, walls and a body force, 41 steps; then back to BGK for 10 steps."""
+    announce(f"d3q19 trt {dtype}")
+    nx, ny, nz = 70, 14, 12
+    m = synthetic.random_mask3(nx, ny, nz, seed=8, solid_fraction=0.12, walls=True)
+    fields = synthetic.random_fields3(nx, ny, nz, seed=5)
+    g = (2e-5, 1e-5, -1e-5)
+    tau_m = oracle_mod.trt_tau_minus(0.7, 0.25)
+    ref = oracle_mod.run3(m, oracle_mod.init3(m, *fields), 0.7, 41, g=g, tau_minus=tau_m)
+    lat = lbm.Lattice3D(m, 0.7, force=g, dtype=dtype)
+    lat.init_equilibrium(*fields)
+    lat.set_trt(0.25)
+    lat.step(41)
+    assert fp_error(lat.get_populations(), ref, m, dtype) <= TOL[dtype]
+    ref = oracle_mod.run3(m, ref, 0.7, 10, g=g)
+    lat.set_trt(0.0)
+    lat.step(10)
+    assert fp_error(lat.get_populations(), ref, m, dtype) <= TOL[dtype]
+    with pytest.raises(lbm.LbmError) as e:
+        lat.set_trt(-1.0)
+    assert e.value.status == -1
+    lat.close()
