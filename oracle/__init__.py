@@ -109,6 +109,10 @@ def lib():
             [ctypes.c_long, ctypes.c_int]
         L.oracle3_run_trt.restype = ctypes.c_int
         L.oracle3_collide_trt.argtypes = [_dp] + [ctypes.c_double] * 5 + [_dp]
+        L.oracle3_run_walls.argtypes = L.oracle3_run_trt.argtypes + [ctypes.c_int]
+        L.oracle3_run_walls.restype = ctypes.c_int
+        L.oracle3_fullway_fill.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp]
+        L.oracle3_fullway_fill.restype = ctypes.c_int
         L.oracle3_macroscopic.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp] + \
             [ctypes.c_double] * 3 + [_dp] * 4
         L.oracle3_macroscopic.restype = ctypes.c_int
@@ -391,19 +395,33 @@ def init3(mask, rho0=None, ux0=None, uy0=None, uz0=None):
     return f
 
 
-def run3(mask, f, tau, steps, g=(0.0, 0.0, 0.0), threads=0, tau_minus=None):
+def run3(mask, f, tau, steps, g=(0.0, 0.0, 0.0), threads=0, tau_minus=None, fullway=False):
     """Advance a copy of the D3Q19 state f by `steps` steps.  tau_minus: antisymmetric
-    relaxation time of the two-relaxation-time collision (None: BGK)."""
+    relaxation time of the two-relaxation-time collision (None: BGK).  fullway: full-way
+    bounce-back (f includes the wall slots)."""
     m = _mask3(mask)
     nz, ny, nx = m.shape
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     if f.shape != (19, nz, ny, nx):
         raise ValueError("f must be [19, nz, ny, nx]")
     tm = float(tau) if tau_minus is None else float(tau_minus)
-    rc = lib().oracle3_run_trt(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
-                               g[2], int(steps), int(threads))
+    rc = lib().oracle3_run_walls(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
+                                 g[2], int(steps), int(threads), int(bool(fullway)))
     if rc:
         raise ValueError(f"oracle3_run failed ({rc})")
+    return f
+
+
+def fullway_fill3(mask, f):
+    """Copy of the D3Q19 state f with the full-way initial wall slots (slot i of wall node w =
+    f_i of the fluid node w - c_i, else 0)."""
+    m = _mask3(mask)
+    nz, ny, nx = m.shape
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    if f.shape != (19, nz, ny, nx):
+        raise ValueError("f must be [19, nz, ny, nx]")
+    if lib().oracle3_fullway_fill(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f)):
+        raise ValueError("oracle3_fullway_fill failed")
     return f
 
 

@@ -6,7 +6,10 @@
  * Eq. 4 BGK; Eq. 6 equilibrium, which holds unchanged in 3D with the D3Q19
  * weights; Eq. 5 viscosity), and the two-relaxation-time collision of the
  * two-dimensional oracle (each population pair split into its symmetric and
- * antisymmetric parts, relaxed at omega_p and omega_m).
+ * antisymmetric parts, relaxed at omega_p and omega_m), and its full-way wall
+ * rule (solid nodes next to fluid hold populations, reverse them instead of
+ * colliding and stream them back; the state then includes those wall slots,
+ * and slots not fed by a fluid node hold 0).
  *
  * TEST INFRASTRUCTURE ONLY.  The GPU library never links, calls, includes or
  * shares anything with this file; only the test-suite and the benchmark's
@@ -167,19 +170,24 @@ int oracle3_init(int nx, int ny, int nz, const uint8_t *mask, const double *rho0
     return 0;
 }
 
-/* One step: collide every fluid node, then push every post-collision
- * population to x + c_i, or back to its origin reversed when x + c_i is
- * solid (halfway bounce-back). */
-static void one_step3(int nx, int ny, int nz, const uint8_t *mask, double *f, double *post,
-                      double omega, double omega_m, double gx, double gy, double gz)
+/* Collision phase: every fluid node collides into `post`; with `wall`
+ * non-NULL (full-way rule) every wall node reverses its populations. */
+static void collide_phase3(int nx, int ny, int nz, const uint8_t *mask, const uint8_t *wall,
+                           const double *f, double *post, double omega, double omega_m,
+                           double gx, double gy, double gz)
 {
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 size_t n = ((size_t)z * ny + y) * nx + x;
-                if (mask[n] != 0)
+                if (mask[n] != 0) {
+                    if (wall && wall[n])
+                        for (int i = 0; i < Q3; ++i)
+                            post[slot3(i, x, y, z, nx, ny, nz)] =
+                                f[slot3(opposite3(i), x, y, z, nx, ny, nz)];
                     continue;
+                }
                 double fl[Q3], fs[Q3];
                 for (int i = 0; i < Q3; ++i)
                     fl[i] = f[slot3(i, x, y, z, nx, ny, nz)];
@@ -190,6 +198,13 @@ static void one_step3(int nx, int ny, int nz, const uint8_t *mask, double *f, do
                 for (int i = 0; i < Q3; ++i)
                     post[slot3(i, x, y, z, nx, ny, nz)] = fs[i];
             }
+}
+
+/* Halfway streaming: push every post-collision population of a fluid node to
+ * x + c_i, or back to its origin reversed when x + c_i is solid. */
+static void stream_halfway3(int nx, int ny, int nz, const uint8_t *mask, double *f,
+                            const double *post)
+{
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
@@ -209,10 +224,87 @@ static void one_step3(int nx, int ny, int nz, const uint8_t *mask, double *f, do
             }
 }
 
+/* Full-way streaming: every post-collision population of a fluid or wall node
+ * moves to x + c_i; a fluid target takes it from either kind of source, a
+ * wall target only from a fluid source (its other slots are cleared). */
+static void stream_fullway3(int nx, int ny, int nz, const uint8_t *mask, const uint8_t *wall,
+                            double *f, const double *post)
+{
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                if (wall[((size_t)z * ny + y) * nx + x])
+                    for (int i = 0; i < Q3; ++i)
+                        f[slot3(i, x, y, z, nx, ny, nz)] = 0.0;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = ((size_t)z * ny + y) * nx + x;
+                if (mask[n] != 0 && !wall[n])
+                    continue;
+                for (int i = 0; i < Q3; ++i) {
+                    int xn = wrap3(x + CX3[i], nx), yn = wrap3(y + CY3[i], ny),
+                        zn = wrap3(z + CZ3[i], nz);
+                    size_t t = ((size_t)zn * ny + yn) * nx + xn;
+                    if (mask[t] == 0 || (wall[t] && mask[n] == 0))
+                        f[slot3(i, xn, yn, zn, nx, ny, nz)] = post[slot3(i, x, y, z, nx, ny, nz)];
+                }
+            }
+}
+
+/* Wall nodes: solid nodes with at least one fluid neighbour. */
+static void find_walls3(int nx, int ny, int nz, const uint8_t *mask, uint8_t *wall)
+{
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = ((size_t)z * ny + y) * nx + x;
+                wall[n] = 0;
+                if (mask[n] == 0)
+                    continue;
+                for (int i = 1; i < Q3; ++i)
+                    if (mask[((size_t)wrap3(z + CZ3[i], nz) * ny + wrap3(y + CY3[i], ny)) * nx +
+                             wrap3(x + CX3[i], nx)] == 0)
+                        wall[n] = 1;
+            }
+}
+
+/* Full-way initial wall slots: slot i of wall node w takes f_i of the fluid
+ * node w - c_i, 0 where w - c_i is not fluid; fluid slots unchanged. */
+int oracle3_fullway_fill(int nx, int ny, int nz, const uint8_t *mask, double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1)
+        return -1;
+    uint8_t *wall = (uint8_t *)malloc((size_t)nx * ny * nz);
+    if (!wall)
+        return -2;
+    find_walls3(nx, ny, nz, mask, wall);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (!wall[((size_t)z * ny + y) * nx + x])
+                    continue;
+                for (int i = 0; i < Q3; ++i) {
+                    int xs = wrap3(x - CX3[i], nx), ys = wrap3(y - CY3[i], ny),
+                        zs = wrap3(z - CZ3[i], nz);
+                    f[slot3(i, x, y, z, nx, ny, nz)] =
+                        mask[((size_t)zs * ny + ys) * nx + xs] == 0
+                            ? f[slot3(i, xs, ys, zs, nx, ny, nz)]
+                            : 0.0;
+                }
+            }
+    free(wall);
+    return 0;
+}
+
 /* nsteps steps in place; tau_m is the antisymmetric relaxation time of the
- * two-relaxation-time collision (tau_m = tau: BGK). */
-int oracle3_run_trt(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
-                    double tau_m, double gx, double gy, double gz, long nsteps, int nthreads)
+ * two-relaxation-time collision (tau_m = tau: BGK); fullway selects the
+ * full-way wall rule. */
+int oracle3_run_walls(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
+                      double tau_m, double gx, double gy, double gz, long nsteps, int nthreads,
+                      int fullway)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !(tau > 0.5) || !(tau_m > 0.5) || nsteps < 0)
         return -1;
@@ -224,13 +316,31 @@ int oracle3_run_trt(int nx, int ny, int nz, const uint8_t *mask, double *f, doub
 #endif
     size_t total = (size_t)Q3 * nx * ny * nz;
     double *post = (double *)calloc(total, sizeof(double));
-    if (!post)
+    uint8_t *wall = fullway ? (uint8_t *)malloc((size_t)nx * ny * nz) : NULL;
+    if (!post || (fullway && !wall)) {
+        free(post);
+        free(wall);
         return -2;
+    }
+    if (wall)
+        find_walls3(nx, ny, nz, mask, wall);
     double omega = 1.0 / tau, omega_m = tau_m == tau ? omega : 1.0 / tau_m;
-    for (long s = 0; s < nsteps; ++s)
-        one_step3(nx, ny, nz, mask, f, post, omega, omega_m, gx, gy, gz);
+    for (long s = 0; s < nsteps; ++s) {
+        collide_phase3(nx, ny, nz, mask, wall, f, post, omega, omega_m, gx, gy, gz);
+        if (wall)
+            stream_fullway3(nx, ny, nz, mask, wall, f, post);
+        else
+            stream_halfway3(nx, ny, nz, mask, f, post);
+    }
     free(post);
+    free(wall);
     return 0;
+}
+
+int oracle3_run_trt(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
+                    double tau_m, double gx, double gy, double gz, long nsteps, int nthreads)
+{
+    return oracle3_run_walls(nx, ny, nz, mask, f, tau, tau_m, gx, gy, gz, nsteps, nthreads, 0);
 }
 
 int oracle3_run(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau, double gx,
