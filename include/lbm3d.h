@@ -6,8 +6,9 @@
  * its future work (Sec. 6).  This interface runs the same update as lbm.h in 3D:
  * the fused pull stream-and-collide step of Algorithm 1 with halfway bounce-back
  * walls (Sec. 3), the BGK operator of Eqs. 3-5 and the equilibrium of Eq. 6 with
- * the D3Q19 weights, plus a body force through Guo's forcing term and, as an
- * option, the two-relaxation-time collision.  One layout:
+ * the D3Q19 weights, plus a body force through Guo's forcing term and, as
+ * options, the two-relaxation-time collision and the full-way wall rule.  One
+ * layout:
  * two dense lattices swapped every step (the A-B scheme of lbm.h's DENSE_AB).
  *
  * Conventions (as in lbm.h, whose status codes, dtype enum and allocator hook
@@ -26,7 +27,8 @@
  *    (+x+z, -x-z), (+x-z, -x+z), (+y+z, -y-z), (+y-z, -y+z).  Weights 1/3 (rest),
  *    1/18 (axes), 1/36 (edges).
  *  - "Canonical" populations are the pre-collision values f_i(x, t) as FP64
- *    [19][nz][ny][nx]; solid slots = 0.
+ *    [19][nz][ny][nx]; solid slots = 0 (full-way rule: see
+ *    lbm3d_set_bounce_back).
  *  - dtype: LBM_F64 stores and computes in FP64; LBM_F32, LBM_F16_SHIFTED and
  *    LBM_BF16_SHIFTED store the deviation f_i - w_i in 32 or 16 bits and compute
  *    in FP32 on the deviations.
@@ -91,6 +93,18 @@ int lbm3d_set_force(lbm3d_ctx *ctx, const double *force);
  * tau_m = 1/2 + magic / (tau - 1/2) (forcing split alike).  Invalid (negative
  * or not finite): LBM_ERR_INVALID. */
 int lbm3d_set_trt(lbm3d_ctx *ctx, double magic);
+
+/* Wall rule, as lbm_set_bounce_back: 0 halfway (the default), 1 full-way (solid
+ * nodes next to fluid hold the populations streamed into them, reverse them in
+ * the next step and stream them back).  Under mode 1 the canonical state also
+ * holds the wall slots (population j of wall node w for every j whose source
+ * w - c_j is fluid): lbm3d_get_populations returns them, lbm3d_set_populations
+ * reads them (finite), lbm3d_mass counts them; lbm3d_init_equilibrium and a
+ * switch from mode 0 set slot j of w to population j of the fluid node
+ * w - c_j.  The fluid populations are kept across a switch.  No extra memory
+ * (the A-B pair holds the state).  Invalid mode: LBM_ERR_INVALID.
+ * Synchronises the stream. */
+int lbm3d_set_bounce_back(lbm3d_ctx *ctx, int32_t mode);
 
 /* Enqueue n >= 0 time steps (one kernel launch each). */
 int lbm3d_step(lbm3d_ctx *ctx, int64_t n);

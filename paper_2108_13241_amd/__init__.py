@@ -329,6 +329,12 @@ class Lattice3D:
         """Two-relaxation-time collision with parameter Lambda = magic (0 = BGK)."""
         self._check(self._lib.lbm3d_set_trt(self._ctx, float(magic)))
 
+    def set_bounce_back(self, mode):
+        """"halfway" (default) or "fullway" wall rule (0 / 1); under full-way the canonical
+        populations include the wall slots of solid nodes next to fluid."""
+        m = {"halfway": 0, "fullway": 1}.get(mode, mode)
+        self._check(self._lib.lbm3d_set_bounce_back(self._ctx, int(m)))
+
     def step(self, n=1):
         self._check(self._lib.lbm3d_step(self._ctx, int(n)))
 

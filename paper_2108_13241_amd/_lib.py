@@ -94,6 +94,7 @@ SIGNATURES = {
     "lbm3d_init_equilibrium": (_c.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbm3d_set_force": (_c.c_int, [_vp, _dp]),
     "lbm3d_set_trt": (_c.c_int, [_vp, _c.c_double]),
+    "lbm3d_set_bounce_back": (_c.c_int, [_vp, _i32]),
     "lbm3d_step": (_c.c_int, [_vp, _i64]),
     "lbm3d_macroscopic": (_c.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbm3d_get_populations": (_c.c_int, [_vp, _dp]),

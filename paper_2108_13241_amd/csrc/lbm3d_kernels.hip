@@ -225,14 +225,19 @@ __device__ __forceinline__ Addr addr_of(int x, int y, int z, int nx, int ny, int
     return a;
 }
 
-// Pull gather: f_i(x) = s_i(x - c_i), or s_opp(i)(x) when x - c_i is solid
-// (bit i of sm).
+// Pull gather: f_i(x) = s_i(x - c_i), or bb_opp(i)(x) when x - c_i is solid
+// (bit i of sm): bb = s for halfway bounce-back; for the full-way rule bb is
+// the other lattice of the A-B pair, which still holds the node's
+// post-collision values of two steps back (the time a population sent into a
+// wall node takes to return).
 template <class ST>
-__device__ __forceinline__ void pull3(const typename ST::mem *__restrict__ s, const Addr &a,
-                                      uint32_t sm, typename ST::real (&f)[Q])
+__device__ __forceinline__ void pull3(const typename ST::mem *__restrict__ s,
+                                      const typename ST::mem *bb, const Addr &a, uint32_t sm,
+                                      typename ST::real (&f)[Q])
 {
     using M = typename ST::mem;
     M *sp = const_cast<M *>(s);
+    M *bp = const_cast<M *>(bb);
     if (sm == 0) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
@@ -241,7 +246,7 @@ __device__ __forceinline__ void pull3(const typename ST::mem *__restrict__ s, co
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        f[i] = ST::ld(((sm >> i) & 1u) ? elem(sp, a, kOpp[i], 1, 1, 1)
+        f[i] = ST::ld(((sm >> i) & 1u) ? elem(bp, a, kOpp[i], 1, 1, 1)
                                        : elem(sp, a, i, 1 - kCz[i], 1 - kCy[i], 1 - kCx[i]),
                       i);
 }
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_step3(
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask,
     const uint32_t *__restrict__ seg_interior, int nx, int ny, int nz, int pitch, uint32_t bpr,
     uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real gz, typename ST::real omega_m)
+    typename ST::real gz, typename ST::real omega_m, int fullway)
 {
     using R = typename ST::real;
     const uint32_t L = xcd_remap(blockIdx.x, nblocks);
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_step3(
     }
     const Addr a = addr_of(x, y, z, nx, ny, nz, (uint32_t)pitch / kChunk);
     R f[Q];
-    pull3<ST>(src, a, sm, f);
+    pull3<ST>(src, fullway ? dst : src, a, sm, f);
     collide3<R, ST::kShift, FORCE, TRT>(f, omega, gx, gy, gz, omega_m);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -288,12 +293,17 @@ __global__ __launch_bounds__(kBlock) void k_step3(
 // Canonical FP64 buffers are [19][nz][ny][pitch].
 
 // Thread gid = node (z * ny + y) * pitch + x: the canonical (pull-gathered)
-// populations of a fluid node; false for padding and solid nodes.
+// populations of a fluid node; false for padding and solid nodes.  bb: the
+// bounce-back source of pull3.  Under the full-way rule (bb not st) the node
+// also reports its wall slots: bit j of wl set <=> node x + c_j is solid, and
+// the population in flight there, f_j(x + c_j), is the node's stored slot j.
 template <class ST>
 __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST::mem *st,
-                                             uint32_t gid, int &x, int &y, int &z,
-                                             double (&fd)[Q])
+                                             const typename ST::mem *bb, uint32_t gid, int &x,
+                                             int &y, int &z, double (&fd)[Q], uint32_t &wl,
+                                             double (&wv)[Q])
 {
+    wl = 0;
     const uint32_t r = gid / (uint32_t)s.pitch;
     x = (int)(gid - r * (uint32_t)s.pitch);
     if (x >= s.nx || r >= (uint32_t)(s.ny * s.nz))
@@ -304,42 +314,69 @@ __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST:
     if (t == kSolid)
         return false;
     const Addr a = addr_of(x, y, z, s.nx, s.ny, s.nz, (uint32_t)s.pitch / kChunk);
+    const uint32_t sm = solid_bits3(t, s.nmask, gid);
     typename ST::real f[Q];
-    pull3<ST>(st, a, solid_bits3(t, s.nmask, gid), f);
+    pull3<ST>(st, bb, a, sm, f);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         fd[i] = ST::canon(f[i], i);
+    if (bb != st)
+        for (int j = 1; j < Q; ++j)
+            if ((sm >> kOpp[j]) & 1u) {  // x + c_j is x - c_opp(j)
+                wl |= 1u << j;
+                wv[j] = ST::canon(ST::ld(elem(const_cast<typename ST::mem *>(st), a, j, 1, 1, 1),
+                                         j),
+                                  j);
+            }
     return true;
+}
+
+// Padded node index of x + c_j (periodic).
+__device__ __forceinline__ uint32_t node_plus(const State3 &s, int x, int y, int z, int j)
+{
+    const int xs = x + kCx[j] < 0 ? s.nx - 1 : (x + kCx[j] >= s.nx ? 0 : x + kCx[j]);
+    const int ys = y + kCy[j] < 0 ? s.ny - 1 : (y + kCy[j] >= s.ny ? 0 : y + kCy[j]);
+    const int zs = z + kCz[j] < 0 ? s.nz - 1 : (z + kCz[j] >= s.nz ? 0 : z + kCz[j]);
+    return ((uint32_t)zs * s.ny + ys) * (uint32_t)s.pitch + xs;
 }
 
 template <class ST>
 __global__ __launch_bounds__(kBlock) void k_gather3(State3 s, const typename ST::mem *st,
+                                                    const typename ST::mem *bb,
                                                     double *__restrict__ fc)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     int x, y, z;
-    double f[Q];
-    if (!canonical_at<ST>(s, st, gid, x, y, z, f))
+    double f[Q], wv[Q];
+    uint32_t wl;
+    if (!canonical_at<ST>(s, st, bb, gid, x, y, z, f, wl, wv))
         return;
     const uint32_t plane = (uint32_t)(s.nz * s.ny) * (uint32_t)s.pitch;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         fc[(uint32_t)i * plane + gid] = f[i];
+    // wall slots (full-way rule): each has exactly one fluid source node
+    for (int j = 1; j < Q; ++j)
+        if ((wl >> j) & 1u)
+            fc[(uint32_t)j * plane + node_plus(s, x, y, z, j)] = wv[j];
 }
 
 // Macroscopic fields (Eq. 2 with the half-force velocity) into [nz][ny][nx]
-// buffers, and per-block partial sums of rho (for the mass).
+// buffers, and per-block partial sums of the mass: rho, plus (full-way rule)
+// the populations in flight in the wall slots the node feeds.
 template <class ST>
 __global__ __launch_bounds__(kBlock) void k_macro3(State3 s, const typename ST::mem *st,
-                                                   double *rho, double *ux, double *uy,
-                                                   double *uz, double *partials)
+                                                   const typename ST::mem *bb, double *rho,
+                                                   double *ux, double *uy, double *uz,
+                                                   double *partials)
 {
     __shared__ double ws[kBlock / 64];
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     int x, y, z;
-    double f[Q];
-    double r = 0.0;
-    if (canonical_at<ST>(s, st, gid, x, y, z, f)) {
+    double f[Q], wv[Q];
+    uint32_t wl;
+    double r = 0.0, mass = 0.0;
+    if (canonical_at<ST>(s, st, bb, gid, x, y, z, f, wl, wv)) {
         double mx = 0.0, my = 0.0, mz = 0.0;
         for (int i = 0; i < Q; ++i) {
             r += f[i];
@@ -354,12 +391,16 @@ __global__ __launch_bounds__(kBlock) void k_macro3(State3 s, const typename ST::
             uy[o] = my / r + 0.5 * s.gy;
             uz[o] = mz / r + 0.5 * s.gz;
         }
+        mass = r;
+        for (int j = 1; j < Q; ++j)
+            if ((wl >> j) & 1u)
+                mass += wv[j];
     }
     if (partials) {
         for (int o = 32; o > 0; o >>= 1)
-            r += __shfl_down(r, o, 64);
+            mass += __shfl_down(mass, o, 64);
         if ((threadIdx.x & 63) == 0)
-            ws[threadIdx.x >> 6] = r;
+            ws[threadIdx.x >> 6] = mass;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
@@ -417,8 +458,13 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium3(State3 s, const double 
 
 // Canonical -> stored A-B state: slot s_j(q) streams into f_j(q + c_j), or,
 // when q + c_j is solid, into f_opp(j)(q) (the inverse of the pull gather).
+// Full-way rule (walls = 1 or 2): s_j(q) = f_j(q + c_j) also when q + c_j is a
+// wall node (its wall slot; walls = 2: the node's own f_j, the initial
+// wall-slot rule), and the other lattice's slot opp(i) of q holds f_i(q) for
+// every bounce-back link i (it returns from the wall at this step).
 template <class ST>
 __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem *st,
+                                                     typename ST::mem *other, int walls,
                                                      const double *__restrict__ fc)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
@@ -436,16 +482,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
     for (int j = 0; j < Q; ++j) {
         double v;
         // q + c_j is node q - c_opp(j): solid iff bit opp(j) is set
-        if ((sm >> kOpp[j]) & 1u) {
-            v = fc[(uint32_t)kOpp[j] * plane + gid];
-        } else {
-            const int xs = x + kCx[j] < 0 ? s.nx - 1 : (x + kCx[j] >= s.nx ? 0 : x + kCx[j]);
-            const int ys = y + kCy[j] < 0 ? s.ny - 1 : (y + kCy[j] >= s.ny ? 0 : y + kCy[j]);
-            const int zs = z + kCz[j] < 0 ? s.nz - 1 : (z + kCz[j] >= s.nz ? 0 : z + kCz[j]);
-            v = fc[(uint32_t)j * plane + ((uint32_t)zs * s.ny + ys) * (uint32_t)s.pitch + xs];
-        }
+        if (((sm >> kOpp[j]) & 1u) == 0 || walls == 1)
+            v = fc[(uint32_t)j * plane + node_plus(s, x, y, z, j)];
+        else
+            v = fc[(uint32_t)(walls == 2 ? j : kOpp[j]) * plane + gid];
         elem(st, a, j, 1, 1, 1) = ST::from_canon(v, j);
     }
+    if (walls != 0)
+        for (int i = 1; i < Q; ++i)
+            if ((sm >> i) & 1u)
+                elem(other, a, kOpp[i], 1, 1, 1) = ST::from_canon(fc[(uint32_t)i * plane + gid],
+                                                                  kOpp[i]);
 }
 
 template <class ST, bool TRT>
@@ -460,11 +507,11 @@ void step_launch3(const State3 &s, int cur)
     if (s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0)
         k_step3<ST, true, TRT><<<nb, kBlock, 0, s.stream>>>(
             src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
-            (R)s.omega, (R)s.gx, (R)s.gy, (R)s.gz, (R)s.omega_m);
+            (R)s.omega, (R)s.gx, (R)s.gy, (R)s.gz, (R)s.omega_m, s.fullway);
     else
         k_step3<ST, false, TRT><<<nb, kBlock, 0, s.stream>>>(
             src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
-            (R)s.omega, R(0), R(0), R(0), (R)s.omega_m);
+            (R)s.omega, R(0), R(0), R(0), (R)s.omega_m, s.fullway);
 }
 
 template <class ST>
@@ -502,42 +549,40 @@ hipError_t launch_equilibrium3(const State3 &s, const double *rho, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_scatter3(const State3 &s, int cur, const double *fc)
+// Calls fn with a value of the storage codec of the context.
+template <class Fn>
+hipError_t by_dtype(int dtype, Fn fn)
 {
-    void *dst = s.f[cur];
-    const uint32_t nb = node_blocks(s);
-    switch (s.dtype) {
-    case 0: k_scatter3<F64><<<nb, kBlock, 0, s.stream>>>(s, (double *)dst, fc); break;
-    case 1: k_scatter3<Shifted<float>><<<nb, kBlock, 0, s.stream>>>(s, (float *)dst, fc); break;
-    case 2:
-        k_scatter3<Shifted<_Float16>><<<nb, kBlock, 0, s.stream>>>(s, (_Float16 *)dst, fc);
-        break;
-    case 3:
-        k_scatter3<Shifted<__bf16>><<<nb, kBlock, 0, s.stream>>>(s, (__bf16 *)dst, fc);
-        break;
+    switch (dtype) {
+    case 0: fn(F64{}); break;
+    case 1: fn(Shifted<float>{}); break;
+    case 2: fn(Shifted<_Float16>{}); break;
+    case 3: fn(Shifted<__bf16>{}); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_scatter3(const State3 &s, int cur, const double *fc, int fill_walls)
+{
+    const uint32_t nb = node_blocks(s);
+    const int walls = s.fullway ? (fill_walls ? 2 : 1) : 0;
+    return by_dtype(s.dtype, [&](auto st) {
+        using M = typename decltype(st)::mem;
+        k_scatter3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, (M *)s.f[cur], (M *)s.f[1 - cur],
+                                                              walls, fc);
+    });
+}
+
 hipError_t launch_gather3(const State3 &s, int cur, double *fc)
 {
-    const void *src = s.f[cur];
     const uint32_t nb = node_blocks(s);
-    switch (s.dtype) {
-    case 0: k_gather3<F64><<<nb, kBlock, 0, s.stream>>>(s, (const double *)src, fc); break;
-    case 1:
-        k_gather3<Shifted<float>><<<nb, kBlock, 0, s.stream>>>(s, (const float *)src, fc);
-        break;
-    case 2:
-        k_gather3<Shifted<_Float16>><<<nb, kBlock, 0, s.stream>>>(s, (const _Float16 *)src, fc);
-        break;
-    case 3:
-        k_gather3<Shifted<__bf16>><<<nb, kBlock, 0, s.stream>>>(s, (const __bf16 *)src, fc);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return by_dtype(s.dtype, [&](auto st) {
+        using M = typename decltype(st)::mem;
+        const M *src = (const M *)s.f[cur];
+        const M *bb = s.fullway ? (const M *)s.f[1 - cur] : src;
+        k_gather3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, src, bb, fc);
+    });
 }
 
 int64_t reduction_capacity3(const State3 &s)
@@ -549,33 +594,20 @@ int64_t reduction_capacity3(const State3 &s)
 hipError_t launch_macro3(const State3 &s, int cur, double *rho, double *ux, double *uy, double *uz,
                          double *mass)
 {
-    const void *src = s.f[cur];
     const uint32_t nb = node_blocks(s);
     double *part = mass ? s.red : nullptr;
-    switch (s.dtype) {
-    case 0:
-        k_macro3<F64><<<nb, kBlock, 0, s.stream>>>(s, (const double *)src, rho, ux, uy, uz, part);
-        break;
-    case 1:
-        k_macro3<Shifted<float>><<<nb, kBlock, 0, s.stream>>>(s, (const float *)src, rho, ux, uy,
-                                                              uz, part);
-        break;
-    case 2:
-        k_macro3<Shifted<_Float16>><<<nb, kBlock, 0, s.stream>>>(s, (const _Float16 *)src, rho,
-                                                                 ux, uy, uz, part);
-        break;
-    case 3:
-        k_macro3<Shifted<__bf16>><<<nb, kBlock, 0, s.stream>>>(s, (const __bf16 *)src, rho, ux, uy,
-                                                               uz, part);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    if (mass) {
-        // fixed-order sums: blocks of 2048 partials, then one block
-        const uint32_t nst = (nb + 2047) / 2048;
-        k_sum3<<<nst, kBlock, 0, s.stream>>>(s.red, nb, 2048, s.red + nb);
-        k_sum3<<<1, kBlock, 0, s.stream>>>(s.red + nb, nst, nst, mass);
-    }
+    hipError_t e = by_dtype(s.dtype, [&](auto st) {
+        using M = typename decltype(st)::mem;
+        const M *src = (const M *)s.f[cur];
+        const M *bb = s.fullway ? (const M *)s.f[1 - cur] : src;
+        k_macro3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, src, bb, rho, ux, uy, uz, part);
+    });
+    if (e != hipSuccess || !mass)
+        return e;
+    // fixed-order sums: blocks of 2048 partials, then one block
+    const uint32_t nst = (nb + 2047) / 2048;
+    k_sum3<<<nst, kBlock, 0, s.stream>>>(s.red, nb, 2048, s.red + nb);
+    k_sum3<<<1, kBlock, 0, s.stream>>>(s.red + nb, nst, nst, mass);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ struct State3 {
     double omega = 1.0, gx = 0.0, gy = 0.0, gz = 0.0;
     int trt = 0;                             // 1: two-relaxation-time collision
     double omega_m = 1.0;                    // its antisymmetric relaxation rate
+    int fullway = 0;                         // 1: full-way bounce-back
     hipStream_t stream = nullptr;
     double *red = nullptr;                   // reduction scratch (reduction_capacity3 doubles)
 };
@@ -40,13 +41,17 @@ hipError_t launch_step3(const State3 &s, int cur);
 // canonical buffer fc (FP64 [19][nz][ny][pitch]).
 hipError_t launch_equilibrium3(const State3 &s, const double *rho, const double *ux,
                                const double *uy, const double *uz, double *fc);
-// Canonical fc -> stored lattice cur.
-hipError_t launch_scatter3(const State3 &s, int cur, const double *fc);
-// Stored lattice cur -> canonical fc at fluid nodes (other slots untouched).
+// Canonical fc -> stored lattice cur (full-way rule: also the other lattice's
+// bounce-back slots; with fill_walls the wall slots come from the fluid nodes
+// that feed them instead of from fc).
+hipError_t launch_scatter3(const State3 &s, int cur, const double *fc, int fill_walls);
+// Stored lattice cur -> canonical fc at fluid nodes and (full-way rule) wall
+// slots; other slots untouched.
 hipError_t launch_gather3(const State3 &s, int cur, double *fc);
 // Macroscopic fields of fluid nodes into FP64 [nz][ny][nx] buffers (rho may be
 // NULL to skip them; other entries untouched) and, when mass is non-NULL, the
-// total mass into *mass (device) through fixed-order sums in s.red.
+// total mass (full-way rule: wall slots included) into *mass (device) through
+// fixed-order sums in s.red.
 hipError_t launch_macro3(const State3 &s, int cur, double *rho, double *ux, double *uy, double *uz,
                          double *mass);
 int64_t reduction_capacity3(const State3 &s);

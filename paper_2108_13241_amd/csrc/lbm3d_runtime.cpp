@@ -153,7 +153,7 @@ int init_state(lbm3d_ctx *c, const double *rho, const double *ux, const double *
     c->t = 0;
     c->cur = 0;
     LBM3_HIP(c, lbm3::launch_equilibrium3(c->s, dp[0], dp[1], dp[2], dp[3], (double *)fc.p));
-    LBM3_HIP(c, lbm3::launch_scatter3(c->s, c->cur, (const double *)fc.p));
+    LBM3_HIP(c, lbm3::launch_scatter3(c->s, c->cur, (const double *)fc.p, 1));
     LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
     return LBM_OK;
 }
@@ -311,6 +311,26 @@ int lbm3d_set_trt(lbm3d_ctx *c, double magic)
     return LBM_OK;
 }
 
+int lbm3d_set_bounce_back(lbm3d_ctx *c, int32_t mode)
+{
+    LBM3_CHECK_CTX(c);
+    if (mode != 0 && mode != 1)
+        return fail(c, LBM_ERR_INVALID, "bounce-back mode must be 0 (halfway) or 1 (full-way)");
+    if (mode == c->s.fullway)
+        return LBM_OK;
+    // keep the fluid populations: gather under the old rule, store under the new
+    // one (switching to full-way fills the wall slots from their sources)
+    Temp fc(c, canonical_bytes(c));
+    if (!fc.p)
+        return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
+    LBM3_HIP(c, lbm::launch_fill((double *)fc.p, canonical_bytes(c) / 8, 0.0, c->s.stream));
+    LBM3_HIP(c, lbm3::launch_gather3(c->s, c->cur, (double *)fc.p));
+    c->s.fullway = mode;
+    LBM3_HIP(c, lbm3::launch_scatter3(c->s, c->cur, (const double *)fc.p, mode));
+    LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+    return LBM_OK;
+}
+
 int lbm3d_step(lbm3d_ctx *c, int64_t n)
 {
     LBM3_CHECK_CTX(c);
@@ -371,6 +391,28 @@ int lbm3d_set_populations(lbm3d_ctx *c, const double *f)
         for (size_t k = 0; k < nn; ++k)
             if (c->mask[k] == 0 && !std::isfinite(f[i * nn + k]))
                 return fail(c, LBM_ERR_INVALID, "populations must be finite at fluid nodes");
+    if (c->s.fullway) {
+        // wall slot j of solid node w is read when w - c_j is fluid
+        static const int cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+        static const int cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+        static const int cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+        const int nx = c->s.nx, ny = c->s.ny, nz = c->s.nz;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const size_t k = ((size_t)z * ny + y) * nx + x;
+                    if (c->mask[k] == 0)
+                        continue;
+                    for (int j = 1; j < Q; ++j) {
+                        const int xs = (x - cx[j] + nx) % nx, ys = (y - cy[j] + ny) % ny,
+                                  zs = (z - cz[j] + nz) % nz;
+                        if (c->mask[((size_t)zs * ny + ys) * nx + xs] == 0 &&
+                            !std::isfinite(f[j * nn + k]))
+                            return fail(c, LBM_ERR_INVALID,
+                                        "populations must be finite in the wall slots");
+                    }
+                }
+    }
     Temp fc(c, canonical_bytes(c));
     if (!fc.p)
         return fail(c, LBM_ERR_NOMEM, "cannot allocate the canonical staging buffer");
@@ -378,7 +420,7 @@ int lbm3d_set_populations(lbm3d_ctx *c, const double *f)
     LBM3_HIP(c, hipMemcpy2DAsync(fc.p, (size_t)c->s.pitch * sizeof(double), f, w, w,
                                  (size_t)Q * c->s.nz * c->s.ny, hipMemcpyHostToDevice,
                                  c->s.stream));
-    LBM3_HIP(c, lbm3::launch_scatter3(c->s, c->cur, (const double *)fc.p));
+    LBM3_HIP(c, lbm3::launch_scatter3(c->s, c->cur, (const double *)fc.p, 0));
     LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
     return LBM_OK;
 }

@@ -121,6 +121,7 @@ def test_null_context3d(lib):
     assert lib.lbm3d_mass(None, ctypes.byref(ctypes.c_double())) == -1
     assert lib.lbm3d_get_info(None, None) == -1
     assert lib.lbm3d_set_trt(None, 0.25) == -1
+    assert lib.lbm3d_set_bounce_back(None, 1) == -1
     lib.lbm3d_destroy(None)
 
 
