@@ -11,11 +11,12 @@ paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on st
               / average kernel duration from HIP events on the stream the kernels run
               on, against the MI355X HBM peak (8 TB/s);
   cpu_baseline = the FP64 CPU oracle on the host cores, a bounded number of steps of
-              the same 4096^2 workload;
-  variants  = the same measurement for the other storage types and the AA layout, the
-              open-boundary channels and the D3Q19 lattice (256^3 three-dimensional
-              Taylor-Green vortex), and, with --suite full, the porous / sparse layouts
-              and the adjoint.
+              the same 4096^2 workload (about 12 s), plus one step on a single thread;
+  variants  = the same measurement for the other storage types, the AA layout and the
+              TRT collision, the open-boundary channels, the end-to-end rate with host
+              transfers and the D3Q19 lattice (256^3 three-dimensional Taylor-Green
+              vortex); with --suite full also 1024^2 / 2048^2, the porous / sparse layouts
+              (halfway and full-way walls), set-up and view costs and the adjoint.
 
   --suite sparse: the paper's sparse-geometry study (Sec. 4.3, Fig. 8): sparse efficiency
               eta_P (Eq. 9) over porosity for regular and random circle obstacles, per layout.

@@ -41,7 +41,6 @@ struct DevState {
     double omega = 1.0, gx = 0.0, gy = 0.0;
     hipStream_t stream = nullptr;
     double *red_partials = nullptr;   // reduction scratch (>= red_capacity doubles)
-    unsigned *red_counter = nullptr;  // zero between reductions
     int64_t red_capacity = 0;
 };
 
