@@ -361,7 +361,11 @@ __device__ __forceinline__ int wrap_inc(int a, int n) { return a == n - 1 ? 0 : 
 //  dense rows : chunks of 64 nodes along x; node (x, y) -> chunk y * cpr + x / 64
 //               (cpr = pitch / 64 chunks per row), stride 64
 //  node lists : chunks of 64 consecutive list entries, stride 64
-//  tiles      : one chunk per 16 x 16 tile (256 nodes), stride 256
+//  tiles      : one chunk per 16 x 16 tile (256 nodes), stride 256; inside a
+//               tile the nodes run in 4 x 4 blocks (tile_slot), so that a
+//               128-byte line holds a compact block of nodes, not a strip of a
+//               row: on sparse geometries fewer lines then mix fluid and solid
+//               nodes (4 tile rows, one wavefront, stay one contiguous run)
 constexpr uint32_t kChunk = 64;
 constexpr uint32_t kTileStride = 256;
 
@@ -376,6 +380,12 @@ __device__ __forceinline__ uint32_t list_base(uint32_t n)
 __device__ __forceinline__ uint32_t tile_base(uint32_t k, uint32_t t)
 {
     return k * (9u * kTileStride) + t;
+}
+// In-tile slot of node (lx, ly), 0 <= lx, ly < 16: bits ly3 ly2 | lx3 lx2 |
+// ly1 ly0 | lx1 lx0 (4 x 4 blocks, blocks row-major, nodes row-major inside).
+__device__ __forceinline__ uint32_t tile_slot(uint32_t lx, uint32_t ly)
+{
+    return ((ly & 12u) << 4) | ((lx & 12u) << 2) | ((ly & 3u) << 2) | (lx & 3u);
 }
 
 // nb[i] = base offset of node x - c_i (periodic) in the dense layout;

@@ -53,7 +53,7 @@ __device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const 
             kk = bx ? tn[dir_of(-cx, 0)] : kk;
         else if (cy != 0)
             kk = by ? tn[dir_of(0, -cy)] : kk;
-        nb[i] = tile_base((uint32_t)kk, (uint32_t)(((sy & 15) << 4) | (sx & 15)));
+        nb[i] = tile_base((uint32_t)kk, tile_slot((uint32_t)(sx & 15), (uint32_t)(sy & 15)));
     }
 }
 
