@@ -129,8 +129,13 @@ int lbm_set_allocator(lbm_alloc_fn alloc, lbm_free_fn free_fn, void *user);
  *            F = rho (g - alpha u).
  * The lattice starts at rest (rho = 1, u = 0; Algorithm 1 initialisation) on
  * the current HIP device, using the default stream until lbm_set_stream.
+ * Size limits (pitch = nx rounded up to 64): DENSE_AB / DENSE_AA take
+ * ny * pitch < 2^31 nodes and 9 * pitch < 2^28, i.e. lattices up to the
+ * device's memory (FP64 A-B: 144 B per node, about 2 G nodes in 288 GB);
+ * TILED16 / TILED16_ALL / INDIRECT use 32-bit offsets and take
+ * 9 * ny * pitch < 2^32 (about 477 M mesh nodes).
  * Errors: INVALID (sizes, tau, non-finite force, mask value), UNSUPPORTED
- * (layout constraint), NOMEM, DEVICE. */
+ * (layout constraint, size limit), NOMEM, DEVICE. */
 int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, double tau,
                const double *force, lbm_dtype dtype, lbm_layout layout);
 

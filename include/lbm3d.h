@@ -63,15 +63,20 @@ typedef struct {
 
 /* Create a D3Q19 lattice (Eq. 5: omega = 1 / tau), at rest (rho = 1, u = 0),
  * on the current HIP device and its default stream.
- *  nx, ny, nz  mesh size, >= 1 each; 19 * nz * ny * (nx rounded up to 64) must
- *              stay below 2^32 (about 226 M nodes, e.g. 576^3).
+ *  nx, ny, nz  mesh size, >= 1 each; with pitch = nx rounded up to 64,
+ *              nz * ny * pitch must stay below 2^31 nodes and 19 * pitch below
+ *              2^28.  Population offsets are 64-bit, so the bound is the
+ *              device's memory: an A-B pair takes 38 * pop_bytes per node, and
+ *              creation, initialisation and population transfers stage 152 B
+ *              per node of FP64 for their duration (FP32 in 288 GB: about
+ *              0.9 G nodes, ~970^3).
  *  node_type   host uint8 [nz][ny][nx], 0 fluid / 1 solid; copied.
  *  tau         relaxation time > 1/2 (nu = (tau - 1/2) / 3).
  *  force       host double[3] body-force acceleration (g_x, g_y, g_z); NULL = 0.
  *              Force density F = rho g through Guo's forcing term.
  *  dtype       storage type (see above).
- * Errors: INVALID (sizes, tau, force, mask values, dtype), UNSUPPORTED (too
- * large for 32-bit offsets), NOMEM, DEVICE. */
+ * Errors: INVALID (sizes, tau, force, mask values, dtype), UNSUPPORTED (size
+ * limit), NOMEM, DEVICE. */
 int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint8_t *node_type,
                  double tau, const double *force, lbm_dtype dtype);
 

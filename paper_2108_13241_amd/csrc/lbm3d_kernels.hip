@@ -189,9 +189,11 @@ __device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz, R
 // column offsets of columns x - 1, x, x + 1: node (x, y, z), direction i has
 // element i * 64 + row[dz + 1][dy + 1] + col[dx + 1].  In a step the rows are
 // wave-uniform (one row segment per workgroup), so an element is addressed as a
-// uniform pointer plus a 32-bit lane offset; column offsets stay below 2^28.
+// uniform pointer (64-bit row offsets: a lattice may exceed 2^32 elements) plus
+// a 32-bit lane offset; column offsets stay below 2^28 (the runtime bounds
+// 19 * pitch).
 struct Addr {
-    uint32_t row[3][3];
+    uint64_t row[3][3];
     uint32_t col[3];
 };
 
@@ -204,7 +206,7 @@ __device__ __forceinline__ uint32_t col_off(int x)
 template <class M>
 __device__ __forceinline__ M &elem(M *s, const Addr &a, int i, int dz, int dy, int dx)
 {
-    M *p = s + ((uint32_t)i * kChunk + a.row[dz][dy]);
+    M *p = s + ((uint64_t)i * kChunk + a.row[dz][dy]);
     return p[a.col[dx]];
 }
 
@@ -217,8 +219,8 @@ __device__ __forceinline__ Addr addr_of(int x, int y, int z, int nx, int ny, int
     for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
-            a.row[dz][dy] = ((uint32_t)zs[dz] * (uint32_t)ny + (uint32_t)ys[dy]) * cpr *
-                            (uint32_t)(Q * kChunk);
+            a.row[dz][dy] = ((uint64_t)zs[dz] * (uint32_t)ny + (uint32_t)ys[dy]) * cpr *
+                            (uint64_t)(Q * kChunk);
     a.col[0] = col_off(wrap_dec(x, nx));
     a.col[1] = col_off(x);
     a.col[2] = col_off(wrap_inc(x, nx));
@@ -351,14 +353,14 @@ __global__ __launch_bounds__(kBlock) void k_gather3(State3 s, const typename ST:
     uint32_t wl;
     if (!canonical_at<ST>(s, st, bb, gid, x, y, z, f, wl, wv))
         return;
-    const uint32_t plane = (uint32_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+    const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        fc[(uint32_t)i * plane + gid] = f[i];
+        fc[(uint64_t)i * plane + gid] = f[i];
     // wall slots (full-way rule): each has exactly one fluid source node
     for (int j = 1; j < Q; ++j)
         if ((wl >> j) & 1u)
-            fc[(uint32_t)j * plane + node_plus(s, x, y, z, j)] = wv[j];
+            fc[(uint64_t)j * plane + node_plus(s, x, y, z, j)] = wv[j];
 }
 
 // Macroscopic fields (Eq. 2 with the half-force velocity) into [nz][ny][nx]
@@ -449,10 +451,10 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium3(State3 s, const double 
     const double d = rho ? rho[o] : 1.0, u = ux ? ux[o] : 0.0, v = uy ? uy[o] : 0.0,
                  w = uz ? uz[o] : 0.0;
     const double usq = u * u + v * v + w * w;
-    const uint32_t plane = (uint32_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+    const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
     for (int i = 0; i < Q; ++i) {
         const double cu = kCx[i] * u + kCy[i] * v + kCz[i] * w;
-        fc[(uint32_t)i * plane + gid] = kW[i] * d * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        fc[(uint64_t)i * plane + gid] = kW[i] * d * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
     }
 }
 
@@ -477,21 +479,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
         return;
     const int y = (int)(r % (uint32_t)s.ny), z = (int)(r / (uint32_t)s.ny);
     const uint32_t sm = solid_bits3(t, s.nmask, gid);
-    const uint32_t plane = (uint32_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+    const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
     const Addr a = addr_of(x, y, z, s.nx, s.ny, s.nz, (uint32_t)s.pitch / kChunk);
     for (int j = 0; j < Q; ++j) {
         double v;
         // q + c_j is node q - c_opp(j): solid iff bit opp(j) is set
         if (((sm >> kOpp[j]) & 1u) == 0 || walls == 1)
-            v = fc[(uint32_t)j * plane + node_plus(s, x, y, z, j)];
+            v = fc[(uint64_t)j * plane + node_plus(s, x, y, z, j)];
         else
-            v = fc[(uint32_t)(walls == 2 ? j : kOpp[j]) * plane + gid];
+            v = fc[(uint64_t)(walls == 2 ? j : kOpp[j]) * plane + gid];
         elem(st, a, j, 1, 1, 1) = ST::from_canon(v, j);
     }
     if (walls != 0)
         for (int i = 1; i < Q; ++i)
             if ((sm >> i) & 1u)
-                elem(other, a, kOpp[i], 1, 1, 1) = ST::from_canon(fc[(uint32_t)i * plane + gid],
+                elem(other, a, kOpp[i], 1, 1, 1) = ST::from_canon(fc[(uint64_t)i * plane + gid],
                                                                   kOpp[i]);
 }
 

@@ -189,8 +189,12 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
     if ((int)dtype < 0 || (int)dtype > 3)
         return fail_tl(LBM_ERR_INVALID, "unknown dtype");
     const int64_t pitch = ((int64_t)nx + 63) / 64 * 64;
-    if ((int64_t)Q * nz * ny * pitch >= (int64_t(1) << 32))
-        return fail_tl(LBM_ERR_UNSUPPORTED, "mesh too large for 32-bit lattice offsets");
+    // population offsets are 64-bit; node indices and lane column offsets are
+    // 32-bit
+    if ((int64_t)nz * ny * pitch >= (int64_t(1) << 31) || Q * pitch >= (int64_t(1) << 28))
+        return fail_tl(LBM_ERR_UNSUPPORTED,
+                       "mesh too large: nz * ny * pitch must stay below 2^31 nodes (pitch = nx "
+                       "rounded up to 64) and 19 * pitch below 2^28");
     const size_t nn = (size_t)nx * ny * nz;
     for (size_t k = 0; k < nn; ++k)
         if (node_type[k] > 1)

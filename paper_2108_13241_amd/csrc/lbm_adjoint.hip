@@ -259,13 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(
         R lam[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (x == x_col && type[gid] != kSolid) {
             const unsigned sm = solid_bits(type[gid], nmask, gid);
-            uint32_t nb[9];
+            uint64_t nb[9];
             dense_bases(x, y, nx, ny, (uint32_t)pitch / kChunk, nb);
             double f[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)kOpp[i] * kChunk + nb[0]
-                                                    : (uint32_t)i * kChunk + nb[i];
+                const uint64_t o = ((sm >> i) & 1u) ? (uint64_t)kOpp[i] * kChunk + nb[0]
+                                                    : (uint64_t)i * kChunk + nb[i];
                 f[i] = ST::canon(ST::ld(state[o], i), i);
             }
             const double al = alpha ? (double)alpha[gid] : 0.0;
@@ -281,10 +281,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(
                 grad_alpha[(size_t)y * nx + x] += scale * (-0.5 * ux * invD);
             gxs = scale * 0.5 * invD;
         }
-        const uint32_t base = dense_base(x, y, (uint32_t)pitch / kChunk);
+        const uint64_t base = dense_base(x, y, (uint32_t)pitch / kChunk);
 #pragma unroll
         for (int j = 0; j < 9; ++j)
-            mu[(uint32_t)j * kChunk + base] = lam[j];
+            mu[(uint64_t)j * kChunk + base] = lam[j];
     }
     double gys = 0.0;
     block_sum2(gxs, gys);
@@ -350,14 +350,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_convert(R *__restrict__ mu,
     const int y = (int)(gid / (uint32_t)pitch), x = (int)(gid - (uint32_t)y * pitch);
     if (y >= ny)
         return;
-    const uint32_t base = dense_base(x, y, (uint32_t)pitch / kChunk);
+    const uint64_t base = dense_base(x, y, (uint32_t)pitch / kChunk);
     const bool fluid = x < nx && type[gid] != kSolid;
     for (int i = 0; i < 9; ++i) {
         if (to_plain) {
             if (x < nx)
-                plain[((size_t)i * ny + y) * nx + x] = fluid ? (double)mu[(uint32_t)i * kChunk + base] : 0.0;
+                plain[((size_t)i * ny + y) * nx + x] = fluid ? (double)mu[(uint64_t)i * kChunk + base] : 0.0;
         } else {
-            mu[(uint32_t)i * kChunk + base] =
+            mu[(uint64_t)i * kChunk + base] =
                 fluid ? (R)plain[((size_t)i * ny + y) * nx + x] : R(0);
         }
     }

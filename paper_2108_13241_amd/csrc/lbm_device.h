@@ -369,9 +369,9 @@ __device__ __forceinline__ int wrap_inc(int a, int n) { return a == n - 1 ? 0 : 
 constexpr uint32_t kChunk = 64;
 constexpr uint32_t kTileStride = 256;
 
-__device__ __forceinline__ uint32_t dense_base(int x, int y, uint32_t cpr)
+__device__ __forceinline__ uint64_t dense_base(int x, int y, uint32_t cpr)
 {
-    return ((uint32_t)y * cpr + ((uint32_t)x >> 6)) * (9u * kChunk) + ((uint32_t)x & 63u);
+    return ((uint64_t)y * cpr + ((uint32_t)x >> 6)) * (9u * kChunk) + ((uint32_t)x & 63u);
 }
 __device__ __forceinline__ uint32_t list_base(uint32_t n)
 {
@@ -389,9 +389,10 @@ __device__ __forceinline__ uint32_t tile_slot(uint32_t lx, uint32_t ly)
 }
 
 // nb[i] = base offset of node x - c_i (periodic) in the dense layout;
-// nb[0] = the node itself.
+// nb[0] = the node itself.  Dense offsets are 64-bit (a lattice may exceed 2^32
+// elements); tile and node-list offsets stay 32-bit.
 __device__ __forceinline__ void dense_bases(int x, int y, int nx, int ny, uint32_t cpr,
-                                            uint32_t (&nb)[9])
+                                            uint64_t (&nb)[9])
 {
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
@@ -410,11 +411,12 @@ __device__ __forceinline__ void dense_bases(int x, int y, int nx, int ny, uint32
 // next step, so the stores bypass the caches' retention (nontemporal).
 // Dense addressing split into row and column parts: node (x, y) has base
 // offset row_off(y) + col_off(x).  A step workgroup is one row segment, so the
-// three row offsets (rows y-1, y, y+1) are uniform (scalar registers) and each
-// lane keeps three column offsets (columns x-1, x, x+1), which stay below 2^28
-// so that loads use a scalar base plus a 32-bit lane offset.
+// three row offsets (rows y-1, y, y+1) are uniform (64-bit, scalar registers)
+// and each lane keeps three column offsets (columns x-1, x, x+1), which stay
+// below 2^28 (the runtime bounds 9 * pitch), so that a load address is a
+// scalar base plus a 32-bit lane offset.
 struct DenseRC {
-    uint32_t r[3];  // rows y-1, y, y+1
+    uint64_t r[3];  // rows y-1, y, y+1
     uint32_t c[3];  // columns x-1, x, x+1
 };
 
@@ -426,10 +428,10 @@ __device__ __forceinline__ uint32_t col_off(int x)
 __device__ __forceinline__ DenseRC dense_rc(int x, int y, int nx, int ny, uint32_t cpr)
 {
     DenseRC a;
-    const uint32_t row = cpr * (9u * kChunk);
-    a.r[0] = (uint32_t)wrap_dec(y, ny) * row;
-    a.r[1] = (uint32_t)y * row;
-    a.r[2] = (uint32_t)wrap_inc(y, ny) * row;
+    const uint64_t row = (uint64_t)cpr * (9u * kChunk);
+    a.r[0] = (uint64_t)wrap_dec(y, ny) * row;
+    a.r[1] = (uint64_t)y * row;
+    a.r[2] = (uint64_t)wrap_inc(y, ny) * row;
     a.c[0] = col_off(wrap_dec(x, nx));
     a.c[1] = col_off(x);
     a.c[2] = col_off(wrap_inc(x, nx));
@@ -441,7 +443,7 @@ __device__ __forceinline__ DenseRC dense_rc(int x, int y, int nx, int ny, uint32
 template <class M>
 __device__ __forceinline__ M &dense_at(M *__restrict__ s, const DenseRC &a, int i, int ri, int ci)
 {
-    M *p = s + ((uint32_t)i * kChunk + a.r[ri]);
+    M *p = s + ((uint64_t)i * kChunk + a.r[ri]);
     return p[a.c[ci]];
 }
 

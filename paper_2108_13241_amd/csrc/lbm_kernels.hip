@@ -136,48 +136,45 @@ __device__ __forceinline__ R lane_shift(R v, R edge)
 // rule; for the full-way rule bb is the other lattice of an A-B pair, which
 // still holds the node's post-collision values of two steps back (a population
 // sent into a wall node returns two steps later).  ds = direction stride of
-// the layout, nb = node base offsets.
-template <class ST>
+// the layout, nb = node base offsets (O: 32-bit for tiles and node lists,
+// 64-bit for dense lattices).
+template <class ST, class O>
 __device__ __forceinline__ void pull_gather(const typename ST::mem *__restrict__ s,
-                                            const typename ST::mem *bb, uint32_t ds,
-                                            const uint32_t (&nb)[9], unsigned sm,
-                                            typename ST::real (&f)[9])
+                                            const typename ST::mem *bb, O ds, const O (&nb)[9],
+                                            unsigned sm, typename ST::real (&f)[9])
 {
     if (sm == 0) {  // interior node: no bounce-back
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            f[i] = ST::ld(s[(uint32_t)i * ds + nb[i]], i);
+            f[i] = ST::ld(s[(O)i * ds + nb[i]], i);
         return;
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        f[i] = ST::ld(((sm >> i) & 1u) ? bb[(uint32_t)kOpp[i] * ds + nb[0]]
-                                       : s[(uint32_t)i * ds + nb[i]],
-                      i);
+        f[i] = ST::ld(((sm >> i) & 1u) ? bb[(O)kOpp[i] * ds + nb[0]] : s[(O)i * ds + nb[i]], i);
 }
 
 // AA pattern, odd step read (and the canonical view after an odd number of
 // steps): f_i(x) = A_opp(i)(x - c_i), or A_i(x) when x - c_i is solid.
-template <class ST>
-__device__ __forceinline__ void aa_odd_gather(const typename ST::mem *__restrict__ s, uint32_t ds,
-                                              const uint32_t (&nb)[9], unsigned sm,
+template <class ST, class O>
+__device__ __forceinline__ void aa_odd_gather(const typename ST::mem *__restrict__ s, O ds,
+                                              const O (&nb)[9], unsigned sm,
                                               typename ST::real (&f)[9])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const uint32_t o = ((sm >> i) & 1u) ? (uint32_t)i * ds + nb[0]
-                                            : (uint32_t)kOpp[i] * ds + nb[i];
+        const O o = ((sm >> i) & 1u) ? (O)i * ds + nb[0] : (O)kOpp[i] * ds + nb[i];
         f[i] = ST::ld(s[o], i);
     }
 }
 
-template <class ST>
-__device__ __forceinline__ void local_gather(const typename ST::mem *__restrict__ s, uint32_t ds,
-                                             uint32_t own, typename ST::real (&f)[9])
+template <class ST, class O>
+__device__ __forceinline__ void local_gather(const typename ST::mem *__restrict__ s, O ds, O own,
+                                             typename ST::real (&f)[9])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        f[i] = ST::ld(s[(uint32_t)i * ds + own], i);
+        f[i] = ST::ld(s[(O)i * ds + own], i);
 }
 
 // Node of a dense step thread: 256-lane row segments, XCD-remapped; L is the
@@ -247,7 +244,7 @@ __device__ __forceinline__ void aligned_load(const typename ST::mem *__restrict_
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         if (kCx[i] != 0)
-            r.e[i] = sp[(uint32_t)i * kChunk + a.r[1 - kCy[i]] + (kCx[i] > 0 ? cl : cr)];
+            r.e[i] = sp[(uint64_t)i * kChunk + a.r[1 - kCy[i]] + (kCx[i] > 0 ? cl : cr)];
 }
 
 template <class ST>
@@ -544,10 +541,11 @@ enum Mode : int { kPull = 0, kAAEven = 1, kAAOdd = 2 };
 // gid = y * pitch + x; tiled: gid = tile * 256 + t; indirect: gid = n).
 // Returns false for padding and solid nodes; else the coordinates, the
 // solid-neighbour bits, the open-boundary code, the direction stride and the
-// node base offsets.
+// node base offsets (64-bit for every layout here: these kernels are not the
+// step).
 __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x, int &y,
-                                        unsigned &sm, unsigned &open, uint32_t &ds,
-                                        uint32_t (&nb)[9])
+                                        unsigned &sm, unsigned &open, uint64_t &ds,
+                                        uint64_t (&nb)[9])
 {
     if (s.layout == kDenseAB || s.layout == kDenseAA) {
         y = (int)(gid / (uint32_t)s.pitch);
@@ -574,14 +572,20 @@ __device__ __forceinline__ bool node_at(const DevState &s, uint32_t gid, int &x,
         int32_t tn[9];
         for (int d = 0; d < 9; ++d)
             tn[d] = s.tile_nbr[k * 9 + d];
-        tiled_offsets(k, t & 15, t >> 4, tn, nb);
+        uint32_t nb32[9];
+        tiled_offsets(k, t & 15, t >> 4, tn, nb32);
+        for (int d = 0; d < 9; ++d)
+            nb[d] = nb32[d];
         x = s.tile_xy[2 * k] * kTile + (t & 15);
         y = s.tile_xy[2 * k + 1] * kTile + (t >> 4);
         ds = kTileStride;
     } else {
         if (gid >= (uint32_t)s.n_fluid)
             return false;
-        sm = indirect_offsets(s.ind_pk, s.ind_info, s.ind_edge, gid, nb, open);
+        uint32_t nb32[9];
+        sm = indirect_offsets(s.ind_pk, s.ind_info, s.ind_edge, gid, nb32, open);
+        for (int d = 0; d < 9; ++d)
+            nb[d] = nb32[d];
         x = s.fluid_xy[2 * gid];
         y = s.fluid_xy[2 * gid + 1];
         ds = kChunk;
@@ -602,7 +606,7 @@ __device__ __forceinline__ bool canonical_at(const DevState &s, const typename S
 {
     using R = typename ST::real;
     unsigned sm = 0, open = 0;
-    uint32_t ds = 0, nb[9];
+    uint64_t ds = 0, nb[9];
     wl = 0;
     if (!node_at(s, gid, x, y, sm, open, ds, nb))
         return false;
@@ -617,7 +621,7 @@ __device__ __forceinline__ bool canonical_at(const DevState &s, const typename S
         for (int j = 1; j < 9; ++j)
             if ((sm >> kOpp[j]) & 1u) {  // x + c_j is x - c_opp(j)
                 wl |= 1u << j;
-                wv[j] = ST::canon(ST::ld(st[(uint32_t)j * ds + nb[0]], j), j);
+                wv[j] = ST::canon(ST::ld(st[(uint64_t)j * ds + nb[0]], j), j);
             }
     }
     // the canonical state satisfies the open-boundary conditions
@@ -649,21 +653,21 @@ __device__ __forceinline__ double block_sum(double v)
 
 struct OpCanonical {
     double *fc;
-    uint32_t plane_c;
+    uint64_t plane_c;
     int pitch, nx, ny;
     static constexpr bool kReduce = false;
     __device__ double operator()(int x, int y, const double (&f)[9], double, unsigned wl,
                                  const double (&wv)[9]) const
     {
-        const uint32_t o = (uint32_t)y * pitch + x;
+        const uint64_t o = (uint64_t)y * pitch + x;
         for (int i = 0; i < 9; ++i)
-            fc[(uint32_t)i * plane_c + o] = f[i];
+            fc[(uint64_t)i * plane_c + o] = f[i];
         // wall slots (full-way rule): each has exactly one fluid source node
         for (int j = 1; j < 9; ++j)
             if ((wl >> j) & 1u) {
                 const int xw = x + kCx[j] < 0 ? nx - 1 : (x + kCx[j] >= nx ? 0 : x + kCx[j]);
                 const int yw = y + kCy[j] < 0 ? ny - 1 : (y + kCy[j] >= ny ? 0 : y + kCy[j]);
-                fc[(uint32_t)j * plane_c + (uint32_t)yw * pitch + xw] = wv[j];
+                fc[(uint64_t)j * plane_c + (uint64_t)yw * pitch + xw] = wv[j];
             }
         return 0.0;
     }
@@ -785,10 +789,10 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(int nx, int ny, int pitc
     const size_t n = (size_t)y * nx + x;
     const double r = rho ? rho[n] : 1.0, u = ux ? ux[n] : 0.0, v = uy ? uy[n] : 0.0;
     const double usq = 1.5 * (u * u + v * v);
-    const uint32_t plane = (uint32_t)ny * pitch;
+    const uint64_t plane = (uint64_t)ny * pitch;
     for (int i = 0; i < 9; ++i) {
         const double cu = kCx[i] * u + kCy[i] * v;
-        fc[(uint32_t)i * plane + gid] = kW[i] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
+        fc[(uint64_t)i * plane + gid] = kW[i] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
     }
 }
 
@@ -808,15 +812,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     int x, y;
     unsigned sm = 0, open = 0;
-    uint32_t ds = 0, nbs[9];
+    uint64_t ds = 0, nbs[9];
     if (!node_at(s, gid, x, y, sm, open, ds, nbs))
         return;
-    uint32_t nb[9];  // canonical (plain planes, dense pitch) offsets of z - c_i
+    uint64_t nb[9];  // canonical (plain planes, dense pitch) offsets of z - c_i
     {
         const int xm = wrap_dec(x, s.nx), xp = wrap_inc(x, s.nx);
         const int ym = wrap_dec(y, s.ny), yp = wrap_inc(y, s.ny);
-        const uint32_t p = (uint32_t)s.pitch;
-        const uint32_t r0 = (uint32_t)y * p, rm = (uint32_t)ym * p, rp = (uint32_t)yp * p;
+        const uint64_t p = (uint64_t)s.pitch;
+        const uint64_t r0 = (uint64_t)y * p, rm = (uint64_t)ym * p, rp = (uint64_t)yp * p;
         nb[0] = r0 + x;
         nb[1] = r0 + xm;
         nb[2] = rm + x;
@@ -827,26 +831,26 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem
         nb[7] = rp + xp;
         nb[8] = rp + xm;
     }
-    const uint32_t pc = (uint32_t)s.ny * s.pitch;
+    const uint64_t pc = (uint64_t)s.ny * s.pitch;
     for (int j = 0; j < 9; ++j) {
         double v;
         if (mode == kAAEven) {
-            v = fc[(uint32_t)j * pc + nb[0]];
+            v = fc[(uint64_t)j * pc + nb[0]];
         } else if (mode == kAAOdd) {
-            v = ((sm >> j) & 1u) ? fc[(uint32_t)j * pc + nb[0]]
-                                 : fc[(uint32_t)kOpp[j] * pc + nb[j]];
+            v = ((sm >> j) & 1u) ? fc[(uint64_t)j * pc + nb[0]]
+                                 : fc[(uint64_t)kOpp[j] * pc + nb[j]];
         } else if (((sm >> kOpp[j]) & 1u) == 0 || walls == 1) {
-            v = fc[(uint32_t)j * pc + nb[kOpp[j]]];  // z + c_j is node z - c_opp(j)
+            v = fc[(uint64_t)j * pc + nb[kOpp[j]]];  // z + c_j is node z - c_opp(j)
         } else {
-            v = fc[(uint32_t)(walls == 2 ? j : kOpp[j]) * pc + nb[0]];
+            v = fc[(uint64_t)(walls == 2 ? j : kOpp[j]) * pc + nb[0]];
         }
-        st[(uint32_t)j * ds + nbs[0]] = ST::from_canon(v, j);
+        st[(uint64_t)j * ds + nbs[0]] = ST::from_canon(v, j);
     }
     if (walls != 0 && mode == kPull)
         for (int i = 1; i < 9; ++i)
             if ((sm >> i) & 1u)
-                other[(uint32_t)kOpp[i] * ds + nbs[0]] =
-                    ST::from_canon(fc[(uint32_t)i * pc + nb[0]], kOpp[i]);
+                other[(uint64_t)kOpp[i] * ds + nbs[0]] =
+                    ST::from_canon(fc[(uint64_t)i * pc + nb[0]], kOpp[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(double *p, size_t n, double v)
@@ -1070,7 +1074,7 @@ hipError_t launch_equilibrium(const DevState &s, const double *rho, const double
 
 hipError_t launch_gather_canonical(const DevState &s, int64_t t, int cur, double *fc)
 {
-    OpCanonical op{fc, (uint32_t)s.ny * (uint32_t)s.pitch, s.pitch, s.nx, s.ny};
+    OpCanonical op{fc, (uint64_t)s.ny * (uint64_t)s.pitch, s.pitch, s.nx, s.ny};
     return visit(s, t, cur, op, nullptr);
 }
 

@@ -271,6 +271,20 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
     const bool all_tiles = layout == LBM_TILED16_ALL;
     if (all_tiles)
         layout = LBM_TILED16;
+    const int64_t pitch = round_up(nx, 64);
+    if (layout == LBM_DENSE_AB || layout == LBM_DENSE_AA) {
+        // dense population offsets are 64-bit; node indices and lane column
+        // offsets are 32-bit
+        if ((int64_t)ny * pitch >= (int64_t(1) << 31) || 9 * pitch >= (int64_t(1) << 28))
+            return fail_tl(LBM_ERR_UNSUPPORTED,
+                           "mesh too large: the dense layouts take ny * pitch < 2^31 nodes "
+                           "(pitch = nx rounded up to 64) and 9 * pitch < 2^28");
+    } else if ((int64_t)9 * ny * pitch >= (int64_t(1) << 32)) {
+        return fail_tl(LBM_ERR_UNSUPPORTED,
+                       "mesh too large: TILED16 and INDIRECT take 9 * ny * pitch < 2^32 "
+                       "(32-bit offsets)");
+    }
+
     const size_t nn = (size_t)nx * ny;
     for (size_t k = 0; k < nn; ++k)
         if (node_type[k] > 1)
@@ -278,10 +292,6 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
     if (layout == LBM_TILED16 && (nx % 16 != 0 || ny % 16 != 0))
         return fail_tl(LBM_ERR_UNSUPPORTED,
                        "TILED16 / TILED16_ALL need nx and ny to be multiples of 16");
-    const int64_t pitch = round_up(nx, 64);
-    if ((int64_t)9 * ny * pitch >= (int64_t(1) << 32))
-        return fail_tl(LBM_ERR_UNSUPPORTED, "mesh too large for 32-bit lattice offsets");
-
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c)
         return fail_tl(LBM_ERR_NOMEM, "cannot allocate the context");
@@ -365,7 +375,8 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
             return fail_create(rc, "cannot upload the edge-node table");
         s.ind_edge = (const int32_t *)p;
     }
-    if ((uint64_t)9 * s.plane >= (uint64_t(1) << 32))
+    if (layout != LBM_DENSE_AB && layout != LBM_DENSE_AA &&
+        (uint64_t)9 * s.plane >= (uint64_t(1) << 32))
         return fail_create(LBM_ERR_UNSUPPORTED, "lattice too large for 32-bit offsets");
     if (!type.empty()) {
         if ((rc = upload(type.data(), type.size(), &p)))

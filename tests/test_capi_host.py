@@ -66,6 +66,22 @@ def test_create_validation(lib, kw, status):
     assert lib.lbm_last_error(None)
 
 
+@pytest.mark.parametrize("nx,ny,layout", [
+    (65536, 32768, 0),        # dense: ny * pitch = 2^31 nodes
+    (65536, 32768, 1),
+    (29826162, 1, 0),         # dense: 9 * pitch >= 2^28 (lane column offsets)
+    (32768, 16384, 3),        # indirect: 9 * ny * pitch >= 2^32
+    (32768, 16384, 2),        # tiled
+])
+def test_create_size_limits(lib, nx, ny, layout):
+    """Meshes beyond a layout's offset range are refused before the mask is read (the
+    one-byte mask passed here would otherwise be overrun)."""
+    st, ctx = _create(lib, nx, ny, np.zeros(1, np.uint8), layout=layout)
+    assert st == -4
+    assert not ctx.value
+    assert b"too large" in lib.lbm_last_error(None)
+
+
 def test_create_rejects_bad_mask(lib):
     m = np.zeros((8, 8), np.uint8)
     m[3, 3] = 2
@@ -93,8 +109,9 @@ def _create3(lib, nx, ny, nz, m, tau=0.8, force=None, dtype=0):
 @pytest.mark.parametrize("args,status", [
     (dict(nx=0), -1), (dict(nz=0), -1), (dict(tau=0.5), -1), (dict(tau=float("nan")), -1),
     (dict(force=(0.0, float("inf"), 0.0)), -1), (dict(dtype=4), -1), (dict(dtype=-1), -1),
-    # 19 * nz * ny * pitch >= 2^32 is refused before any allocation
-    (dict(nx=1024, ny=1024, nz=256), -4),
+    # nz * ny * pitch >= 2^31 nodes, or 19 * pitch >= 2^28, is refused before the
+    # mask is read or anything is allocated
+    (dict(nx=1024, ny=2048, nz=1024), -4), (dict(nx=14128700, ny=1, nz=1), -4),
 ])
 def test_create3d_validation(lib, args, status):
     kw = dict(nx=12, ny=10, nz=6)
