@@ -131,7 +131,9 @@ int lbm_set_allocator(lbm_alloc_fn alloc, lbm_free_fn free_fn, void *user);
  * the current HIP device, using the default stream until lbm_set_stream.
  * Size limits (pitch = nx rounded up to 64): DENSE_AB / DENSE_AA take
  * ny * pitch < 2^31 nodes and 9 * pitch < 2^28, i.e. lattices up to the
- * device's memory (FP64 A-B: 144 B per node, about 2 G nodes in 288 GB);
+ * device's memory (FP64 A-B: 144 B per node, about 2 G nodes in 288 GB; the
+ * rest state is written in place, while initialisation from fields and
+ * population transfers stage 72 B per node of FP64 for their duration);
  * TILED16 / TILED16_ALL / INDIRECT use 32-bit offsets and take
  * 9 * ny * pitch < 2^32 (about 477 M mesh nodes).
  * Errors: INVALID (sizes, tau, non-finite force, mask value), UNSUPPORTED
@@ -145,7 +147,8 @@ int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
 
 /* Algorithm 1 initialisation: f_i = f^eq_i(rho0, u0) (Eq. 6) at every fluid
  * node, as the canonical state at time 0.  Host FP64 [ny][nx] fields; NULL
- * means rho0 = 1 / u0 = 0.  Resets the step counter to 0. */
+ * means rho0 = 1 / u0 = 0 (all three NULL: the rest state f_i = w_i, written
+ * in place without a staging buffer).  Resets the step counter to 0. */
 int lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy);
 
 /* Per-node Brinkman drag coefficient alpha (host FP32 [ny][nx], each in [0, 1];

@@ -66,10 +66,10 @@ typedef struct {
  *  nx, ny, nz  mesh size, >= 1 each; with pitch = nx rounded up to 64,
  *              nz * ny * pitch must stay below 2^31 nodes and 19 * pitch below
  *              2^28.  Population offsets are 64-bit, so the bound is the
- *              device's memory: an A-B pair takes 38 * pop_bytes per node, and
- *              creation, initialisation and population transfers stage 152 B
- *              per node of FP64 for their duration (FP32 in 288 GB: about
- *              0.9 G nodes, ~970^3).
+ *              device's memory: an A-B pair takes 38 * pop_bytes per node
+ *              (FP32: about 1.8 G nodes in 288 GB).  Creation writes the rest
+ *              state in place; initialisation from fields and population
+ *              transfers stage 152 B per node of FP64 for their duration.
  *  node_type   host uint8 [nz][ny][nx], 0 fluid / 1 solid; copied.
  *  tau         relaxation time > 1/2 (nu = (tau - 1/2) / 3).
  *  force       host double[3] body-force acceleration (g_x, g_y, g_z); NULL = 0.
@@ -85,7 +85,9 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
 int lbm3d_set_stream(lbm3d_ctx *ctx, void *hip_stream);
 
 /* Reset to the equilibrium (Eq. 6) of host FP64 [nz][ny][nx] fields; any field
- * may be NULL (rho = 1, u = 0).  rho > 0 and finite values at fluid nodes. */
+ * may be NULL (rho = 1, u = 0; all four NULL: the rest state f_i = w_i, written
+ * in place without a staging buffer).  rho > 0 and finite values at fluid
+ * nodes. */
 int lbm3d_init_equilibrium(lbm3d_ctx *ctx, const double *rho, const double *ux,
                            const double *uy, const double *uz);
 

@@ -497,6 +497,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
                                                                   kOpp[i]);
 }
 
+// Rest state (rho = 1, u = 0) written straight into a stored lattice: every
+// slot of direction i holds w_i in storage form.  At rest the canonical ->
+// stored map (k_scatter3) sends each slot an equilibrium of its own direction
+// or of the opposite one, and w_opp(i) = w_i, so this is what the scatter of a
+// rest state stores (it also fills solid and padding slots, which nothing reads).
+template <class ST>
+__global__ __launch_bounds__(kBlock) void k_rest3(typename ST::mem *p, uint64_t n)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * kBlock) {
+        const int i = (int)((e / kChunk) % (uint64_t)Q);
+        p[e] = ST::from_canon(kW[i], i);
+    }
+}
+
 template <class ST, bool TRT>
 void step_launch3(const State3 &s, int cur)
 {
@@ -573,6 +588,18 @@ hipError_t launch_scatter3(const State3 &s, int cur, const double *fc, int fill_
         using M = typename decltype(st)::mem;
         k_scatter3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, (M *)s.f[cur], (M *)s.f[1 - cur],
                                                               walls, fc);
+    });
+}
+
+hipError_t launch_rest3(const State3 &s, void *lattice)
+{
+    const uint64_t n = (uint64_t)Q * s.nz * s.ny * s.pitch;
+    uint64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 65536)
+        blocks = 65536;
+    return by_dtype(s.dtype, [&](auto st) {
+        using M = typename decltype(st)::mem;
+        k_rest3<decltype(st)><<<(uint32_t)blocks, kBlock, 0, s.stream>>>((M *)lattice, n);
     });
 }
 

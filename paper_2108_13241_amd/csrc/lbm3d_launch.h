@@ -41,6 +41,9 @@ hipError_t launch_step3(const State3 &s, int cur);
 // canonical buffer fc (FP64 [19][nz][ny][pitch]).
 hipError_t launch_equilibrium3(const State3 &s, const double *rho, const double *ux,
                                const double *uy, const double *uz, double *fc);
+// Rest state (rho = 1, u = 0) straight into one stored lattice, without a
+// canonical staging buffer.
+hipError_t launch_rest3(const State3 &s, void *lattice);
 // Canonical fc -> stored lattice cur (full-way rule: also the other lattice's
 // bounce-back slots; with fill_walls the wall slots come from the fluid nodes
 // that feed them instead of from fc).

@@ -134,6 +134,16 @@ size_t field_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s
 int init_state(lbm3d_ctx *c, const double *rho, const double *ux, const double *uy,
                const double *uz)
 {
+    if (!rho && !ux && !uy && !uz) {
+        // rest state: written in place, no staging; both lattices (the full-way
+        // rule keeps bounce-back slots in the other one)
+        c->t = 0;
+        c->cur = 0;
+        LBM3_HIP(c, lbm3::launch_rest3(c->s, c->s.f[0]));
+        LBM3_HIP(c, lbm3::launch_rest3(c->s, c->s.f[1]));
+        LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
+        return LBM_OK;
+    }
     const size_t field = field_nodes(c) * sizeof(double);
     Temp fc(c, canonical_bytes(c));
     if (!fc.p)

@@ -853,6 +853,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevState s, typename ST::mem
                     ST::from_canon(fc[(uint64_t)i * pc + nb[0]], kOpp[i]);
 }
 
+// Rest state (rho = 1, u = 0; the initialisation of Algorithm 1) written straight
+// into a stored lattice: every slot of direction i holds w_i in storage form.
+// At rest the canonical -> stored map (k_scatter) sends each slot an
+// equilibrium of its own direction or of the opposite one, and w_opp(i) = w_i,
+// so this is what the scatter of a rest state stores (it also fills slots that
+// nothing reads: solid nodes, padding).  run = nodes per population run of the
+// layout (64: dense rows and node lists; 256: tiles).
+template <class ST>
+__global__ __launch_bounds__(kBlock) void k_rest(typename ST::mem *p, uint64_t n, uint32_t run)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * kBlock) {
+        const int i = (int)((e / run) % 9u);
+        p[e] = ST::from_canon(kW[i], i);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double *p, size_t n, double v)
 {
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
@@ -1061,6 +1078,23 @@ hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const
     case kBF16S: return scatter_typed<BF16S>(s, t, cur, fc, fill_walls);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_rest(const DevState &s, void *lattice)
+{
+    const uint64_t n = (uint64_t)9 * s.plane;
+    const uint32_t run = s.layout == kTiled16 ? kTileStride : kChunk;
+    uint64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 65536)
+        blocks = 65536;
+    switch (s.dtype) {
+    case kF64: k_rest<F64><<<(uint32_t)blocks, kBlock, 0, s.stream>>>((F64::mem *)lattice, n, run); break;
+    case kF32: k_rest<F32><<<(uint32_t)blocks, kBlock, 0, s.stream>>>((F32::mem *)lattice, n, run); break;
+    case kF16S: k_rest<F16S><<<(uint32_t)blocks, kBlock, 0, s.stream>>>((F16S::mem *)lattice, n, run); break;
+    case kBF16S: k_rest<BF16S><<<(uint32_t)blocks, kBlock, 0, s.stream>>>((BF16S::mem *)lattice, n, run); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_equilibrium(const DevState &s, const double *rho, const double *ux,

@@ -61,6 +61,9 @@ hipError_t launch_step(const DevState &s, int64_t t, int cur);
 // (slot j of wall node w <- f_j(w - c_j)).
 hipError_t launch_scatter_canonical(const DevState &s, int64_t t, int cur, const double *fc,
                                     int fill_walls);
+// Rest state (rho = 1, u = 0) straight into one stored lattice (all 9 * plane
+// slots), without a canonical staging buffer.
+hipError_t launch_rest(const DevState &s, void *lattice);
 // Equilibrium (Eq. 6) from device FP64 [ny][nx] fields (null = rest) -> fc.
 hipError_t launch_equilibrium(const DevState &s, const double *rho, const double *ux,
                               const double *uy, double *fc);

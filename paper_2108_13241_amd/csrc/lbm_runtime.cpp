@@ -183,6 +183,18 @@ int scatter_from_device_canonical(lbm_ctx *c, const double *fc_dev, int fill_wal
 
 int init_state(lbm_ctx *c, const double *rho, const double *ux, const double *uy)
 {
+    if (!rho && !ux && !uy) {
+        // rest state: written in place, no staging (lattices may fill the device);
+        // both lattices of an A-B pair, which covers the full-way rule's
+        // bounce-back slots in the other lattice
+        c->t = 0;
+        c->cur = 0;
+        LBM_HIP(c, lbm::launch_rest(c->s, c->s.f[0]));
+        if (c->s.f[1])
+            LBM_HIP(c, lbm::launch_rest(c->s, c->s.f[1]));
+        LBM_HIP(c, hipStreamSynchronize(c->s.stream));
+        return LBM_OK;
+    }
     const size_t field = (size_t)c->s.nx * c->s.ny * sizeof(double);
     Temp fc(c, canonical_bytes(c));
     if (!fc.p)
