@@ -27,42 +27,47 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 
 # ------------------------------------------------------------ torch memory --
 _torch_blocks = {}
-_alloc_cb = None
-_free_cb = None
+# The ctypes callbacks are made once and kept for the life of the process: a
+# context keeps the allocator it was created with, so its free callback must
+# stay callable after the hook is switched off for newer contexts.
+_hooks = None
+_hook_active = False
 
 
 def _install_torch_allocator():
     """Route the library's device allocations through torch's caching allocator."""
-    global _alloc_cb, _free_cb
-    if _alloc_cb is not None:
+    global _hooks, _hook_active
+    if _hook_active:
         return
-    import torch
+    if _hooks is None:
+        import torch
 
-    from ._lib import ALLOC_FN, FREE_FN
+        from ._lib import ALLOC_FN, FREE_FN
 
-    def _alloc(nbytes, _user):
-        try:
-            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
-        except Exception:  # noqa: BLE001 - report NULL to the library (LBM_ERR_NOMEM)
-            return None
-        p = t.data_ptr()
-        _torch_blocks[p] = t
-        return p
+        def _alloc(nbytes, _user):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            except Exception:  # noqa: BLE001 - report NULL to the library (LBM_ERR_NOMEM)
+                return None
+            p = t.data_ptr()
+            _torch_blocks[p] = t
+            return p
 
-    def _free(ptr, _user):
-        _torch_blocks.pop(ptr, None)
+        def _free(ptr, _user):
+            _torch_blocks.pop(ptr, None)
 
-    _alloc_cb = ALLOC_FN(_alloc)
-    _free_cb = FREE_FN(_free)
-    check(load().lbm_set_allocator(ctypes.cast(_alloc_cb, ctypes.c_void_p),
-                                   ctypes.cast(_free_cb, ctypes.c_void_p), None))
+        _hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+    check(load().lbm_set_allocator(ctypes.cast(_hooks[0], ctypes.c_void_p),
+                                   ctypes.cast(_hooks[1], ctypes.c_void_p), None))
+    _hook_active = True
 
 
 def _uninstall_torch_allocator():
-    """Back to hipMalloc / hipFree for contexts created from now on."""
-    global _alloc_cb, _free_cb
+    """Back to hipMalloc / hipFree for contexts created from now on (contexts created with
+    torch memory keep it)."""
+    global _hook_active
     check(load().lbm_set_allocator(None, None, None))
-    _alloc_cb = _free_cb = None
+    _hook_active = False
 
 
 def _ptr(t):
@@ -72,6 +77,33 @@ def _ptr(t):
     if isinstance(t, int):
         return t
     return t.data_ptr()
+
+
+def _dev(t, nbytes, what, dtype=None, optional=False):
+    """Address of a caller-owned device buffer for the library to read or write: a CUDA torch
+    tensor, checked here (on a GPU, contiguous, at least `nbytes` long, of `dtype` if given),
+    so that a wrong buffer raises instead of being overrun; or a raw int address, taken as
+    is (the caller vouches for its size)."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{what}: a device buffer is required")
+    if isinstance(t, int):
+        return t
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what}: expected a CUDA tensor or a device address")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: the tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what}: expected {dtype}, got {t.dtype}")
+    if t.nbytes < nbytes:
+        raise ValueError(f"{what}: needs {nbytes} bytes, the tensor has {t.nbytes}")
+    return t.data_ptr()
+
+
+def _f64t():
+    import torch
+    return torch.float64
 
 
 def _f64(a, shape=None):
@@ -191,7 +223,11 @@ class Lattice:
         return tuple(out)
 
     def macroscopic_device(self, rho=None, ux=None, uy=None):
-        self._check(self._lib.lbm_macroscopic_device(self._ctx, _ptr(rho), _ptr(ux), _ptr(uy)))
+        """Fields into device FP64 [ny, nx] tensors (None: skipped); asynchronous."""
+        n, d = 8 * self.ny * self.nx, _f64t()
+        self._check(self._lib.lbm_macroscopic_device(
+            self._ctx, _dev(rho, n, "rho", d, True), _dev(ux, n, "ux", d, True),
+            _dev(uy, n, "uy", d, True)))
 
     def get_populations(self):
         f = np.zeros((9, self.ny, self.nx))
@@ -213,10 +249,10 @@ class Lattice:
         return b.value
 
     def save_state(self, dst):
-        self._check(self._lib.lbm_save_state(self._ctx, _ptr(dst)))
+        self._check(self._lib.lbm_save_state(self._ctx, _dev(dst, self.state_bytes(), "dst")))
 
     def load_state(self, src):
-        self._check(self._lib.lbm_load_state(self._ctx, _ptr(src)))
+        self._check(self._lib.lbm_load_state(self._ctx, _dev(src, self.state_bytes(), "src")))
 
     def objective_outlet_ux(self, x_col):
         J = ctypes.c_double()
@@ -235,32 +271,55 @@ class Lattice:
         self._check(self._lib.lbm_adjoint_bytes(self._ctx, ctypes.byref(b), ctypes.byref(p)))
         return b.value, p.value
 
+    def _mu(self, mu, what):
+        return _dev(mu, self._adjoint_nbytes(), what)
+
+    def _adjoint_nbytes(self):
+        if getattr(self, "_adj_nbytes", None) is None:
+            self._adj_nbytes = self.adjoint_bytes()[0]
+        return self._adj_nbytes
+
+    def _grads(self, grad_alpha, grad_g):
+        d = _f64t()
+        return (_dev(grad_alpha, 8 * self.ny * self.nx, "grad_alpha", d, True),
+                _dev(grad_g, 16, "grad_g", d))
+
+    def _slots(self, T, K):
+        """Checkpoint slots of a T-step run with interval K (0 for arguments the library
+        refuses anyway)."""
+        return (int(T) + int(K) - 1) // int(K) if int(K) > 0 and int(T) > 0 else 0
+
     def adjoint_get(self, mu):
         """Adjoint field -> host FP64 [9, ny, nx]."""
         out = np.zeros((9, self.ny, self.nx))
-        self._check(self._lib.lbm_adjoint_get(self._ctx, _ptr(mu), _dptr(out)))
+        self._check(self._lib.lbm_adjoint_get(self._ctx, self._mu(mu, "mu"), _dptr(out)))
         return out
 
     def adjoint_set(self, mu, values):
         v = _f64(values, (9, self.ny, self.nx))
-        self._check(self._lib.lbm_adjoint_set(self._ctx, _ptr(mu), _dptr(v)))
+        self._check(self._lib.lbm_adjoint_set(self._ctx, self._mu(mu, "mu"), _dptr(v)))
 
     def adjoint_seed_outlet_ux(self, x_col, dJ, mu, grad_alpha, grad_g):
         self._check(self._lib.lbm_adjoint_seed_outlet_ux(self._ctx, int(x_col), float(dJ),
-                                                         _ptr(mu), _ptr(grad_alpha),
-                                                         _ptr(grad_g)))
+                                                         self._mu(mu, "mu"),
+                                                         *self._grads(grad_alpha, grad_g)))
 
     def adjoint_step(self, state, mu_in, mu_out, grad_alpha, grad_g):
-        self._check(self._lib.lbm_adjoint_step(self._ctx, _ptr(state), _ptr(mu_in), _ptr(mu_out),
-                                               _ptr(grad_alpha), _ptr(grad_g)))
+        self._check(self._lib.lbm_adjoint_step(
+            self._ctx, _dev(state, self.state_bytes(), "state"), self._mu(mu_in, "mu_in"),
+            self._mu(mu_out, "mu_out"), *self._grads(grad_alpha, grad_g)))
 
     def run_checkpointed(self, T, K, ckpt):
-        self._check(self._lib.lbm_run_checkpointed(self._ctx, int(T), int(K), _ptr(ckpt)))
+        n = self._slots(T, K) * self.state_bytes()
+        self._check(self._lib.lbm_run_checkpointed(self._ctx, int(T), int(K),
+                                                   _dev(ckpt, n, "ckpt")))
 
     def adjoint_checkpointed(self, T, K, ckpt, seg, x_col, dJ, grad_alpha, grad_g):
-        self._check(self._lib.lbm_adjoint_checkpointed(self._ctx, int(T), int(K), _ptr(ckpt),
-                                                        _ptr(seg), int(x_col), float(dJ),
-                                                        _ptr(grad_alpha), _ptr(grad_g)))
+        sb = self.state_bytes()
+        self._check(self._lib.lbm_adjoint_checkpointed(
+            self._ctx, int(T), int(K), _dev(ckpt, self._slots(T, K) * sb, "ckpt"),
+            _dev(seg, max(int(K), 0) * sb, "seg"), int(x_col), float(dJ),
+            *self._grads(grad_alpha, grad_g)))
 
 
 # ------------------------------------------------------------ host planning --
@@ -393,7 +452,9 @@ def plan_indirect(mask):
 
 def copy_kernel(src, dst, nbytes, stream=None):
     raw = getattr(stream, "cuda_stream", stream) or 0
-    check(load().lbm_copy_kernel(_ptr(src), _ptr(dst), int(nbytes), ctypes.c_void_p(int(raw))))
+    n = int(nbytes)
+    check(load().lbm_copy_kernel(_dev(src, n, "src"), _dev(dst, n, "dst"), n,
+                                 ctypes.c_void_p(int(raw))))
 
 
 from .adjoint import ChannelObjective  # noqa: E402

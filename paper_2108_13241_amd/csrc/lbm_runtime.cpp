@@ -55,7 +55,7 @@ struct lbm_ctx {
     int64_t t = 0;  // steps since (re)initialisation
     int cur = 0;    // A-B layouts: lattice holding the current state
     bool broken = false;
-    std::string last_error = "no error";
+    mutable std::string last_error = "no error";  // also set by const queries that fail
     std::vector<uint8_t> mask;  // host copy [ny][nx]
     std::vector<std::pair<void *, size_t>> owned;
     size_t device_bytes = 0;
@@ -946,16 +946,23 @@ static int check_grads(lbm_ctx *c, double *grad_alpha, double *grad_g)
 
 int lbm_adjoint_bytes(const lbm_ctx *c, size_t *bytes, int32_t *pitch)
 {
-    if (!c || !bytes)
+    if (!c)
         return fail_tl(LBM_ERR_INVALID, "NULL argument");
+    // a const query: its message goes to the context (lbm_last_error(ctx)) too
+    auto refuse = [c](int status, const char *msg) {
+        c->last_error = msg;
+        return fail_tl(status, msg);
+    };
+    if (!bytes)
+        return refuse(LBM_ERR_INVALID, "NULL argument");
     if (c->s.layout != LBM_DENSE_AB || (c->s.dtype != LBM_F64 && c->s.dtype != LBM_F32))
-        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
+        return refuse(LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
     if (c->n_open)
-        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
+        return refuse(LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
     if (c->s.trt)
-        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
+        return refuse(LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
     if (c->s.fullway)
-        return fail_tl(LBM_ERR_UNSUPPORTED, "the adjoint supports halfway bounce-back only");
+        return refuse(LBM_ERR_UNSUPPORTED, "the adjoint supports halfway bounce-back only");
     *bytes = adjoint_field_bytes(c);
     if (pitch)
         *pitch = c->s.pitch;

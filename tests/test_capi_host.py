@@ -209,3 +209,32 @@ def test_porous_generator_deterministic():
     assert np.array_equal(a, b)
     assert abs(ia["phi_achieved"] - 0.5) < 0.01
     assert (a[0] == 1).all() and (a[-1] == 1).all()
+
+
+def test_allocator_hooks_outlive_switch(lib):
+    """The torch allocator callbacks are made once and stay referenced after the hook is
+    switched off (contexts created with them call them at destroy time)."""
+    import paper_2108_13241_amd as pkg
+    pkg._install_torch_allocator()
+    hooks = pkg._hooks
+    assert hooks is not None and pkg._hook_active
+    pkg._uninstall_torch_allocator()
+    assert pkg._hooks is hooks and not pkg._hook_active
+    pkg._install_torch_allocator()
+    assert pkg._hooks is hooks and pkg._hook_active
+
+
+def test_device_buffer_checks():
+    """Caller buffers handed to the library are checked in the binding: CPU tensors, too
+    small, wrong dtype or non-contiguous tensors raise before any call; raw addresses pass."""
+    import torch
+
+    from paper_2108_13241_amd import _dev
+    assert _dev(None, 8, "x", optional=True) is None
+    assert _dev(12345, 8, "x") == 12345
+    with pytest.raises(ValueError, match="required"):
+        _dev(None, 8, "x")
+    with pytest.raises(ValueError, match="CUDA"):
+        _dev(torch.zeros(4), 8, "x")
+    with pytest.raises(ValueError, match="CUDA"):
+        _dev(np.zeros(4), 8, "x")

@@ -117,7 +117,7 @@ def test_allocator_failure_reports_nomem(lbm):
         assert L.lbm3d_last_error(None)
     finally:
         import paper_2108_13241_amd as pkg
-        pkg._alloc_cb = None
+        pkg._hook_active = False  # the hook was replaced by hand above
         _install_torch_allocator()
     lat = lbm.Lattice(np.zeros((16, 16), np.uint8), 0.8)
     lat.step(3)
@@ -135,6 +135,70 @@ def test_hipmalloc_path(lbm):
     b.step(30)
     assert np.array_equal(b.get_populations(), fa)
     b.close()
+
+
+def test_device_buffer_validation(lbm):
+    """Wrong caller buffers raise ValueError in the binding (nothing is overrun); the context
+    stays usable; a refused adjoint query names its reason."""
+    import torch
+    announce("device buffer validation")
+    m = synthetic.channel_mask(64, 16)
+    lat = lbm.Lattice(m, 0.8, force=(1e-5, 0.0), dtype="f32")
+    sb = lat.state_bytes()
+    with pytest.raises(ValueError, match="bytes"):
+        lat.save_state(torch.empty(sb - 1, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError, match="contiguous"):
+        lat.load_state(torch.empty((2, sb), dtype=torch.uint8, device="cuda")[:, 0])
+    with pytest.raises(ValueError, match="float64"):
+        lat.macroscopic_device(torch.empty((16, 64), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="bytes"):
+        lat.macroscopic_device(None, torch.empty((16, 63), dtype=torch.float64, device="cuda"))
+    ab, _ = lat.adjoint_bytes()
+    mu = torch.zeros(ab, dtype=torch.uint8, device="cuda")
+    gg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError, match="mu"):
+        lat.adjoint_seed_outlet_ux(63, 1.0, mu[:-8], None, gg)
+    with pytest.raises(ValueError, match="grad_g"):
+        lat.adjoint_seed_outlet_ux(63, 1.0, mu, None, gg[:1])
+    with pytest.raises(ValueError, match="ckpt"):
+        lat.run_checkpointed(10, 4, torch.empty(2 * sb, dtype=torch.uint8, device="cuda"))
+    out = torch.zeros((16, 64), dtype=torch.float64, device="cuda")
+    lat.step(5)
+    lat.macroscopic_device(None, out, None)
+    torch.cuda.synchronize()
+    assert float(out[8, 10].item()) > 0.0
+    lat.set_trt(0.25)
+    with pytest.raises(lbm.LbmError) as e:
+        lat.adjoint_bytes()
+    assert e.value.status == -4 and "BGK" in str(e.value)
+    lat.close()
+
+
+def test_allocator_switch_keeps_older_contexts(lbm):
+    """A context created with torch's allocator keeps it after the hook is switched off for
+    newer contexts: it still steps, and closing it returns its blocks to torch (the callbacks
+    outlive the switch and a garbage collection)."""
+    import gc
+
+    import torch
+    announce("allocator switch")
+    m = synthetic.random_mask(64, 32, seed=12, solid_fraction=0.2)
+    a = lbm.Lattice(m, 0.7, force=(1e-4, 0.0), dtype="f32", torch_memory=True)
+    b = lbm.Lattice(m, 0.7, force=(1e-4, 0.0), dtype="f32", torch_memory=False)
+    gc.collect()
+    a.step(9)
+    b.step(9)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    a.close()
+    assert torch.cuda.memory_allocated() <= before - 2 * 9 * 32 * 64 * 4
+    b.close()
+    from paper_2108_13241_amd import _install_torch_allocator
+    _install_torch_allocator()
+    c = lbm.Lattice(m, 0.7, dtype="f32")
+    c.step(2)
+    c.close()
 
 
 def test_d3q19_memory_paths(lbm):
