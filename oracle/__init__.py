@@ -122,6 +122,11 @@ def lib():
         L.oracle_run_trt.restype = ctypes.c_int
         L.oracle_run_walls.argtypes = L.oracle_run_trt.argtypes + [ctypes.c_int]
         L.oracle_run_walls.restype = ctypes.c_int
+        L.oracle_mrt_matrix.argtypes = [_dp]
+        L.oracle_collide_mrt.argtypes = [_dp] + [ctypes.c_double] * 3 + [_dp, _dp]
+        L.oracle_run_mrt.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp] + \
+            [ctypes.c_double] * 6 + [_dp, _u8p, _dp, ctypes.c_long, ctypes.c_int, ctypes.c_int]
+        L.oracle_run_mrt.restype = ctypes.c_int
         L.oracle_fullway_fill.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp]
         L.oracle_fullway_fill.restype = ctypes.c_int
         _lib = L
@@ -184,6 +189,25 @@ def collide_trt(f, omega_p, omega_m, alpha=0.0, g=(0.0, 0.0)):
     f = _f64(f)
     out = np.zeros(9)
     lib().oracle_collide_trt(_d(f), alpha, g[0], g[1], omega_p, omega_m, _d(out))
+    return out
+
+
+def mrt_matrix():
+    """The MRT moment matrix M [9, 9] (rows: rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy)."""
+    M = np.zeros((9, 9))
+    lib().oracle_mrt_matrix(_d(M))
+    return M
+
+
+def collide_mrt(f, rates, alpha=0.0, g=(0.0, 0.0)):
+    """Multiple-relaxation-time collision with the nine moment rates `rates` (row order of
+    mrt_matrix)."""
+    f = _f64(f)
+    r = np.ascontiguousarray(rates, dtype=np.float64)
+    if r.shape != (9,):
+        raise ValueError("rates must hold 9 values")
+    out = np.zeros(9)
+    lib().oracle_collide_mrt(_d(f), alpha, g[0], g[1], _d(r), _d(out))
     return out
 
 
@@ -255,11 +279,12 @@ def init(mask, rho0=None, ux0=None, uy0=None, bc=None, value=None):
 
 
 def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value=None,
-        tau_minus=None, fullway=False):
+        tau_minus=None, fullway=False, mrt=None):
     """Advance a copy of f by `steps` time steps; returns the new array.  tau_minus: the
     antisymmetric relaxation time of the two-relaxation-time collision (None: BGK).
-    fullway: full-way bounce-back (f then includes the wall slots of solid nodes next to
-    fluid)."""
+    mrt: (s_e, s_eps, s_q) selects the multiple-relaxation-time collision (shear rate
+    1 / tau).  fullway: full-way bounce-back (f then includes the wall slots of solid nodes
+    next to fluid)."""
     m = _mask(mask)
     ny, nx = m.shape
     f = np.array(f, dtype=np.float64, order="C", copy=True)
@@ -267,6 +292,16 @@ def run(mask, f, tau, steps, g=(0.0, 0.0), alpha=None, threads=0, bc=None, value
         raise ValueError("f must be [9, ny, nx]")
     alpha = _f64(alpha)
     bc, value = _bc_args(m, bc, value)
+    if mrt is not None:
+        if tau_minus is not None:
+            raise ValueError("tau_minus and mrt are exclusive")
+        se, sp, sq = (float(v) for v in mrt)
+        rc = lib().oracle_run_mrt(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, se, sp, sq, g[0],
+                                  g[1], _d(alpha), None if bc is None else bc.ctypes.data_as(_u8p),
+                                  _d(value), int(steps), int(threads), int(bool(fullway)))
+        if rc:
+            raise ValueError(f"oracle_run failed ({rc})")
+        return f
     tm = float(tau) if tau_minus is None else float(tau_minus)
     rc = lib().oracle_run_walls(nx, ny, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
                                 _d(alpha), None if bc is None else bc.ctypes.data_as(_u8p),

@@ -40,6 +40,8 @@
  *     tangential velocity) and the non-equilibrium part of the normal
  *     population equals that of its opposite.  Whatever streamed into those
  *     slots across the periodic seam is discarded;
+ *   - the multiple-relaxation-time collision (oracle_collide_mrt) uses the
+ *     moment basis of Lallemand and Luo with Guo's forcing in moment space;
  *   - full-way bounce-back (the alternative wall rule, selected per run): the
  *     paper's bounce-back boundary nodes hold and move populations without
  *     computing anything (Sec. 4.3).  Solid nodes with at least one fluid
@@ -188,6 +190,77 @@ void oracle_collide_trt(const double *f, double alpha, double gx, double gy, dou
     }
 }
 
+/* Multiple-relaxation-time collision (another collision model beyond the
+ * paper's BGK; the moment basis of Lallemand and Luo, 2000).  Nine moments
+ * m = M f, each row of M a polynomial of the velocity c = v_i:
+ *   rho: 1              e: -4 + 3|c|^2     eps: 4 - 21/2 |c|^2 + 9/2 |c|^4
+ *   j_x: c_x            q_x: (-5 + 3|c|^2) c_x
+ *   j_y: c_y            q_y: (-5 + 3|c|^2) c_y
+ *   p_xx: c_x^2 - c_y^2 p_xy: c_x c_y
+ * The rows are orthogonal, so M^-1 = M^T diag(1 / |row_k|^2).  Each moment
+ * relaxes towards the moment of f^eq (Eq. 6) with its own rate s_k, and the
+ * Guo term enters in moment space with the factor (1 - s_k / 2):
+ *   mstar_k = m_k - s_k (m_k - (M f^eq)_k) + (1 - s_k / 2) (M S)_k,
+ *   fstar   = M^-1 mstar.
+ * rates[9] = s_k in the row order above; all s_k = omega is the BGK collision,
+ * s_k = omega+ on the even rows (rho, e, eps, p_xx, p_xy) and omega- on the odd
+ * ones (j, q) the TRT collision.  The rates of rho and j do not matter (those
+ * moments are conserved, j up to the force, whatever s_k). */
+static double mrt_row(int k, int i)
+{
+    double cx = CX[i], cy = CY[i], c2 = cx * cx + cy * cy;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return -4.0 + 3.0 * c2;
+    case 2: return 4.0 - 10.5 * c2 + 4.5 * c2 * c2;
+    case 3: return cx;
+    case 4: return (-5.0 + 3.0 * c2) * cx;
+    case 5: return cy;
+    case 6: return (-5.0 + 3.0 * c2) * cy;
+    case 7: return cx * cx - cy * cy;
+    default: return cx * cy;
+    }
+}
+
+void oracle_mrt_matrix(double *M)
+{
+    for (int k = 0; k < Q; ++k)
+        for (int i = 0; i < Q; ++i)
+            M[k * Q + i] = mrt_row(k, i);
+}
+
+void oracle_collide_mrt(const double *f, double alpha, double gx, double gy, const double *rates,
+                        double *fstar)
+{
+    double mo[3];
+    oracle_node_velocity(f, alpha, gx, gy, mo);
+    double rho = mo[0], ux = mo[1], uy = mo[2];
+    double Fx = rho * (gx - alpha * ux);
+    double Fy = rho * (gy - alpha * uy);
+    double feq[Q], S[Q], mstar[Q];
+    oracle_equilibrium(rho, ux, uy, feq);
+    oracle_guo_source(ux, uy, Fx, Fy, S);
+    for (int k = 0; k < Q; ++k) {
+        double m = 0.0, meq = 0.0, ms = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            m += mrt_row(k, i) * f[i];
+            meq += mrt_row(k, i) * feq[i];
+            ms += mrt_row(k, i) * S[i];
+        }
+        mstar[k] = m - rates[k] * (m - meq) + (1.0 - 0.5 * rates[k]) * ms;
+    }
+    for (int i = 0; i < Q; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < Q; ++k) {
+            double norm = 0.0;
+            for (int l = 0; l < Q; ++l)
+                norm += mrt_row(k, l) * mrt_row(k, l);
+            v += mrt_row(k, i) * mstar[k] / norm;
+        }
+        fstar[i] = v;
+    }
+}
+
 /* Initialisation (Algorithm 1, first loop): f_i = f^eq_i(rho0, u0) at every
  * fluid node.  NULL fields mean rho0 = 1, u0 = 0.  Solid slots are zeroed. */
 int oracle_init(int nx, int ny, const uint8_t *mask, const double *rho0, const double *ux0,
@@ -306,7 +379,7 @@ int oracle_apply_boundaries(int nx, int ny, const uint8_t *mask, const uint8_t *
  * `post`. */
 static void collide_phase(int nx, int ny, const uint8_t *mask, const uint8_t *wall,
                           const double *f, double *post, double omega, double omega_m,
-                          double gx, double gy, const double *alpha)
+                          const double *mrt, double gx, double gy, const double *alpha)
 {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
@@ -321,7 +394,9 @@ static void collide_phase(int nx, int ny, const uint8_t *mask, const uint8_t *wa
             double fl[Q], fs[Q];
             for (int i = 0; i < Q; ++i)
                 fl[i] = f[slot(i, x, y, nx, ny)];
-            if (omega_m == omega)
+            if (mrt)
+                oracle_collide_mrt(fl, alpha ? alpha[n] : 0.0, gx, gy, mrt, fs);
+            else if (omega_m == omega)
                 oracle_collide(fl, alpha ? alpha[n] : 0.0, gx, gy, omega, fs);
             else
                 oracle_collide_trt(fl, alpha ? alpha[n] : 0.0, gx, gy, omega, omega_m, fs);
@@ -427,9 +502,10 @@ int oracle_fullway_fill(int nx, int ny, const uint8_t *mask, double *f)
  * (no open boundaries); else the boundary conditions are applied after every
  * streaming phase.  fullway selects the full-way wall rule (the state then
  * includes the wall slots).  nthreads <= 0 keeps the OpenMP default. */
-int oracle_run_walls(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
-                     double gx, double gy, const double *alpha, const uint8_t *bc,
-                     const double *value, long nsteps, int nthreads, int fullway)
+static int run_general(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
+                       const double *mrt, double gx, double gy, const double *alpha,
+                       const uint8_t *bc, const double *value, long nsteps, int nthreads,
+                       int fullway)
 {
     if (nx < 1 || ny < 1 || !(tau > 0.5) || !(tau_m > 0.5) || nsteps < 0)
         return -1;
@@ -452,7 +528,7 @@ int oracle_run_walls(int nx, int ny, const uint8_t *mask, double *f, double tau,
         find_walls(nx, ny, mask, wall);
     int rc = 0;
     for (long s = 0; s < nsteps && rc == 0; ++s) {
-        collide_phase(nx, ny, mask, wall, f, post, omega, omega_m, gx, gy, alpha);
+        collide_phase(nx, ny, mask, wall, f, post, omega, omega_m, mrt, gx, gy, alpha);
         if (wall)
             stream_fullway(nx, ny, mask, wall, f, post);
         else
@@ -463,6 +539,30 @@ int oracle_run_walls(int nx, int ny, const uint8_t *mask, double *f, double tau,
     free(post);
     free(wall);
     return rc;
+}
+
+int oracle_run_walls(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
+                     double gx, double gy, const double *alpha, const uint8_t *bc,
+                     const double *value, long nsteps, int nthreads, int fullway)
+{
+    return run_general(nx, ny, mask, f, tau, tau_m, NULL, gx, gy, alpha, bc, value, nsteps,
+                       nthreads, fullway);
+}
+
+/* As oracle_run_walls with the multiple-relaxation-time collision: the shear
+ * moments p_xx, p_xy relax with omega = 1/tau (which sets the viscosity as in
+ * Eq. 5), e with s_e, eps with s_eps, q_x and q_y with s_q; rho and j with 1. */
+int oracle_run_mrt(int nx, int ny, const uint8_t *mask, double *f, double tau, double s_e,
+                   double s_eps, double s_q, double gx, double gy, const double *alpha,
+                   const uint8_t *bc, const double *value, long nsteps, int nthreads,
+                   int fullway)
+{
+    if (!(tau > 0.5))
+        return -1;
+    double omega = 1.0 / tau;
+    double rates[Q] = {1.0, s_e, s_eps, 1.0, s_q, 1.0, s_q, omega, omega};
+    return run_general(nx, ny, mask, f, tau, tau, rates, gx, gy, alpha, bc, value, nsteps,
+                       nthreads, fullway);
 }
 
 int oracle_run_trt(int nx, int ny, const uint8_t *mask, double *f, double tau, double tau_m,
@@ -649,7 +749,7 @@ int oracle_outlet_ux_gradient(int nx, int ny, const uint8_t *mask, const double 
         memcpy(states + (size_t)(t + 1) * total, states + (size_t)t * total,
                total * sizeof(double));
         double *ft = states + (size_t)(t + 1) * total;
-        collide_phase(nx, ny, mask, NULL, ft, post, omega, omega, gx, gy, alpha);
+        collide_phase(nx, ny, mask, NULL, ft, post, omega, omega, NULL, gx, gy, alpha);
         stream_halfway(nx, ny, mask, ft, post);
     }
     const double *fT = states + (size_t)T * total;
