@@ -13,7 +13,7 @@ paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on st
   cpu_baseline = the FP64 CPU oracle on the host cores, a bounded number of steps of
               the same 4096^2 workload (about 12 s), plus one step on a single thread;
   variants  = the same measurement for the other storage types, the AA layout and the
-              TRT collision, the open-boundary channels, the end-to-end rate with host
+              TRT and MRT collisions, the open-boundary channels, the end-to-end rate with host
               transfers and the D3Q19 lattice (256^3 three-dimensional Taylor-Green
               vortex); with --suite full also 1024^2 / 2048^2, the porous / sparse layouts
               (halfway and full-way walls), set-up and view costs and the adjoint.
@@ -108,11 +108,13 @@ def time_steps(lat, steps, warmup):
     return ms / 1e3, ms / max(steps, 1)
 
 
-def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0):
+def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0, mrt=None):
     import synthetic
     m = synthetic.all_fluid(n, n)
     lat = lbm.Lattice(m, 0.6, dtype=dtype, layout=layout)
     lat.set_trt(trt)
+    if mrt is not None:
+        lat.set_mrt(mrt)
     lat.init_equilibrium(*fields)
     secs, ms = time_steps(lat, steps, warmup)
     info = lat.info()
@@ -121,7 +123,9 @@ def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0):
     nf = info["n_fluid"]
     glups = nf * steps / secs / 1e9
     bpn = algorithmic_bytes_per_node(dtype)
-    return {"workload": f"taylor-green {n}^2" + (f" TRT magic={trt:g}" if trt else ""),
+    model = (f" TRT magic={trt:g}" if trt else "") + \
+        (" MRT s_e,s_eps,s_q=" + ",".join(f"{v:g}" for v in mrt) if mrt is not None else "")
+    return {"workload": f"taylor-green {n}^2" + model,
             "dtype": dtype, "layout": layout,
             "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
             "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
@@ -545,6 +549,11 @@ def main():
             r = measure_dense(lbm, n, dtype, "dense_ab", args.steps, args.warmup, fields,
                               trt=3.0 / 16.0)
             log(f"[bench]   {dtype} dense_ab TRT: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
+            variants.append(r)
+        for dtype in ("f64", "f32", "f16s"):
+            r = measure_dense(lbm, n, dtype, "dense_ab", args.steps, args.warmup, fields,
+                              mrt=(1.19, 1.4, 1.2))
+            log(f"[bench]   {dtype} dense_ab MRT: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
             variants.append(r)
         c = measure_copy(lbm, 1 << 30)
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")

@@ -188,6 +188,23 @@ int lbm_set_boundaries(lbm_ctx *ctx, const uint8_t *bc, const double *value);
  * (LBM_ERR_UNSUPPORTED).  Discards captured step graphs. */
 int lbm_set_trt(lbm_ctx *ctx, double magic);
 
+/* Multiple-relaxation-time collision (another collision model beyond the
+ * paper's BGK; the moment basis of Lallemand and Luo, 2000).  The populations
+ * are mapped to nine orthogonal moments: rho, energy e, energy square eps,
+ * momentum j_x, j_y, energy flux q_x, q_y, and the shear moments p_xx, p_xy.
+ * Each relaxes towards the moment of f^eq (Eq. 6) at its own rate, with Guo's
+ * forcing applied in moment space with the factor (1 - s / 2):
+ *   rates  host double[3] = (s_e, s_eps, s_q), each in (0, 2); the shear
+ *          moments relax with omega = 1 / tau (the viscosity of Eq. 5), rho
+ *          and j are conserved (j gains the force).  NULL switches MRT off
+ *          (back to BGK).
+ * All rates equal to omega is BGK; s_e = s_eps = omega and
+ * s_q = 1 / (1/2 + magic / (tau - 1/2)) is the TRT collision of lbm_set_trt.
+ * Selecting MRT switches TRT off and vice versa.  Invalid rates:
+ * LBM_ERR_INVALID, nothing changed.  Contexts using MRT have no adjoint
+ * (LBM_ERR_UNSUPPORTED).  Discards captured step graphs. */
+int lbm_set_mrt(lbm_ctx *ctx, const double *rates);
+
 /* Wall rule.  mode 0: halfway bounce-back (the default; see the conventions
  * above).  mode 1: full-way bounce-back, the boundary nodes of Sec. 4.3 that
  * hold and move populations without computing: a solid node with a fluid

@@ -57,6 +57,7 @@ SIGNATURES = {
     "lbm_set_porosity": (_c.c_int, [_vp, _c.POINTER(_c.c_float)]),
     "lbm_set_boundaries": (_c.c_int, [_vp, _c.c_void_p, _c.c_void_p]),
     "lbm_set_trt": (_c.c_int, [_vp, _c.c_double]),
+    "lbm_set_mrt": (_c.c_int, [_vp, _c.c_void_p]),
     "lbm_set_bounce_back": (_c.c_int, [_vp, _i32]),
     "lbm_set_force": (_c.c_int, [_vp, _dp]),
     "lbm_step": (_c.c_int, [_vp, _i64]),

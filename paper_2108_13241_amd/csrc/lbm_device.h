@@ -155,10 +155,50 @@ __device__ __forceinline__ R pair_dot(int k, R vx, R vy)
 //   M = (1 - omega_m) fm + omega_m odd  [+ (1 - omega_m/2) S_odd],
 //   f_i <- P + M,  f_opp(i) <- P - M,
 // with even / odd the parts of f^eq; omega_m = omega is BGK.
-template <class R, bool DRAG, bool SHIFT, bool FORCE = true, bool EXACT = true, bool TRT = false>
-__device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, const R gy,
-                                        const R alpha, const R omega_m = R(0))
+// MRT: multiple-relaxation-time collision (moment basis of Lallemand and Luo:
+// rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy, orthogonal rows with squared
+// norms 9, 36, 36, 6, 12, 6, 12, 4, 4).  The moments of d = f - f^eq and of
+// the forcing term S relax as
+//   Delta_k = s_k d_k - (1 - s_k / 2) S_k,   f_i <- f_i - sum_k M_ki Delta_k / |M_k|^2,
+// with s = s_e, s_eps on the energy moments, s_q on the energy fluxes and omega
+// on the shear moments (viscosity of Eq. 5).  The conserved moments are set
+// directly: Delta_rho = 0 and Delta_j = -F (whatever their rates, since
+// j - j^eq = -F / 2 and S_j = F).
+template <class R>
+struct Rates {
+    R omega_m;        // TRT: antisymmetric rate
+    R s_e, s_eps, s_q;  // MRT: energy, energy square, energy flux
+};
+
+// The nine MRT moments of v in the row order above.
+template <class R>
+struct MrtMoments {
+    R e, eps, qx, qy, pxx, pxy;
+};
+template <class R>
+__device__ __forceinline__ MrtMoments<R> mrt_moments(const R (&v)[9])
 {
+    const R ax = v[1] + v[3], ay = v[2] + v[4];
+    const R dg = (v[5] + v[6]) + (v[7] + v[8]);
+    const R sx = v[1] - v[3], sy = v[2] - v[4];
+    const R dx = (v[5] - v[6]) + (v[8] - v[7]);
+    const R dy = (v[5] + v[6]) - (v[7] + v[8]);
+    MrtMoments<R> m;
+    m.e = R(-4) * v[0] - (ax + ay) + R(2) * dg;
+    m.eps = R(4) * v[0] - R(2) * (ax + ay) + dg;
+    m.qx = R(-2) * sx + dx;
+    m.qy = R(-2) * sy + dy;
+    m.pxx = ax - ay;
+    m.pxy = (v[5] + v[7]) - (v[6] + v[8]);
+    return m;
+}
+
+template <class R, bool DRAG, bool SHIFT, bool FORCE = true, bool EXACT = true, bool TRT = false,
+          bool MRT = false>
+__device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, const R gy,
+                                        const R alpha, const Rates<R> &rt = Rates<R>{})
+{
+    const R omega_m = rt.omega_m;
     const R sum = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
     const R mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
@@ -206,6 +246,65 @@ __device__ __forceinline__ void collide(R (&f)[9], const R omega, const R gx, co
     const R keep = R(1) - omega;
     const R guo = R(1) - R(0.5) * omega;
     const R uF = ux * Fx + uy * Fy;
+    if constexpr (MRT) {
+        R d[9], sg[9];
+        {
+            const R w = R(kW[0]);
+            d[0] = f[0] - w * C0;
+            sg[0] = FORCE ? w * (R(-3) * uF) : R(0);
+        }
+        constexpr int PM[4] = {1, 2, 5, 6};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = PM[k], j = kOpp[i];
+            const R w = R(kW[i]);
+            const R cu = pair_dot(k, ux, uy);
+            const R even = w * (C0 + rho_times(R(4.5) * (cu * cu)));
+            const R odd = w * rho_times(R(3) * cu);
+            d[i] = f[i] - (even + odd);
+            d[j] = f[j] - (even - odd);
+            if constexpr (FORCE) {
+                const R cF = pair_dot(k, Fx, Fy);
+                const R se = w * (R(9) * cu * cF - R(3) * uF);
+                const R so = R(3) * w * cF;
+                sg[i] = se + so;
+                sg[j] = se - so;
+            } else {
+                sg[i] = sg[j] = R(0);
+            }
+        }
+        const MrtMoments<R> md = mrt_moments(d);
+        MrtMoments<R> ms{};
+        if constexpr (FORCE)
+            ms = mrt_moments(sg);
+        auto relax = [](R s, R dk, R sk) {
+            if constexpr (FORCE)
+                return s * dk - (R(1) - R(0.5) * s) * sk;
+            else
+                return s * dk;
+        };
+        const R b = relax(rt.s_e, md.e, ms.e) * R(1.0 / 36.0);
+        const R c = relax(rt.s_eps, md.eps, ms.eps) * R(1.0 / 36.0);
+        const R qx = relax(rt.s_q, md.qx, ms.qx) * R(1.0 / 12.0);
+        const R qy = relax(rt.s_q, md.qy, ms.qy) * R(1.0 / 12.0);
+        const R p = relax(omega, md.pxx, ms.pxx) * R(0.25);
+        const R r = relax(omega, md.pxy, ms.pxy) * R(0.25);
+        const R jx = FORCE ? Fx * R(-1.0 / 6.0) : R(0);
+        const R jy = FORCE ? Fy * R(-1.0 / 6.0) : R(0);
+        // f_i -= sum_k M_ki Delta_k / |M_k|^2 (rows written out per direction)
+        f[0] -= R(4) * (c - b);
+        const R A = -(b + R(2) * c), D = R(2) * b + c;
+        const R X = jx + qx, Y = jy + qy;
+        f[1] -= A + (jx - R(2) * qx) + p;
+        f[3] -= A - (jx - R(2) * qx) + p;
+        f[2] -= A + (jy - R(2) * qy) - p;
+        f[4] -= A - (jy - R(2) * qy) - p;
+        f[5] -= D + X + Y + r;
+        f[6] -= D - X + Y - r;
+        f[7] -= D - X - Y + r;
+        f[8] -= D + X - Y - r;
+        return;
+    }
     // rest population
     {
         const R w = R(kW[0]);

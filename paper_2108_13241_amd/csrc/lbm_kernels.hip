@@ -274,8 +274,8 @@ __device__ __forceinline__ void dense_pull_aligned(const typename ST::mem *__res
 // Physics variant of a step kernel: plain BGK (no body force, no drag), body
 // force, or body force with a drag field; plus kOpen when the lattice has
 // open-boundary nodes (lattices without them run kernels free of that branch);
-// plus kTRT for the two-relaxation-time collision.
-enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2, kOpenBC = 4, kTRT = 8 };
+// plus kTRT / kMRT for the two- / multiple-relaxation-time collisions.
+enum Phys : int { kBGK = 0, kForced = 1, kDragged = 2, kOpenBC = 4, kTRT = 8, kMRT = 16 };
 
 // Arguments shared by the dense A-B step kernels.
 template <class ST>
@@ -289,7 +289,8 @@ struct DenseArgs {
     const double *__restrict__ bc_val;
     int nx, ny, pitch;
     uint32_t bpr, nblocks;
-    typename ST::real omega, gx, gy, omega_m;
+    typename ST::real omega, gx, gy;
+    Rates<typename ST::real> rt;
     int fullway;
 };
 
@@ -300,9 +301,10 @@ __device__ __forceinline__ void dense_collide_store(const DenseArgs<ST> &k, cons
                                                     uint32_t n, typename ST::real (&f)[9])
 {
     using R = typename ST::real;
-    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK, TRT = (PH & kTRT) != 0;
-    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, k.omega, k.gx, k.gy,
-                                                         DRAG ? (R)k.alpha[n] : R(0), k.omega_m);
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK, TRT = (PH & kTRT) != 0,
+                   MRT = (PH & kMRT) != 0;
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, k.omega, k.gx, k.gy,
+                                                         DRAG ? (R)k.alpha[n] : R(0), k.rt);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dense_at(k.dst, a, i, 1, 1), ST::st(f[i], i));
@@ -404,11 +406,12 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     const uint8_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior,
     const float *__restrict__ alpha, const double *__restrict__ bc_val, int nx, int ny, int pitch,
     uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
-    typename ST::real gy, typename ST::real omega_m)
+    typename ST::real gy, Rates<typename ST::real> rt)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0,
+                   MRT = (PH & kMRT) != 0;
     int x, y;
     uint32_t L;
     if (!dense_node(bpr, nblocks, nx, x, y, L))
@@ -427,8 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
             f[i] = ST::ld(dense_at(A, a, i, 1, 1), i);
         if (OPEN && open)
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
-                                                             DRAG ? (R)alpha[n] : R(0), omega_m);
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
+                                                             DRAG ? (R)alpha[n] : R(0), rt);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             store_nt(&dense_at(A, a, kOpp[i], 1, 1), ST::st(f[i], i));
@@ -447,8 +450,8 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
         }
         if (OPEN && open)
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
-                                                             DRAG ? (R)alpha[n] : R(0), omega_m);
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
+                                                             DRAG ? (R)alpha[n] : R(0), rt);
         // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
         if (sm == 0) {
 #pragma unroll
@@ -471,11 +474,12 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
     const float *__restrict__ alpha, const double *__restrict__ bc_val,
     const int32_t *__restrict__ tile_nbr, uint32_t n_tiles, typename ST::real omega,
-    typename ST::real gx, typename ST::real gy, typename ST::real omega_m, int fullway)
+    typename ST::real gx, typename ST::real gy, Rates<typename ST::real> rt, int fullway)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0,
+                   MRT = (PH & kMRT) != 0;
     const uint32_t k = xcd_remap(blockIdx.x, n_tiles);
     const int t = (int)threadIdx.x, lx = t & 15, ly = t >> 4;
     const uint32_t n = k * kTileNodes + t;
@@ -495,8 +499,8 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
         if (const unsigned open = open_code(ty))
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
     }
-    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
-                                                         DRAG ? (R)alpha[n] : R(0), omega_m);
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
+                                                         DRAG ? (R)alpha[n] : R(0), rt);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kTileStride + nb[0]], ST::st(f[i], i));
@@ -510,11 +514,12 @@ __global__ __launch_bounds__(kBlock) void k_step_indirect(
     const int32_t *__restrict__ edge, const float *__restrict__ alpha,
     const double *__restrict__ bc_val, uint32_t n_fluid, uint32_t nblocks,
     typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real omega_m, int fullway)
+    Rates<typename ST::real> rt, int fullway)
 {
     using R = typename ST::real;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0;
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0,
+                   MRT = (PH & kMRT) != 0;
     const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
     if (n >= n_fluid)
         return;
@@ -525,8 +530,8 @@ __global__ __launch_bounds__(kBlock) void k_step_indirect(
     pull_gather<ST>(src, fullway ? dst : src, kChunk, nb, sm, f);
     if (OPEN && open)
         apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT>(f, omega, gx, gy,
-                                                         DRAG ? (R)alpha[n] : R(0), omega_m);
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
+                                                         DRAG ? (R)alpha[n] : R(0), rt);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         store_nt(&dst[(uint32_t)i * kChunk + nb[0]], ST::st(f[i], i));
@@ -896,7 +901,8 @@ void step_launch(const DevState &s, int64_t t, int cur)
 {
     using M = typename ST::mem;
     using R = typename ST::real;
-    const R om = (R)s.omega, gx = (R)s.gx, gy = (R)s.gy, omm = (R)s.omega_m;
+    const R om = (R)s.omega, gx = (R)s.gx, gy = (R)s.gy;
+    const Rates<R> omm{(R)s.omega_m, (R)s.s_e, (R)s.s_eps, (R)s.s_q};
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
     if (s.layout == kDenseAB || s.layout == kDenseAA) {
@@ -951,7 +957,12 @@ void step_phys(const DevState &s, int64_t t, int cur)
 template <class ST>
 hipError_t step_typed(const DevState &s, int64_t t, int cur)
 {
-    if (s.trt) {
+    if (s.mrt) {
+        if (s.open)
+            step_phys<ST, kOpenBC | kMRT>(s, t, cur);
+        else
+            step_phys<ST, kMRT>(s, t, cur);
+    } else if (s.trt) {
         if (s.open)
             step_phys<ST, kOpenBC | kTRT>(s, t, cur);
         else

@@ -37,6 +37,8 @@ struct DevState {
     int trt = 0;                      // 1: two-relaxation-time collision (omega_m below)
     int fullway = 0;                  // 1: full-way bounce-back (A-B layouts)
     double omega_m = 1.0;             // antisymmetric relaxation rate (TRT)
+    int mrt = 0;                      // 1: multiple-relaxation-time collision
+    double s_e = 1.0, s_eps = 1.0, s_q = 1.0;  // its energy, energy-square, flux rates
     int64_t n_tiles = 0, n_fluid = 0;
     double omega = 1.0, gx = 0.0, gy = 0.0;
     hipStream_t stream = nullptr;

@@ -608,7 +608,30 @@ int lbm_set_trt(lbm_ctx *c, double magic)
     const double tau = 1.0 / s.omega;
     const double tau_m = 0.5 + magic / (tau - 0.5);
     s.trt = 1;
+    s.mrt = 0;
     s.omega_m = 1.0 / tau_m;
+    return LBM_OK;
+}
+
+int lbm_set_mrt(lbm_ctx *c, const double *rates)
+{
+    LBM_CHECK_CTX(c);
+    lbm::DevState &s = c->s;
+    if (!rates) {
+        drop_graphs(c);
+        s.mrt = 0;
+        return LBM_OK;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (!(std::isfinite(rates[k]) && rates[k] > 0.0 && rates[k] < 2.0))
+            return fail(c, LBM_ERR_INVALID, "MRT rates must lie in (0, 2)");
+    drop_graphs(c);
+    s.mrt = 1;
+    s.trt = 0;
+    s.omega_m = s.omega;
+    s.s_e = rates[0];
+    s.s_eps = rates[1];
+    s.s_q = rates[2];
     return LBM_OK;
 }
 
@@ -897,7 +920,7 @@ static int adjoint_supported(lbm_ctx *c)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
     if (c->n_open)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
-    if (c->s.trt)
+    if (c->s.trt || c->s.mrt)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
     if (c->s.fullway)
         return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint supports halfway bounce-back only");
@@ -959,7 +982,7 @@ int lbm_adjoint_bytes(const lbm_ctx *c, size_t *bytes, int32_t *pitch)
         return refuse(LBM_ERR_UNSUPPORTED, "the adjoint supports DENSE_AB with F64 or F32");
     if (c->n_open)
         return refuse(LBM_ERR_UNSUPPORTED, "the adjoint does not support open boundaries");
-    if (c->s.trt)
+    if (c->s.trt || c->s.mrt)
         return refuse(LBM_ERR_UNSUPPORTED, "the adjoint supports the BGK collision only");
     if (c->s.fullway)
         return refuse(LBM_ERR_UNSUPPORTED, "the adjoint supports halfway bounce-back only");

@@ -94,6 +94,7 @@ def test_null_context(lib):
     import ctypes
     assert lib.lbm_step(None, 1) == -1
     assert lib.lbm_mass(None, ctypes.byref(ctypes.c_double())) == -1
+    assert lib.lbm_set_mrt(None, None) == -1
     lib.lbm_destroy(None)
 
 
