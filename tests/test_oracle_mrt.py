@@ -1,5 +1,5 @@
-"""Pins of the oracle's multiple-relaxation-time collision (a more complex collision model, which
-the paper names as future work; moment basis of Lallemand and Luo), against what does not depend
+"""Pins of the oracle's multiple-relaxation-time collision (a richer collision model, which
+the paper plans as future work; moment basis of Lallemand and Luo), against what does not depend
 on the oracle's own arithmetic:
 
 * the moment matrix has orthogonal rows with norms 9, 36, 36, 6, 12, 6, 12, 4, 4, its rows rho,
