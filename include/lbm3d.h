@@ -7,9 +7,11 @@
  * the fused pull stream-and-collide step of Algorithm 1 with halfway bounce-back
  * walls (Sec. 3), the BGK operator of Eqs. 3-5 and the equilibrium of Eq. 6 with
  * the D3Q19 weights, plus a body force through Guo's forcing term and, as
- * options, the two-relaxation-time collision and the full-way wall rule.  One
- * layout:
- * two dense lattices swapped every step (the A-B scheme of lbm.h's DENSE_AB).
+ * options, the two-relaxation-time collision and the full-way wall rule.  Two
+ * layouts, as lbm.h's dense ones: DENSE_AB, two dense lattices swapped every
+ * step, and DENSE_AA, one dense lattice updated in place with the AA access
+ * pattern (even steps read and write each node's own slots, odd steps read from
+ * and write to the neighbours; half the memory).
  *
  * Conventions (as in lbm.h, whose status codes, dtype enum and allocator hook
  * this interface shares)
@@ -52,6 +54,7 @@ typedef struct lbm3d_ctx lbm3d_ctx; /* opaque; owned by the library until lbm3d_
 typedef struct {
     int32_t nx, ny, nz;
     int32_t dtype;
+    int32_t layout;              /* LBM_DENSE_AB or LBM_DENSE_AA */
     int64_t n_nodes;             /* nx * ny * nz */
     int64_t n_fluid;             /* fluid nodes: the ones counted for LUPS (Eq. 8) */
     int64_t time_step;           /* steps since the last (re)initialisation */
@@ -75,10 +78,12 @@ typedef struct {
  *  force       host double[3] body-force acceleration (g_x, g_y, g_z); NULL = 0.
  *              Force density F = rho g through Guo's forcing term.
  *  dtype       storage type (see above).
- * Errors: INVALID (sizes, tau, force, mask values, dtype), UNSUPPORTED (size
- * limit), NOMEM, DEVICE. */
+ *  layout      LBM_DENSE_AB or LBM_DENSE_AA (one lattice: 19 * pop_bytes per
+ *              node, half of DENSE_AB); the other layouts are UNSUPPORTED.
+ * Errors: INVALID (sizes, tau, force, mask values, dtype, layout), UNSUPPORTED
+ * (size limit, sparse layout), NOMEM, DEVICE. */
 int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint8_t *node_type,
-                 double tau, const double *force, lbm_dtype dtype);
+                 double tau, const double *force, lbm_dtype dtype, lbm_layout layout);
 
 /* Enqueue later work on `hip_stream` (NULL = default stream), after waiting for
  * the work already enqueued. */
@@ -109,8 +114,9 @@ int lbm3d_set_trt(lbm3d_ctx *ctx, double magic);
  * reads them (finite), lbm3d_mass counts them; lbm3d_init_equilibrium and a
  * switch from mode 0 set slot j of w to population j of the fluid node
  * w - c_j.  The fluid populations are kept across a switch.  No extra memory
- * (the A-B pair holds the state).  Invalid mode: LBM_ERR_INVALID.
- * Synchronises the stream. */
+ * (the A-B pair holds the state).  Invalid mode: LBM_ERR_INVALID; mode 1 on a
+ * DENSE_AA lattice: LBM_ERR_UNSUPPORTED (in place, no lattice holds the values
+ * of two steps back).  Synchronises the stream. */
 int lbm3d_set_bounce_back(lbm3d_ctx *ctx, int32_t mode);
 
 /* Enqueue n >= 0 time steps (one kernel launch each). */

@@ -343,12 +343,13 @@ def _force3(g):
 
 
 class Lattice3D:
-    """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B
-    layout, BGK with Guo forcing, halfway bounce-back.  Arrays are [nz, ny, nx]; canonical
-    populations [19, nz, ny, nx] in the velocity order of include/lbm3d.h."""
+    """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B or
+    AA layout, BGK (or TRT) with Guo forcing, halfway (or full-way) bounce-back.  Arrays are
+    [nz, ny, nx]; canonical populations [19, nz, ny, nx] in the velocity order of
+    include/lbm3d.h."""
 
     def __init__(self, mask, tau, force=(0.0, 0.0, 0.0), dtype="f64", stream=None,
-                 torch_memory=True):
+                 torch_memory=True, layout="dense_ab"):
         import torch
 
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
@@ -366,8 +367,10 @@ class Lattice3D:
         self._ctx = ctypes.c_void_p()
         g = _force3(force)
         check3(self._lib.lbm3d_create(ctypes.byref(self._ctx), self.nx, self.ny, self.nz,
-                                      mask.ctypes.data_as(_u8p), float(tau), g, DTYPES[dtype]),
+                                      mask.ctypes.data_as(_u8p), float(tau), g, DTYPES[dtype],
+                                      LAYOUTS[layout]),
                None)
+        self.layout = layout
         self.set_stream(stream if stream is not None else torch.cuda.current_stream())
 
     def _check(self, status):

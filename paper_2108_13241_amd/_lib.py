@@ -36,7 +36,7 @@ class LbmInfo(ctypes.Structure):
 
 class Lbm3dInfo(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("layout", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_fluid", ctypes.c_int64), ("time_step", ctypes.c_int64),
                 ("pop_bytes", ctypes.c_int32), ("bytes_per_fluid_node", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t)]
@@ -90,7 +90,7 @@ SIGNATURES = {
     "lbm_destroy": (None, [_vp]),
     # include/lbm3d.h
     "lbm3d_create": (_c.c_int, [_c.POINTER(_vp), _i32, _i32, _i32, _c.POINTER(_c.c_uint8),
-                                _c.c_double, _dp, _c.c_int]),
+                                _c.c_double, _dp, _c.c_int, _c.c_int]),
     "lbm3d_set_stream": (_c.c_int, [_vp, _vp]),
     "lbm3d_init_equilibrium": (_c.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbm3d_set_force": (_c.c_int, [_vp, _dp]),

@@ -291,6 +291,80 @@ __global__ __launch_bounds__(kBlock) void k_step3(
         store_nt(&elem(dst, a, i, 1, 1, 1), ST::st(f[i], i));
 }
 
+// AA pattern (DENSE_AA: one lattice updated in place).  Even steps read node
+// x's own slots and write f*_i to its slot opp(i); odd steps read
+// f_i = A_opp(i)(x - c_i) (A_i(x) when x - c_i is solid) and write f*_i to
+// A_i(x + c_i) (A_opp(i)(x) when x + c_i is solid).  Slot j of node y is read
+// and written only by node y in even steps and only by node y - c_j in odd
+// steps, so the update is race-free.  After an even number of steps the
+// canonical state is local (f_i = A_i(x)); after an odd number it is the odd
+// read above.
+template <class ST>
+__device__ __forceinline__ void aa_odd3(const typename ST::mem *s, const Addr &a, uint32_t sm,
+                                        typename ST::real (&f)[Q])
+{
+    using M = typename ST::mem;
+    M *sp = const_cast<M *>(s);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        f[i] = ST::ld(((sm >> i) & 1u) ? elem(sp, a, i, 1, 1, 1)
+                                       : elem(sp, a, kOpp[i], 1 - kCz[i], 1 - kCy[i], 1 - kCx[i]),
+                      i);
+}
+
+template <class ST>
+__device__ __forceinline__ void local3(const typename ST::mem *s, const Addr &a,
+                                       typename ST::real (&f)[Q])
+{
+    using M = typename ST::mem;
+    M *sp = const_cast<M *>(s);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        f[i] = ST::ld(elem(sp, a, i, 1, 1, 1), i);
+}
+
+template <class ST, bool FORCE, bool TRT, bool ODD>
+__global__ __launch_bounds__(kBlock) void k_step3_aa(
+    typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
+    const uint32_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior, int nx, int ny,
+    int nz, int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega,
+    typename ST::real gx, typename ST::real gy, typename ST::real gz, typename ST::real omega_m)
+{
+    using R = typename ST::real;
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t r = L / bpr;  // row index z * ny + y
+    const int x = (int)(L - r * bpr) * kBlock + (int)threadIdx.x;
+    if (x >= nx)
+        return;
+    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
+    const uint32_t n = r * (uint32_t)pitch + (uint32_t)x;
+    uint32_t sm = 0;
+    if (!seg_interior[L]) {
+        const uint8_t t = type[n];
+        if (t == kSolid)
+            return;
+        sm = solid_bits3(t, nmask, n);
+    }
+    const Addr a = addr_of(x, y, z, nx, ny, nz, (uint32_t)pitch / kChunk);
+    R f[Q];
+    if constexpr (ODD)
+        aa_odd3<ST>(A, a, sm, f);
+    else
+        local3<ST>(A, a, f);
+    collide3<R, ST::kShift, FORCE, TRT>(f, omega, gx, gy, gz, omega_m);
+    if constexpr (ODD) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            store_nt(((sm >> kOpp[i]) & 1u) ? &elem(A, a, kOpp[i], 1, 1, 1)
+                                            : &elem(A, a, i, 1 + kCz[i], 1 + kCy[i], 1 + kCx[i]),
+                     ST::st(f[i], i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            store_nt(&elem(A, a, kOpp[i], 1, 1, 1), ST::st(f[i], i));
+    }
+}
+
 // ------------------------------------------------------------ canonical views --
 // Canonical FP64 buffers are [19][nz][ny][pitch].
 
@@ -299,11 +373,15 @@ __global__ __launch_bounds__(kBlock) void k_step3(
 // bounce-back source of pull3.  Under the full-way rule (bb not st) the node
 // also reports its wall slots: bit j of wl set <=> node x + c_j is solid, and
 // the population in flight there, f_j(x + c_j), is the node's stored slot j.
+// mode: kPull3 (A-B), kAAEven3 / kAAOdd3 (DENSE_AA after an even / odd number
+// of steps).
+enum Mode3 : int { kPull3 = 0, kAAEven3 = 1, kAAOdd3 = 2 };
+
 template <class ST>
 __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST::mem *st,
-                                             const typename ST::mem *bb, uint32_t gid, int &x,
-                                             int &y, int &z, double (&fd)[Q], uint32_t &wl,
-                                             double (&wv)[Q])
+                                             const typename ST::mem *bb, int mode, uint32_t gid,
+                                             int &x, int &y, int &z, double (&fd)[Q],
+                                             uint32_t &wl, double (&wv)[Q])
 {
     wl = 0;
     const uint32_t r = gid / (uint32_t)s.pitch;
@@ -318,7 +396,12 @@ __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST:
     const Addr a = addr_of(x, y, z, s.nx, s.ny, s.nz, (uint32_t)s.pitch / kChunk);
     const uint32_t sm = solid_bits3(t, s.nmask, gid);
     typename ST::real f[Q];
-    pull3<ST>(st, bb, a, sm, f);
+    if (mode == kAAEven3)
+        local3<ST>(st, a, f);
+    else if (mode == kAAOdd3)
+        aa_odd3<ST>(st, a, sm, f);
+    else
+        pull3<ST>(st, bb, a, sm, f);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         fd[i] = ST::canon(f[i], i);
@@ -344,14 +427,14 @@ __device__ __forceinline__ uint32_t node_plus(const State3 &s, int x, int y, int
 
 template <class ST>
 __global__ __launch_bounds__(kBlock) void k_gather3(State3 s, const typename ST::mem *st,
-                                                    const typename ST::mem *bb,
+                                                    const typename ST::mem *bb, int mode,
                                                     double *__restrict__ fc)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     int x, y, z;
     double f[Q], wv[Q];
     uint32_t wl;
-    if (!canonical_at<ST>(s, st, bb, gid, x, y, z, f, wl, wv))
+    if (!canonical_at<ST>(s, st, bb, mode, gid, x, y, z, f, wl, wv))
         return;
     const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
 #pragma unroll
@@ -368,7 +451,8 @@ __global__ __launch_bounds__(kBlock) void k_gather3(State3 s, const typename ST:
 // the populations in flight in the wall slots the node feeds.
 template <class ST>
 __global__ __launch_bounds__(kBlock) void k_macro3(State3 s, const typename ST::mem *st,
-                                                   const typename ST::mem *bb, double *rho,
+                                                   const typename ST::mem *bb, int mode,
+                                                   double *rho,
                                                    double *ux, double *uy, double *uz,
                                                    double *partials)
 {
@@ -378,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_macro3(State3 s, const typename ST::
     double f[Q], wv[Q];
     uint32_t wl;
     double r = 0.0, mass = 0.0;
-    if (canonical_at<ST>(s, st, bb, gid, x, y, z, f, wl, wv)) {
+    if (canonical_at<ST>(s, st, bb, mode, gid, x, y, z, f, wl, wv)) {
         double mx = 0.0, my = 0.0, mz = 0.0;
         for (int i = 0; i < Q; ++i) {
             r += f[i];
@@ -464,9 +548,12 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium3(State3 s, const double 
 // wall node (its wall slot; walls = 2: the node's own f_j, the initial
 // wall-slot rule), and the other lattice's slot opp(i) of q holds f_i(q) for
 // every bounce-back link i (it returns from the wall at this step).
+// DENSE_AA (mode kAAEven3 / kAAOdd3, the inverse of the AA reads): even,
+// s_j(q) = f_j(q); odd, s_j(q) = f_opp(j)(q - c_j), or f_j(q) when q - c_j is
+// solid.
 template <class ST>
 __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem *st,
-                                                     typename ST::mem *other, int walls,
+                                                     typename ST::mem *other, int walls, int mode,
                                                      const double *__restrict__ fc)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
@@ -481,6 +568,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
     const uint32_t sm = solid_bits3(t, s.nmask, gid);
     const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
     const Addr a = addr_of(x, y, z, s.nx, s.ny, s.nz, (uint32_t)s.pitch / kChunk);
+    if (mode != kPull3) {
+        for (int j = 0; j < Q; ++j) {
+            const double v = mode == kAAEven3 || ((sm >> j) & 1u)
+                                 ? fc[(uint64_t)j * plane + gid]
+                                 : fc[(uint64_t)kOpp[j] * plane + node_plus(s, x, y, z, kOpp[j])];
+            elem(st, a, j, 1, 1, 1) = ST::from_canon(v, j);
+        }
+        return;
+    }
     for (int j = 0; j < Q; ++j) {
         double v;
         // q + c_j is node q - c_opp(j): solid iff bit opp(j) is set
@@ -519,9 +615,24 @@ void step_launch3(const State3 &s, int cur)
     using R = typename ST::real;
     const uint32_t bpr = (uint32_t)((s.nx + kBlock - 1) / kBlock);
     const uint32_t nb = bpr * (uint32_t)s.ny * (uint32_t)s.nz;
+    const bool force = s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0;
+    if (s.aa) {
+        M *A = (M *)s.f[0];
+        const R g[3] = {force ? (R)s.gx : R(0), force ? (R)s.gy : R(0), force ? (R)s.gz : R(0)};
+        auto go = [&](auto kernel) {
+            kernel<<<nb, kBlock, 0, s.stream>>>(A, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
+                                                s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1],
+                                                g[2], (R)s.omega_m);
+        };
+        if (force)
+            cur ? go(k_step3_aa<ST, true, TRT, true>) : go(k_step3_aa<ST, true, TRT, false>);
+        else
+            cur ? go(k_step3_aa<ST, false, TRT, true>) : go(k_step3_aa<ST, false, TRT, false>);
+        return;
+    }
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
-    if (s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0)
+    if (force)
         k_step3<ST, true, TRT><<<nb, kBlock, 0, s.stream>>>(
             src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
             (R)s.omega, (R)s.gx, (R)s.gy, (R)s.gz, (R)s.omega_m, s.fullway);
@@ -539,6 +650,11 @@ hipError_t step_typed(const State3 &s, int cur)
     else
         step_launch3<ST, false>(s, cur);
     return hipGetLastError();
+}
+
+int view_mode(const State3 &s, int cur)
+{
+    return s.aa ? (cur ? kAAOdd3 : kAAEven3) : kPull3;
 }
 
 uint32_t node_blocks(const State3 &s)
@@ -586,8 +702,12 @@ hipError_t launch_scatter3(const State3 &s, int cur, const double *fc, int fill_
     const int walls = s.fullway ? (fill_walls ? 2 : 1) : 0;
     return by_dtype(s.dtype, [&](auto st) {
         using M = typename decltype(st)::mem;
-        k_scatter3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, (M *)s.f[cur], (M *)s.f[1 - cur],
-                                                              walls, fc);
+        if (s.aa)
+            k_scatter3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(
+                s, (M *)s.f[0], nullptr, 0, cur ? kAAOdd3 : kAAEven3, fc);
+        else
+            k_scatter3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(
+                s, (M *)s.f[cur], (M *)s.f[1 - cur], walls, kPull3, fc);
     });
 }
 
@@ -608,9 +728,9 @@ hipError_t launch_gather3(const State3 &s, int cur, double *fc)
     const uint32_t nb = node_blocks(s);
     return by_dtype(s.dtype, [&](auto st) {
         using M = typename decltype(st)::mem;
-        const M *src = (const M *)s.f[cur];
+        const M *src = (const M *)s.f[s.aa ? 0 : cur];
         const M *bb = s.fullway ? (const M *)s.f[1 - cur] : src;
-        k_gather3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, src, bb, fc);
+        k_gather3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, src, bb, view_mode(s, cur), fc);
     });
 }
 
@@ -627,9 +747,10 @@ hipError_t launch_macro3(const State3 &s, int cur, double *rho, double *ux, doub
     double *part = mass ? s.red : nullptr;
     hipError_t e = by_dtype(s.dtype, [&](auto st) {
         using M = typename decltype(st)::mem;
-        const M *src = (const M *)s.f[cur];
+        const M *src = (const M *)s.f[s.aa ? 0 : cur];
         const M *bb = s.fullway ? (const M *)s.f[1 - cur] : src;
-        k_macro3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, src, bb, rho, ux, uy, uz, part);
+        k_macro3<decltype(st)><<<nb, kBlock, 0, s.stream>>>(s, src, bb, view_mode(s, cur), rho,
+                                                            ux, uy, uz, part);
     });
     if (e != hipSuccess || !mass)
         return e;

@@ -23,7 +23,8 @@ struct State3 {
     int dtype = 0;
     int nx = 0, ny = 0, nz = 0;
     int pitch = 0;                           // nx rounded up to a multiple of 64
-    void *f[2] = {nullptr, nullptr};         // the two lattices (A-B)
+    void *f[2] = {nullptr, nullptr};         // the two lattices (A-B); DENSE_AA: f[0] only
+    int aa = 0;                              // 1: DENSE_AA, one lattice updated in place
     const uint8_t *type = nullptr;           // 0 fluid, 1 solid, 2 fluid next to a solid
     const uint32_t *nmask = nullptr;         // bit i-1 set <=> node x - c_i is solid
     const uint32_t *seg_interior = nullptr;  // per 256-node row segment: 1 = all type 0
@@ -35,7 +36,10 @@ struct State3 {
     double *red = nullptr;                   // reduction scratch (reduction_capacity3 doubles)
 };
 
-// One step from lattice cur into lattice 1 - cur.
+// One step from lattice cur into lattice 1 - cur.  DENSE_AA (s.aa): one lattice,
+// and cur is the parity of the steps taken so far (0: even, the canonical state
+// is local; the runtime flips it after every step as for A-B).  The view,
+// scatter and macro launches read cur the same way.
 hipError_t launch_step3(const State3 &s, int cur);
 // Equilibrium of device FP64 [nz][ny][nx] fields (NULL: rho = 1, u = 0) into the
 // canonical buffer fc (FP64 [19][nz][ny][pitch]).

@@ -140,7 +140,8 @@ int init_state(lbm3d_ctx *c, const double *rho, const double *ux, const double *
         c->t = 0;
         c->cur = 0;
         LBM3_HIP(c, lbm3::launch_rest3(c->s, c->s.f[0]));
-        LBM3_HIP(c, lbm3::launch_rest3(c->s, c->s.f[1]));
+        if (c->s.f[1])
+            LBM3_HIP(c, lbm3::launch_rest3(c->s, c->s.f[1]));
         LBM3_HIP(c, hipStreamSynchronize(c->s.stream));
         return LBM_OK;
     }
@@ -183,7 +184,7 @@ void lbm3d_destroy(lbm3d_ctx *c)
 }
 
 int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint8_t *node_type,
-                 double tau, const double *force, lbm_dtype dtype)
+                 double tau, const double *force, lbm_dtype dtype, lbm_layout layout)
 {
     if (!out)
         return fail_tl(LBM_ERR_INVALID, "out is NULL");
@@ -198,6 +199,10 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
         return fail_tl(LBM_ERR_INVALID, "force must be finite");
     if ((int)dtype < 0 || (int)dtype > 3)
         return fail_tl(LBM_ERR_INVALID, "unknown dtype");
+    if ((int)layout < 0 || (int)layout > 4)
+        return fail_tl(LBM_ERR_INVALID, "unknown layout");
+    if (layout != LBM_DENSE_AB && layout != LBM_DENSE_AA)
+        return fail_tl(LBM_ERR_UNSUPPORTED, "D3Q19 lattices take DENSE_AB or DENSE_AA");
     const int64_t pitch = ((int64_t)nx + 63) / 64 * 64;
     // population offsets are 64-bit; node indices and lane column offsets are
     // 32-bit
@@ -258,7 +263,8 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
         return fail_create(rc, "cannot upload the segment flags");
     s.seg_interior = (const uint32_t *)p;
     const size_t lattice = (size_t)Q * padded_nodes(c) * c->pop_bytes;
-    for (int k = 0; k < 2; ++k) {
+    s.aa = layout == LBM_DENSE_AA ? 1 : 0;
+    for (int k = 0; k < (s.aa ? 1 : 2); ++k) {
         s.f[k] = own_alloc(c, lattice);
         if (!s.f[k])
             return fail_create(LBM_ERR_NOMEM, "cannot allocate the lattice");
@@ -332,6 +338,9 @@ int lbm3d_set_bounce_back(lbm3d_ctx *c, int32_t mode)
         return fail(c, LBM_ERR_INVALID, "bounce-back mode must be 0 (halfway) or 1 (full-way)");
     if (mode == c->s.fullway)
         return LBM_OK;
+    if (mode == 1 && c->s.aa)
+        return fail(c, LBM_ERR_UNSUPPORTED,
+                    "full-way bounce-back needs the two-lattice layout (not DENSE_AA)");
     // keep the fluid populations: gather under the old rule, store under the new
     // one (switching to full-way fills the wall slots from their sources)
     Temp fc(c, canonical_bytes(c));
@@ -460,6 +469,7 @@ int lbm3d_get_info(const lbm3d_ctx *c, lbm3d_info_t *info)
     info->ny = c->s.ny;
     info->nz = c->s.nz;
     info->dtype = c->s.dtype;
+    info->layout = c->s.aa ? LBM_DENSE_AA : LBM_DENSE_AB;
     info->n_nodes = (int64_t)c->s.nx * c->s.ny * c->s.nz;
     info->n_fluid = c->n_fluid;
     info->time_step = c->t;

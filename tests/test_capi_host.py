@@ -98,18 +98,20 @@ def test_null_context(lib):
     lib.lbm_destroy(None)
 
 
-def _create3(lib, nx, ny, nz, m, tau=0.8, force=None, dtype=0):
+def _create3(lib, nx, ny, nz, m, tau=0.8, force=None, dtype=0, layout=0):
     import ctypes
     ctx = ctypes.c_void_p(1)
     g = (ctypes.c_double * 3)(*force) if force is not None else None
     st = lib.lbm3d_create(ctypes.byref(ctx), nx, ny, nz,
-                          m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tau, g, dtype)
+                          m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tau, g, dtype,
+                          layout)
     return st, ctx
 
 
 @pytest.mark.parametrize("args,status", [
     (dict(nx=0), -1), (dict(nz=0), -1), (dict(tau=0.5), -1), (dict(tau=float("nan")), -1),
     (dict(force=(0.0, float("inf"), 0.0)), -1), (dict(dtype=4), -1), (dict(dtype=-1), -1),
+    (dict(layout=7), -1), (dict(layout=2), -4), (dict(layout=3), -4), (dict(layout=4), -4),
     # nz * ny * pitch >= 2^31 nodes, or 19 * pitch >= 2^28, is refused before the
     # mask is read or anything is allocated
     (dict(nx=1024, ny=2048, nz=1024), -4), (dict(nx=14128700, ny=1, nz=1), -4),

@@ -110,7 +110,7 @@ def test_allocator_failure_reports_nomem(lbm):
         m3 = np.zeros((4, 8, 8), np.uint8)
         g3 = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
         st = L.lbm3d_create(ctypes.byref(ctx), 8, 8, 4,
-                            m3.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0.8, g3, 0)
+                            m3.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0.8, g3, 0, 0)
         assert st == -2
         assert not ctx.value
         assert calls["alloc"] > n0
