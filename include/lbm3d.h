@@ -126,6 +126,20 @@ int lbm3d_step(lbm3d_ctx *ctx, int64_t n);
  * FP64 [nz][ny][nx] arrays (any may be NULL); solid nodes get 0.  Synchronises. */
 int lbm3d_macroscopic(lbm3d_ctx *ctx, double *rho, double *ux, double *uy, double *uz);
 
+/* Same fields into caller-owned device FP64 [nz][ny][nx] buffers (all four
+ * required; solid nodes get 0), on the context's stream.  Asynchronous. */
+int lbm3d_macroscopic_device(lbm3d_ctx *ctx, void *rho, void *ux, void *uy, void *uz);
+
+/* Raw device checkpoints of the stored state: lbm3d_state_bytes bytes
+ * (19 * nz * ny * pitch * pop_bytes), copied on the context's stream to / from a
+ * caller-owned device buffer.  A state saved at step t and loaded later
+ * reproduces the run from t bitwise (DENSE_AA: load only at a step count of the
+ * same parity as at save time).  Under the full-way rule the state spans both
+ * lattices: LBM_ERR_UNSUPPORTED. */
+int lbm3d_state_bytes(const lbm3d_ctx *ctx, size_t *bytes);
+int lbm3d_save_state(lbm3d_ctx *ctx, void *dev_dst);
+int lbm3d_load_state(lbm3d_ctx *ctx, const void *dev_src);
+
 /* Canonical populations to / from host FP64 [19][nz][ny][nx].  set requires
  * finite values at fluid nodes (solid slots are ignored) and rounds to the
  * storage type.  Both synchronise. */

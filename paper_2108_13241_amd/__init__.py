@@ -417,6 +417,24 @@ class Lattice3D:
         self._check(self._lib.lbm3d_macroscopic(self._ctx, *[_dptr(o) for o in out]))
         return tuple(out)
 
+    def macroscopic_device(self, rho, ux, uy, uz):
+        """Fields into device FP64 [nz, ny, nx] tensors (all four); asynchronous."""
+        n, d = 8 * self.nx * self.ny * self.nz, _f64t()
+        self._check(self._lib.lbm3d_macroscopic_device(
+            self._ctx, _dev(rho, n, "rho", d), _dev(ux, n, "ux", d), _dev(uy, n, "uy", d),
+            _dev(uz, n, "uz", d)))
+
+    def state_bytes(self):
+        b = ctypes.c_size_t()
+        self._check(self._lib.lbm3d_state_bytes(self._ctx, ctypes.byref(b)))
+        return b.value
+
+    def save_state(self, dst):
+        self._check(self._lib.lbm3d_save_state(self._ctx, _dev(dst, self.state_bytes(), "dst")))
+
+    def load_state(self, src):
+        self._check(self._lib.lbm3d_load_state(self._ctx, _dev(src, self.state_bytes(), "src")))
+
     def get_populations(self):
         f = np.zeros((19,) + self.shape)
         self._check(self._lib.lbm3d_get_populations(self._ctx, _dptr(f)))

@@ -386,6 +386,60 @@ int lbm3d_macroscopic(lbm3d_ctx *c, double *rho, double *ux, double *uy, double 
     return LBM_OK;
 }
 
+int lbm3d_macroscopic_device(lbm3d_ctx *c, void *rho, void *ux, void *uy, void *uz)
+{
+    LBM3_CHECK_CTX(c);
+    if (!rho || !ux || !uy || !uz)
+        return fail(c, LBM_ERR_INVALID, "the four device fields must all be given");
+    const size_t nn = field_nodes(c);
+    double *o[4] = {(double *)rho, (double *)ux, (double *)uy, (double *)uz};
+    for (double *p : o)
+        LBM3_HIP(c, lbm::launch_fill(p, nn, 0.0, c->s.stream));
+    LBM3_HIP(c, lbm3::launch_macro3(c->s, c->cur, o[0], o[1], o[2], o[3], nullptr));
+    return LBM_OK;
+}
+
+int lbm3d_state_bytes(const lbm3d_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes)
+        return fail_tl(LBM_ERR_INVALID, "NULL argument");
+    *bytes = (size_t)Q * padded_nodes(c) * c->pop_bytes;
+    return LBM_OK;
+}
+
+// The lattice that holds the state: f[cur] (A-B) or the single AA lattice.
+static void *state_lattice3(lbm3d_ctx *c) { return c->s.f[c->s.aa ? 0 : c->cur]; }
+
+int lbm3d_save_state(lbm3d_ctx *c, void *dev_dst)
+{
+    LBM3_CHECK_CTX(c);
+    if (!dev_dst)
+        return fail(c, LBM_ERR_INVALID, "destination is NULL");
+    if (c->s.fullway)
+        return fail(c, LBM_ERR_UNSUPPORTED,
+                    "raw state checkpoints hold one lattice; the full-way rule keeps state in both");
+    size_t b = 0;
+    lbm3d_state_bytes(c, &b);
+    LBM3_HIP(c, hipMemcpyAsync(dev_dst, state_lattice3(c), b, hipMemcpyDeviceToDevice,
+                               c->s.stream));
+    return LBM_OK;
+}
+
+int lbm3d_load_state(lbm3d_ctx *c, const void *dev_src)
+{
+    LBM3_CHECK_CTX(c);
+    if (!dev_src)
+        return fail(c, LBM_ERR_INVALID, "source is NULL");
+    if (c->s.fullway)
+        return fail(c, LBM_ERR_UNSUPPORTED,
+                    "raw state checkpoints hold one lattice; the full-way rule keeps state in both");
+    size_t b = 0;
+    lbm3d_state_bytes(c, &b);
+    LBM3_HIP(c, hipMemcpyAsync(state_lattice3(c), dev_src, b, hipMemcpyDeviceToDevice,
+                               c->s.stream));
+    return LBM_OK;
+}
+
 int lbm3d_get_populations(lbm3d_ctx *c, double *f)
 {
     LBM3_CHECK_CTX(c);

@@ -123,3 +123,42 @@ def test_aa_views_roundtrip_mass_and_errors(lbm, oracle_mod):
     assert np.array_equal(lat.get_populations()[:, m == 0], oracle_mod.init3(m)[:, m == 0])
     assert lat.info()["time_step"] == 0
     lat.close()
+
+
+@pytest.mark.parametrize("layout", ["dense_ab", "dense_aa"])
+def test_state_checkpoints_and_device_fields(lbm, layout):
+    """save_state / load_state reproduce a run bitwise (AA: loaded at a step count of the
+    same parity); macroscopic_device equals the host fields bitwise; full-way checkpoints
+    and missing device fields are refused; undersized buffers raise in the binding."""
+    import torch
+    announce(f"d3q19 checkpoints and device fields {layout}")
+    nx, ny, nz = 40, 12, 10
+    m = synthetic.random_mask3(nx, ny, nz, seed=51, solid_fraction=0.1, walls=True)
+    lat = lbm.Lattice3D(m, 0.75, force=(2e-5, 0.0, -1e-5), dtype="f32", layout=layout)
+    lat.init_equilibrium(*synthetic.random_fields3(nx, ny, nz, seed=52))
+    lat.step(5)
+    buf = torch.empty(lat.state_bytes(), dtype=torch.uint8, device="cuda")
+    lat.save_state(buf)
+    lat.step(6)
+    a = lat.get_populations()
+    lat.load_state(buf)
+    lat.step(6)
+    assert np.array_equal(lat.get_populations(), a)
+    host = lat.macroscopic()
+    dev = [torch.full((nz, ny, nx), 7.0, dtype=torch.float64, device="cuda") for _ in range(4)]
+    lat.macroscopic_device(*dev)
+    torch.cuda.synchronize()
+    for h, d in zip(host, dev):
+        assert np.array_equal(h, d.cpu().numpy())
+    with pytest.raises(ValueError, match="bytes"):
+        lat.save_state(buf[:-1])
+    with pytest.raises(lbm.LbmError) as e:
+        lat._check(lat._lib.lbm3d_macroscopic_device(lat._ctx, dev[0].data_ptr(), None, None,
+                                                     None))
+    assert e.value.status == -1
+    if layout == "dense_ab":
+        lat.set_bounce_back("fullway")
+        with pytest.raises(lbm.LbmError) as e:
+            lat.save_state(buf)
+        assert e.value.status == -4
+    lat.close()
