@@ -110,6 +110,11 @@ def lib():
         L.oracle3_run_trt.restype = ctypes.c_int
         L.oracle3_collide_trt.argtypes = [_dp] + [ctypes.c_double] * 5 + [_dp]
         L.oracle3_run_walls.argtypes = L.oracle3_run_trt.argtypes + [ctypes.c_int]
+        L.oracle3_mrt_matrix.argtypes = [_dp]
+        L.oracle3_collide_mrt.argtypes = [_dp] + [ctypes.c_double] * 3 + [_dp, _dp]
+        L.oracle3_run_mrt.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp, ctypes.c_double, _dp] + \
+            [ctypes.c_double] * 3 + [ctypes.c_long, ctypes.c_int, ctypes.c_int]
+        L.oracle3_run_mrt.restype = ctypes.c_int
         L.oracle3_run_walls.restype = ctypes.c_int
         L.oracle3_fullway_fill.argtypes = [ctypes.c_int] * 3 + [_u8p, _dp]
         L.oracle3_fullway_fill.restype = ctypes.c_int
@@ -430,15 +435,46 @@ def init3(mask, rho0=None, ux0=None, uy0=None, uz0=None):
     return f
 
 
-def run3(mask, f, tau, steps, g=(0.0, 0.0, 0.0), threads=0, tau_minus=None, fullway=False):
+def mrt_matrix3():
+    """The D3Q19 MRT moment matrix M [19, 19] (row order of oracle3_collide_mrt)."""
+    M = np.zeros((19, 19))
+    lib().oracle3_mrt_matrix(_d(M))
+    return M
+
+
+def collide3_mrt(f, rates, g=(0.0, 0.0, 0.0)):
+    """D3Q19 multiple-relaxation-time collision with the 19 moment rates `rates`."""
+    f = _f64(f)
+    r = np.ascontiguousarray(rates, dtype=np.float64)
+    if r.shape != (19,):
+        raise ValueError("rates must hold 19 values")
+    out = np.zeros(19)
+    lib().oracle3_collide_mrt(_d(f), g[0], g[1], g[2], _d(r), _d(out))
+    return out
+
+
+def run3(mask, f, tau, steps, g=(0.0, 0.0, 0.0), threads=0, tau_minus=None, fullway=False,
+         mrt=None):
     """Advance a copy of the D3Q19 state f by `steps` steps.  tau_minus: antisymmetric
-    relaxation time of the two-relaxation-time collision (None: BGK).  fullway: full-way
-    bounce-back (f includes the wall slots)."""
+    relaxation time of the two-relaxation-time collision (None: BGK).  mrt: (s_e, s_eps, s_q,
+    s_pi, s_m) selects the multiple-relaxation-time collision (shear rate 1 / tau).  fullway:
+    full-way bounce-back (f includes the wall slots)."""
     m = _mask3(mask)
     nz, ny, nx = m.shape
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     if f.shape != (19, nz, ny, nx):
         raise ValueError("f must be [19, nz, ny, nx]")
+    if mrt is not None:
+        if tau_minus is not None:
+            raise ValueError("tau_minus and mrt are exclusive")
+        r5 = np.ascontiguousarray(mrt, dtype=np.float64)
+        if r5.shape != (5,):
+            raise ValueError("mrt takes five rates (s_e, s_eps, s_q, s_pi, s_m)")
+        rc = lib().oracle3_run_mrt(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), tau, _d(r5), g[0],
+                                   g[1], g[2], int(steps), int(threads), int(bool(fullway)))
+        if rc:
+            raise ValueError(f"oracle3_run failed ({rc})")
+        return f
     tm = float(tau) if tau_minus is None else float(tau_minus)
     rc = lib().oracle3_run_walls(nx, ny, nz, m.ctypes.data_as(_u8p), _d(f), tau, tm, g[0], g[1],
                                  g[2], int(steps), int(threads), int(bool(fullway)))

@@ -6,7 +6,9 @@
  * Eq. 4 BGK; Eq. 6 equilibrium, which holds unchanged in 3D with the D3Q19
  * weights; Eq. 5 viscosity), and the two-relaxation-time collision of the
  * two-dimensional oracle (each population pair split into its symmetric and
- * antisymmetric parts, relaxed at omega_p and omega_m), and its full-way wall
+ * antisymmetric parts, relaxed at omega_p and omega_m), the multiple-relaxation-
+ * time collision in the D3Q19 moment basis of d'Humieres et al. (oracle3_collide_mrt),
+ * and its full-way wall
  * rule (solid nodes next to fluid hold populations, reverse them instead of
  * colliding and stream them back; the state then includes those wall slots,
  * and slots not fed by a fluid node hold 0).
@@ -150,6 +152,85 @@ void oracle3_collide_trt(const double *f, double gx, double gy, double gz, doubl
     }
 }
 
+/* Multiple-relaxation-time collision (a richer collision model beyond BGK; the
+ * D3Q19 moment basis of d'Humieres, Ginzburg, Krafczyk, Lallemand and Luo,
+ * 2002).  Nineteen moments m = M f, each row a polynomial of c = v_i:
+ *   0 rho: 1            1 e: 19|c|^2 - 30     2 eps: (21|c|^4 - 53|c|^2 + 24) / 2
+ *   3 j_x: c_x          4 q_x: (5|c|^2 - 9) c_x
+ *   5 j_y: c_y          6 q_y: (5|c|^2 - 9) c_y
+ *   7 j_z: c_z          8 q_z: (5|c|^2 - 9) c_z
+ *   9 3p_xx: 3c_x^2 - |c|^2      10 3pi_xx: (3|c|^2 - 5)(3c_x^2 - |c|^2)
+ *   11 p_ww: c_y^2 - c_z^2       12 pi_ww: (3|c|^2 - 5)(c_y^2 - c_z^2)
+ *   13 p_xy: c_x c_y   14 p_yz: c_y c_z   15 p_xz: c_x c_z
+ *   16 m_x: (c_y^2 - c_z^2) c_x  17 m_y: (c_z^2 - c_x^2) c_y  18 m_z: (c_x^2 - c_y^2) c_z
+ * The rows are orthogonal, so M^-1 = M^T diag(1 / |row_k|^2); as in the D2Q9
+ * oracle, every moment relaxes towards the moment of f^eq (Eq. 6) with its own
+ * rate and Guo's term enters with (1 - s_k / 2):
+ *   mstar_k = m_k - s_k (m_k - (M f^eq)_k) + (1 - s_k / 2) (M S)_k,  fstar = M^-1 mstar.
+ * All rates omega is BGK; omega+ on the even rows (0-2, 9-15) and omega- on the
+ * odd ones (3-8, 16-18) is TRT. */
+static double mrt3_row(int k, int i)
+{
+    double cx = CX3[i], cy = CY3[i], cz = CZ3[i], c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return cx;
+    case 4: return (5.0 * c2 - 9.0) * cx;
+    case 5: return cy;
+    case 6: return (5.0 * c2 - 9.0) * cy;
+    case 7: return cz;
+    case 8: return (5.0 * c2 - 9.0) * cz;
+    case 9: return 3.0 * cx * cx - c2;
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * cx * cx - c2);
+    case 11: return cy * cy - cz * cz;
+    case 12: return (3.0 * c2 - 5.0) * (cy * cy - cz * cz);
+    case 13: return cx * cy;
+    case 14: return cy * cz;
+    case 15: return cx * cz;
+    case 16: return (cy * cy - cz * cz) * cx;
+    case 17: return (cz * cz - cx * cx) * cy;
+    default: return (cx * cx - cy * cy) * cz;
+    }
+}
+
+void oracle3_mrt_matrix(double *M)
+{
+    for (int k = 0; k < Q3; ++k)
+        for (int i = 0; i < Q3; ++i)
+            M[k * Q3 + i] = mrt3_row(k, i);
+}
+
+void oracle3_collide_mrt(const double *f, double gx, double gy, double gz, const double *rates,
+                         double *fstar)
+{
+    double mo[4];
+    oracle3_node_velocity(f, gx, gy, gz, mo);
+    double feq[Q3], S[Q3], mstar[Q3];
+    oracle3_equilibrium(mo[0], mo[1], mo[2], mo[3], feq);
+    oracle3_guo_source(mo[1], mo[2], mo[3], mo[0] * gx, mo[0] * gy, mo[0] * gz, S);
+    for (int k = 0; k < Q3; ++k) {
+        double m = 0.0, meq = 0.0, ms = 0.0;
+        for (int i = 0; i < Q3; ++i) {
+            m += mrt3_row(k, i) * f[i];
+            meq += mrt3_row(k, i) * feq[i];
+            ms += mrt3_row(k, i) * S[i];
+        }
+        mstar[k] = m - rates[k] * (m - meq) + (1.0 - 0.5 * rates[k]) * ms;
+    }
+    for (int i = 0; i < Q3; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < Q3; ++k) {
+            double norm = 0.0;
+            for (int l = 0; l < Q3; ++l)
+                norm += mrt3_row(k, l) * mrt3_row(k, l);
+            v += mrt3_row(k, i) * mstar[k] / norm;
+        }
+        fstar[i] = v;
+    }
+}
+
 /* f_i = f^eq_i(rho0, u0) at fluid nodes; NULL fields mean rho0 = 1, u0 = 0. */
 int oracle3_init(int nx, int ny, int nz, const uint8_t *mask, const double *rho0,
                  const double *ux0, const double *uy0, const double *uz0, double *f)
@@ -174,7 +255,7 @@ int oracle3_init(int nx, int ny, int nz, const uint8_t *mask, const double *rho0
  * non-NULL (full-way rule) every wall node reverses its populations. */
 static void collide_phase3(int nx, int ny, int nz, const uint8_t *mask, const uint8_t *wall,
                            const double *f, double *post, double omega, double omega_m,
-                           double gx, double gy, double gz)
+                           const double *mrt, double gx, double gy, double gz)
 {
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
@@ -191,7 +272,9 @@ static void collide_phase3(int nx, int ny, int nz, const uint8_t *mask, const ui
                 double fl[Q3], fs[Q3];
                 for (int i = 0; i < Q3; ++i)
                     fl[i] = f[slot3(i, x, y, z, nx, ny, nz)];
-                if (omega_m == omega)
+                if (mrt)
+                    oracle3_collide_mrt(fl, gx, gy, gz, mrt, fs);
+                else if (omega_m == omega)
                     oracle3_collide(fl, gx, gy, gz, omega, fs);
                 else
                     oracle3_collide_trt(fl, gx, gy, gz, omega, omega_m, fs);
@@ -302,9 +385,9 @@ int oracle3_fullway_fill(int nx, int ny, int nz, const uint8_t *mask, double *f)
 /* nsteps steps in place; tau_m is the antisymmetric relaxation time of the
  * two-relaxation-time collision (tau_m = tau: BGK); fullway selects the
  * full-way wall rule. */
-int oracle3_run_walls(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
-                      double tau_m, double gx, double gy, double gz, long nsteps, int nthreads,
-                      int fullway)
+static int run_general3(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
+                        double tau_m, const double *mrt, double gx, double gy, double gz,
+                        long nsteps, int nthreads, int fullway)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !(tau > 0.5) || !(tau_m > 0.5) || nsteps < 0)
         return -1;
@@ -326,7 +409,7 @@ int oracle3_run_walls(int nx, int ny, int nz, const uint8_t *mask, double *f, do
         find_walls3(nx, ny, nz, mask, wall);
     double omega = 1.0 / tau, omega_m = tau_m == tau ? omega : 1.0 / tau_m;
     for (long s = 0; s < nsteps; ++s) {
-        collide_phase3(nx, ny, nz, mask, wall, f, post, omega, omega_m, gx, gy, gz);
+        collide_phase3(nx, ny, nz, mask, wall, f, post, omega, omega_m, mrt, gx, gy, gz);
         if (wall)
             stream_fullway3(nx, ny, nz, mask, wall, f, post);
         else
@@ -335,6 +418,31 @@ int oracle3_run_walls(int nx, int ny, int nz, const uint8_t *mask, double *f, do
     free(post);
     free(wall);
     return 0;
+}
+
+int oracle3_run_walls(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
+                      double tau_m, double gx, double gy, double gz, long nsteps, int nthreads,
+                      int fullway)
+{
+    return run_general3(nx, ny, nz, mask, f, tau, tau_m, NULL, gx, gy, gz, nsteps, nthreads,
+                        fullway);
+}
+
+/* As oracle3_run_walls with the multiple-relaxation-time collision: the shear
+ * moments (3p_xx, p_ww, p_xy, p_yz, p_xz) relax with omega = 1/tau, e with s_e,
+ * eps with s_eps, q with s_q, the pi moments with s_pi, the m moments with s_m;
+ * rho and j with 1. */
+int oracle3_run_mrt(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
+                    const double *r5, double gx, double gy, double gz, long nsteps, int nthreads,
+                    int fullway)
+{
+    if (!(tau > 0.5) || !r5)
+        return -1;
+    double w = 1.0 / tau;
+    double rates[Q3] = {1.0, r5[0], r5[1], 1.0, r5[2], 1.0, r5[2], 1.0, r5[2], w,
+                        r5[3], w,   r5[3], w,   w,     w,   r5[4], r5[4], r5[4]};
+    return run_general3(nx, ny, nz, mask, f, tau, tau, rates, gx, gy, gz, nsteps, nthreads,
+                        fullway);
 }
 
 int oracle3_run_trt(int nx, int ny, int nz, const uint8_t *mask, double *f, double tau,
