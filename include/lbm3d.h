@@ -106,6 +106,20 @@ int lbm3d_set_force(lbm3d_ctx *ctx, const double *force);
  * or not finite): LBM_ERR_INVALID. */
 int lbm3d_set_trt(lbm3d_ctx *ctx, double magic);
 
+/* Multiple-relaxation-time collision in the D3Q19 moment basis of d'Humieres,
+ * Ginzburg, Krafczyk, Lallemand and Luo (2002): nineteen orthogonal moments
+ * (rho; energy e; energy square eps; momentum j; energy flux q; the shear
+ * moments 3p_xx, p_ww, p_xy, p_yz, p_xz; the fourth-order pi_xx, pi_ww; the
+ * third-order m), each relaxing towards the moment of f^eq (Eq. 6) at its own
+ * rate, with Guo's forcing in moment space (factor 1 - s / 2):
+ *   rates  host double[5] = (s_e, s_eps, s_q, s_pi, s_m), each in (0, 2); the
+ *          shear moments relax with omega = 1 / tau (Eq. 5), rho and j are
+ *          conserved (j gains the force).  NULL switches MRT off (BGK).
+ * All rates omega is BGK; s_e = s_eps = s_pi = omega and s_q = s_m =
+ * 1 / (1/2 + magic / (tau - 1/2)) is the TRT collision.  MRT and TRT exclude
+ * each other (the last call wins).  Invalid rates: LBM_ERR_INVALID. */
+int lbm3d_set_mrt(lbm3d_ctx *ctx, const double *rates);
+
 /* Wall rule, as lbm_set_bounce_back: 0 halfway (the default), 1 full-way (solid
  * nodes next to fluid hold the populations streamed into them, reverse them in
  * the next step and stream them back).  Under mode 1 the canonical state also

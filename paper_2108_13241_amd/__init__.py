@@ -403,6 +403,17 @@ class Lattice3D:
         """Two-relaxation-time collision with parameter Lambda = magic (0 = BGK)."""
         self._check(self._lib.lbm3d_set_trt(self._ctx, float(magic)))
 
+    def set_mrt(self, rates):
+        """Multiple-relaxation-time collision with rates (s_e, s_eps, s_q, s_pi, s_m) (the
+        shear moments relax with 1 / tau); None switches it off (BGK)."""
+        if rates is None:
+            self._check(self._lib.lbm3d_set_mrt(self._ctx, None))
+            return
+        r = np.ascontiguousarray(rates, dtype=np.float64)
+        if r.shape != (5,):
+            raise ValueError("D3Q19 MRT takes five rates (s_e, s_eps, s_q, s_pi, s_m)")
+        self._check(self._lib.lbm3d_set_mrt(self._ctx, r.ctypes.data))
+
     def set_bounce_back(self, mode):
         """"halfway" (default) or "fullway" wall rule (0 / 1); under full-way the canonical
         populations include the wall slots of solid nodes next to fluid."""

@@ -92,6 +92,7 @@ SIGNATURES = {
     "lbm3d_create": (_c.c_int, [_c.POINTER(_vp), _i32, _i32, _i32, _c.POINTER(_c.c_uint8),
                                 _c.c_double, _dp, _c.c_int, _c.c_int]),
     "lbm3d_set_stream": (_c.c_int, [_vp, _vp]),
+    "lbm3d_set_mrt": (_c.c_int, [_vp, _vp]),
     "lbm3d_macroscopic_device": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm3d_state_bytes": (_c.c_int, [_vp, _c.POINTER(_c.c_size_t)]),
     "lbm3d_save_state": (_c.c_int, [_vp, _vp]),

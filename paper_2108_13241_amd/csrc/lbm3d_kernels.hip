@@ -100,9 +100,57 @@ __device__ __forceinline__ R pair_dot(int k, R vx, R vy, R vz)
 // TRT: the pair's symmetric part P = (f_i + f_opp)/2 relaxes with omega and its
 // antisymmetric part M = (f_i - f_opp)/2 with omega_m (forcing split alike);
 // f_i = P + M, f_opp = P - M.
-template <class R, bool SHIFT, bool FORCE, bool TRT = false>
-__device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz, R omega_m = R(0))
+// MRT: multiple-relaxation-time collision in the D3Q19 moment basis of
+// d'Humieres et al. (rows, as polynomials of c: rho 1; e 19|c|^2 - 30;
+// eps (21|c|^4 - 53|c|^2 + 24)/2; j c; q (5|c|^2 - 9) c; 3p_xx 3c_x^2 - |c|^2;
+// 3pi_xx (3|c|^2 - 5)(3c_x^2 - |c|^2); p_ww c_y^2 - c_z^2; pi_ww (3|c|^2 - 5)
+// (c_y^2 - c_z^2); p_xy, p_yz, p_xz; m_x (c_y^2 - c_z^2) c_x, m_y (c_z^2 - c_x^2)
+// c_y, m_z (c_x^2 - c_y^2) c_z; orthogonal, squared norms kMrt3Norm).  The
+// moments of d = f - f^eq and of the forcing term relax as
+//   Delta_k = s_k d_k - (1 - s_k / 2) S_k,  f_i <- f_i - sum_k M_ki Delta_k / |M_k|^2,
+// with s_e, s_eps, s_q, s_pi, s_m and omega on the shear moments (3p_xx, p_ww,
+// p_xy, p_yz, p_xz); Delta_rho = 0 and Delta_j = -F (the conserved moments).
+template <class R>
+struct Rates3 {
+    R omega_m;                         // TRT: antisymmetric rate
+    R s_e, s_eps, s_q, s_pi, s_m;      // MRT
+};
+
+// Row k of the D3Q19 MRT matrix at direction i (small integers); with the
+// loops unrolled every coefficient folds to a constant.
+__device__ __forceinline__ constexpr int mrt3_coef(int k, int i)
 {
+    const int cx = kCx[i], cy = kCy[i], cz = kCz[i], c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+    case 0: return 1;
+    case 1: return 19 * c2 - 30;
+    case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+    case 3: return cx;
+    case 4: return (5 * c2 - 9) * cx;
+    case 5: return cy;
+    case 6: return (5 * c2 - 9) * cy;
+    case 7: return cz;
+    case 8: return (5 * c2 - 9) * cz;
+    case 9: return 3 * cx * cx - c2;
+    case 10: return (3 * c2 - 5) * (3 * cx * cx - c2);
+    case 11: return cy * cy - cz * cz;
+    case 12: return (3 * c2 - 5) * (cy * cy - cz * cz);
+    case 13: return cx * cy;
+    case 14: return cy * cz;
+    case 15: return cx * cz;
+    case 16: return (cy * cy - cz * cz) * cx;
+    case 17: return (cz * cz - cx * cx) * cy;
+    default: return (cx * cx - cy * cy) * cz;
+    }
+}
+__device__ constexpr int kMrt3Norm[Q] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36,
+                                         72, 12,   24,  4,  4,  4,  8,  8,  8};
+
+template <class R, bool SHIFT, bool FORCE, bool TRT = false, bool MRT = false>
+__device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz,
+                                         const Rates3<R> &rt = Rates3<R>{})
+{
+    const R omega_m = rt.omega_m;
     R sum = f[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i)
@@ -146,6 +194,83 @@ __device__ __forceinline__ void collide3(R (&f)[Q], R omega, R gx, R gy, R gz, R
     const R C0 = SHIFT ? sum - rho_times(usq) : rho_times(R(1) - usq);
     const R keep = R(1) - omega, guo = R(1) - R(0.5) * omega;
     const R uF = ux * Fx + uy * Fy + uz * Fz;
+    if constexpr (MRT) {
+        R d[Q], sg[Q];
+        d[0] = f[0] - R(kW[0]) * C0;
+        sg[0] = FORCE ? R(kW[0]) * (R(-3) * uF) : R(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int i = 2 * k + 1, j = i + 1;
+            const R w = R(kW[i]);
+            const R cu = pair_dot(k, ux, uy, uz);
+            const R even = w * (C0 + rho_times(R(4.5) * (cu * cu)));
+            const R odd = w * rho_times(R(3) * cu);
+            d[i] = f[i] - (even + odd);
+            d[j] = f[j] - (even - odd);
+            if constexpr (FORCE) {
+                const R cF = pair_dot(k, Fx, Fy, Fz);
+                const R se = w * (R(9) * cu * cF - R(3) * uF);
+                const R so = R(3) * w * cF;
+                sg[i] = se + so;
+                sg[j] = se - so;
+            } else {
+                sg[i] = sg[j] = R(0);
+            }
+        }
+        // Delta_k / |M_k|^2 for every row (conserved rows set directly)
+        R del[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            if (k == 0) {
+                del[k] = R(0);
+                continue;
+            }
+            if (k == 3 || k == 5 || k == 7) {
+                const R Fk = k == 3 ? Fx : k == 5 ? Fy : Fz;
+                del[k] = FORCE ? -Fk * R(1.0 / kMrt3Norm[k]) : R(0);
+                continue;
+            }
+            R dk = R(0), sk = R(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int c = mrt3_coef(k, i);
+                if (c == 1) {
+                    dk += d[i];
+                    if constexpr (FORCE) sk += sg[i];
+                } else if (c == -1) {
+                    dk -= d[i];
+                    if constexpr (FORCE) sk -= sg[i];
+                } else if (c != 0) {
+                    dk += R(c) * d[i];
+                    if constexpr (FORCE) sk += R(c) * sg[i];
+                }
+            }
+            const R sr = k == 1 ? rt.s_e : k == 2 ? rt.s_eps
+                       : (k == 4 || k == 6 || k == 8) ? rt.s_q
+                       : (k == 10 || k == 12) ? rt.s_pi
+                       : (k >= 16) ? rt.s_m : omega;
+            R dl = sr * dk;
+            if constexpr (FORCE)
+                dl -= (R(1) - R(0.5) * sr) * sk;
+            del[k] = dl * R(1.0 / kMrt3Norm[k]);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            R acc = R(0);
+#pragma unroll
+            for (int k = 1; k < Q; ++k) {
+                const int c = mrt3_coef(k, i);
+                if (c == 1)
+                    acc += del[k];
+                else if (c == -1)
+                    acc -= del[k];
+                else if (c != 0)
+                    acc += R(c) * del[k];
+            }
+            f[i] -= acc;
+        }
+        return;
+    }
     {
         R s = keep * f[0] + omega * (R(kW[0]) * C0);
         if constexpr (FORCE)
@@ -259,13 +384,13 @@ __device__ __forceinline__ uint32_t solid_bits3(uint8_t t, const uint32_t *__res
     return t == kBoundary ? nmask[n] << 1 : 0u;
 }
 
-template <class ST, bool FORCE, bool TRT>
+template <class ST, bool FORCE, bool TRT, bool MRT>
 __global__ __launch_bounds__(kBlock) void k_step3(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask,
     const uint32_t *__restrict__ seg_interior, int nx, int ny, int nz, int pitch, uint32_t bpr,
     uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real gz, typename ST::real omega_m, int fullway)
+    typename ST::real gz, Rates3<typename ST::real> rt, int fullway)
 {
     using R = typename ST::real;
     const uint32_t L = xcd_remap(blockIdx.x, nblocks);
@@ -285,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_step3(
     const Addr a = addr_of(x, y, z, nx, ny, nz, (uint32_t)pitch / kChunk);
     R f[Q];
     pull3<ST>(src, fullway ? dst : src, a, sm, f);
-    collide3<R, ST::kShift, FORCE, TRT>(f, omega, gx, gy, gz, omega_m);
+    collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         store_nt(&elem(dst, a, i, 1, 1, 1), ST::st(f[i], i));
@@ -323,12 +448,12 @@ __device__ __forceinline__ void local3(const typename ST::mem *s, const Addr &a,
         f[i] = ST::ld(elem(sp, a, i, 1, 1, 1), i);
 }
 
-template <class ST, bool FORCE, bool TRT, bool ODD>
+template <class ST, bool FORCE, bool TRT, bool MRT, bool ODD>
 __global__ __launch_bounds__(kBlock) void k_step3_aa(
     typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
     const uint32_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior, int nx, int ny,
     int nz, int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega,
-    typename ST::real gx, typename ST::real gy, typename ST::real gz, typename ST::real omega_m)
+    typename ST::real gx, typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt)
 {
     using R = typename ST::real;
     const uint32_t L = xcd_remap(blockIdx.x, nblocks);
@@ -351,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_step3_aa(
         aa_odd3<ST>(A, a, sm, f);
     else
         local3<ST>(A, a, f);
-    collide3<R, ST::kShift, FORCE, TRT>(f, omega, gx, gy, gz, omega_m);
+    collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
     if constexpr (ODD) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
@@ -608,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_rest3(typename ST::mem *p, uint64_t 
     }
 }
 
-template <class ST, bool TRT>
+template <class ST, bool TRT, bool MRT>
 void step_launch3(const State3 &s, int cur)
 {
     using M = typename ST::mem;
@@ -616,39 +741,45 @@ void step_launch3(const State3 &s, int cur)
     const uint32_t bpr = (uint32_t)((s.nx + kBlock - 1) / kBlock);
     const uint32_t nb = bpr * (uint32_t)s.ny * (uint32_t)s.nz;
     const bool force = s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0;
+    const R g[3] = {force ? (R)s.gx : R(0), force ? (R)s.gy : R(0), force ? (R)s.gz : R(0)};
+    const Rates3<R> rt{(R)s.omega_m, (R)s.s_e, (R)s.s_eps, (R)s.s_q, (R)s.s_pi, (R)s.s_m};
     if (s.aa) {
         M *A = (M *)s.f[0];
-        const R g[3] = {force ? (R)s.gx : R(0), force ? (R)s.gy : R(0), force ? (R)s.gz : R(0)};
         auto go = [&](auto kernel) {
             kernel<<<nb, kBlock, 0, s.stream>>>(A, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
                                                 s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1],
-                                                g[2], (R)s.omega_m);
+                                                g[2], rt);
         };
         if (force)
-            cur ? go(k_step3_aa<ST, true, TRT, true>) : go(k_step3_aa<ST, true, TRT, false>);
+            cur ? go(k_step3_aa<ST, true, TRT, MRT, true>)
+                : go(k_step3_aa<ST, true, TRT, MRT, false>);
         else
-            cur ? go(k_step3_aa<ST, false, TRT, true>) : go(k_step3_aa<ST, false, TRT, false>);
+            cur ? go(k_step3_aa<ST, false, TRT, MRT, true>)
+                : go(k_step3_aa<ST, false, TRT, MRT, false>);
         return;
     }
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
+    auto go = [&](auto kernel) {
+        kernel<<<nb, kBlock, 0, s.stream>>>(src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
+                                            s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1], g[2],
+                                            rt, s.fullway);
+    };
     if (force)
-        k_step3<ST, true, TRT><<<nb, kBlock, 0, s.stream>>>(
-            src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
-            (R)s.omega, (R)s.gx, (R)s.gy, (R)s.gz, (R)s.omega_m, s.fullway);
+        go(k_step3<ST, true, TRT, MRT>);
     else
-        k_step3<ST, false, TRT><<<nb, kBlock, 0, s.stream>>>(
-            src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny, s.nz, s.pitch, bpr, nb,
-            (R)s.omega, R(0), R(0), R(0), (R)s.omega_m, s.fullway);
+        go(k_step3<ST, false, TRT, MRT>);
 }
 
 template <class ST>
 hipError_t step_typed(const State3 &s, int cur)
 {
-    if (s.trt)
-        step_launch3<ST, true>(s, cur);
+    if (s.mrt)
+        step_launch3<ST, false, true>(s, cur);
+    else if (s.trt)
+        step_launch3<ST, true, false>(s, cur);
     else
-        step_launch3<ST, false>(s, cur);
+        step_launch3<ST, false, false>(s, cur);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ struct State3 {
     double omega = 1.0, gx = 0.0, gy = 0.0, gz = 0.0;
     int trt = 0;                             // 1: two-relaxation-time collision
     double omega_m = 1.0;                    // its antisymmetric relaxation rate
+    int mrt = 0;                             // 1: multiple-relaxation-time collision
+    double s_e = 1.0, s_eps = 1.0, s_q = 1.0, s_pi = 1.0, s_m = 1.0;  // its rates
     int fullway = 0;                         // 1: full-way bounce-back
     hipStream_t stream = nullptr;
     double *red = nullptr;                   // reduction scratch (reduction_capacity3 doubles)

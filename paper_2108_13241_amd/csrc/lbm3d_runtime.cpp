@@ -327,7 +327,30 @@ int lbm3d_set_trt(lbm3d_ctx *c, double magic)
     }
     const double tau = 1.0 / s.omega;
     s.trt = 1;
+    s.mrt = 0;
     s.omega_m = 1.0 / (0.5 + magic / (tau - 0.5));
+    return LBM_OK;
+}
+
+int lbm3d_set_mrt(lbm3d_ctx *c, const double *rates)
+{
+    LBM3_CHECK_CTX(c);
+    lbm3::State3 &s = c->s;
+    if (!rates) {
+        s.mrt = 0;
+        return LBM_OK;
+    }
+    for (int k = 0; k < 5; ++k)
+        if (!(std::isfinite(rates[k]) && rates[k] > 0.0 && rates[k] < 2.0))
+            return fail(c, LBM_ERR_INVALID, "MRT rates must lie in (0, 2)");
+    s.mrt = 1;
+    s.trt = 0;
+    s.omega_m = s.omega;
+    s.s_e = rates[0];
+    s.s_eps = rates[1];
+    s.s_q = rates[2];
+    s.s_pi = rates[3];
+    s.s_m = rates[4];
     return LBM_OK;
 }
 
