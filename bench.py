@@ -219,6 +219,21 @@ def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask, wall="halfwa
     return out
 
 
+def measure_porous3(lbm, n, phi, dtype, layout, steps, warmup, mask):
+    """D3Q19 sphere packing (walls in z, body force along x): dense A-B (solid nodes skipped)
+    against the fluid-node list, GLUPS per fluid node."""
+    lat = lbm.Lattice3D(mask, 0.6, force=(1e-6, 0.0, 0.0), dtype=dtype, layout=layout)
+    secs, ms = time_steps(lat, steps, warmup)
+    info = lat.info()
+    lat.close()
+    nf = info["n_fluid"]
+    glups = nf * steps / secs / 1e9
+    bpn = info["bytes_per_fluid_node"]
+    return {"workload": f"d3q19 sphere packing {n}^3 phi={phi}", "dtype": dtype,
+            "layout": layout, "n_fluid": nf, "glups_per_fluid_node": glups, "ms_per_step": ms,
+            "bytes_per_fluid_node": bpn, "frac_of_peak": glups * bpn / HBM_PEAK_GBPS}
+
+
 def measure_open_channel(lbm, inlet, dtype, layout, steps, warmup, nx=4096, ny=512):
     """The paper's channel cases (Sec. 4.1): chan_v (inlet u = 0.1) or chan_p (inlet
     rho = 1.016, initial 1.008), outlet rho = 1, bounce-back walls, nu = 0.25 (tau = 1.25)."""
@@ -591,6 +606,16 @@ def main():
                 f"({r['frac_of_peak']:.3f})")
             variants.append(r)
     if args.suite == "full":
+        for phi in (0.7, 0.4):
+            m3 = synthetic.random_spheres3(256, phi)
+            for dtype in ("f32", "f64"):
+                for layout in ("dense_ab", "indirect"):
+                    r = measure_porous3(lbm, 256, phi, dtype, layout, args.steps // 2,
+                                        args.warmup, m3)
+                    log(f"[bench]   d3q19 spheres 256^3 phi={phi} {dtype} {layout}: "
+                        f"{r['glups_per_fluid_node']:.2f} GLUPS per fluid node "
+                        f"({r['frac_of_peak']:.3f})")
+                    variants.append(r)
         for nn in (1024, 2048):
             f2 = synthetic.taylor_green(nn, 0.01)
             for dtype in ("f64", "f32"):

@@ -11,7 +11,10 @@
  * layouts, as lbm.h's dense ones: DENSE_AB, two dense lattices swapped every
  * step, and DENSE_AA, one dense lattice updated in place with the AA access
  * pattern (even steps read and write each node's own slots, odd steps read from
- * and write to the neighbours; half the memory).
+ * and write to the neighbours; half the memory); and INDIRECT, the sparse
+ * layout: two lattices holding the fluid nodes only (row-major order) with a
+ * per-node table of the 18 pull sources (the fluid-index-array approach of
+ * lbm.h's INDIRECT, Sec. 1).
  *
  * Conventions (as in lbm.h, whose status codes, dtype enum and allocator hook
  * this interface shares)
@@ -60,7 +63,8 @@ typedef struct {
     int64_t time_step;           /* steps since the last (re)initialisation */
     int32_t pop_bytes;           /* bytes per stored population: 8, 4 or 2 */
     double bytes_per_fluid_node; /* algorithmic bytes per fluid node per step:
-                                    38 * pop_bytes + 1 (node type) */
+                                    38 * pop_bytes + 1 (node type; INDIRECT:
+                                    + 72, the 18 pull sources) */
     size_t device_bytes;         /* device memory held by the context */
 } lbm3d_info_t;
 
@@ -78,8 +82,11 @@ typedef struct {
  *  force       host double[3] body-force acceleration (g_x, g_y, g_z); NULL = 0.
  *              Force density F = rho g through Guo's forcing term.
  *  dtype       storage type (see above).
- *  layout      LBM_DENSE_AB or LBM_DENSE_AA (one lattice: 19 * pop_bytes per
- *              node, half of DENSE_AB); the other layouts are UNSUPPORTED.
+ *  layout      LBM_DENSE_AB, LBM_DENSE_AA (one lattice: 19 * pop_bytes per
+ *              node, half of DENSE_AB) or LBM_INDIRECT (fluid nodes only:
+ *              38 * pop_bytes + 84 bytes per fluid node: two lattices, the
+ *              source table and the coordinates); the tiled layouts are
+ *              UNSUPPORTED.
  * Errors: INVALID (sizes, tau, force, mask values, dtype, layout), UNSUPPORTED
  * (size limit, sparse layout), NOMEM, DEVICE. */
 int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint8_t *node_type,
@@ -130,7 +137,7 @@ int lbm3d_set_mrt(lbm3d_ctx *ctx, const double *rates);
  * w - c_j.  The fluid populations are kept across a switch.  No extra memory
  * (the A-B pair holds the state).  Invalid mode: LBM_ERR_INVALID; mode 1 on a
  * DENSE_AA lattice: LBM_ERR_UNSUPPORTED (in place, no lattice holds the values
- * of two steps back).  Synchronises the stream. */
+ * of two steps back), likewise on INDIRECT.  Synchronises the stream. */
 int lbm3d_set_bounce_back(lbm3d_ctx *ctx, int32_t mode);
 
 /* Enqueue n >= 0 time steps (one kernel launch each). */

@@ -490,6 +490,47 @@ __global__ __launch_bounds__(kBlock) void k_step3_aa(
     }
 }
 
+// INDIRECT (node list): element of direction i of list node n in the chunked
+// list layout [np/64][19][64].
+__device__ __forceinline__ uint64_t lelem(uint32_t n, int i)
+{
+    return (uint64_t)(n >> 6) * (Q * kChunk) + (uint64_t)i * kChunk + (n & 63u);
+}
+
+// Pull gather of list node n: f_i = s_i(source), or the node's own slot opp(i)
+// when the source is solid (halfway bounce-back).
+template <class ST>
+__device__ __forceinline__ void pull_list(const typename ST::mem *__restrict__ s,
+                                          const int32_t *__restrict__ nbr, uint64_t np,
+                                          uint32_t n, typename ST::real (&f)[Q])
+{
+    f[0] = ST::ld(s[lelem(n, 0)], 0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int32_t src = nbr[(uint64_t)(i - 1) * np + n];
+        f[i] = ST::ld(src >= 0 ? s[lelem((uint32_t)src, i)] : s[lelem(n, kOpp[i])], i);
+    }
+}
+
+template <class ST, bool FORCE, bool TRT, bool MRT>
+__global__ __launch_bounds__(kBlock) void k_step3_list(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
+    const int32_t *__restrict__ nbr, uint64_t np, uint32_t n_fluid, uint32_t nblocks,
+    typename ST::real omega, typename ST::real gx, typename ST::real gy, typename ST::real gz,
+    Rates3<typename ST::real> rt)
+{
+    using R = typename ST::real;
+    const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
+    if (n >= n_fluid)
+        return;
+    R f[Q];
+    pull_list<ST>(src, nbr, np, n, f);
+    collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        store_nt(&dst[lelem(n, i)], ST::st(f[i], i));
+}
+
 // ------------------------------------------------------------ canonical views --
 // Canonical FP64 buffers are [19][nz][ny][pitch].
 
@@ -509,6 +550,19 @@ __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST:
                                              uint32_t &wl, double (&wv)[Q])
 {
     wl = 0;
+    if (s.list) {  // gid = list index
+        if (gid >= (uint64_t)s.n_fluid)
+            return false;
+        x = s.fxyz[3 * (uint64_t)gid];
+        y = s.fxyz[3 * (uint64_t)gid + 1];
+        z = s.fxyz[3 * (uint64_t)gid + 2];
+        typename ST::real f[Q];
+        pull_list<ST>(st, s.nbr, (uint64_t)s.np, gid, f);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            fd[i] = ST::canon(f[i], i);
+        return true;
+    }
     const uint32_t r = gid / (uint32_t)s.pitch;
     x = (int)(gid - r * (uint32_t)s.pitch);
     if (x >= s.nx || r >= (uint32_t)(s.ny * s.nz))
@@ -562,9 +616,10 @@ __global__ __launch_bounds__(kBlock) void k_gather3(State3 s, const typename ST:
     if (!canonical_at<ST>(s, st, bb, mode, gid, x, y, z, f, wl, wv))
         return;
     const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+    const uint64_t o = ((uint64_t)z * s.ny + y) * (uint32_t)s.pitch + x;  // gid unless a list
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        fc[(uint64_t)i * plane + gid] = f[i];
+        fc[(uint64_t)i * plane + o] = f[i];
     // wall slots (full-way rule): each has exactly one fluid source node
     for (int j = 1; j < Q; ++j)
         if ((wl >> j) & 1u)
@@ -682,6 +737,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
                                                      const double *__restrict__ fc)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    if (s.list) {  // INDIRECT: gid = list index; s_j(q) = f_j(q + c_j), or f_opp(j)(q)
+        if (gid >= (uint64_t)s.n_fluid)
+            return;
+        const int x = s.fxyz[3 * (uint64_t)gid], y = s.fxyz[3 * (uint64_t)gid + 1],
+                  z = s.fxyz[3 * (uint64_t)gid + 2];
+        const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+        const uint64_t own = ((uint64_t)z * s.ny + y) * (uint32_t)s.pitch + x;
+        for (int j = 0; j < Q; ++j) {
+            // q + c_j is the pull source of direction opp(j)
+            const bool fluid = j == 0 || s.nbr[(uint64_t)(kOpp[j] - 1) * s.np + gid] >= 0;
+            const double v = fluid ? fc[(uint64_t)j * plane + node_plus(s, x, y, z, j)]
+                                   : fc[(uint64_t)kOpp[j] * plane + own];
+            st[lelem(gid, j)] = ST::from_canon(v, j);
+        }
+        return;
+    }
     const uint32_t r = gid / (uint32_t)s.pitch;
     const int x = (int)(gid - r * (uint32_t)s.pitch);
     if (x >= s.nx || r >= (uint32_t)(s.ny * s.nz))
@@ -743,6 +814,23 @@ void step_launch3(const State3 &s, int cur)
     const bool force = s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0;
     const R g[3] = {force ? (R)s.gx : R(0), force ? (R)s.gy : R(0), force ? (R)s.gz : R(0)};
     const Rates3<R> rt{(R)s.omega_m, (R)s.s_e, (R)s.s_eps, (R)s.s_q, (R)s.s_pi, (R)s.s_m};
+    if (s.list) {
+        const uint32_t nbl = (uint32_t)((s.n_fluid + kBlock - 1) / kBlock);
+        if (nbl == 0)
+            return;
+        const M *src = (const M *)s.f[cur];
+        M *dst = (M *)s.f[1 - cur];
+        auto go = [&](auto kernel) {
+            kernel<<<nbl, kBlock, 0, s.stream>>>(src, dst, s.nbr, (uint64_t)s.np,
+                                                 (uint32_t)s.n_fluid, nbl, (R)s.omega, g[0], g[1],
+                                                 g[2], rt);
+        };
+        if (force)
+            go(k_step3_list<ST, true, TRT, MRT>);
+        else
+            go(k_step3_list<ST, false, TRT, MRT>);
+        return;
+    }
     if (s.aa) {
         M *A = (M *)s.f[0];
         auto go = [&](auto kernel) {
@@ -788,9 +876,18 @@ int view_mode(const State3 &s, int cur)
     return s.aa ? (cur ? kAAOdd3 : kAAEven3) : kPull3;
 }
 
-uint32_t node_blocks(const State3 &s)
+uint32_t dense_blocks(const State3 &s)
 {
     return (uint32_t)(((int64_t)s.nz * s.ny * s.pitch + kBlock - 1) / kBlock);
+}
+
+// Blocks of a per-node view kernel: every padded node (dense layouts) or every
+// list node (INDIRECT); 0 for an empty list.
+uint32_t node_blocks(const State3 &s)
+{
+    if (s.list)
+        return (uint32_t)((s.n_fluid + kBlock - 1) / kBlock);
+    return dense_blocks(s);
 }
 
 }  // namespace
@@ -809,7 +906,7 @@ hipError_t launch_step3(const State3 &s, int cur)
 hipError_t launch_equilibrium3(const State3 &s, const double *rho, const double *ux,
                                const double *uy, const double *uz, double *fc)
 {
-    k_equilibrium3<<<node_blocks(s), kBlock, 0, s.stream>>>(s, rho, ux, uy, uz, fc);
+    k_equilibrium3<<<dense_blocks(s), kBlock, 0, s.stream>>>(s, rho, ux, uy, uz, fc);
     return hipGetLastError();
 }
 
@@ -830,6 +927,8 @@ hipError_t by_dtype(int dtype, Fn fn)
 hipError_t launch_scatter3(const State3 &s, int cur, const double *fc, int fill_walls)
 {
     const uint32_t nb = node_blocks(s);
+    if (nb == 0)
+        return hipSuccess;
     const int walls = s.fullway ? (fill_walls ? 2 : 1) : 0;
     return by_dtype(s.dtype, [&](auto st) {
         using M = typename decltype(st)::mem;
@@ -844,7 +943,7 @@ hipError_t launch_scatter3(const State3 &s, int cur, const double *fc, int fill_
 
 hipError_t launch_rest3(const State3 &s, void *lattice)
 {
-    const uint64_t n = (uint64_t)Q * s.nz * s.ny * s.pitch;
+    const uint64_t n = (uint64_t)Q * (s.list ? (uint64_t)s.np : (uint64_t)s.nz * s.ny * s.pitch);
     uint64_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 65536)
         blocks = 65536;
@@ -857,6 +956,8 @@ hipError_t launch_rest3(const State3 &s, void *lattice)
 hipError_t launch_gather3(const State3 &s, int cur, double *fc)
 {
     const uint32_t nb = node_blocks(s);
+    if (nb == 0)
+        return hipSuccess;
     return by_dtype(s.dtype, [&](auto st) {
         using M = typename decltype(st)::mem;
         const M *src = (const M *)s.f[s.aa ? 0 : cur];
@@ -875,6 +976,11 @@ hipError_t launch_macro3(const State3 &s, int cur, double *rho, double *ux, doub
                          double *mass)
 {
     const uint32_t nb = node_blocks(s);
+    if (nb == 0) {  // no fluid node: zero mass
+        if (mass)
+            k_sum3<<<1, kBlock, 0, s.stream>>>(s.red, 0, 1, mass);
+        return hipGetLastError();
+    }
     double *part = mass ? s.red : nullptr;
     hipError_t e = by_dtype(s.dtype, [&](auto st) {
         using M = typename decltype(st)::mem;

@@ -128,6 +128,8 @@ struct Temp {
 };
 
 size_t padded_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s.pitch; }
+// Nodes of the stored lattice: the padded mesh, or the padded node list.
+size_t stored_nodes(const lbm3d_ctx *c) { return c->s.list ? (size_t)c->s.np : padded_nodes(c); }
 size_t canonical_bytes(const lbm3d_ctx *c) { return (size_t)Q * padded_nodes(c) * sizeof(double); }
 size_t field_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s.nx; }
 
@@ -201,8 +203,8 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
         return fail_tl(LBM_ERR_INVALID, "unknown dtype");
     if ((int)layout < 0 || (int)layout > 4)
         return fail_tl(LBM_ERR_INVALID, "unknown layout");
-    if (layout != LBM_DENSE_AB && layout != LBM_DENSE_AA)
-        return fail_tl(LBM_ERR_UNSUPPORTED, "D3Q19 lattices take DENSE_AB or DENSE_AA");
+    if (layout != LBM_DENSE_AB && layout != LBM_DENSE_AA && layout != LBM_INDIRECT)
+        return fail_tl(LBM_ERR_UNSUPPORTED, "D3Q19 lattices take DENSE_AB, DENSE_AA or INDIRECT");
     const int64_t pitch = ((int64_t)nx + 63) / 64 * 64;
     // population offsets are 64-bit; node indices and lane column offsets are
     // 32-bit
@@ -248,21 +250,39 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
             return LBM_ERR_DEVICE;
         return LBM_OK;
     };
-    std::vector<uint8_t> type;
-    std::vector<uint32_t> nbits, seg;
-    lbm::plan::dense_types3(node_type, nx, ny, nz, (int)pitch, type, nbits, seg);
     void *p = nullptr;
     int rc;
-    if ((rc = upload(type.data(), type.size(), &p)))
-        return fail_create(rc, "cannot upload the node types");
-    s.type = (const uint8_t *)p;
-    if ((rc = upload(nbits.data(), nbits.size() * 4, &p)))
-        return fail_create(rc, "cannot upload the neighbour bits");
-    s.nmask = (const uint32_t *)p;
-    if ((rc = upload(seg.data(), seg.size() * 4, &p)))
-        return fail_create(rc, "cannot upload the segment flags");
-    s.seg_interior = (const uint32_t *)p;
-    const size_t lattice = (size_t)Q * padded_nodes(c) * c->pop_bytes;
+    if (layout == LBM_INDIRECT) {
+        // fluid nodes only: the list with its coordinates and pull-source table
+        s.list = 1;
+        s.np = (c->n_fluid + 63) / 64 * 64;
+        if (s.np == 0)
+            s.np = 64;
+        if ((int64_t)Q * s.np >= (int64_t(1) << 32) || c->n_fluid >= (int64_t(1) << 31))
+            return fail_create(LBM_ERR_UNSUPPORTED, "too many fluid nodes for the node list");
+        lbm::plan::Fluid3 fl = lbm::plan::fluid_list3(node_type, nx, ny, nz, s.np);
+        s.n_fluid = fl.n_fluid;
+        if ((rc = upload(fl.nbr.data(), fl.nbr.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the neighbour table");
+        s.nbr = (const int32_t *)p;
+        if ((rc = upload(fl.xyz.data(), fl.xyz.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the node coordinates");
+        s.fxyz = (const int32_t *)p;
+    } else {
+        std::vector<uint8_t> type;
+        std::vector<uint32_t> nbits, seg;
+        lbm::plan::dense_types3(node_type, nx, ny, nz, (int)pitch, type, nbits, seg);
+        if ((rc = upload(type.data(), type.size(), &p)))
+            return fail_create(rc, "cannot upload the node types");
+        s.type = (const uint8_t *)p;
+        if ((rc = upload(nbits.data(), nbits.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the neighbour bits");
+        s.nmask = (const uint32_t *)p;
+        if ((rc = upload(seg.data(), seg.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the segment flags");
+        s.seg_interior = (const uint32_t *)p;
+    }
+    const size_t lattice = (size_t)Q * stored_nodes(c) * c->pop_bytes;
     s.aa = layout == LBM_DENSE_AA ? 1 : 0;
     for (int k = 0; k < (s.aa ? 1 : 2); ++k) {
         s.f[k] = own_alloc(c, lattice);
@@ -364,6 +384,8 @@ int lbm3d_set_bounce_back(lbm3d_ctx *c, int32_t mode)
     if (mode == 1 && c->s.aa)
         return fail(c, LBM_ERR_UNSUPPORTED,
                     "full-way bounce-back needs the two-lattice layout (not DENSE_AA)");
+    if (mode == 1 && c->s.list)
+        return fail(c, LBM_ERR_UNSUPPORTED, "full-way bounce-back needs a dense layout");
     // keep the fluid populations: gather under the old rule, store under the new
     // one (switching to full-way fills the wall slots from their sources)
     Temp fc(c, canonical_bytes(c));
@@ -426,7 +448,7 @@ int lbm3d_state_bytes(const lbm3d_ctx *c, size_t *bytes)
 {
     if (!c || !bytes)
         return fail_tl(LBM_ERR_INVALID, "NULL argument");
-    *bytes = (size_t)Q * padded_nodes(c) * c->pop_bytes;
+    *bytes = (size_t)Q * stored_nodes(c) * c->pop_bytes;
     return LBM_OK;
 }
 
@@ -546,12 +568,13 @@ int lbm3d_get_info(const lbm3d_ctx *c, lbm3d_info_t *info)
     info->ny = c->s.ny;
     info->nz = c->s.nz;
     info->dtype = c->s.dtype;
-    info->layout = c->s.aa ? LBM_DENSE_AA : LBM_DENSE_AB;
+    info->layout = c->s.list ? LBM_INDIRECT : c->s.aa ? LBM_DENSE_AA : LBM_DENSE_AB;
     info->n_nodes = (int64_t)c->s.nx * c->s.ny * c->s.nz;
     info->n_fluid = c->n_fluid;
     info->time_step = c->t;
     info->pop_bytes = c->pop_bytes;
-    info->bytes_per_fluid_node = 2.0 * Q * c->pop_bytes + 1.0;
+    // node list: the 18 four-byte pull sources instead of the type byte
+    info->bytes_per_fluid_node = 2.0 * Q * c->pop_bytes + (c->s.list ? 72.0 : 1.0);
     info->device_bytes = c->device_bytes;
     return LBM_OK;
 }

@@ -205,5 +205,35 @@ void dense_types3(const uint8_t *mask, int nx, int ny, int nz, int pitch,
                 seg[r * bpr + x / 256] = 0;
 }
 
+Fluid3 fluid_list3(const uint8_t *mask, int nx, int ny, int nz, int64_t padded)
+{
+    Fluid3 fl;
+    const size_t nn = (size_t)nx * ny * nz;
+    std::vector<int64_t> rank(nn, -1);
+    for (size_t k = 0; k < nn; ++k)
+        if (mask[k] == 0)
+            rank[k] = fl.n_fluid++;
+    fl.xyz.reserve((size_t)fl.n_fluid * 3);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                if (mask[((size_t)z * ny + y) * nx + x] == 0) {
+                    fl.xyz.push_back(x);
+                    fl.xyz.push_back(y);
+                    fl.xyz.push_back(z);
+                }
+    const int64_t np = padded > fl.n_fluid ? padded : fl.n_fluid;
+    fl.nbr.assign((size_t)18 * np, -1);
+    for (int64_t n = 0; n < fl.n_fluid; ++n) {
+        const int x = fl.xyz[3 * n], y = fl.xyz[3 * n + 1], z = fl.xyz[3 * n + 2];
+        for (int i = 1; i < 19; ++i) {
+            const int xs = wrapi(x - kHostCx3[i], nx), ys = wrapi(y - kHostCy3[i], ny),
+                      zs = wrapi(z - kHostCz3[i], nz);
+            fl.nbr[(size_t)(i - 1) * np + n] = (int32_t)rank[((size_t)zs * ny + ys) * nx + xs];
+        }
+    }
+    return fl;
+}
+
 }  // namespace plan
 }  // namespace lbm

@@ -78,6 +78,18 @@ IndirectCompact indirect_compact(const Fluid &fl, const uint8_t *mask, int nx, i
 // a solid neighbour; nbits[p] bit i-1 set iff node x - c_i (periodic) is solid,
 // i = 1..18 in the velocity order of include/lbm3d.h; seg[(z ny + y) bpr + s]
 // = 1 iff every node of 256-node row segment s has type 0 (bpr = ceil(nx / 256)).
+// D3Q19 node list: fluid nodes in row-major order (x fastest, then y, z) with
+// their coordinates xyz[3 n + {0, 1, 2}] and the pull-source table
+// nbr[(i - 1) * np + n] = list index of node x - c_i (periodic), or -1 when it
+// is solid (bounce-back); np >= n_fluid is the padded list length (entries
+// beyond n_fluid are -1).
+struct Fluid3 {
+    int64_t n_fluid = 0;
+    std::vector<int32_t> xyz;
+    std::vector<int32_t> nbr;
+};
+Fluid3 fluid_list3(const uint8_t *mask, int nx, int ny, int nz, int64_t padded);
+
 void dense_types3(const uint8_t *mask, int nx, int ny, int nz, int pitch,
                   std::vector<uint8_t> &type, std::vector<uint32_t> &nbits,
                   std::vector<uint32_t> &seg);

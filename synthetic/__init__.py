@@ -360,6 +360,30 @@ def random_mask3(nx: int, ny: int, nz: int, seed: int, solid_fraction: float = 0
     return m
 
 
+def random_spheres3(n: int, phi: float, seed: int | None = None, rmin: int = 4,
+                    rmax: int = 16) -> np.ndarray:
+    """n^3 mask (uint8 [nz, ny, nx]) of a 3-D porous medium: solid spheres with integer radii
+    uniform in [rmin, rmax] and centres uniform over the periodic box (overlap allowed), added
+    until the fluid fraction is <= phi; walls at z = 0 and n - 1.  Seeded by
+    default_rng(3000 + round(100 phi)) unless `seed` is given."""
+    rng = np.random.default_rng(3000 + int(round(100 * phi)) if seed is None else seed)
+    m = np.zeros((n, n, n), np.uint8)
+    m[0] = 1
+    m[n - 1] = 1
+    target = (1.0 - phi) * m.size
+    solid = int(m.sum())
+    while solid < target:
+        r = int(rng.integers(rmin, rmax + 1))
+        c = rng.integers(0, n, size=3)
+        d = np.arange(-r, r + 1)
+        dz, dy, dx = np.meshgrid(d, d, d, indexing="ij")
+        inside = dx * dx + dy * dy + dz * dz <= r * r
+        zz, yy, xx = ((c[0] + dz) % n)[inside], ((c[1] + dy) % n)[inside], ((c[2] + dx) % n)[inside]
+        solid += int((m[zz, yy, xx] == 0).sum())  # distinct cells: 2 r + 1 <= n
+        m[zz, yy, xx] = 1
+    return m
+
+
 def random_fields3(nx: int, ny: int, nz: int, seed: int, rho_spread: float = 0.03,
                    u_amp: float = 0.03):
     """rho in [1 - spread, 1 + spread], each velocity component in [-u_amp, u_amp]."""
