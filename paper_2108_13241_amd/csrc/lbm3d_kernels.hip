@@ -497,34 +497,103 @@ __device__ __forceinline__ uint64_t lelem(uint32_t n, int i)
     return (uint64_t)(n >> 6) * (Q * kChunk) + (uint64_t)i * kChunk + (n & 63u);
 }
 
+// Compact source table of the node list (36 B per node instead of 72): info[n]
+// holds the solid bits (bit i-1 <=> x - c_i solid) and kListBorder for nodes at
+// x = 0 or nx - 1; rank8[r np + n] is the number of fluid nodes before position
+// (x, y + dy_r, z + dz_r) in row-major order, rows r in the order of
+// list_row().  Since the list is row-major, the source of direction i is
+//   n -+ 1 in the node's own row (x -+ 1),
+//   q_r, q_r - 1 or q_r + [(x, row r) fluid] in row r for x, x - 1, x + 1,
+// except across the periodic seam in x: border nodes take their 18 sources from
+// edge[(i - 1) ne + slot], slot = rank8[n].
+constexpr uint32_t kListBorder = 1u << 31;
+
+__device__ constexpr int list_row(int dy, int dz)
+{
+    return dz == 0 ? (dy < 0 ? 0 : 1)
+         : dy == 0 ? (dz < 0 ? 2 : 3)
+         : dz < 0  ? (dy < 0 ? 4 : 5)
+                   : (dy < 0 ? 6 : 7);
+}
+
+// Direction with velocity (0, cy, cz).
+__device__ constexpr int axis_dir(int cy, int cz)
+{
+    for (int j = 1; j < Q; ++j)
+        if (kCx[j] == 0 && kCy[j] == cy && kCz[j] == cz)
+            return j;
+    return 0;
+}
+
+struct ListTable {
+    const int32_t *rank8;
+    const uint32_t *info;
+    const int32_t *edge;
+    uint64_t np, ne;
+};
+
+__host__ __device__ inline ListTable list_table(const State3 &s)
+{
+    return ListTable{s.rank8, s.info, s.edge, (uint64_t)s.np, (uint64_t)s.ne};
+}
+
 // Pull gather of list node n: f_i = s_i(source), or the node's own slot opp(i)
 // when the source is solid (halfway bounce-back).
 template <class ST>
 __device__ __forceinline__ void pull_list(const typename ST::mem *__restrict__ s,
-                                          const int32_t *__restrict__ nbr, uint64_t np,
-                                          uint32_t n, typename ST::real (&f)[Q])
+                                          const ListTable &t, uint32_t n,
+                                          typename ST::real (&f)[Q])
 {
+    const uint32_t bits = t.info[n];
     f[0] = ST::ld(s[lelem(n, 0)], 0);
+    if (bits & kListBorder) {
+        const uint64_t slot = (uint32_t)t.rank8[n];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int32_t src = t.edge[(uint64_t)(i - 1) * t.ne + slot];
+            f[i] = ST::ld(src >= 0 ? s[lelem((uint32_t)src, i)] : s[lelem(n, kOpp[i])], i);
+        }
+        return;
+    }
+    int32_t q[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        q[r] = t.rank8[(uint64_t)r * t.np + n];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int32_t src = nbr[(uint64_t)(i - 1) * np + n];
-        f[i] = ST::ld(src >= 0 ? s[lelem((uint32_t)src, i)] : s[lelem(n, kOpp[i])], i);
+        if ((bits >> (i - 1)) & 1u) {
+            f[i] = ST::ld(s[lelem(n, kOpp[i])], i);
+            continue;
+        }
+        const int dx = -kCx[i], dy = -kCy[i], dz = -kCz[i];
+        uint32_t src;
+        if (dy == 0 && dz == 0) {
+            src = n + dx;
+        } else {
+            const int32_t qr = q[list_row(dy, dz)];
+            if (dx == 0)
+                src = (uint32_t)qr;
+            else if (dx < 0)
+                src = (uint32_t)(qr - 1);
+            else
+                src = (uint32_t)qr + (((bits >> (axis_dir(-dy, -dz) - 1)) & 1u) ^ 1u);
+        }
+        f[i] = ST::ld(s[lelem(src, i)], i);
     }
 }
 
 template <class ST, bool FORCE, bool TRT, bool MRT>
 __global__ __launch_bounds__(kBlock) void k_step3_list(
-    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
-    const int32_t *__restrict__ nbr, uint64_t np, uint32_t n_fluid, uint32_t nblocks,
-    typename ST::real omega, typename ST::real gx, typename ST::real gy, typename ST::real gz,
-    Rates3<typename ST::real> rt)
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst, ListTable tab,
+    uint32_t n_fluid, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt)
 {
     using R = typename ST::real;
     const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
     if (n >= n_fluid)
         return;
     R f[Q];
-    pull_list<ST>(src, nbr, np, n, f);
+    pull_list<ST>(src, tab, n, f);
     collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -557,7 +626,7 @@ __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST:
         y = s.fxyz[3 * (uint64_t)gid + 1];
         z = s.fxyz[3 * (uint64_t)gid + 2];
         typename ST::real f[Q];
-        pull_list<ST>(st, s.nbr, (uint64_t)s.np, gid, f);
+        pull_list<ST>(st, list_table(s), gid, f);
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             fd[i] = ST::canon(f[i], i);
@@ -746,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
         const uint64_t own = ((uint64_t)z * s.ny + y) * (uint32_t)s.pitch + x;
         for (int j = 0; j < Q; ++j) {
             // q + c_j is the pull source of direction opp(j)
-            const bool fluid = j == 0 || s.nbr[(uint64_t)(kOpp[j] - 1) * s.np + gid] >= 0;
+            const bool fluid = j == 0 || ((s.info[gid] >> (kOpp[j] - 1)) & 1u) == 0;
             const double v = fluid ? fc[(uint64_t)j * plane + node_plus(s, x, y, z, j)]
                                    : fc[(uint64_t)kOpp[j] * plane + own];
             st[lelem(gid, j)] = ST::from_canon(v, j);
@@ -821,9 +890,8 @@ void step_launch3(const State3 &s, int cur)
         const M *src = (const M *)s.f[cur];
         M *dst = (M *)s.f[1 - cur];
         auto go = [&](auto kernel) {
-            kernel<<<nbl, kBlock, 0, s.stream>>>(src, dst, s.nbr, (uint64_t)s.np,
-                                                 (uint32_t)s.n_fluid, nbl, (R)s.omega, g[0], g[1],
-                                                 g[2], rt);
+            kernel<<<nbl, kBlock, 0, s.stream>>>(src, dst, list_table(s), (uint32_t)s.n_fluid,
+                                                 nbl, (R)s.omega, g[0], g[1], g[2], rt);
         };
         if (force)
             go(k_step3_list<ST, true, TRT, MRT>);

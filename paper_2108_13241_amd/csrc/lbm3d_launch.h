@@ -26,12 +26,14 @@ struct State3 {
     void *f[2] = {nullptr, nullptr};         // the two lattices (A-B); DENSE_AA: f[0] only
     int aa = 0;                              // 1: DENSE_AA, one lattice updated in place
     // INDIRECT (list = 1): fluid nodes only, in row-major order; populations
-    // [np/64][19][64] (np = n_fluid rounded up to 64); nbr[(i - 1) np + n] = list
-    // index of the pull source x - c_i of node n, or -1 (solid: bounce-back);
-    // fxyz[3 n + {0, 1, 2}] = its coordinates.
+    // [np/64][19][64] (np = n_fluid rounded up to 64); the compact source table
+    // (rank8 [8][np], info [np], edge [18][ne] for the border nodes; see
+    // pull_list); fxyz[3 n + {0, 1, 2}] = the node's coordinates.
     int list = 0;
-    int64_t n_fluid = 0, np = 0;
-    const int32_t *nbr = nullptr;
+    int64_t n_fluid = 0, np = 0, ne = 1;
+    const int32_t *rank8 = nullptr;
+    const uint32_t *info = nullptr;
+    const int32_t *edge = nullptr;
     const int32_t *fxyz = nullptr;
     const uint8_t *type = nullptr;           // 0 fluid, 1 solid, 2 fluid next to a solid
     const uint32_t *nmask = nullptr;         // bit i-1 set <=> node x - c_i is solid

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -262,9 +263,16 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
             return fail_create(LBM_ERR_UNSUPPORTED, "too many fluid nodes for the node list");
         lbm::plan::Fluid3 fl = lbm::plan::fluid_list3(node_type, nx, ny, nz, s.np);
         s.n_fluid = fl.n_fluid;
-        if ((rc = upload(fl.nbr.data(), fl.nbr.size() * 4, &p)))
-            return fail_create(rc, "cannot upload the neighbour table");
-        s.nbr = (const int32_t *)p;
+        s.ne = std::max<int64_t>(fl.n_edge, 1);
+        if ((rc = upload(fl.rank8.data(), fl.rank8.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the row ranks");
+        s.rank8 = (const int32_t *)p;
+        if ((rc = upload(fl.info.data(), fl.info.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the neighbour bits");
+        s.info = (const uint32_t *)p;
+        if ((rc = upload(fl.edge.data(), fl.edge.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the border-node table");
+        s.edge = (const int32_t *)p;
         if ((rc = upload(fl.xyz.data(), fl.xyz.size() * 4, &p)))
             return fail_create(rc, "cannot upload the node coordinates");
         s.fxyz = (const int32_t *)p;
@@ -573,8 +581,8 @@ int lbm3d_get_info(const lbm3d_ctx *c, lbm3d_info_t *info)
     info->n_fluid = c->n_fluid;
     info->time_step = c->t;
     info->pop_bytes = c->pop_bytes;
-    // node list: the 18 four-byte pull sources instead of the type byte
-    info->bytes_per_fluid_node = 2.0 * Q * c->pop_bytes + (c->s.list ? 72.0 : 1.0);
+    // node list: eight row ranks and the solid bits (36 B) instead of the type byte
+    info->bytes_per_fluid_node = 2.0 * Q * c->pop_bytes + (c->s.list ? 36.0 : 1.0);
     info->device_bytes = c->device_bytes;
     return LBM_OK;
 }

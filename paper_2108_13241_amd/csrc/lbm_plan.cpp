@@ -5,6 +5,8 @@
 // neighbour table (fluid index array, Sec. 1).
 #include "lbm_plan.h"
 
+#include <algorithm>
+
 namespace lbm {
 namespace plan {
 
@@ -205,14 +207,22 @@ void dense_types3(const uint8_t *mask, int nx, int ny, int nz, int pitch,
                 seg[r * bpr + x / 256] = 0;
 }
 
+// Source rows of the compact list table: (dy, dz) of the row holding x - c.
+static const int kRowDy[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+static const int kRowDz[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+
 Fluid3 fluid_list3(const uint8_t *mask, int nx, int ny, int nz, int64_t padded)
 {
     Fluid3 fl;
     const size_t nn = (size_t)nx * ny * nz;
-    std::vector<int64_t> rank(nn, -1);
-    for (size_t k = 0; k < nn; ++k)
+    // before[k] = fluid nodes before position k in row-major order (the rank a
+    // node at k has, or would have)
+    std::vector<int64_t> rank(nn, -1), before(nn, 0);
+    for (size_t k = 0; k < nn; ++k) {
+        before[k] = fl.n_fluid;
         if (mask[k] == 0)
             rank[k] = fl.n_fluid++;
+    }
     fl.xyz.reserve((size_t)fl.n_fluid * 3);
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
@@ -224,14 +234,37 @@ Fluid3 fluid_list3(const uint8_t *mask, int nx, int ny, int nz, int64_t padded)
                 }
     const int64_t np = padded > fl.n_fluid ? padded : fl.n_fluid;
     fl.nbr.assign((size_t)18 * np, -1);
+    fl.rank8.assign((size_t)8 * np, 0);
+    fl.info.assign((size_t)np, 0);
+    std::vector<int64_t> border;
     for (int64_t n = 0; n < fl.n_fluid; ++n) {
         const int x = fl.xyz[3 * n], y = fl.xyz[3 * n + 1], z = fl.xyz[3 * n + 2];
+        uint32_t bits = 0;
         for (int i = 1; i < 19; ++i) {
             const int xs = wrapi(x - kHostCx3[i], nx), ys = wrapi(y - kHostCy3[i], ny),
                       zs = wrapi(z - kHostCz3[i], nz);
-            fl.nbr[(size_t)(i - 1) * np + n] = (int32_t)rank[((size_t)zs * ny + ys) * nx + xs];
+            const int64_t src = rank[((size_t)zs * ny + ys) * nx + xs];
+            fl.nbr[(size_t)(i - 1) * np + n] = (int32_t)src;
+            if (src < 0)
+                bits |= 1u << (i - 1);
         }
+        for (int r = 0; r < 8; ++r) {
+            const int ys = wrapi(y + kRowDy[r], ny), zs = wrapi(z + kRowDz[r], nz);
+            fl.rank8[(size_t)r * np + n] = (int32_t)before[((size_t)zs * ny + ys) * nx + x];
+        }
+        if (x == 0 || x == nx - 1) {  // the x wrap breaks the rank arithmetic
+            bits |= kListBorder;
+            fl.rank8[n] = (int32_t)border.size();
+            border.push_back(n);
+        }
+        fl.info[n] = bits;
     }
+    fl.n_edge = (int64_t)border.size();
+    fl.edge.assign((size_t)18 * std::max<int64_t>(fl.n_edge, 1), -1);
+    for (int64_t e = 0; e < fl.n_edge; ++e)
+        for (int i = 0; i < 18; ++i)
+            fl.edge[(size_t)i * std::max<int64_t>(fl.n_edge, 1) + e] =
+                fl.nbr[(size_t)i * np + border[e]];
     return fl;
 }
 

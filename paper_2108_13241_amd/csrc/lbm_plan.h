@@ -79,14 +79,27 @@ IndirectCompact indirect_compact(const Fluid &fl, const uint8_t *mask, int nx, i
 // i = 1..18 in the velocity order of include/lbm3d.h; seg[(z ny + y) bpr + s]
 // = 1 iff every node of 256-node row segment s has type 0 (bpr = ceil(nx / 256)).
 // D3Q19 node list: fluid nodes in row-major order (x fastest, then y, z) with
-// their coordinates xyz[3 n + {0, 1, 2}] and the pull-source table
+// their coordinates xyz[3 n + {0, 1, 2}] and the full pull-source table
 // nbr[(i - 1) * np + n] = list index of node x - c_i (periodic), or -1 when it
 // is solid (bounce-back); np >= n_fluid is the padded list length (entries
-// beyond n_fluid are -1).
+// beyond n_fluid are -1).  The compact form the device uses:
+//   info[n]  bit i-1 set <=> x - c_i is solid; kListBorder set for x = 0 or
+//            nx - 1, where the periodic wrap in x breaks the rank arithmetic;
+//   rank8[r * np + n] = fluid nodes before position (x, y + dy_r, z + dz_r) in
+//            row-major order, rows r = (dy, dz) = (-1,0), (1,0), (0,-1), (0,1),
+//            (-1,-1), (1,-1), (-1,1), (1,1) (the rank of that node if fluid, and
+//            x -+ 1 in that row is rank -1 / rank + [node fluid]); for a border
+//            node rank8[n] is instead its slot in
+//   edge[(i - 1) * max(n_edge, 1) + slot] = the full source table of the border nodes.
+constexpr uint32_t kListBorder = 1u << 31;
 struct Fluid3 {
     int64_t n_fluid = 0;
     std::vector<int32_t> xyz;
     std::vector<int32_t> nbr;
+    std::vector<int32_t> rank8;
+    std::vector<uint32_t> info;
+    std::vector<int32_t> edge;
+    int64_t n_edge = 0;
 };
 Fluid3 fluid_list3(const uint8_t *mask, int nx, int ny, int nz, int64_t padded);
 

@@ -241,3 +241,105 @@ def test_dense_types3_brute_force(planner3, oracle_mod, shape):
                 if t != 0:
                     exp_seg[(z * ny + y) * bpr + x // 256] = 0
     assert np.array_equal(seg, exp_seg)
+
+
+DRIVER_LIST3 = textwrap.dedent(r"""
+    #include <algorithm>
+    #include <cstdio>
+    #include <vector>
+    #include "lbm_plan.h"
+    int main() {
+        int nx, ny, nz;
+        if (std::scanf("%d %d %d", &nx, &ny, &nz) != 3) return 2;
+        std::vector<uint8_t> mask((size_t)nx * ny * nz);
+        for (auto &m : mask) { int v; if (std::scanf("%d", &v) != 1) return 2; m = (uint8_t)v; }
+        long n_f = 0;
+        for (auto m : mask) n_f += m == 0;
+        const long np = std::max(64L, (n_f + 63) / 64 * 64);
+        lbm::plan::Fluid3 fl = lbm::plan::fluid_list3(mask.data(), nx, ny, nz, np);
+        const long ne = std::max<long>(fl.n_edge, 1);
+        for (long n = 0; n < fl.n_fluid; ++n) {
+            std::printf("%d %d %d %u", fl.xyz[3 * n], fl.xyz[3 * n + 1], fl.xyz[3 * n + 2],
+                        fl.info[n]);
+            for (int i = 0; i < 18; ++i) std::printf(" %d", fl.nbr[(size_t)i * np + n]);
+            for (int r = 0; r < 8; ++r) std::printf(" %d", fl.rank8[(size_t)r * np + n]);
+            if (fl.info[n] & lbm::plan::kListBorder)
+                for (int i = 0; i < 18; ++i) std::printf(" %d", fl.edge[(size_t)i * ne + fl.rank8[n]]);
+            std::printf("\n");
+        }
+        for (long n = fl.n_fluid; n < np; ++n)
+            for (int i = 0; i < 18; ++i)
+                if (fl.nbr[(size_t)i * np + n] != -1) return 3;
+        return 0;
+    }
+""")
+
+CX3 = [0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0]
+CY3 = [0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1]
+CZ3 = [0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1]
+ROWS3 = [(-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, -1), (-1, 1), (1, 1)]
+
+
+def _decode_list3(n, info, rank8, edge):
+    """Pull sources of list node n from the compact form, by the documented rule."""
+    if info & (1 << 31):
+        return list(edge)
+    solid = lambda i: (info >> (i - 1)) & 1
+    out = []
+    for i in range(1, 19):
+        if solid(i):
+            out.append(-1)
+            continue
+        dx, dy, dz = -CX3[i], -CY3[i], -CZ3[i]
+        if dy == 0 and dz == 0:
+            out.append(n + dx)
+            continue
+        q = rank8[ROWS3.index((dy, dz))]
+        if dx == 0:
+            out.append(q)
+        elif dx < 0:
+            out.append(q - 1)
+        else:  # x + 1 in that row: q plus one if (x, row) itself is fluid
+            j = [k for k in range(1, 19) if (CX3[k], CY3[k], CZ3[k]) == (0, -dy, -dz)][0]
+            out.append(q + (1 - solid(j)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def planner_list3(tmp_path_factory):
+    d = tmp_path_factory.mktemp("plan_list3")
+    src = d / "drv.cpp"
+    src.write_text(DRIVER_LIST3)
+    exe = d / "drv"
+    subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-I", CSRC, str(src),
+                    os.path.join(CSRC, "lbm_plan.cpp"), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+@pytest.mark.parametrize("shape,frac", [((13, 7, 5), 0.35), ((9, 6, 4), 0.0), ((5, 4, 3), 0.7),
+                                        ((2, 3, 3), 0.3)])
+def test_fluid_list3(planner_list3, shape, frac):
+    """The full source table against brute force; the compact form (solid bits, eight row
+    ranks, border nodes through the edge table) decodes to the same table."""
+    nx, ny, nz = shape
+    m = synthetic.random_mask3(nx, ny, nz, seed=nx * ny + nz, solid_fraction=frac)
+    inp = f"{nx} {ny} {nz}\n" + " ".join(str(int(v)) for v in m.ravel())
+    r = subprocess.run([planner_list3], input=inp, capture_output=True, text=True)
+    assert r.returncode == 0, r.returncode
+    rows = [list(map(int, ln.split())) for ln in r.stdout.split("\n") if ln.strip()]
+    fluid = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx) if m[z, y, x] == 0]
+    index = {p: k for k, p in enumerate(fluid)}
+    assert len(rows) == len(fluid)
+    border = 0
+    for n, row in enumerate(rows):
+        x, y, z, info = row[:4]
+        assert (x, y, z) == fluid[n]
+        nbr = row[4:22]
+        for i in range(1, 19):
+            src = ((x - CX3[i]) % nx, (y - CY3[i]) % ny, (z - CZ3[i]) % nz)
+            assert nbr[i - 1] == index.get(src, -1), (n, i)
+        border += bool(info & (1 << 31))
+        assert _decode_list3(n, info, row[22:30], row[30:48]) == nbr, n
+    if frac < 0.5 and nx > 2:
+        assert 0 < border < len(rows)
