@@ -137,7 +137,7 @@ int lbm3d_set_mrt(lbm3d_ctx *ctx, const double *rates);
  * w - c_j.  The fluid populations are kept across a switch.  No extra memory
  * (the A-B pair holds the state).  Invalid mode: LBM_ERR_INVALID; mode 1 on a
  * DENSE_AA lattice: LBM_ERR_UNSUPPORTED (in place, no lattice holds the values
- * of two steps back), likewise on INDIRECT.  Synchronises the stream. */
+ * of two steps back).  Synchronises the stream. */
 int lbm3d_set_bounce_back(lbm3d_ctx *ctx, int32_t mode);
 
 /* Enqueue n >= 0 time steps (one kernel launch each). */

@@ -537,12 +537,13 @@ __host__ __device__ inline ListTable list_table(const State3 &s)
     return ListTable{s.rank8, s.info, s.edge, (uint64_t)s.np, (uint64_t)s.ne};
 }
 
-// Pull gather of list node n: f_i = s_i(source), or the node's own slot opp(i)
-// when the source is solid (halfway bounce-back).
+// Pull gather of list node n: f_i = s_i(source), or, when the source is solid,
+// slot opp(i) of the node in bb (bb = s: halfway bounce-back; the other lattice
+// of the pair: full-way, the value of two steps back).
 template <class ST>
 __device__ __forceinline__ void pull_list(const typename ST::mem *__restrict__ s,
-                                          const ListTable &t, uint32_t n,
-                                          typename ST::real (&f)[Q])
+                                          const typename ST::mem *bb, const ListTable &t,
+                                          uint32_t n, typename ST::real (&f)[Q])
 {
     const uint32_t bits = t.info[n];
     f[0] = ST::ld(s[lelem(n, 0)], 0);
@@ -551,7 +552,7 @@ __device__ __forceinline__ void pull_list(const typename ST::mem *__restrict__ s
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const int32_t src = t.edge[(uint64_t)(i - 1) * t.ne + slot];
-            f[i] = ST::ld(src >= 0 ? s[lelem((uint32_t)src, i)] : s[lelem(n, kOpp[i])], i);
+            f[i] = ST::ld(src >= 0 ? s[lelem((uint32_t)src, i)] : bb[lelem(n, kOpp[i])], i);
         }
         return;
     }
@@ -562,7 +563,7 @@ __device__ __forceinline__ void pull_list(const typename ST::mem *__restrict__ s
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if ((bits >> (i - 1)) & 1u) {
-            f[i] = ST::ld(s[lelem(n, kOpp[i])], i);
+            f[i] = ST::ld(bb[lelem(n, kOpp[i])], i);
             continue;
         }
         const int dx = -kCx[i], dy = -kCy[i], dz = -kCz[i];
@@ -586,14 +587,14 @@ template <class ST, bool FORCE, bool TRT, bool MRT>
 __global__ __launch_bounds__(kBlock) void k_step3_list(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst, ListTable tab,
     uint32_t n_fluid, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
-    typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt)
+    typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt, int fullway)
 {
     using R = typename ST::real;
     const uint32_t n = xcd_remap(blockIdx.x, nblocks) * kBlock + threadIdx.x;
     if (n >= n_fluid)
         return;
     R f[Q];
-    pull_list<ST>(src, tab, n, f);
+    pull_list<ST>(src, fullway ? dst : src, tab, n, f);
     collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -626,10 +627,18 @@ __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST:
         y = s.fxyz[3 * (uint64_t)gid + 1];
         z = s.fxyz[3 * (uint64_t)gid + 2];
         typename ST::real f[Q];
-        pull_list<ST>(st, list_table(s), gid, f);
+        pull_list<ST>(st, bb, list_table(s), gid, f);
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             fd[i] = ST::canon(f[i], i);
+        if (bb != st) {  // full-way: the wall slots this node feeds
+            const uint32_t sm = s.info[gid] << 1;
+            for (int j = 1; j < Q; ++j)
+                if ((sm >> kOpp[j]) & 1u) {
+                    wl |= 1u << j;
+                    wv[j] = ST::canon(ST::ld(st[lelem(gid, j)], j), j);
+                }
+        }
         return true;
     }
     const uint32_t r = gid / (uint32_t)s.pitch;
@@ -813,13 +822,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
                   z = s.fxyz[3 * (uint64_t)gid + 2];
         const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
         const uint64_t own = ((uint64_t)z * s.ny + y) * (uint32_t)s.pitch + x;
+        const uint32_t sm = s.info[gid] << 1;  // bit i <=> x - c_i solid
         for (int j = 0; j < Q; ++j) {
-            // q + c_j is the pull source of direction opp(j)
-            const bool fluid = j == 0 || ((s.info[gid] >> (kOpp[j] - 1)) & 1u) == 0;
-            const double v = fluid ? fc[(uint64_t)j * plane + node_plus(s, x, y, z, j)]
-                                   : fc[(uint64_t)kOpp[j] * plane + own];
+            // q + c_j is the pull source of direction opp(j); full-way walls as the
+            // dense scatter below
+            double v;
+            if (((sm >> kOpp[j]) & 1u) == 0 || walls == 1)
+                v = fc[(uint64_t)j * plane + node_plus(s, x, y, z, j)];
+            else
+                v = fc[(uint64_t)(walls == 2 ? j : kOpp[j]) * plane + own];
             st[lelem(gid, j)] = ST::from_canon(v, j);
         }
+        if (walls != 0)
+            for (int i = 1; i < Q; ++i)
+                if ((sm >> i) & 1u)
+                    other[lelem(gid, kOpp[i])] =
+                        ST::from_canon(fc[(uint64_t)i * plane + own], kOpp[i]);
         return;
     }
     const uint32_t r = gid / (uint32_t)s.pitch;
@@ -891,7 +909,8 @@ void step_launch3(const State3 &s, int cur)
         M *dst = (M *)s.f[1 - cur];
         auto go = [&](auto kernel) {
             kernel<<<nbl, kBlock, 0, s.stream>>>(src, dst, list_table(s), (uint32_t)s.n_fluid,
-                                                 nbl, (R)s.omega, g[0], g[1], g[2], rt);
+                                                 nbl, (R)s.omega, g[0], g[1], g[2], rt,
+                                                 s.fullway);
         };
         if (force)
             go(k_step3_list<ST, true, TRT, MRT>);

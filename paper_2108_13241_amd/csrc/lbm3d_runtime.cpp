@@ -392,8 +392,6 @@ int lbm3d_set_bounce_back(lbm3d_ctx *c, int32_t mode)
     if (mode == 1 && c->s.aa)
         return fail(c, LBM_ERR_UNSUPPORTED,
                     "full-way bounce-back needs the two-lattice layout (not DENSE_AA)");
-    if (mode == 1 && c->s.list)
-        return fail(c, LBM_ERR_UNSUPPORTED, "full-way bounce-back needs a dense layout");
     // keep the fluid populations: gather under the old rule, store under the new
     // one (switching to full-way fills the wall slots from their sources)
     Temp fc(c, canonical_bytes(c));

@@ -71,8 +71,8 @@ def test_list_matches_dense_bitwise(lbm, dtype):
 
 def test_list_views_state_and_errors(lbm, oracle_mod):
     """macroscopic fields and mass against the oracle; set / get populations exact; save / load
-    replays bitwise; full-way refused; info reports the layout and fewer device bytes than the
-    dense layout on a sparse geometry; an all-solid mesh has an empty list."""
+    replays bitwise; info reports the layout and fewer device bytes than the dense layout on a
+    sparse geometry; an all-solid mesh has an empty list."""
     import torch
     announce("d3q19 list views and state")
     nx, ny, nz = 48, 20, 16
@@ -105,9 +105,6 @@ def test_list_views_state_and_errors(lbm, oracle_mod):
     lat.step(5)
     assert np.array_equal(lat.get_populations(), a)
     assert fp_error(a, oracle_mod.run3(m, f, 0.7, 5, g=g), m, "f64") <= TOL["f64"]
-    with pytest.raises(lbm.LbmError) as e:
-        lat.set_bounce_back("fullway")
-    assert e.value.status == -4
     lat.close()
     empty = lbm.Lattice3D(np.ones((4, 6, 70), np.uint8), 0.8, force=g, dtype="f32",
                           layout="indirect")
@@ -116,3 +113,37 @@ def test_list_views_state_and_errors(lbm, oracle_mod):
     assert empty.mass() == 0.0
     assert not np.any(empty.get_populations())
     empty.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_list_fullway(lbm, oracle_mod, dtype):
+    """Full-way walls on the node list: against the oracle (fluid and wall slots), bitwise
+    against the dense A-B layout, a switch back to halfway, and the mass with wall slots."""
+    announce(f"d3q19 list fullway {dtype}")
+    nx, ny, nz = 70, 12, 10
+    m = synthetic.random_mask3(nx, ny, nz, seed=78, solid_fraction=0.25, walls=True)
+    fields = synthetic.random_fields3(nx, ny, nz, seed=79)
+    g = (2e-5, -1e-5, 1e-5)
+    f0 = oracle_mod.fullway_fill3(m, oracle_mod.init3(m, *fields))
+    ref = oracle_mod.run3(m, f0, 0.7, 31, g=g, fullway=True)
+    out = {}
+    for layout in ("dense_ab", "indirect"):
+        lat = lbm.Lattice3D(m, 0.7, force=g, dtype=dtype, layout=layout)
+        lat.set_bounce_back("fullway")
+        lat.init_equilibrium(*fields)
+        M0 = lat.mass()
+        lat.step(31)
+        out[layout] = lat.get_populations()
+        if dtype == "f64":
+            assert abs(lat.mass() - M0) <= 1e-12 * M0
+        lat.set_bounce_back("halfway")
+        lat.step(4)
+        out[layout + " halfway"] = lat.get_populations()
+        lat.close()
+    assert np.array_equal(out["indirect"], out["dense_ab"])
+    assert np.array_equal(out["indirect halfway"], out["dense_ab halfway"])
+    got = out["indirect"]
+    sel = (m[None] == 0) | (ref != 0)
+    a, b = got[sel], ref[sel]
+    err = np.abs(a - b).max() if dtype == "f64" else (np.abs(a - b) / np.abs(b)).max()
+    assert err <= TOL[dtype]
