@@ -533,7 +533,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py measures one GPU: this build runs the step on a single MI355X and has "
+        print("bench.py measures one GPU: the step runs on a single MI355X and there is "
               "no multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 

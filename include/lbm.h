@@ -89,7 +89,7 @@ typedef enum {
     LBM_ERR_INVALID = -1,     /* bad argument; nothing changed */
     LBM_ERR_NOMEM = -2,       /* device or host allocation failed */
     LBM_ERR_DEVICE = -3,      /* HIP runtime error; the context is now broken */
-    LBM_ERR_UNSUPPORTED = -4, /* valid request this build does not implement */
+    LBM_ERR_UNSUPPORTED = -4, /* valid request the library does not implement */
     LBM_ERR_STATE = -5        /* context broken by an earlier device error */
 } lbm_status;
 
