@@ -7,8 +7,8 @@
  * the fused pull stream-and-collide step of Algorithm 1 with halfway bounce-back
  * walls (Sec. 3), the BGK operator of Eqs. 3-5 and the equilibrium of Eq. 6 with
  * the D3Q19 weights, plus a body force through Guo's forcing term and, as
- * options, the two-relaxation-time collision and the full-way wall rule.  Two
- * layouts, as lbm.h's dense ones: DENSE_AB, two dense lattices swapped every
+ * options, the two- and multiple-relaxation-time collisions and the full-way
+ * wall rule.  Three layouts, as lbm.h's: DENSE_AB, two dense lattices swapped every
  * step, and DENSE_AA, one dense lattice updated in place with the AA access
  * pattern (even steps read and write each node's own slots, odd steps read from
  * and write to the neighbours; half the memory); and INDIRECT, the sparse
@@ -57,14 +57,15 @@ typedef struct lbm3d_ctx lbm3d_ctx; /* opaque; owned by the library until lbm3d_
 typedef struct {
     int32_t nx, ny, nz;
     int32_t dtype;
-    int32_t layout;              /* LBM_DENSE_AB or LBM_DENSE_AA */
+    int32_t layout;              /* LBM_DENSE_AB, LBM_DENSE_AA or LBM_INDIRECT */
     int64_t n_nodes;             /* nx * ny * nz */
     int64_t n_fluid;             /* fluid nodes: the ones counted for LUPS (Eq. 8) */
     int64_t time_step;           /* steps since the last (re)initialisation */
     int32_t pop_bytes;           /* bytes per stored population: 8, 4 or 2 */
     double bytes_per_fluid_node; /* algorithmic bytes per fluid node per step:
                                     38 * pop_bytes + 1 (node type; INDIRECT:
-                                    + 72, the 18 pull sources) */
+                                    + 36 instead, the source table: eight
+                                    row ranks and the solid bits) */
     size_t device_bytes;         /* device memory held by the context */
 } lbm3d_info_t;
 
@@ -84,8 +85,10 @@ typedef struct {
  *  dtype       storage type (see above).
  *  layout      LBM_DENSE_AB, LBM_DENSE_AA (one lattice: 19 * pop_bytes per
  *              node, half of DENSE_AB) or LBM_INDIRECT (fluid nodes only:
- *              38 * pop_bytes + 84 bytes per fluid node: two lattices, the
- *              source table and the coordinates); the tiled layouts are
+ *              38 * pop_bytes + 48 bytes per fluid node: two lattices, the
+ *              compact source table (eight row ranks, the solid bits) and the
+ *              coordinates, plus 72 bytes per fluid node at x = 0 or nx - 1,
+ *              whose 18 sources are listed in full); the tiled layouts are
  *              UNSUPPORTED.
  * Errors: INVALID (sizes, tau, force, mask values, dtype, layout), UNSUPPORTED
  * (size limit, sparse layout), NOMEM, DEVICE. */

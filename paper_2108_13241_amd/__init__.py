@@ -343,10 +343,10 @@ def _force3(g):
 
 
 class Lattice3D:
-    """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B or
-    AA layout, BGK (or TRT) with Guo forcing, halfway (or full-way) bounce-back.  Arrays are
-    [nz, ny, nx]; canonical populations [19, nz, ny, nx] in the velocity order of
-    include/lbm3d.h."""
+    """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B, AA or
+    fluid-node-list ("indirect") layout; BGK, TRT or MRT collision with Guo forcing; halfway
+    (or, except on AA, full-way) bounce-back.  Arrays are [nz, ny, nx]; canonical populations
+    [19, nz, ny, nx] in the velocity order of include/lbm3d.h."""
 
     def __init__(self, mask, tau, force=(0.0, 0.0, 0.0), dtype="f64", stream=None,
                  torch_memory=True, layout="dense_ab"):
