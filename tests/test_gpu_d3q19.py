@@ -24,8 +24,9 @@ def lbm():
     return m
 
 
-def run_gpu(lbm, mask, tau, steps, dtype, g=(0.0, 0.0, 0.0), fields=None, f0=None):
-    lat = lbm.Lattice3D(mask, tau, force=g, dtype=dtype)
+def run_gpu(lbm, mask, tau, steps, dtype, g=(0.0, 0.0, 0.0), fields=None, f0=None,
+            layout="dense_ab"):
+    lat = lbm.Lattice3D(mask, tau, force=g, dtype=dtype, layout=layout)
     if fields is not None:
         lat.init_equilibrium(*fields)
     if f0 is not None:
@@ -85,19 +86,21 @@ def test_taylor_green3_vs_oracle(lbm, oracle_mod, dtype):
     assert fp_error(got, ref, m, dtype) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("layout", ["dense_ab", "dense_aa", "indirect"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 5), (3, 1, 1), (2, 3, 1), (65, 2, 3),
-                                   (64, 1, 2)])
-def test_degenerate_shapes(lbm, oracle_mod, dtype, shape):
+                                   (64, 1, 2), (6, 1, 2), (1, 4, 3)])
+def test_degenerate_shapes(lbm, oracle_mod, dtype, shape, layout):
     """One-node and one-wide lattices (a node is its own periodic neighbour), and a lattice
-    exactly one chunk wide, with random solids."""
+    exactly one chunk wide, with random solids; an odd step count (AA ends on its odd
+    kernel)."""
     nx, ny, nz = shape
-    announce(f"d3q19 degenerate {nx}x{ny}x{nz} {dtype}")
+    announce(f"d3q19 degenerate {nx}x{ny}x{nz} {dtype} {layout}")
     m = synthetic.random_mask3(nx, ny, nz, seed=nx * 100 + ny * 10 + nz, solid_fraction=0.25)
     f0 = synthetic.random_populations(oracle_mod.constants3()[3], (nz, ny, nx), seed=3,
                                       amp=0.1) * (m == 0)
     ref = run_oracle(oracle_mod, m, 0.9, 17, g=(1e-4, 2e-4, -1e-4), f0=f0)
-    got = run_gpu(lbm, m, 0.9, 17, dtype, g=(1e-4, 2e-4, -1e-4), f0=f0)
+    got = run_gpu(lbm, m, 0.9, 17, dtype, g=(1e-4, 2e-4, -1e-4), f0=f0, layout=layout)
     assert fp_error(got, ref, m, dtype) <= TOL[dtype]
 
 

@@ -318,10 +318,14 @@ def planner_list3(tmp_path_factory):
 
 
 @pytest.mark.parametrize("shape,frac", [((13, 7, 5), 0.35), ((9, 6, 4), 0.0), ((5, 4, 3), 0.7),
-                                        ((2, 3, 3), 0.3)])
+                                        ((2, 3, 3), 0.3), ((1, 1, 1), 0.0), ((3, 1, 1), 0.0),
+                                        ((6, 1, 2), 0.3), ((5, 2, 1), 0.2), ((1, 4, 3), 0.25),
+                                        ((7, 3, 1), 0.3), ((4, 4, 4), 1.0)])
 def test_fluid_list3(planner_list3, shape, frac):
     """The full source table against brute force; the compact form (solid bits, eight row
-    ranks, border nodes through the edge table) decodes to the same table."""
+    ranks, border nodes through the edge table) decodes to the same table.  The small shapes
+    are one or two nodes wide in some axis, where a node's neighbour rows coincide with its
+    own row (or the wrap in x makes every node a border node)."""
     nx, ny, nz = shape
     m = synthetic.random_mask3(nx, ny, nz, seed=nx * ny + nz, solid_fraction=frac)
     inp = f"{nx} {ny} {nz}\n" + " ".join(str(int(v)) for v in m.ravel())
