@@ -504,8 +504,10 @@ __device__ __forceinline__ uint64_t lelem(uint32_t n, int i)
 // list_row().  Since the list is row-major, the source of direction i is
 //   n -+ 1 in the node's own row (x -+ 1),
 //   q_r, q_r - 1 or q_r + [(x, row r) fluid] in row r for x, x - 1, x + 1,
-// except across the periodic seam in x: border nodes take their 18 sources from
-// edge[(i - 1) ne + slot], slot = rank8[n].
+// except across the periodic seam in x: a border node's rank8[n] holds its slot
+// in the full table edge[(i - 1) ne + slot], from which it takes the sources the
+// seam or the slot breaks (c_x != 0, and the row-0 source with c_x = 0); the
+// other rows' ranks stay valid.
 constexpr uint32_t kListBorder = 1u << 31;
 
 __device__ constexpr int list_row(int dy, int dz)
@@ -546,41 +548,37 @@ __device__ __forceinline__ void pull_list(const typename ST::mem *__restrict__ s
                                           uint32_t n, typename ST::real (&f)[Q])
 {
     const uint32_t bits = t.info[n];
-    f[0] = ST::ld(s[lelem(n, 0)], 0);
-    if (bits & kListBorder) {
-        const uint64_t slot = (uint32_t)t.rank8[n];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const int32_t src = t.edge[(uint64_t)(i - 1) * t.ne + slot];
-            f[i] = ST::ld(src >= 0 ? s[lelem((uint32_t)src, i)] : bb[lelem(n, kOpp[i])], i);
-        }
-        return;
-    }
     int32_t q[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r)
         q[r] = t.rank8[(uint64_t)r * t.np + n];
+    uint32_t src[Q];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        if ((bits >> (i - 1)) & 1u) {
-            f[i] = ST::ld(bb[lelem(n, kOpp[i])], i);
-            continue;
-        }
         const int dx = -kCx[i], dy = -kCy[i], dz = -kCz[i];
-        uint32_t src;
         if (dy == 0 && dz == 0) {
-            src = n + dx;
+            src[i] = n + dx;
         } else {
             const int32_t qr = q[list_row(dy, dz)];
             if (dx == 0)
-                src = (uint32_t)qr;
+                src[i] = (uint32_t)qr;
             else if (dx < 0)
-                src = (uint32_t)(qr - 1);
+                src[i] = (uint32_t)(qr - 1);
             else
-                src = (uint32_t)qr + (((bits >> (axis_dir(-dy, -dz) - 1)) & 1u) ^ 1u);
+                src[i] = (uint32_t)qr + (((bits >> (axis_dir(-dy, -dz) - 1)) & 1u) ^ 1u);
         }
-        f[i] = ST::ld(s[lelem(src, i)], i);
     }
+    if (bits & kListBorder) {
+        const uint64_t slot = (uint32_t)q[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+            if (kCx[i] != 0 || (kCz[i] == 0 && kCy[i] > 0))
+                src[i] = (uint32_t)t.edge[(uint64_t)(i - 1) * t.ne + slot];
+    }
+    f[0] = ST::ld(s[lelem(n, 0)], 0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        f[i] = ST::ld((bits >> (i - 1)) & 1u ? bb[lelem(n, kOpp[i])] : s[lelem(src[i], i)], i);
 }
 
 template <class ST, bool FORCE, bool TRT, bool MRT>

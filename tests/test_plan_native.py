@@ -281,9 +281,11 @@ ROWS3 = [(-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, -1), (-1, 1), (1, 1)]
 
 
 def _decode_list3(n, info, rank8, edge):
-    """Pull sources of list node n from the compact form, by the documented rule."""
-    if info & (1 << 31):
-        return list(edge)
+    """Pull sources of list node n from the compact form, by the documented rule: a border
+    node (bit 31) holds its slot in the border table in place of the row-0 rank and takes
+    from that table the sources with c_x != 0 and the row-0 source; every other source comes
+    from the rank arithmetic."""
+    border = bool(info & (1 << 31))
     solid = lambda i: (info >> (i - 1)) & 1
     out = []
     for i in range(1, 19):
@@ -291,6 +293,9 @@ def _decode_list3(n, info, rank8, edge):
             out.append(-1)
             continue
         dx, dy, dz = -CX3[i], -CY3[i], -CZ3[i]
+        if border and (dx != 0 or (dz == 0 and dy < 0)):
+            out.append(edge[i - 1])
+            continue
         if dy == 0 and dz == 0:
             out.append(n + dx)
             continue
