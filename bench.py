@@ -20,9 +20,11 @@ paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on st
 
   --suite sparse: the paper's sparse-geometry study (Sec. 4.3, Fig. 8): sparse efficiency
               eta_P (Eq. 9) over porosity for regular and random circle obstacles, per layout.
+  --suite spheres3: the copy kernel and the D3Q19 256^3 sphere packings (dense A-B against
+              the fluid-node list), for the list kernel's counters.
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 100]
-                       [--suite default|full|headline|sparse]
+                       [--suite default|full|headline|sparse|spheres3]
 """
 from __future__ import annotations
 
@@ -527,7 +529,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--suite", default="default",
-                    choices=["default", "full", "headline", "sparse"])
+                    choices=["default", "full", "headline", "sparse", "spheres3"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-reps", type=int, default=20)
     args = ap.parse_args()
@@ -605,7 +607,11 @@ def main():
             log(f"[bench]   d3q19 256^3 {dtype} MRT: {r['glups']:.2f} GLUPS "
                 f"({r['frac_of_peak']:.3f})")
             variants.append(r)
-    if args.suite == "full":
+    if args.suite == "spheres3":
+        c = measure_copy(lbm, 1 << 30, reps=args.copy_reps)
+        log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
+        variants.append({"workload": "copy kernel 1 GiB", **c})
+    if args.suite in ("full", "spheres3"):
         for phi in (0.7, 0.4):
             m3 = synthetic.random_spheres3(256, phi)
             for dtype in ("f32", "f64"):
@@ -616,6 +622,7 @@ def main():
                         f"{r['glups_per_fluid_node']:.2f} GLUPS per fluid node "
                         f"({r['frac_of_peak']:.3f})")
                     variants.append(r)
+    if args.suite == "full":
         for nn in (1024, 2048):
             f2 = synthetic.taylor_green(nn, 0.01)
             for dtype in ("f64", "f32"):
