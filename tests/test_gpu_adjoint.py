@@ -153,7 +153,7 @@ def test_autograd_function(lbm):
     J = lbm.ChannelObjective.apply(a, gt, spec)
     J.backward()
     J2, ga, gg = gpu_gradient(lbm, m, alpha, g, 0.8, 300, "f64")
-    assert float(J) == pytest.approx(J2, rel=1e-14)
+    assert float(J.detach()) == pytest.approx(J2, rel=1e-14)
     ga64, gg64 = lbm.ChannelObjective.last_grads
     assert np.array_equal(ga64.cpu().numpy(), ga)
     assert np.allclose(gt.grad.cpu().numpy(), gg, rtol=1e-14)
