@@ -2,9 +2,9 @@
 """Throughput of the fused D2Q9 stream-and-collide step on one MI355X.
 
 Default workload: decaying Taylor-Green vortex on a fully periodic 4096 x 4096 lattice
-(u0 = 0.01, wavenumber 2 pi / N, tau = 0.6), FP64 populations, dense A-B layout; W
-untimed warm-up steps, then K timed steps bracketed by device synchronisation (the
-paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on stdout:
+(u0 = 0.01, wavenumber 2 pi / N, tau = 0.6), FP64 populations, dense A-B layout; exactly W
+untimed warm-up steps, then K timed steps bracketed by device synchronisation (the paper's
+protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on stdout:
 
   value     = GLUPS = fluid nodes * K / time / 1e9 of the whole job (one GPU);
   roofline  = algorithmic bytes per step kernel ((18 * pop_bytes + 1) per fluid node)
@@ -12,11 +12,22 @@ paper's protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on st
               on, against the MI355X HBM peak (8 TB/s);
   cpu_baseline = the FP64 CPU oracle on the host cores, a bounded number of steps of
               the same 4096^2 workload (about 12 s), plus one step on a single thread;
-  variants  = the same measurement for the other storage types, the AA layout and the
-              TRT and MRT collisions, the open-boundary channels, the end-to-end rate with host
-              transfers and the D3Q19 lattice (256^3 three-dimensional Taylor-Green
-              vortex); with --suite full also 1024^2 / 2048^2, the porous / sparse layouts
-              (halfway and full-way walls), set-up and view costs and the adjoint.
+  variants  = the same measurement for the other storage types (16-bit rows with their
+              velocity error against the FP64 run and their mass drift), the AA layout and
+              the TRT and MRT collisions; the sparse geometries (4096^2 porous discs at fluid
+              fractions 0.9, 0.5, 0.2: dense, tiled and indirect layouts, FP64 and FP32,
+              GLUPS per fluid node and time per fluid node against the dense all-fluid
+              step); reduced-precision storage at 5000 steps (2048^2 Taylor-Green, 4096^2
+              porous discs at 0.5: velocity L2 error against FP64 and the closed form, mass
+              drift, GLUPS against the FP32 path); the adjoint against the forward step
+              (1024 x 256 channel with drag field, T = 2000, sqrt(T) checkpoints); the copy
+              kernel, the open-boundary channels, the end-to-end rate with host transfers and
+              the D3Q19 lattice (256^3 three-dimensional Taylor-Green vortex); with
+              --suite full also 1024^2 / 2048^2, full-way walls, set-up and view costs and
+              the adjoint at 4096^2.
+  Each variant states the warm-up it ran ("warmup_steps"): lattices small enough to replay
+  their steps as HIP graphs warm up by at least 64 steps, so that the graphs are captured
+  before the timed region.
 
   --suite sparse: the paper's sparse-geometry study (Sec. 4.3, Fig. 8): sparse efficiency
               eta_P (Eq. 9) over porosity for regular and random circle obstacles, per layout.
@@ -92,13 +103,16 @@ def measured_traffic(kernel_key):
     return rec.get("bytes_per_launch")
 
 
-def time_steps(lat, steps, warmup):
-    """(seconds for `steps` steps, per-step ms) with HIP events on the lattice's stream.
-    The warm-up is at least 64 steps, so that a lattice replaying its steps as HIP graphs
-    has captured them (a one-time cost of a few ms) before the timed region."""
+def time_steps(lat, steps, warmup, min_warmup=0):
+    """(seconds for `steps` steps, per-step ms, warm-up steps run) with HIP events on the
+    lattice's stream, after max(warmup, min_warmup) untimed steps.  Lattices that replay
+    their steps as HIP graphs (small ones) pass min_warmup = 64, so that both parity graphs
+    are captured (a one-time cost of a few ms) before the timed region; each record states
+    the warm-up it ran."""
     import torch
     stream = torch.cuda.current_stream()
-    lat.step(max(warmup, 64))
+    warm = max(warmup, min_warmup)
+    lat.step(warm)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -107,10 +121,45 @@ def time_steps(lat, steps, warmup):
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
-    return ms / 1e3, ms / max(steps, 1)
+    return ms / 1e3, ms / max(steps, 1), warm
 
 
-def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0, mrt=None):
+def device_velocity(lat):
+    """(u_x, u_y) of a D2Q9 lattice as device FP64 tensors [ny, nx] (solid nodes 0)."""
+    import torch
+    ux = torch.empty((lat.ny, lat.nx), dtype=torch.float64, device="cuda")
+    uy = torch.empty_like(ux)
+    lat.macroscopic_device(None, ux, uy)
+    return ux, uy
+
+
+def l2_rel(u, ref):
+    """Relative L2 distance of velocity fields (tuples of device FP64 tensors; solid nodes
+    hold 0 in both, so they add nothing)."""
+    import torch
+    num = sum(((a - b) ** 2).sum() for a, b in zip(u, ref))
+    den = sum((b ** 2).sum() for b in ref)
+    return float(torch.sqrt(num / den))
+
+
+def taylor_green_velocity(n, u0, tau, t):
+    """Closed-form Taylor-Green velocity after t steps: the initial field decayed by
+    exp(-2 nu k^2 t), nu = (tau - 1/2) / 3 (Eq. 5), k = 2 pi / n; device FP64 tensors."""
+    import torch
+    k = 2.0 * math.pi / n
+    nu = (tau - 0.5) / 3.0
+    dec = math.exp(-2.0 * nu * k * k * t)
+    x = torch.arange(n, dtype=torch.float64, device="cuda")[None, :]
+    y = torch.arange(n, dtype=torch.float64, device="cuda")[:, None]
+    return (-u0 * dec * torch.cos(k * x) * torch.sin(k * y),
+            u0 * dec * torch.sin(k * x) * torch.cos(k * y))
+
+
+def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0, mrt=None, ref=None,
+                  keep=False):
+    """Taylor-Green n^2 throughput.  ref: the FP64 velocity field after the same number of
+    steps (device tensors), against which the row's velocity error is stated; keep: also
+    return this run's velocity field (for use as such a reference)."""
     import synthetic
     m = synthetic.all_fluid(n, n)
     lat = lbm.Lattice(m, 0.6, dtype=dtype, layout=layout)
@@ -118,41 +167,70 @@ def measure_dense(lbm, n, dtype, layout, steps, warmup, fields, trt=0.0, mrt=Non
     if mrt is not None:
         lat.set_mrt(mrt)
     lat.init_equilibrium(*fields)
-    secs, ms = time_steps(lat, steps, warmup)
+    M0 = lat.mass() if (ref is not None or keep) else None
+    secs, ms, warm = time_steps(lat, steps, warmup)
     info = lat.info()
-    mass_ok = None
+    u = None
+    extra = {}
+    if ref is not None or keep:
+        u = device_velocity(lat)
+        extra["mass_drift"] = (lat.mass() - M0) / M0
+        if ref is not None:
+            extra["l2_err_vs_fp64"] = l2_rel(u, ref)
+            extra["l2_err_reference"] = ("FP64 HIP path, same layout, collision and step count "
+                                         "(pinned to the oracle by sampled-window parity at "
+                                         "4096^2)")
     lat.close()
     nf = info["n_fluid"]
     glups = nf * steps / secs / 1e9
     bpn = algorithmic_bytes_per_node(dtype)
     model = (f" TRT magic={trt:g}" if trt else "") + \
         (" MRT s_e,s_eps,s_q=" + ",".join(f"{v:g}" for v in mrt) if mrt is not None else "")
-    return {"workload": f"taylor-green {n}^2" + model,
-            "dtype": dtype, "layout": layout,
-            "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
-            "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
-            "paper_U_B_bytes": 18 * POP_BYTES[dtype], "bytes_per_node": bpn,
-            "mass_check": mass_ok}
+    row = {"workload": f"taylor-green {n}^2" + model,
+           "dtype": dtype, "layout": layout,
+           "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
+           "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
+           "paper_U_B_bytes": 18 * POP_BYTES[dtype], "bytes_per_node": bpn,
+           "steps": steps, "warmup_steps": warm, **extra}
+    return (row, u) if keep else row
 
 
-def measure_d3q19(lbm, n, dtype, steps, warmup, layout="dense_ab", mrt=None):
+def measure_d3q19(lbm, n, dtype, steps, warmup, layout="dense_ab", mrt=None, ref=None,
+                  keep=False):
     """D3Q19 dense A-B (or AA) step on the periodic n^3 three-dimensional Taylor-Green
-    vortex.  AA timings cover an even number of steps (odd and even kernels alike)."""
+    vortex.  AA timings cover an even number of steps (odd and even kernels alike).  ref /
+    keep: as for measure_dense (velocity fields as device tensors)."""
+    import torch
+
     import synthetic
     m = np.zeros((n, n, n), np.uint8)
     lat = lbm.Lattice3D(m, 0.6, dtype=dtype, layout=layout)
     if mrt is not None:
         lat.set_mrt(mrt)
     lat.init_equilibrium(*synthetic.taylor_green3(n, 0.01))
-    secs, ms = time_steps(lat, steps, warmup)
+    M0 = lat.mass() if (ref is not None or keep) else None
+    secs, ms, warm = time_steps(lat, steps, warmup)
     nf = lat.info()["n_fluid"]
+    u = None
+    extra = {}
+    if ref is not None or keep:
+        fields = [torch.empty((n, n, n), dtype=torch.float64, device="cuda") for _ in range(4)]
+        lat.macroscopic_device(*fields)
+        u = tuple(fields[1:])
+        extra["mass_drift"] = (lat.mass() - M0) / M0
+        if ref is not None:
+            extra["l2_err_vs_fp64"] = l2_rel(u, ref)
+            extra["l2_err_reference"] = "FP64 HIP path, same layout and step count"
+        del fields
     lat.close()
     glups = nf * steps / secs / 1e9
     bpn = 38 * POP_BYTES[dtype] + 1
-    return {"workload": f"d3q19 taylor-green {n}^3" + (" MRT" if mrt is not None else ""),
-            "dtype": dtype, "layout": layout,
-            "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
-            "frac_of_peak": glups * bpn / HBM_PEAK_GBPS, "bytes_per_node": bpn}
+    row = {"workload": f"d3q19 taylor-green {n}^3" + (" MRT" if mrt is not None else ""),
+           "dtype": dtype, "layout": layout,
+           "glups": glups, "ms_per_step": ms, "hbm_gbps": glups * bpn,
+           "frac_of_peak": glups * bpn / HBM_PEAK_GBPS, "bytes_per_node": bpn,
+           "steps": steps, "warmup_steps": warm, **extra}
+    return (row, u) if keep else row
 
 
 def measure_end_to_end(lbm, n, fields, steps):
@@ -201,10 +279,15 @@ def measure_copy(lbm, nbytes, reps=20):
     return {"bytes": nbytes, "gbps": 2 * nbytes / s / 1e9, "frac_of_peak": 2 * nbytes / s / 1e9 / HBM_PEAK_GBPS}
 
 
-def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask, wall="halfway"):
+def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask, wall="halfway",
+                   dense_ms_per_node=None):
+    """Porous discs (walls at y = 0 and n - 1, periodic x, g_x = 1e-6, tau = 0.6): GLUPS per
+    fluid node (Eq. 8 counts non-solid nodes only).  dense_ms_per_node: time per node of the
+    dense A-B step on the all-fluid n^2 lattice in the same dtype; the row then states its
+    time per fluid node relative to it (the sparse target is 1.3)."""
     lat = lbm.Lattice(mask, 0.6, force=(1e-6, 0.0), dtype=dtype, layout=layout)
     lat.set_bounce_back(wall)
-    secs, ms = time_steps(lat, steps, warmup)
+    secs, ms, warm = time_steps(lat, steps, warmup)
     info = lat.info()
     lat.close()
     nf = info["n_fluid"]
@@ -215,17 +298,72 @@ def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask, wall="halfwa
            "dtype": dtype, "layout": layout,
            "n_fluid": nf, "glups_per_fluid_node": glups, "ms_per_step": ms,
            "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
-           "bytes_moved_per_step": info["bytes_moved_per_step"]}
+           "bytes_moved_per_step": info["bytes_moved_per_step"],
+           "steps": steps, "warmup_steps": warm}
+    if dense_ms_per_node:
+        out["time_per_fluid_node_over_dense_all_fluid"] = (ms / nf) / dense_ms_per_node
     if layout == "tiled16":
         out["tile_occupancy"] = nf / max(1, info["n_tiles"] * 256)
     return out
+
+
+def measure_reduced(lbm, case, n, steps=5000):
+    """Reduced-precision storage at the stated configuration: `steps` steps from the initial
+    state, for FP64 (the reference), FP32, FP16 and BF16 shifted storage.  case "tgv": the
+    n^2 Taylor-Green vortex, dense A-B; case "porous": the n^2 porous discs at fluid fraction
+    0.5 with g_x = 1e-6, tiled layout.  Each row: GLUPS (timed over the `steps` steps) and its
+    ratio to the FP32 path, the velocity field's relative L2 error against the FP64 run and
+    (vortex) against the closed-form decay, and the relative mass drift."""
+    import torch
+
+    import synthetic
+    if case == "tgv":
+        mask = synthetic.all_fluid(n, n)
+        fields, g, layout = synthetic.taylor_green(n, 0.01), (0.0, 0.0), "dense_ab"
+        name = f"reduced precision: taylor-green {n}^2, {steps} steps"
+        exact = taylor_green_velocity(n, 0.01, 0.6, steps)
+    else:
+        mask, _ = synthetic.porous_discs(n, 0.5)
+        fields, g, layout = None, (1e-6, 0.0), "tiled16"
+        name = f"reduced precision: porous discs {n}^2 phi=0.5 g_x=1e-6, {steps} steps"
+        exact = None
+    rows, ref = [], None
+    for dtype in ("f64", "f32", "f16s", "bf16s"):
+        lat = lbm.Lattice(mask, 0.6, force=g, dtype=dtype, layout=layout)
+        if fields is not None:
+            lat.init_equilibrium(*fields)
+        M0 = lat.mass()
+        secs, ms, _ = time_steps(lat, steps, 0)
+        u = device_velocity(lat)
+        drift = (lat.mass() - M0) / M0
+        nf = lat.info()["n_fluid"]
+        lat.close()
+        row = {"workload": name, "dtype": dtype, "layout": layout, "steps": steps,
+               "glups": nf * steps / secs / 1e9, "ms_per_step": ms, "mass_drift": drift}
+        if ref is None:
+            ref = u
+        else:
+            row["l2_err_vs_fp64"] = l2_rel(u, ref)
+            row["l2_err_reference"] = ("FP64 HIP path, same layout and step count (pinned to "
+                                       "the oracle by sampled-window parity at 4096^2)")
+        if exact is not None:
+            row["l2_err_vs_closed_form"] = l2_rel(u, exact)
+        rows.append(row)
+        if dtype != "f64":
+            del u
+    f32 = next(r["glups"] for r in rows if r["dtype"] == "f32")
+    for r in rows:
+        r["glups_over_fp32_path"] = r["glups"] / f32
+    del ref, exact
+    torch.cuda.empty_cache()
+    return rows
 
 
 def measure_porous3(lbm, n, phi, dtype, layout, steps, warmup, mask):
     """D3Q19 sphere packing (walls in z, body force along x): dense A-B (solid nodes skipped)
     against the fluid-node list, GLUPS per fluid node."""
     lat = lbm.Lattice3D(mask, 0.6, force=(1e-6, 0.0, 0.0), dtype=dtype, layout=layout)
-    secs, ms = time_steps(lat, steps, warmup)
+    secs, ms, _ = time_steps(lat, steps, warmup)
     info = lat.info()
     lat.close()
     nf = info["n_fluid"]
@@ -245,7 +383,7 @@ def measure_open_channel(lbm, inlet, dtype, layout, steps, warmup, nx=4096, ny=5
     lat.set_boundaries(bc, val)
     if inlet == "pressure":
         lat.init_equilibrium(np.full((ny, nx), 1.008), None, None)
-    secs, ms = time_steps(lat, steps, warmup)
+    secs, ms, _ = time_steps(lat, steps, warmup, min_warmup=64)
     nf = lat.info()["n_fluid"]
     lat.close()
     glups = nf * steps / secs / 1e9
@@ -265,7 +403,7 @@ def measure_small_channel(lbm, steps=2000):
     for name, g in (("launch_per_step", 0), ("hip_graph_32", 32)):
         lat = lbm.Lattice(m, 0.8, force=(1e-6, 0.0), dtype="f64", layout="dense_ab")
         lat.set_graph_steps(g)
-        secs, ms = time_steps(lat, steps, 64)
+        secs, ms, _ = time_steps(lat, steps, 64)
         out[f"us_per_step_{name}"] = ms * 1e3
         lat.close()
     return out
@@ -331,7 +469,7 @@ def measure_sparse_geometry(lbm, geom, dtype, layout, steps, warmup):
     m, bc, val, info = geom
     lat = lbm.Lattice(m, 2.0, dtype=dtype, layout=layout)
     lat.set_boundaries(bc, val)
-    secs, ms = time_steps(lat, steps, warmup)
+    secs, ms, _ = time_steps(lat, steps, warmup, min_warmup=64)
     li = lat.info()
     lat.close()
     nf = li["n_fluid"]
@@ -392,9 +530,9 @@ def measure_adjoint(lbm, steps=200, T=2000):
     lat = lbm.Lattice(m, 0.8, force=(1e-5, 0.0), dtype="f32", layout="dense_ab")
     lat.set_porosity(alpha)
     lat.set_graph_steps(0)
-    fwd_s, fwd_ms = time_steps(lat, steps, 20)
+    fwd_s, fwd_ms, _ = time_steps(lat, steps, 20)
     lat.set_graph_steps(-1)
-    _, fwd_graph_ms = time_steps(lat, steps, 20)
+    _, fwd_graph_ms, _ = time_steps(lat, steps, 64)
     sb = lat.state_bytes()
     state = torch.empty(sb, dtype=torch.uint8, device="cuda")
     lat.save_state(state)
@@ -454,7 +592,7 @@ def measure_adjoint_large(lbm, n=4096, steps=50):
     alpha = synthetic.brinkman_alpha(n, n, seed=7, sigma=8.0).astype(np.float32)
     lat = lbm.Lattice(m, 0.8, force=(1e-5, 0.0), dtype="f32", layout="dense_ab")
     lat.set_porosity(alpha)
-    fwd_s, fwd_ms = time_steps(lat, steps, 10)
+    fwd_s, fwd_ms, _ = time_steps(lat, steps, 10)
     state = torch.empty(lat.state_bytes(), dtype=torch.uint8, device="cuda")
     lat.save_state(state)
     ab, _ = lat.adjoint_bytes()
@@ -551,7 +689,10 @@ def main():
     fields = synthetic.taylor_green(n, 0.01)
 
     log(f"[bench] headline: taylor-green {n}^2 f64 dense_ab, {args.warmup}+{args.steps} steps")
-    head = measure_dense(lbm, n, "f64", "dense_ab", args.steps, args.warmup, fields)
+    keep = args.suite in ("default", "full")
+    head = measure_dense(lbm, n, "f64", "dense_ab", args.steps, args.warmup, fields, keep=keep)
+    if keep:
+        head, u64 = head
     log(f"[bench]   {head['glups']:.2f} GLUPS, {head['hbm_gbps']:.0f} GB/s")
     variants = []
     if args.suite == "sparse":
@@ -561,21 +702,63 @@ def main():
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
         variants.append({"workload": "copy kernel 1 GiB", **c})
     if args.suite in ("default", "full"):
+        dense_ms_per_node = {"f64": head["ms_per_step"] / (n * n)}
         for dtype, layout in [("f32", "dense_ab"), ("f64", "dense_aa"), ("f32", "dense_aa"),
                               ("f16s", "dense_ab"), ("bf16s", "dense_ab")]:
-            r = measure_dense(lbm, n, dtype, layout, args.steps, args.warmup, fields)
-            log(f"[bench]   {dtype} {layout}: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
+            r = measure_dense(lbm, n, dtype, layout, args.steps, args.warmup, fields,
+                              ref=u64 if dtype in ("f16s", "bf16s") else None)
+            err = f", L2 err vs FP64 {r['l2_err_vs_fp64']:.2e}" if "l2_err_vs_fp64" in r else ""
+            log(f"[bench]   {dtype} {layout}: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f}){err}")
             variants.append(r)
+            if layout == "dense_ab" and dtype == "f32":
+                dense_ms_per_node["f32"] = r["ms_per_step"] / (n * n)
+        del u64
         for dtype in ("f64", "f32"):
             r = measure_dense(lbm, n, dtype, "dense_ab", args.steps, args.warmup, fields,
                               trt=3.0 / 16.0)
             log(f"[bench]   {dtype} dense_ab TRT: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
             variants.append(r)
+        u_mrt = None
         for dtype in ("f64", "f32", "f16s"):
             r = measure_dense(lbm, n, dtype, "dense_ab", args.steps, args.warmup, fields,
-                              mrt=(1.19, 1.4, 1.2))
-            log(f"[bench]   {dtype} dense_ab MRT: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
+                              mrt=(1.19, 1.4, 1.2), keep=dtype == "f64",
+                              ref=u_mrt if dtype == "f16s" else None)
+            if dtype == "f64":
+                r, u_mrt = r
+            err = f", L2 err vs FP64 {r['l2_err_vs_fp64']:.2e}" if "l2_err_vs_fp64" in r else ""
+            log(f"[bench]   {dtype} dense_ab MRT: {r['glups']:.2f} GLUPS "
+                f"({r['frac_of_peak']:.3f}){err}")
             variants.append(r)
+        del u_mrt
+        # sparse geometries (porous discs at three fluid fractions; per-fluid-node rates)
+        for phi in (0.9, 0.5, 0.2):
+            mask, minfo = synthetic.porous_discs(n, phi)
+            log(f"[bench]   porous phi={phi}: achieved {minfo['phi_achieved']:.3f}")
+            for dtype in ("f64", "f32"):
+                for layout in ("dense_ab", "tiled16", "indirect"):
+                    r = measure_porous(lbm, n, phi, dtype, layout, args.steps, args.warmup,
+                                       mask, dense_ms_per_node=dense_ms_per_node[dtype])
+                    r["phi_achieved"] = minfo["phi_achieved"]
+                    log(f"[bench]   phi={phi} {dtype} {layout}: "
+                        f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid, time per fluid node "
+                        f"{r['time_per_fluid_node_over_dense_all_fluid']:.2f}x dense")
+                    variants.append(r)
+            del mask
+        # reduced-precision storage at its stated configuration
+        for case, nn in (("tgv", 2048), ("porous", n)):
+            for r in measure_reduced(lbm, case, nn):
+                cf = (f", vs closed form {r['l2_err_vs_closed_form']:.2e}"
+                      if "l2_err_vs_closed_form" in r else "")
+                ef = f", L2 err vs FP64 {r['l2_err_vs_fp64']:.2e}" if "l2_err_vs_fp64" in r else ""
+                log(f"[bench]   {r['workload']} {r['dtype']}: {r['glups']:.2f} GLUPS "
+                    f"({r['glups_over_fp32_path']:.2f}x FP32){ef}{cf}, "
+                    f"mass drift {r['mass_drift']:.1e}")
+                variants.append(r)
+        # adjoint against forward (1024 x 256 channel with drag field, T = 2000)
+        a = measure_adjoint(lbm)
+        log(f"[bench]   adjoint/forward = {a['adjoint_over_forward']:.2f} per step; "
+            f"checkpointed backward/forward = {a['checkpointed_backward_over_forward']:.2f}")
+        variants.append(a)
         c = measure_copy(lbm, 1 << 30)
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
         variants.append({"workload": "copy kernel 1 GiB", **c})
@@ -592,10 +775,17 @@ def main():
             f"(upload + init {r['upload_init_s'] * 1e3:.0f} ms, read-back "
             f"{r['download_macroscopic_s'] * 1e3:.0f} ms)")
         variants.append(r)
+        u3 = None
         for dtype in ("f64", "f32", "f16s"):
-            r = measure_d3q19(lbm, 256, dtype, args.steps // 2, args.warmup)
-            log(f"[bench]   d3q19 256^3 {dtype}: {r['glups']:.2f} GLUPS ({r['frac_of_peak']:.3f})")
+            r = measure_d3q19(lbm, 256, dtype, args.steps // 2, args.warmup, keep=dtype == "f64",
+                              ref=u3 if dtype == "f16s" else None)
+            if dtype == "f64":
+                r, u3 = r
+            err = f", L2 err vs FP64 {r['l2_err_vs_fp64']:.2e}" if "l2_err_vs_fp64" in r else ""
+            log(f"[bench]   d3q19 256^3 {dtype}: {r['glups']:.2f} GLUPS "
+                f"({r['frac_of_peak']:.3f}){err}")
             variants.append(r)
+        del u3
         for dtype in ("f64", "f32"):
             r = measure_d3q19(lbm, 256, dtype, 2 * (args.steps // 4), args.warmup, "dense_aa")
             log(f"[bench]   d3q19 256^3 {dtype} dense_aa: {r['glups']:.2f} GLUPS "
@@ -630,16 +820,6 @@ def main():
                     r = measure_dense(lbm, nn, dtype, layout, args.steps, args.warmup, f2)
                     log(f"[bench]   {nn} {dtype} {layout}: {r['glups']:.2f} GLUPS")
                     variants.append(r)
-        for phi in (0.9, 0.5, 0.2):
-            mask, info = synthetic.porous_discs(n, phi)
-            log(f"[bench]   porous phi={phi}: achieved {info['phi_achieved']:.3f}")
-            for dtype in ("f32", "f64"):
-                for layout in ("dense_ab", "tiled16", "indirect"):
-                    r = measure_porous(lbm, n, phi, dtype, layout, args.steps // 2,
-                                       args.warmup // 2, mask)
-                    log(f"[bench]   phi={phi} {dtype} {layout}: "
-                        f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid")
-                    variants.append(r)
         mask_p, _ = synthetic.porous_discs(n, 0.5)
         for dtype in ("f32", "f64"):
             for layout in ("dense_ab", "indirect"):
@@ -661,10 +841,6 @@ def main():
             f"({al['adjoint_frac_of_peak']:.3f}) vs forward {al['forward_ms_per_step'] * 1e3:.1f} us "
             f"({al['forward_frac_of_peak']:.3f}): {al['adjoint_over_forward']:.2f}x")
         variants.append(al)
-        a = measure_adjoint(lbm)
-        log(f"[bench]   adjoint/forward = {a['adjoint_over_forward']:.2f} per step; "
-            f"checkpointed backward/forward = {a['checkpointed_backward_over_forward']:.2f}")
-        variants.append(a)
 
     bpn = algorithmic_bytes_per_node("f64")
     bytes_per_launch = bpn * n * n
