@@ -306,6 +306,22 @@ int lbm_adjoint_seed_outlet_ux(lbm_ctx *ctx, int32_t x_col, double dJ, void *mu_
 int lbm_adjoint_step(lbm_ctx *ctx, const void *state_t_dev, const void *mu_in_dev,
                      void *mu_out_dev, double *grad_alpha_dev, double *grad_g_dev);
 
+/* lbm_adjoint_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and arguments and bitwise the same results, but the per-block
+ * dJ/dg partials and their reduction stage live in a fixed array of 2^17 doubles
+ * (1 MiB) that each GPU the library runs on holds until the process ends, so
+ * the call allocates nothing (lbm_adjoint_step allocates its partials on first
+ * use).  The array fits lattices of up to 16376 row segments of 256 nodes
+ * (ceil(nx / 256) * ny <= 16376, e.g. 1024 x 4094 or 2048 x 2047); larger
+ * lattices get LBM_ERR_UNSUPPORTED and nothing is launched.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from different host threads) race on it; calls queued on one
+ * stream do not.  The first call on a device looks the array up
+ * (hipGetSymbolAddress) and may synchronise with that device. */
+int lbm_adjoint_step_noalloc(lbm_ctx *ctx, const void *state_t_dev, const void *mu_in_dev,
+                             void *mu_out_dev, double *grad_alpha_dev, double *grad_g_dev);
+
 /* Checkpointed forward run: advance T steps from the current state, saving the
  * raw state before steps 0, K, 2K, ... into ckpt_dev (ceil(T / K) slots of
  * lbm_state_bytes each, caller-owned). */

@@ -321,6 +321,13 @@ class Lattice:
             self._ctx, _dev(state, self.state_bytes(), "state"), self._mu(mu_in, "mu_in"),
             self._mu(mu_out, "mu_out"), *self._grads(grad_alpha, grad_g)))
 
+    def adjoint_step_noalloc(self, state, mu_in, mu_out, grad_alpha, grad_g):
+        """adjoint_step without any device allocation (partials in the library's fixed
+        per-device scratch array; lattices up to 16376 row segments of 256 nodes)."""
+        self._check(self._lib.lbm_adjoint_step_noalloc(
+            self._ctx, _dev(state, self.state_bytes(), "state"), self._mu(mu_in, "mu_in"),
+            self._mu(mu_out, "mu_out"), *self._grads(grad_alpha, grad_g)))
+
     def run_checkpointed(self, T, K, ckpt):
         n = self._slots(T, K) * self.state_bytes()
         self._check(self._lib.lbm_run_checkpointed(self._ctx, int(T), int(K),

@@ -76,6 +76,7 @@ SIGNATURES = {
     "lbm_adjoint_set": (_c.c_int, [_vp, _vp, _dp]),
     "lbm_adjoint_seed_outlet_ux": (_c.c_int, [_vp, _i32, _c.c_double, _vp, _vp, _vp]),
     "lbm_adjoint_step": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "lbm_adjoint_step_noalloc": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_run_checkpointed": (_c.c_int, [_vp, _i64, _i64, _vp]),
     "lbm_adjoint_checkpointed": (_c.c_int, [_vp, _i64, _i64, _vp, _vp, _i32, _c.c_double, _vp,
                                             _vp]),

@@ -12,6 +12,8 @@
 // collision's statements backwards (reverse-mode differentiation by hand).
 // Gradients accumulate in FP64; the per-block dJ/dg partials are summed in a
 // fixed order, so results are repeatable.
+#include <mutex>
+
 #include "lbm_device.h"
 #include "lbm_launch.h"
 
@@ -458,6 +460,57 @@ hipError_t launch_partials_into(double *partials, int64_t n, double *grad_g,
     k_pairs_stage<<<(uint32_t)nst, kBlock, 0, stream>>>(partials, (uint32_t)n, stage);
     k_partials_into<<<1, kBlock, 0, stream>>>(stage, (uint32_t)nst, grad_g);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ allocation-free scratch --
+// dJ/dg partial pairs (and their reduction stage) of lbm_adjoint_step_noalloc,
+// in a fixed array that each GPU the library runs on holds until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host it
+// names a stand-in, not device memory): it takes the device address from
+// hipGetSymbolAddress, once per device with that device current, and passes
+// that.  Every call on one GPU shares its array.
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+int64_t adjoint_step_scratch_doubles(const DevState &s)
+{
+    const int64_t n = adjoint_step_partials(s);
+    // the partial pairs, then (above 4 * kSumPer pairs) one stage pair per kSumPer
+    return 2 * (n + (n > 4 * (int64_t)kSumPer ? (n + kSumPer - 1) / kSumPer : 0));
+}
+
+hipError_t noalloc_scratch(int device, double **ptr)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess)
+            return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess)
+            return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess)
+                e = e2;
+        }
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = (double *)p;
+    }
+    *ptr = g_scratch_addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_zero(double *p, int64_t n, hipStream_t stream)

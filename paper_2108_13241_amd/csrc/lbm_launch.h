@@ -108,5 +108,13 @@ hipError_t launch_adjoint_convert(const DevState &s, void *mu, double *plain, in
 hipError_t launch_partials_into(double *partials, int64_t n, double *grad_g,
                                 hipStream_t stream);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
+// Allocation-free adjoint step: its dJ/dg partials live in a fixed per-device
+// array of kNoAllocScratchDoubles doubles (1 MiB).  adjoint_step_scratch_doubles
+// = the doubles one step needs there (partials plus reduction stage);
+// noalloc_scratch = that array's device address on `device` (looked up once
+// per device with hipGetSymbolAddress, then cached).
+constexpr int64_t kNoAllocScratchDoubles = int64_t(1) << 17;
+int64_t adjoint_step_scratch_doubles(const DevState &s);
+hipError_t noalloc_scratch(int device, double **ptr);
 
 }  // namespace lbm

@@ -1078,6 +1078,37 @@ int lbm_adjoint_step(lbm_ctx *c, const void *state_t_dev, const void *mu_in_dev,
     return LBM_OK;
 }
 
+int lbm_adjoint_step_noalloc(lbm_ctx *c, const void *state_t_dev, const void *mu_in_dev,
+                             void *mu_out_dev, double *grad_alpha_dev, double *grad_g_dev)
+{
+    LBM_CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc)
+        return rc;
+    if (!state_t_dev || !mu_in_dev || !mu_out_dev || mu_in_dev == mu_out_dev)
+        return fail(c, LBM_ERR_INVALID, "state / mu buffers must be non-NULL and mu_in != mu_out");
+    if ((rc = check_grads(c, grad_alpha_dev, grad_g_dev)))
+        return rc;
+    const int64_t need = lbm::adjoint_step_scratch_doubles(c->s);
+    if (need > lbm::kNoAllocScratchDoubles)
+        return fail(c, LBM_ERR_UNSUPPORTED,
+                    "lattice too large for the allocation-free adjoint step: it needs " +
+                        std::to_string(need) + " doubles of scratch, the fixed array holds " +
+                        std::to_string(lbm::kNoAllocScratchDoubles) +
+                        " (use lbm_adjoint_step)");
+    double *scratch = nullptr;
+    const hipError_t e = lbm::noalloc_scratch(c->device, &scratch);
+    if (e != hipSuccess)
+        return fail(c, LBM_ERR_DEVICE,
+                    std::string("cannot locate the scratch array: ") + hipGetErrorString(e));
+    // the step kernel writes (not adds) every partial pair, so nothing needs clearing
+    LBM_HIP(c, lbm::launch_adjoint_step_raw(c->s, state_t_dev, mu_in_dev, mu_out_dev,
+                                            grad_alpha_dev, scratch, 0));
+    LBM_HIP(c, lbm::launch_partials_into(scratch, lbm::adjoint_step_partials(c->s), grad_g_dev,
+                                         c->s.stream));
+    return LBM_OK;
+}
+
 int lbm_run_checkpointed(lbm_ctx *c, int64_t T, int64_t K, void *ckpt_dev)
 {
     LBM_CHECK_CTX(c);
