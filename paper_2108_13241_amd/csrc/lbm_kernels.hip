@@ -33,12 +33,12 @@ __host__ __device__ constexpr int dir_of(int ox, int oy)
 }
 
 // ------------------------------------------------------------ addressing --
-// Tiled layout: nb[i] = base offset of node x - c_i, which may lie in one of
-// the neighbouring tiles (tile_nbr row `tn` of the current tile k).  When that
-// tile is absent the offset is meaningless, but the node is then solid and
-// the caller never uses it.
-__device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const int32_t (&tn)[9],
-                                              uint32_t (&nb)[9])
+// Tiled layout: the source node x - c_i of the node at (lx, ly) of tile k lies
+// in tile kk[i] (k itself, or one of the neighbouring tiles of tile_nbr row
+// `tn`; -1 when that tile is absent, in which case the source is solid) at
+// in-tile slot sl[i].
+__device__ __forceinline__ void tiled_sources(uint32_t k, int lx, int ly, const int32_t (&tn)[9],
+                                              int32_t (&kk)[9], uint32_t (&sl)[9])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -46,15 +46,30 @@ __device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const 
         const int sx = lx - cx, sy = ly - cy;
         const bool bx = cx != 0 && (unsigned)sx > 15u;
         const bool by = cy != 0 && (unsigned)sy > 15u;
-        int32_t kk = (int32_t)k;
+        int32_t t = (int32_t)k;
         if (cx != 0 && cy != 0)
-            kk = bx ? (by ? tn[dir_of(-cx, -cy)] : tn[dir_of(-cx, 0)]) : (by ? tn[dir_of(0, -cy)] : kk);
+            t = bx ? (by ? tn[dir_of(-cx, -cy)] : tn[dir_of(-cx, 0)]) : (by ? tn[dir_of(0, -cy)] : t);
         else if (cx != 0)
-            kk = bx ? tn[dir_of(-cx, 0)] : kk;
+            t = bx ? tn[dir_of(-cx, 0)] : t;
         else if (cy != 0)
-            kk = by ? tn[dir_of(0, -cy)] : kk;
-        nb[i] = tile_base((uint32_t)kk, tile_slot((uint32_t)(sx & 15), (uint32_t)(sy & 15)));
+            t = by ? tn[dir_of(0, -cy)] : t;
+        kk[i] = t;
+        sl[i] = tile_slot((uint32_t)(sx & 15), (uint32_t)(sy & 15));
     }
+}
+
+// nb[i] = base offset of node x - c_i in the tiled layout (meaningless where
+// that node's tile is absent: the node is then solid and the caller never uses
+// it).
+__device__ __forceinline__ void tiled_offsets(uint32_t k, int lx, int ly, const int32_t (&tn)[9],
+                                              uint32_t (&nb)[9])
+{
+    int32_t kk[9];
+    uint32_t sl[9];
+    tiled_sources(k, lx, ly, tn, kk, sl);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        nb[i] = tile_base((uint32_t)kk[i], sl[i]);
 }
 
 // Indirect layout, compact neighbour description (see lbm_plan.h): info[n]
@@ -468,33 +483,108 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
 }
 
 // ------------------------------------------------------------- step: tiled --
+// One 256-lane workgroup per kept tile; lane s handles in-tile slot s (node
+// (lx, ly) = tile_node(s)), so the wavefront of slots 64 w .. 64 w + 63 covers
+// tile rows 4 w .. 4 w + 3.  Per step every fluid lane issues, at once and
+// without waiting on any node data: its nine own slots (aligned, whole lines),
+// the sources of its pulls that lie in a neighbouring tile (edge lanes only),
+// and its solid-neighbour bits.  Which lanes are fluid comes from the tile's
+// scalar description (TileMeta: the neighbouring tiles and, per wavefront, a
+// 64-bit fluid mask), so solid lanes load nothing and lines without a fluid
+// node are never fetched.
+// The own slots are staged in LDS; after one barrier each lane reads its
+// in-tile pull sources from LDS.  Bounce-back (halfway rule) takes the node's
+// own slot opp(i), already in registers; the full-way rule reads it from the
+// other lattice instead (one more load, boundary lanes only).
+__device__ __forceinline__ void tile_node(uint32_t s, int &lx, int &ly)
+{
+    lx = (int)((s & 3u) | ((s >> 2) & 12u));
+    ly = (int)(((s >> 2) & 3u) | ((s >> 4) & 12u));
+}
+
 template <class ST, int PH>
 __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
     const uint8_t *__restrict__ type, const uint8_t *__restrict__ nmask,
     const float *__restrict__ alpha, const double *__restrict__ bc_val,
-    const int32_t *__restrict__ tile_nbr, uint32_t n_tiles, typename ST::real omega,
+    const TileMeta *__restrict__ meta, uint32_t n_tiles, typename ST::real omega,
     typename ST::real gx, typename ST::real gy, Rates<typename ST::real> rt, int fullway)
 {
     using R = typename ST::real;
+    using M = typename ST::mem;
     constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
                    OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0,
                    MRT = (PH & kMRT) != 0;
+    __shared__ M stage[9 * kTileNodes];
     const uint32_t k = xcd_remap(blockIdx.x, n_tiles);
-    const int t = (int)threadIdx.x, lx = t & 15, ly = t >> 4;
-    const uint32_t n = k * kTileNodes + t;
-    const uint8_t ty = type[n];
-    if (ty == kSolid)
-        return;
-    const unsigned sm = solid_bits(ty, nmask, n);
+    const uint32_t s = threadIdx.x;
+    // per-tile scalars: the wavefront's fluid lanes and the neighbouring tiles
+    const uint32_t w = __builtin_amdgcn_readfirstlane(s >> 6);
+    const uint64_t fm = meta[k].fluid[w];
     int32_t tn[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d)
-        tn[d] = tile_nbr[k * 9 + d];
-    uint32_t nb[9];
-    tiled_offsets(k, lx, ly, tn, nb);
+        tn[d] = meta[k].nbr[d];
+    // all scalar loads (these ten and the lattice and neighbour-bit pointers) in
+    // flight together, complete before the first branch
+    asm volatile("" ::"s"(tn[0]), "s"(tn[1]), "s"(tn[2]), "s"(tn[3]), "s"(tn[4]), "s"(tn[5]),
+                 "s"(tn[6]), "s"(tn[7]), "s"(tn[8]), "s"(fm), "s"(src), "s"(nmask));
+    const bool fluid = (fm >> (s & 63u)) & 1u;
+    int lx, ly;
+    tile_node(s, lx, ly);
+    const uint32_t n = k * kTileNodes + (uint32_t)(ly * kTile + lx);  // row-major node index
+    const uint32_t own = tile_base(k, s);
+    int32_t kk[9];
+    uint32_t sl[9];
+    tiled_sources(k, lx, ly, tn, kk, sl);
+    M v[9], h[9];
+    unsigned sm = 0;
+    uint8_t ty = kFluid;
+    if (fluid) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            v[i] = src[(uint32_t)i * kTileStride + own];
+        sm = (unsigned)nmask[n] << 1;  // 0 for interior fluid nodes
+        if constexpr (OPEN)
+            ty = type[n];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            // sources in a neighbouring tile; one in an absent tile is solid
+            // (bounce-back): nothing to load
+            h[i] = M(0);
+            if (kk[i] != (int32_t)k && kk[i] >= 0)
+                h[i] = src[(uint32_t)i * kTileStride + tile_base((uint32_t)kk[i], sl[i])];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            stage[(uint32_t)i * kTileNodes + s] = v[i];
+    }
+    __syncthreads();
+    if (!fluid)
+        return;
+    // in-tile sources from the stage (read for every direction; slot sl[i] is in
+    // range whichever tile the source lies in)
+    M x[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        x[i] = stage[(uint32_t)i * kTileNodes + sl[i]];
+    M bb[9];  // bounce-back values: own slot opp(i), this lattice or (full-way) the other
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        bb[i] = v[kOpp[i]];
+    if (fullway && sm) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            if ((sm >> i) & 1u)
+                bb[i] = dst[(uint32_t)kOpp[i] * kTileStride + own];
+    }
     R f[9];
-    pull_gather<ST>(src, fullway ? dst : src, kTileStride, nb, sm, f);
+    f[0] = ST::ld(v[0], 0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const M y = ((sm >> i) & 1u) ? bb[i] : (kk[i] != (int32_t)k ? h[i] : x[i]);
+        f[i] = ST::ld(y, i);
+    }
     if constexpr (OPEN) {
         if (const unsigned open = open_code(ty))
             apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
@@ -503,7 +593,7 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
                                                          DRAG ? (R)alpha[n] : R(0), rt);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        store_nt(&dst[(uint32_t)i * kTileStride + nb[0]], ST::st(f[i], i));
+        store_nt(&dst[(uint32_t)i * kTileStride + own], ST::st(f[i], i));
 }
 
 // ---------------------------------------------------------- step: indirect --
@@ -931,7 +1021,7 @@ void step_launch(const DevState &s, int64_t t, int cur)
         const uint32_t nt = (uint32_t)s.n_tiles;
         if (nt > 0)
             k_step_tiled<ST, PH><<<nt, kTileNodes, 0, s.stream>>>(
-                src, dst, s.type, s.nmask, s.alpha, s.bc_val, s.tile_nbr, nt, om, gx, gy, omm,
+                src, dst, s.type, s.nmask, s.alpha, s.bc_val, s.tile_meta, nt, om, gx, gy, omm,
                 s.fullway);
     } else {
         const uint32_t nf = (uint32_t)s.n_fluid;

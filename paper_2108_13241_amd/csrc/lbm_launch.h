@@ -14,6 +14,17 @@ enum Layout : int { kDenseAB = 0, kDenseAA = 1, kTiled16 = 2, kIndirect = 3 };
 constexpr int kTile = 16;
 constexpr int kTileNodes = kTile * kTile;
 
+// Per-tile scalars of the tiled step, one 128-byte row per kept tile: the
+// tile-neighbour row (as tile_nbr; entry 0 = the tile itself) and, per 64-slot
+// wavefront w, its fluid lanes (bit l of fluid[w] <=> slot 64 w + l is fluid).
+struct alignas(128) TileMeta {
+    int32_t nbr[9];
+    int32_t pad[7];
+    uint64_t fluid[4];
+    uint64_t pad2[4];
+};
+static_assert(sizeof(TileMeta) == 128, "one 128-byte row per tile");
+
 // Everything a kernel launch needs to know about a context's device state.
 struct DevState {
     int dtype = 0, layout = 0;
@@ -27,6 +38,7 @@ struct DevState {
     const float *alpha = nullptr;     // drag coefficient, same indexing as type
                                       // (INDIRECT: per compacted node); may be null
     const int32_t *tile_xy = nullptr, *tile_nbr = nullptr;  // TILED16
+    const TileMeta *tile_meta = nullptr;  // TILED16: [n_tiles], the step's per-tile scalars
     const int32_t *fluid_xy = nullptr;                      // INDIRECT: [n][2]
     const uint32_t *ind_pk = nullptr;                       // INDIRECT: packed row offsets
     const uint16_t *ind_info = nullptr;                     // INDIRECT: solid bits + edge flag

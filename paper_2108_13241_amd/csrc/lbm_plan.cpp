@@ -104,6 +104,19 @@ void tiled_types(const uint8_t *mask, int nx, int ny, const Tiles &t, std::vecto
         }
 }
 
+void tile_fluid_masks(const Tiles &t, const std::vector<uint8_t> &type,
+                      std::vector<uint64_t> &fluid)
+{
+    fluid.assign((size_t)t.n_tiles * 4, 0);
+    for (int64_t k = 0; k < t.n_tiles; ++k)
+        for (unsigned s = 0; s < 256; ++s) {
+            const unsigned lx = (s & 3u) | ((s >> 2) & 12u);
+            const unsigned ly = ((s >> 2) & 3u) | ((s >> 4) & 12u);
+            if (type[(size_t)k * 256 + ly * 16 + lx] != 1)
+                fluid[(size_t)k * 4 + (s >> 6)] |= uint64_t(1) << (s & 63u);
+        }
+}
+
 Fluid fluid_list(const uint8_t *mask, int nx, int ny)
 {
     Fluid f;

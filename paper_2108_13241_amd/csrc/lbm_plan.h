@@ -41,6 +41,12 @@ Tiles tiles16(const uint8_t *mask, int nx, int ny, bool keep_all = false);
 // Tile-layout type codes / nmask / node lists ([n_tiles][256]).
 void tiled_types(const uint8_t *mask, int nx, int ny, const Tiles &t, std::vector<uint8_t> &type,
                  std::vector<uint8_t> &nmask);
+// Fluid bit masks of the tiles' in-tile slots, four 64-slot words per tile:
+// bit l of fluid[4 k + w] set <=> the node in slot 64 w + l of tile k is fluid.
+// Slots hold the tile's nodes in 4 x 4 blocks: slot bits ly3 ly2 | lx3 lx2 |
+// ly1 ly0 | lx1 lx0; `type` is the row-major [n_tiles][256] array of tiled_types.
+void tile_fluid_masks(const Tiles &t, const std::vector<uint8_t> &type,
+                      std::vector<uint64_t> &fluid);
 
 struct Fluid {
     int64_t n_fluid = 0;

@@ -368,6 +368,20 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
         if ((rc = upload(c->tiles.nbr.data(), c->tiles.nbr.size() * 4, &p)))
             return fail_create(rc, "cannot upload the tile-neighbour table");
         s.tile_nbr = (const int32_t *)p;
+        std::vector<uint64_t> fluid;
+        lbm::plan::tile_fluid_masks(c->tiles, type, fluid);
+        std::vector<lbm::TileMeta> meta((size_t)s.n_tiles);
+        for (int64_t k = 0; k < s.n_tiles; ++k) {
+            lbm::TileMeta &m = meta[(size_t)k];
+            std::memset(&m, 0, sizeof(m));
+            for (int d = 0; d < 9; ++d)
+                m.nbr[d] = c->tiles.nbr[(size_t)k * 9 + d];
+            for (int w = 0; w < 4; ++w)
+                m.fluid[w] = fluid[(size_t)k * 4 + w];
+        }
+        if ((rc = upload(meta.data(), meta.size() * sizeof(lbm::TileMeta), &p)))
+            return fail_create(rc, "cannot upload the tile descriptions");
+        s.tile_meta = (const lbm::TileMeta *)p;
     } else {
         c->fluid = lbm::plan::fluid_list(node_type, nx, ny);
         s.n_fluid = c->fluid.n_fluid;
