@@ -55,7 +55,9 @@ __device__ __forceinline__ unsigned open_code(uint8_t code)
 // kExact: FP32 reciprocals are Newton-refined; the 16-bit codecs, whose storage
 // rounding (2^-11 or 2^-8 of a deviation) dwarfs a 1-ulp FP32 reciprocal error,
 // use the raw hardware reciprocal and save the refinement's instructions.
-// kAligned: interior dense segments gather with aligned loads and lane shifts
+// kAligned: in the per-node path of the dense step (interior wavefronts of a
+// row's partial last segment; whole interior segments are staged in LDS), full
+// interior wavefronts gather with aligned loads and lane shifts
 // (dense_pull_aligned).  It pays off for the 2-byte formats, whose shifted
 // 128-byte wavefront loads would touch two cache lines instead of one; for FP32
 // and FP64 the plain shifted loads are as fast and move slightly fewer bytes.

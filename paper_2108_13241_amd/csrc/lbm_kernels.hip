@@ -13,6 +13,7 @@
 #include "lbm_device.h"
 #include "lbm_launch.h"
 
+
 namespace lbm {
 namespace {
 
@@ -362,14 +363,125 @@ __device__ __forceinline__ void dense_ab_node(const DenseArgs<ST> &k, int x, int
     dense_collide_store<ST, PH>(k, a, n, f);
 }
 
+// Per-node A-B step (one node per lane, shifted loads straight from the
+// lattice): the kernel for lattices small enough that a step is bound by
+// latency rather than bandwidth, where staging a segment through LDS and a
+// barrier costs more than it saves.
 template <class ST, int PH>
-__global__ __launch_bounds__(kBlock) void k_step_dense_ab(const DenseArgs<ST> k)
+__global__ __launch_bounds__(kBlock) void k_step_dense_ab_direct(const DenseArgs<ST> k)
 {
     int x, y;
     uint32_t L;
     if (!dense_node(k.bpr, k.nblocks, k.nx, x, y, L))
         return;
     dense_ab_node<ST, PH>(k, x, y, L);
+}
+
+// A-B step: a workgroup updates one 256-node row segment.  When the segment is
+// all-interior and whole (x0 + 256 <= nx), it first copies, for each direction
+// i, the 256 source values of its row (row y - c_i.y, columns x0 - c_i.x ..)
+// into LDS with aligned 16-byte loads (each 64-node chunk run is contiguous and
+// 512 B aligned), all in flight together, plus the one column beyond the
+// segment's end that the x-shifted directions need; after a barrier every lane
+// reads its nine shifted sources from LDS.  FP64 also returns its results
+// through LDS and writes them as aligned 16-byte vectors (measured: 1 % faster
+// for FP64, 1-3 % slower for the narrower types, which store directly).  Other
+// segments (solid or boundary nodes, or the row's partial last segment) run the
+// per-node path.
+template <class ST, int PH>
+__global__ __launch_bounds__(kBlock) void k_step_dense_ab(const DenseArgs<ST> k)
+{
+    using R = typename ST::real;
+    using M = typename ST::mem;
+    constexpr uint32_t kE = 16u / (uint32_t)sizeof(M);  // elements per 16-byte vector
+    constexpr uint32_t kVpc = kChunk / kE;             // vectors per 64-node chunk run
+    constexpr uint32_t kV = 9u * 4u * kVpc;            // vectors per segment
+    // row i: [kE - 1] = column x0 - 1, [kE .. kE + 255] = the segment (16-byte
+    // aligned), [kE + 256] = column x0 + 256
+    __shared__ __align__(16) M stage[9][kBlock + 2 * kE];
+    const uint32_t L = xcd_remap(blockIdx.x, k.nblocks);
+    const int y = (int)(L / k.bpr);
+    const int x0 = (int)(L - (uint32_t)y * k.bpr) * kBlock;
+    const int x = x0 + (int)threadIdx.x;
+    const bool whole = k.seg_interior[L] != 0 && x0 + kBlock <= k.nx;
+    if (!whole) {
+        if (x < k.nx)
+            dense_ab_node<ST, PH>(k, x, y, L);
+        return;
+    }
+    const uint32_t cpr = (uint32_t)k.pitch / kChunk;
+    const uint64_t row = (uint64_t)cpr * (9u * kChunk);
+    const uint64_t rb[3] = {(uint64_t)wrap_dec(y, k.ny) * row, (uint64_t)y * row,
+                            (uint64_t)wrap_inc(y, k.ny) * row};
+    const uint32_t c0 = (uint32_t)x0 >> 6;
+    // c_i of a runtime direction index, without a table lookup
+    auto dcx = [](uint32_t i) { return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0); };
+    auto dcy = [](uint32_t i) { return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0); };
+    // halo: lanes 1..8 with c_i.x != 0 fetch the column beyond the segment on
+    // the side direction i pulls from
+    M hv = M(0);
+    const uint32_t hi = threadIdx.x;
+    const int hcx = hi < 9u ? dcx(hi) : 0;
+    if (hcx != 0) {
+        const int xs = hcx > 0 ? wrap_dec(x0, k.nx) : wrap_inc(x0 + kBlock - 1, k.nx);
+        hv = k.src[rb[1 - dcy(hi)] + (uint64_t)hi * kChunk + col_off(xs)];
+    }
+    // the segment's runs: all loads in flight before any LDS write, no branch
+    // in between (indices past the last vector repeat the last one: the same
+    // value to the same place)
+    constexpr uint32_t kIter = (kV + kBlock - 1) / kBlock;
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u vv[kIter];
+    uint32_t dst_el[kIter];
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m) {
+        const uint32_t q = min(threadIdx.x + m * kBlock, kV - 1u);
+        const uint32_t i = q / (4u * kVpc), r = q - i * (4u * kVpc);
+        const uint32_t cc = r / kVpc, pc = r - cc * kVpc;
+        const uint64_t off = rb[1 - dcy(i)] + (uint64_t)(c0 + cc) * (9u * kChunk) +
+                             (uint64_t)i * kChunk + (uint64_t)pc * kE;
+        vv[m] = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(k.src + off));
+        dst_el[m] = i * (kBlock + 2 * kE) + kE + cc * kChunk + pc * kE;
+    }
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m)
+        *reinterpret_cast<v4u *>(&stage[0][0] + dst_el[m]) = vv[m];
+    if (hcx != 0)
+        stage[hi][hcx > 0 ? kE - 1 : kE + kBlock] = hv;
+    __syncthreads();
+    R f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = ST::ld(stage[i][(int)kE + (int)threadIdx.x - kCx[i]], i);
+    if constexpr (sizeof(M) != 8) {
+        const DenseRC a = dense_rc(x, y, k.nx, k.ny, cpr);
+        dense_collide_store<ST, PH>(k, a, (uint32_t)y * k.pitch + x, f);
+    } else {
+        // results back through LDS, then stored as aligned 16-byte vectors
+        using RR = R;
+        constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
+                       TRT = (PH & kTRT) != 0, MRT = (PH & kMRT) != 0;
+        const uint32_t n = (uint32_t)y * k.pitch + x;
+        collide<RR, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, k.omega, k.gx, k.gy,
+                                                                DRAG ? (RR)k.alpha[n] : RR(0), k.rt);
+        __syncthreads();  // every lane has read its sources
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            stage[i][kE + threadIdx.x] = ST::st(f[i], i);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t m = 0; m < kIter; ++m) {
+            const uint32_t q = threadIdx.x + m * kBlock;
+            if (q < kV) {
+                const uint32_t i = q / (4u * kVpc), r = q - i * (4u * kVpc);
+                const uint32_t cc = r / kVpc, pc = r - cc * kVpc;
+                const uint64_t off = rb[1] + (uint64_t)(c0 + cc) * (9u * kChunk) +
+                                     (uint64_t)i * kChunk + (uint64_t)pc * kE;
+                const v4u v = *reinterpret_cast<const v4u *>(&stage[i][kE + cc * kChunk + pc * kE]);
+                __builtin_nontemporal_store(v, reinterpret_cast<v4u *>(k.dst + off));
+            }
+        }
+    }
 }
 
 // Two rows per workgroup (rows y0 = 2 p and y0 + 1 of one 256-column segment),
@@ -560,8 +672,25 @@ __global__ __launch_bounds__(kTileNodes) void k_step_tiled(
             stage[(uint32_t)i * kTileNodes + s] = v[i];
     }
     __syncthreads();
-    if (!fluid)
+    if (!fluid) {
+        if constexpr (sizeof(M) >= 4) {
+            // FP64 / FP32: a solid slot sharing its 128-byte line with a fluid
+            // slot stores a placeholder (never read: pulls from solid nodes take
+            // bounce-back values), so that every line the step writes is written
+            // whole.  Lines left partly written cost the memory system more than
+            // the extra bytes (measured: 8 % / 14 % faster at fluid fraction 0.5;
+            // 256- or 512-byte granules and the 2-byte types gain nothing).
+            constexpr uint32_t G = 128u / (uint32_t)sizeof(M);
+            const uint32_t l = s & 63u;
+            const uint64_t gm = (fm >> (l & ~(G - 1u))) & ((uint64_t(1) << G) - 1u);
+            if (gm) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    store_nt(&dst[(uint32_t)i * kTileStride + own], M(0));
+            }
+        }
         return;
+    }
     // in-tile sources from the stage (read for every direction; slot sl[i] is in
     // range whichever tile the source lies in)
     M x[9];
@@ -986,6 +1115,7 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src
 }
 
 // ---------------------------------------------------------------- dispatch --
+
 template <class ST, int PH>
 void step_launch(const DevState &s, int64_t t, int cur)
 {
@@ -1002,9 +1132,18 @@ void step_launch(const DevState &s, int64_t t, int cur)
             DenseArgs<ST> k{src,   dst,  s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val,
                             s.nx,  s.ny, s.pitch, bpr,   nblocks,        om,      gx,
                             gy,    omm,  s.fullway};
-            if constexpr (ST::kAligned) {
-                k.nblocks = bpr * (uint32_t)((s.ny + 1) / 2);
-                k_step_dense_ab2<ST, PH><<<k.nblocks, kBlock, 0, s.stream>>>(k);
+            // Kernel choice (measured): the per-node kernel while a step moves less
+            // than 128 MiB (latency-bound: 1024 x 256 FP32 forward 4.8 us against
+            // 5.6 us through LDS); the two-row kernel for 16-bit MRT (109 us against
+            // 123 us at 4096^2); the LDS-staged kernel otherwise.
+            const bool small = 18.0 * (double)s.plane * sizeof(M) < 128.0 * (1 << 20);
+            if (small || (ST::kAligned && (PH & kMRT))) {
+                if constexpr (ST::kAligned) {
+                    k.nblocks = bpr * (uint32_t)((s.ny + 1) / 2);
+                    k_step_dense_ab2<ST, PH><<<k.nblocks, kBlock, 0, s.stream>>>(k);
+                } else {
+                    k_step_dense_ab_direct<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(k);
+                }
             } else {
                 k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(k);
             }

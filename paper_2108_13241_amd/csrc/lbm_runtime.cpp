@@ -78,6 +78,12 @@ struct lbm_ctx {
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     int32_t graph_len = 0;
     hipStream_t capture_stream = nullptr;
+    // Overlapped checkpointed adjoint: a second segment buffer (library-owned),
+    // an auxiliary stream for the segment recomputation and its events.
+    void *seg2 = nullptr;
+    size_t seg2_bytes = 0;
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -255,6 +261,13 @@ void lbm_destroy(lbm_ctx *c)
     drop_graphs(c);
     if (c->capture_stream)
         (void)hipStreamDestroy(c->capture_stream);
+    if (c->aux_stream) {
+        (void)hipStreamSynchronize(c->aux_stream);
+        (void)hipStreamDestroy(c->aux_stream);
+    }
+    for (auto &e : c->ev)
+        if (e)
+            (void)hipEventDestroy(e);
     for (auto &b : c->owned)
         raw_free(c->alloc, b.first);
     delete c;
@@ -1142,6 +1155,27 @@ int lbm_run_checkpointed(lbm_ctx *c, int64_t T, int64_t K, void *ckpt_dev)
     return LBM_OK;
 }
 
+// Segment recomputation of the checkpointed adjoint: the states of segment
+// `seg` (steps t0 .. t0 + len - 1) from its checkpoint; st[0] = the checkpoint,
+// st[j] = slot j of the segment buffer, stepped on the stream of r.
+static int recompute_segment(lbm_ctx *c, lbm::DevState &r, const void *ckpt_dev, void *buf,
+                             int64_t seg, int64_t K, int64_t T, size_t sb,
+                             std::vector<const void *> &st)
+{
+    const int64_t t0 = seg * K, len = std::min<int64_t>(K, T - t0);
+    st[0] = (const char *)ckpt_dev + (size_t)seg * sb;
+    for (int64_t j = 1; j < len; ++j) {
+        st[j] = (const char *)buf + (size_t)j * sb;
+        r.f[0] = const_cast<void *>(st[j - 1]);
+        r.f[1] = const_cast<void *>(st[j]);
+        LBM_HIP(c, lbm::launch_step(r, t0 + j - 1, 0));
+    }
+    return LBM_OK;
+}
+
+// Largest second segment buffer the overlapped adjoint allocates on its own.
+constexpr size_t kOverlapBudget = size_t(2) << 30;
+
 int lbm_adjoint_checkpointed(lbm_ctx *c, int64_t T, int64_t K, const void *ckpt_dev, void *seg_dev,
                              int32_t x_col, double dJ, double *grad_alpha_dev, double *grad_g_dev)
 {
@@ -1168,21 +1202,81 @@ int lbm_adjoint_checkpointed(lbm_ctx *c, int64_t T, int64_t K, const void *ckpt_
     // state at T) are never written.
     lbm::DevState r = c->s;
     const int64_t nseg = (T + K - 1) / K;
-    std::vector<const void *> st((size_t)K);
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t t0 = seg * K, len = std::min<int64_t>(K, T - t0);
-        st[0] = (const char *)ckpt_dev + (size_t)seg * sb;
-        for (int64_t j = 1; j < len; ++j) {
-            st[j] = (const char *)seg_dev + (size_t)j * sb;
-            r.f[0] = const_cast<void *>(st[j - 1]);
-            r.f[1] = const_cast<void *>(st[j]);
-            LBM_HIP(c, lbm::launch_step(r, t0 + j - 1, 0));
-        }
+    auto adjoint_segment = [&](const std::vector<const void *> &st, int64_t seg) -> int {
+        const int64_t len = std::min<int64_t>(K, T - seg * K);
         for (int64_t j = len - 1; j >= 0; --j) {
             LBM_HIP(c, lbm::launch_adjoint_step_raw(c->s, st[j], c->mu_buf[mu], c->mu_buf[1 - mu],
                                                     grad_alpha_dev, c->adj_partials, 1));
             mu ^= 1;
         }
+        return LBM_OK;
+    };
+    // With a second segment buffer the recomputation of segment s - 1 runs on an
+    // auxiliary stream while the adjoint steps of segment s run on the context's
+    // stream: at sizes where one kernel leaves most of the GPU idle the two
+    // overlap.  The buffer is library-owned, allocated on first use when it
+    // fits kOverlapBudget; otherwise (or for one segment) the two alternate.
+    const size_t seg_bytes = (size_t)K * sb;
+    bool overlap = nseg > 1 && K > 1 && seg_bytes <= kOverlapBudget;
+    if (overlap && c->seg2_bytes < seg_bytes) {
+        void *p = own_alloc(c, seg_bytes);
+        if (p) {
+            c->seg2 = p;
+            c->seg2_bytes = seg_bytes;
+        } else {
+            overlap = false;
+        }
+    }
+    if (overlap && !c->aux_stream) {
+        if (hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) != hipSuccess) {
+            c->aux_stream = nullptr;
+            overlap = false;
+        }
+    }
+    for (int k = 0; overlap && k < 5; ++k)
+        if (!c->ev[k] && hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) {
+            c->ev[k] = nullptr;
+            overlap = false;
+        }
+    if (!overlap) {
+        std::vector<const void *> st((size_t)K);
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            if ((rc = recompute_segment(c, r, ckpt_dev, seg_dev, seg, K, T, sb, st)))
+                return rc;
+            if ((rc = adjoint_segment(st, seg)))
+                return rc;
+        }
+    } else {
+        // ev[0]: start (everything enqueued so far on the context's stream);
+        // ev[1 + b]: segment buffer b recomputed; ev[3 + b]: buffer b no longer read.
+        void *buf[2] = {seg_dev, c->seg2};
+        std::vector<const void *> st[2] = {std::vector<const void *>((size_t)K),
+                                           std::vector<const void *>((size_t)K)};
+        hipStream_t s0 = c->s.stream, s1 = c->aux_stream;
+        r.stream = s1;
+        LBM_HIP(c, hipEventRecord(c->ev[0], s0));
+        LBM_HIP(c, hipStreamWaitEvent(s1, c->ev[0], 0));
+        if ((rc = recompute_segment(c, r, ckpt_dev, buf[0], nseg - 1, K, T, sb, st[0])))
+            return rc;
+        LBM_HIP(c, hipEventRecord(c->ev[1], s1));
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const int b = (int)((nseg - 1 - seg) & 1);
+            if (seg > 0) {
+                // buffer 1 - b was last read by the adjoint steps of segment seg + 1
+                if (seg + 1 <= nseg - 1)
+                    LBM_HIP(c, hipStreamWaitEvent(s1, c->ev[3 + (1 - b)], 0));
+                if ((rc = recompute_segment(c, r, ckpt_dev, buf[1 - b], seg - 1, K, T, sb,
+                                            st[1 - b])))
+                    return rc;
+                LBM_HIP(c, hipEventRecord(c->ev[1 + (1 - b)], s1));
+            }
+            LBM_HIP(c, hipStreamWaitEvent(s0, c->ev[1 + b], 0));
+            if ((rc = adjoint_segment(st[b], seg)))
+                return rc;
+            LBM_HIP(c, hipEventRecord(c->ev[3 + b], s0));
+        }
+        // the last recomputation (segment 0) was waited for above, so the
+        // context's stream is now ordered after all work of the auxiliary one
     }
     LBM_HIP(c, lbm::launch_partials_into(c->adj_partials, nb, grad_g_dev, c->s.stream));
     return LBM_OK;
