@@ -29,13 +29,15 @@ protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on stdout:
   their steps as HIP graphs warm up by at least 64 steps, so that the graphs are captured
   before the timed region.
 
+  --suite porous: the headline, the FP32 dense step and the 4096^2 porous-disc rows only
+              (the sparse layouts' profiling workload).
   --suite sparse: the paper's sparse-geometry study (Sec. 4.3, Fig. 8): sparse efficiency
               eta_P (Eq. 9) over porosity for regular and random circle obstacles, per layout.
   --suite spheres3: the copy kernel and the D3Q19 256^3 sphere packings (dense A-B against
               the fluid-node list), for the list kernel's counters.
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 100]
-                       [--suite default|full|headline|sparse|spheres3]
+                       [--suite default|full|headline|porous|sparse|spheres3]
 """
 from __future__ import annotations
 
@@ -307,6 +309,28 @@ def measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask, wall="halfwa
     return out
 
 
+def porous_rows(lbm, n, steps, warmup, dense_ms_per_node):
+    """The n^2 porous discs at fluid fractions 0.9, 0.5 and 0.2 in the dense, tiled and
+    indirect layouts, FP64 and FP32 (GLUPS per fluid node and time per fluid node against
+    the dense all-fluid step of the same dtype)."""
+    import synthetic
+    rows = []
+    for phi in (0.9, 0.5, 0.2):
+        mask, minfo = synthetic.porous_discs(n, phi)
+        log(f"[bench]   porous phi={phi}: achieved {minfo['phi_achieved']:.3f}")
+        for dtype in ("f64", "f32"):
+            for layout in ("dense_ab", "tiled16", "indirect"):
+                r = measure_porous(lbm, n, phi, dtype, layout, steps, warmup, mask,
+                                   dense_ms_per_node=dense_ms_per_node[dtype])
+                r["phi_achieved"] = minfo["phi_achieved"]
+                log(f"[bench]   phi={phi} {dtype} {layout}: "
+                    f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid, time per fluid node "
+                    f"{r['time_per_fluid_node_over_dense_all_fluid']:.2f}x dense")
+                rows.append(r)
+        del mask
+    return rows
+
+
 def measure_reduced(lbm, case, n, steps=5000):
     """Reduced-precision storage at the stated configuration: `steps` steps from the initial
     state, for FP64 (the reference), FP32, FP16 and BF16 shifted storage.  case "tgv": the
@@ -551,10 +575,14 @@ def measure_adjoint(lbm, steps=200, T=2000):
     e1.record()
     torch.cuda.synchronize()
     adj_ms = e0.elapsed_time(e1) / steps
-    # checkpointed drivers
+    # checkpointed drivers (one untimed forward + backward first: the first backward on a
+    # context also creates its auxiliary stream and second segment buffer)
     K = int(math.ceil(math.sqrt(T)))
     ckpt = torch.empty(((T + K - 1) // K) * sb, dtype=torch.uint8, device="cuda")
     seg = torch.empty(K * sb, dtype=torch.uint8, device="cuda")
+    lat.init_equilibrium(None, None, None)
+    lat.run_checkpointed(T, K, ckpt)
+    lat.adjoint_checkpointed(T, K, ckpt, seg, nx - 1, 1.0, ga, gg)
     lat.init_equilibrium(None, None, None)
     torch.cuda.synchronize()
     e0.record()
@@ -667,7 +695,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--suite", default="default",
-                    choices=["default", "full", "headline", "sparse", "spheres3"])
+                    choices=["default", "full", "headline", "porous", "sparse", "spheres3"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-reps", type=int, default=20)
     args = ap.parse_args()
@@ -697,6 +725,12 @@ def main():
     variants = []
     if args.suite == "sparse":
         variants.extend(sparse_study(lbm, n, max(args.steps // 5, 20), max(args.warmup // 5, 5)))
+    if args.suite == "porous":
+        f32 = measure_dense(lbm, n, "f32", "dense_ab", args.steps, args.warmup, fields)
+        variants.append(f32)
+        variants.extend(porous_rows(lbm, n, args.steps, args.warmup,
+                                    {"f64": head["ms_per_step"] / (n * n),
+                                     "f32": f32["ms_per_step"] / (n * n)}))
     if args.suite == "headline":
         c = measure_copy(lbm, 1 << 30, reps=args.copy_reps)
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
@@ -731,19 +765,7 @@ def main():
             variants.append(r)
         del u_mrt
         # sparse geometries (porous discs at three fluid fractions; per-fluid-node rates)
-        for phi in (0.9, 0.5, 0.2):
-            mask, minfo = synthetic.porous_discs(n, phi)
-            log(f"[bench]   porous phi={phi}: achieved {minfo['phi_achieved']:.3f}")
-            for dtype in ("f64", "f32"):
-                for layout in ("dense_ab", "tiled16", "indirect"):
-                    r = measure_porous(lbm, n, phi, dtype, layout, args.steps, args.warmup,
-                                       mask, dense_ms_per_node=dense_ms_per_node[dtype])
-                    r["phi_achieved"] = minfo["phi_achieved"]
-                    log(f"[bench]   phi={phi} {dtype} {layout}: "
-                        f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid, time per fluid node "
-                        f"{r['time_per_fluid_node_over_dense_all_fluid']:.2f}x dense")
-                    variants.append(r)
-            del mask
+        variants.extend(porous_rows(lbm, n, args.steps, args.warmup, dense_ms_per_node))
         # reduced-precision storage at its stated configuration
         for case, nn in (("tgv", 2048), ("porous", n)):
             for r in measure_reduced(lbm, case, nn):
