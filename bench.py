@@ -22,7 +22,9 @@ protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on stdout:
               drift, GLUPS against the FP32 path); the adjoint against the forward step
               (1024 x 256 channel with drag field, T = 2000, sqrt(T) checkpoints); the copy
               kernel, the open-boundary channels, the end-to-end rate with host transfers and
-              the D3Q19 lattice (256^3 three-dimensional Taylor-Green vortex); with
+              the D3Q19 lattice (256^3 three-dimensional Taylor-Green vortex; a 256^3 sphere
+              packing at fluid fraction 0.4 in the dense, 4 x 4 x 4-block tiled and
+              node-list layouts, time per fluid node against the dense all-fluid step); with
               --suite full also 1024^2 / 2048^2, full-way walls, set-up and view costs and
               the adjoint at 4096^2.
   Each variant states the warm-up it ran ("warmup_steps"): lattices small enough to replay
@@ -33,8 +35,9 @@ protocol is 100 warm-up + 1000 timed kernel calls).  One JSON line on stdout:
               (the sparse layouts' profiling workload).
   --suite sparse: the paper's sparse-geometry study (Sec. 4.3, Fig. 8): sparse efficiency
               eta_P (Eq. 9) over porosity for regular and random circle obstacles, per layout.
-  --suite spheres3: the copy kernel and the D3Q19 256^3 sphere packings (dense A-B against
-              the fluid-node list), for the list kernel's counters.
+  --suite spheres3: the copy kernel and the D3Q19 256^3 sphere packings (dense A-B, the
+              4 x 4 x 4-block tiled layout and the fluid-node list), for the sparse D3Q19
+              kernels' counters.
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 100]
                        [--suite default|full|headline|porous|sparse|spheres3]
@@ -383,19 +386,28 @@ def measure_reduced(lbm, case, n, steps=5000):
     return rows
 
 
-def measure_porous3(lbm, n, phi, dtype, layout, steps, warmup, mask):
-    """D3Q19 sphere packing (walls in z, body force along x): dense A-B (solid nodes skipped)
-    against the fluid-node list, GLUPS per fluid node."""
+def measure_porous3(lbm, n, phi, dtype, layout, steps, warmup, mask, dense_ms_per_node=None):
+    """D3Q19 sphere packing (walls in z, body force along x): dense A-B (solid nodes skipped),
+    the 4 x 4 x 4-block tiled layout and the fluid-node list, GLUPS per fluid node.
+    dense_ms_per_node: time per node of the dense A-B step on the all-fluid n^3 lattice in the
+    same dtype; the row then states its time per fluid node relative to it."""
     lat = lbm.Lattice3D(mask, 0.6, force=(1e-6, 0.0, 0.0), dtype=dtype, layout=layout)
-    secs, ms, _ = time_steps(lat, steps, warmup)
+    secs, ms, warm = time_steps(lat, steps, warmup)
     info = lat.info()
     lat.close()
     nf = info["n_fluid"]
     glups = nf * steps / secs / 1e9
     bpn = info["bytes_per_fluid_node"]
-    return {"workload": f"d3q19 sphere packing {n}^3 phi={phi}", "dtype": dtype,
-            "layout": layout, "n_fluid": nf, "glups_per_fluid_node": glups, "ms_per_step": ms,
-            "bytes_per_fluid_node": bpn, "frac_of_peak": glups * bpn / HBM_PEAK_GBPS}
+    out = {"workload": f"d3q19 sphere packing {n}^3 phi={phi}", "dtype": dtype,
+           "layout": layout, "n_fluid": nf, "glups_per_fluid_node": glups, "ms_per_step": ms,
+           "bytes_per_fluid_node": bpn, "frac_of_peak": glups * bpn / HBM_PEAK_GBPS,
+           "steps": steps, "warmup_steps": warm}
+    if dense_ms_per_node:
+        out["time_per_fluid_node_over_dense_all_fluid"] = (ms / nf) / dense_ms_per_node
+    if layout == "tiled16":
+        b = (mask.reshape(n // 4, 4, n // 4, 4, n // 4, 4) == 0).any(axis=(1, 3, 5))
+        out["block_occupancy"] = nf / max(1, int(b.sum()) * 64)
+    return out
 
 
 def measure_open_channel(lbm, inlet, dtype, layout, steps, warmup, nx=4096, ny=512):
@@ -798,11 +810,13 @@ def main():
             f"{r['download_macroscopic_s'] * 1e3:.0f} ms)")
         variants.append(r)
         u3 = None
+        d3_ms_per_node = {}
         for dtype in ("f64", "f32", "f16s"):
             r = measure_d3q19(lbm, 256, dtype, args.steps // 2, args.warmup, keep=dtype == "f64",
                               ref=u3 if dtype == "f16s" else None)
             if dtype == "f64":
                 r, u3 = r
+            d3_ms_per_node[dtype] = r["ms_per_step"] / 256 ** 3
             err = f", L2 err vs FP64 {r['l2_err_vs_fp64']:.2e}" if "l2_err_vs_fp64" in r else ""
             log(f"[bench]   d3q19 256^3 {dtype}: {r['glups']:.2f} GLUPS "
                 f"({r['frac_of_peak']:.3f}){err}")
@@ -819,6 +833,18 @@ def main():
             log(f"[bench]   d3q19 256^3 {dtype} MRT: {r['glups']:.2f} GLUPS "
                 f"({r['frac_of_peak']:.3f})")
             variants.append(r)
+        # sparse D3Q19: sphere packing at fluid fraction 0.4 in the dense, block-tiled and
+        # node-list layouts, time per fluid node against the all-fluid dense step above
+        m3 = synthetic.random_spheres3(256, 0.4)
+        for dtype in ("f64", "f32"):
+            for layout in ("dense_ab", "tiled16", "indirect"):
+                r = measure_porous3(lbm, 256, 0.4, dtype, layout, args.steps // 2, args.warmup,
+                                    m3, dense_ms_per_node=d3_ms_per_node[dtype])
+                log(f"[bench]   d3q19 spheres 256^3 phi=0.4 {dtype} {layout}: "
+                    f"{r['glups_per_fluid_node']:.2f} GLUPS/fluid, time per fluid node "
+                    f"{r['time_per_fluid_node_over_dense_all_fluid']:.2f}x dense")
+                variants.append(r)
+        del m3
     if args.suite == "spheres3":
         c = measure_copy(lbm, 1 << 30, reps=args.copy_reps)
         log(f"[bench]   copy kernel: {c['gbps']:.0f} GB/s")
@@ -827,7 +853,7 @@ def main():
         for phi in (0.7, 0.4):
             m3 = synthetic.random_spheres3(256, phi)
             for dtype in ("f32", "f64"):
-                for layout in ("dense_ab", "indirect"):
+                for layout in ("dense_ab", "tiled16", "indirect"):
                     r = measure_porous3(lbm, 256, phi, dtype, layout, args.steps // 2,
                                         args.warmup, m3)
                     log(f"[bench]   d3q19 spheres 256^3 phi={phi} {dtype} {layout}: "

@@ -8,13 +8,17 @@
  * walls (Sec. 3), the BGK operator of Eqs. 3-5 and the equilibrium of Eq. 6 with
  * the D3Q19 weights, plus a body force through Guo's forcing term and, as
  * options, the two- and multiple-relaxation-time collisions and the full-way
- * wall rule.  Three layouts, as lbm.h's: DENSE_AB, two dense lattices swapped every
- * step, and DENSE_AA, one dense lattice updated in place with the AA access
- * pattern (even steps read and write each node's own slots, odd steps read from
- * and write to the neighbours; half the memory); and INDIRECT, the sparse
+ * wall rule.  Four layouts, as lbm.h's: DENSE_AB, two dense lattices swapped
+ * every step, and DENSE_AA, one dense lattice updated in place with the AA
+ * access pattern (even steps read and write each node's own slots, odd steps
+ * read from and write to the neighbours; half the memory); INDIRECT, a sparse
  * layout: two lattices holding the fluid nodes only (row-major order) with a
  * per-node table of the 18 pull sources (the fluid-index-array approach of
- * lbm.h's INDIRECT, Sec. 1).
+ * lbm.h's INDIRECT, Sec. 1); and TILED16, the tiled sparse layout of Sec. 4.3
+ * cut for three dimensions: the mesh in 4 x 4 x 4-node blocks (64 nodes, one
+ * wavefront), only the blocks that hold a fluid node stored (TILED16_ALL: all
+ * blocks), each block's 19 directions as contiguous runs of 64, with an
+ * 18-entry block-neighbour table per block.
  *
  * Conventions (as in lbm.h, whose status codes, dtype enum and allocator hook
  * this interface shares)
@@ -57,7 +61,8 @@ typedef struct lbm3d_ctx lbm3d_ctx; /* opaque; owned by the library until lbm3d_
 typedef struct {
     int32_t nx, ny, nz;
     int32_t dtype;
-    int32_t layout;              /* LBM_DENSE_AB, LBM_DENSE_AA or LBM_INDIRECT */
+    int32_t layout;              /* LBM_DENSE_AB, LBM_DENSE_AA, LBM_INDIRECT,
+                                    LBM_TILED16 or LBM_TILED16_ALL */
     int64_t n_nodes;             /* nx * ny * nz */
     int64_t n_fluid;             /* fluid nodes: the ones counted for LUPS (Eq. 8) */
     int64_t time_step;           /* steps since the last (re)initialisation */
@@ -65,7 +70,9 @@ typedef struct {
     double bytes_per_fluid_node; /* algorithmic bytes per fluid node per step:
                                     38 * pop_bytes + 1 (node type; INDIRECT:
                                     + 36 instead, the source table: eight
-                                    row ranks and the solid bits) */
+                                    row ranks and the solid bits; TILED16:
+                                    + 88 / 64, the block table and fluid
+                                    bits per stored node) */
     size_t device_bytes;         /* device memory held by the context */
 } lbm3d_info_t;
 
@@ -88,10 +95,14 @@ typedef struct {
  *              38 * pop_bytes + 48 bytes per fluid node: two lattices, the
  *              compact source table (eight row ranks, the solid bits) and the
  *              coordinates, plus 72 bytes per fluid node at x = 0 or nx - 1,
- *              whose 18 sources are listed in full); the tiled layouts are
- *              UNSUPPORTED.
+ *              whose 18 sources are listed in full), LBM_TILED16 (4 x 4 x 4
+ *              blocks holding a fluid node, nx, ny and nz multiples of 4:
+ *              38 * pop_bytes * 64 bytes per stored block for the two
+ *              lattices, plus 100 bytes of block table, fluid bits and
+ *              coordinates) or LBM_TILED16_ALL (the same with every block).
  * Errors: INVALID (sizes, tau, force, mask values, dtype, layout), UNSUPPORTED
- * (size limit, sparse layout), NOMEM, DEVICE. */
+ * (size limit, block layout on sizes that are not multiples of 4), NOMEM,
+ * DEVICE. */
 int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint8_t *node_type,
                  double tau, const double *force, lbm_dtype dtype, lbm_layout layout);
 

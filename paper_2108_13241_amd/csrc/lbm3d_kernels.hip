@@ -599,6 +599,178 @@ __global__ __launch_bounds__(kBlock) void k_step3_list(
         store_nt(&dst[lelem(n, i)], ST::st(f[i], i));
 }
 
+// ------------------------------------------------------- TILED16: 4x4x4 blocks --
+// The tiled layout of the paper's sparse study (Sec. 4.3: only tiles that hold
+// fluid nodes are stored, with a table of neighbour tiles) cut for D3Q19: blocks
+// of 4 x 4 x 4 nodes, one wavefront each, populations [n_blocks][19][64] with
+// node (lx, ly, lz) of a block in slot lx + 4 ly + 16 lz, so that every
+// direction's 64 values of a block are one contiguous run.  The pull source
+// x - c_i of a node lies in its own block or, on the faces the step crosses, in
+// the neighbour block whose offset has the components of -c_i on the crossed
+// axes; that offset is itself a D3Q19 velocity (no D3Q19 velocity has three
+// non-zero components), so the 18-entry neighbour table covers every source.
+constexpr uint32_t kBlockElems = Q * kChunk;
+constexpr uint32_t kBlockMeta = 20;  // words per block of the block table
+
+__device__ __forceinline__ uint64_t belem(uint32_t k, int i, uint32_t l)
+{
+    return (uint64_t)k * kBlockElems + (uint32_t)i * kChunk + l;
+}
+
+// Direction with velocity (cx, cy, cz); 0 when there is none (with constant
+// arguments the search folds away).
+__device__ __forceinline__ constexpr int dir3(int cx, int cy, int cz)
+{
+    for (int j = 1; j < Q; ++j)
+        if (kCx[j] == cx && kCy[j] == cy && kCz[j] == cz)
+            return j;
+    return 0;
+}
+
+struct BlockTable {
+    const uint32_t *meta;   // [n_blocks][20]: neighbours in directions 1..18, all-fluid flag
+    const uint64_t *fluid;  // [n_blocks + 1]: fluid bits per slot (entry n_blocks = 0)
+};
+
+// Block k's neighbourhood: nb[j] = the block at offset c_j (nb[0] = k; a
+// dropped block reads as index n_blocks, whose fluid bits are 0), fm[j] its
+// fluid bits, interior = every node of the 19 blocks is fluid.
+struct BlockNbrs {
+    uint32_t nb[Q];
+    uint64_t fm[Q];
+    bool interior;
+};
+
+__device__ __forceinline__ void load_block_nbrs(const BlockTable &t, uint32_t k, BlockNbrs &n)
+{
+    const uint32_t *m = t.meta + (uint64_t)k * kBlockMeta;
+    n.nb[0] = k;
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+        n.nb[j] = m[j - 1];
+    n.interior = m[18] != 0;
+    n.fm[0] = t.fluid[k];
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+        n.fm[j] = n.interior ? ~uint64_t(0) : t.fluid[n.nb[j]];
+}
+
+// v[d] of the block holding x - c_i, for the crossed faces X, Y, Z (each only
+// possible on an axis where c_i is non-zero, and never all three).
+template <class T>
+__device__ __forceinline__ T pick_cross(int i, bool X, bool Y, bool Z, const T (&v)[Q])
+{
+    T r = v[0];
+    if (X)
+        r = v[dir3(-kCx[i], 0, 0)];
+    if (Y)
+        r = X ? v[dir3(-kCx[i], -kCy[i], 0)] : v[dir3(0, -kCy[i], 0)];
+    if (Z)
+        r = X ? v[dir3(-kCx[i], 0, -kCz[i])]
+              : (Y ? v[dir3(0, -kCy[i], -kCz[i])] : v[dir3(0, 0, -kCz[i])]);
+    return r;
+}
+
+// Pull source of direction i for slot l of block k: its block b and slot, and
+// whether it is solid.  INTERIOR: the caller knows that every source is fluid.
+template <bool INTERIOR>
+__device__ __forceinline__ void block_link(const BlockNbrs &n, uint32_t l, int i, uint32_t &b,
+                                           uint32_t &slot, bool &solid)
+{
+    const int lx = (int)(l & 3u), ly = (int)((l >> 2) & 3u), lz = (int)(l >> 4);
+    const bool X = kCx[i] > 0 ? lx == 0 : (kCx[i] < 0 ? lx == 3 : false);
+    const bool Y = kCy[i] > 0 ? ly == 0 : (kCy[i] < 0 ? ly == 3 : false);
+    const bool Z = kCz[i] > 0 ? lz == 0 : (kCz[i] < 0 ? lz == 3 : false);
+    b = pick_cross(i, X, Y, Z, n.nb);
+    slot = (uint32_t)((lx - kCx[i]) & 3) | ((uint32_t)((ly - kCy[i]) & 3) << 2) |
+           ((uint32_t)((lz - kCz[i]) & 3) << 4);
+    solid = false;
+    if constexpr (!INTERIOR)
+        solid = ((pick_cross(i, X, Y, Z, n.fm) >> slot) & 1u) == 0;
+}
+
+// Pull gather of slot l of block k (pull3 for the block layout): f_i = the
+// source's slot i, or slot opp(i) of the node in bb when the source is solid
+// (bb = s: halfway bounce-back; the other lattice: full-way).  sm: bit i set
+// <=> x - c_i is solid.
+template <class ST, bool INTERIOR>
+__device__ __forceinline__ void pull_block(const typename ST::mem *__restrict__ s,
+                                           const typename ST::mem *bb, const BlockNbrs &n,
+                                           uint32_t l, uint32_t &sm, typename ST::real (&f)[Q])
+{
+    const uint32_t k = n.nb[0];
+    sm = 0;
+    f[0] = ST::ld(s[belem(k, 0, l)], 0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        uint32_t b, slot;
+        bool solid;
+        block_link<INTERIOR>(n, l, i, b, slot, solid);
+        sm |= (uint32_t)solid << i;
+        const typename ST::mem *p = solid ? &bb[belem(k, kOpp[i], l)] : &s[belem(b, i, slot)];
+        f[i] = ST::ld(*p, i);
+    }
+}
+
+// TILED16 step: a wavefront updates one block (four per workgroup).  Solid
+// lanes load nothing, so a 128-byte line of a run that holds only solid slots
+// is neither read nor written; in a line that holds a fluid slot every lane
+// stores (solid slots receive zero, which nothing reads), so that lines are
+// written whole.
+template <class ST, bool FORCE, bool TRT, bool MRT, bool INTERIOR>
+__device__ __forceinline__ void block_update(const typename ST::mem *__restrict__ src,
+                                             typename ST::mem *__restrict__ dst,
+                                             const BlockNbrs &n, uint32_t l,
+                                             typename ST::real omega, typename ST::real gx,
+                                             typename ST::real gy, typename ST::real gz,
+                                             const Rates3<typename ST::real> &rt, int fullway)
+{
+    using R = typename ST::real;
+    constexpr uint32_t G = 128u / (uint32_t)sizeof(typename ST::mem);  // slots per line
+    constexpr uint64_t kLine = G >= 64 ? ~uint64_t(0) : (uint64_t(1) << G) - 1u;
+    const bool fluid = INTERIOR || ((n.fm[0] >> l) & 1u) != 0;
+    const bool fill = INTERIOR || ((n.fm[0] >> (l & ~(G - 1u))) & kLine) != 0;
+    R f[Q];
+    if (fluid) {
+        uint32_t sm;
+        pull_block<ST, INTERIOR>(src, fullway ? dst : src, n, l, sm, f);
+        collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            f[i] = R(0);
+    }
+    if (fill) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            store_nt(&dst[belem(n.nb[0], i, l)], ST::st(f[i], i));
+    }
+}
+
+template <class ST, bool FORCE, bool TRT, bool MRT>
+__global__ __launch_bounds__(kBlock) void k_step3_blocks(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst, BlockTable t,
+    uint32_t n_blocks, uint32_t nwg, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt, int fullway)
+{
+    const uint32_t k = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, nwg) * 4u +
+                                                      (threadIdx.x >> 6));
+    if (k >= n_blocks)
+        return;
+    const uint32_t l = threadIdx.x & 63u;
+    BlockNbrs n;
+    load_block_nbrs(t, k, n);
+    if (n.interior)
+        block_update<ST, FORCE, TRT, MRT, true>(src, dst, n, l, omega, gx, gy, gz, rt, fullway);
+    else
+        block_update<ST, FORCE, TRT, MRT, false>(src, dst, n, l, omega, gx, gy, gz, rt, fullway);
+}
+
+__host__ __device__ inline BlockTable block_table(const State3 &s)
+{
+    return BlockTable{s.bmeta, s.bfluid};
+}
+
 // ------------------------------------------------------------ canonical views --
 // Canonical FP64 buffers are [19][nz][ny][pitch].
 
@@ -618,6 +790,31 @@ __device__ __forceinline__ bool canonical_at(const State3 &s, const typename ST:
                                              uint32_t &wl, double (&wv)[Q])
 {
     wl = 0;
+    if (s.blocks) {  // gid = 64 * block + slot
+        const uint32_t k = gid >> 6, l = gid & 63u;
+        if (k >= (uint64_t)s.n_blocks)
+            return false;
+        BlockNbrs n;
+        load_block_nbrs(block_table(s), k, n);
+        if (((n.fm[0] >> l) & 1u) == 0)
+            return false;
+        x = 4 * s.bxyz[3 * (uint64_t)k] + (int)(l & 3u);
+        y = 4 * s.bxyz[3 * (uint64_t)k + 1] + (int)((l >> 2) & 3u);
+        z = 4 * s.bxyz[3 * (uint64_t)k + 2] + (int)(l >> 4);
+        typename ST::real f[Q];
+        uint32_t sm;
+        pull_block<ST, false>(st, bb, n, l, sm, f);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            fd[i] = ST::canon(f[i], i);
+        if (bb != st)  // full-way: the wall slots this node feeds
+            for (int j = 1; j < Q; ++j)
+                if ((sm >> kOpp[j]) & 1u) {
+                    wl |= 1u << j;
+                    wv[j] = ST::canon(ST::ld(st[belem(k, j, l)], j), j);
+                }
+        return true;
+    }
     if (s.list) {  // gid = list index
         if (gid >= (uint64_t)s.n_fluid)
             return false;
@@ -813,6 +1010,41 @@ __global__ __launch_bounds__(kBlock) void k_scatter3(State3 s, typename ST::mem 
                                                      const double *__restrict__ fc)
 {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    if (s.blocks) {  // TILED16: gid = 64 * block + slot; as the node list below
+        const uint32_t k = gid >> 6, l = gid & 63u;
+        if (k >= (uint64_t)s.n_blocks)
+            return;
+        BlockNbrs n;
+        load_block_nbrs(block_table(s), k, n);
+        if (((n.fm[0] >> l) & 1u) == 0)
+            return;
+        const int x = 4 * s.bxyz[3 * (uint64_t)k] + (int)(l & 3u),
+                  y = 4 * s.bxyz[3 * (uint64_t)k + 1] + (int)((l >> 2) & 3u),
+                  z = 4 * s.bxyz[3 * (uint64_t)k + 2] + (int)(l >> 4);
+        const uint64_t plane = (uint64_t)(s.nz * s.ny) * (uint32_t)s.pitch;
+        const uint64_t own = ((uint64_t)z * s.ny + y) * (uint32_t)s.pitch + x;
+        uint32_t sm = 0;  // bit i <=> x - c_i solid
+        for (int i = 1; i < Q; ++i) {
+            uint32_t b, slot;
+            bool solid;
+            block_link<false>(n, l, i, b, slot, solid);
+            sm |= (uint32_t)solid << i;
+        }
+        for (int j = 0; j < Q; ++j) {
+            double v;
+            if (((sm >> kOpp[j]) & 1u) == 0 || walls == 1)
+                v = fc[(uint64_t)j * plane + node_plus(s, x, y, z, j)];
+            else
+                v = fc[(uint64_t)(walls == 2 ? j : kOpp[j]) * plane + own];
+            st[belem(k, j, l)] = ST::from_canon(v, j);
+        }
+        if (walls != 0)
+            for (int i = 1; i < Q; ++i)
+                if ((sm >> i) & 1u)
+                    other[belem(k, kOpp[i], l)] =
+                        ST::from_canon(fc[(uint64_t)i * plane + own], kOpp[i]);
+        return;
+    }
     if (s.list) {  // INDIRECT: gid = list index; s_j(q) = f_j(q + c_j), or f_opp(j)(q)
         if (gid >= (uint64_t)s.n_fluid)
             return;
@@ -899,6 +1131,23 @@ void step_launch3(const State3 &s, int cur)
     const bool force = s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0;
     const R g[3] = {force ? (R)s.gx : R(0), force ? (R)s.gy : R(0), force ? (R)s.gz : R(0)};
     const Rates3<R> rt{(R)s.omega_m, (R)s.s_e, (R)s.s_eps, (R)s.s_q, (R)s.s_pi, (R)s.s_m};
+    if (s.blocks) {
+        const uint32_t nwg = (uint32_t)((s.n_blocks + 3) / 4);
+        if (nwg == 0)
+            return;
+        const M *src = (const M *)s.f[cur];
+        M *dst = (M *)s.f[1 - cur];
+        auto go = [&](auto kernel) {
+            kernel<<<nwg, kBlock, 0, s.stream>>>(src, dst, block_table(s), (uint32_t)s.n_blocks,
+                                                 nwg, (R)s.omega, g[0], g[1], g[2], rt,
+                                                 s.fullway);
+        };
+        if (force)
+            go(k_step3_blocks<ST, true, TRT, MRT>);
+        else
+            go(k_step3_blocks<ST, false, TRT, MRT>);
+        return;
+    }
     if (s.list) {
         const uint32_t nbl = (uint32_t)((s.n_fluid + kBlock - 1) / kBlock);
         if (nbl == 0)
@@ -970,6 +1219,8 @@ uint32_t dense_blocks(const State3 &s)
 // list node (INDIRECT); 0 for an empty list.
 uint32_t node_blocks(const State3 &s)
 {
+    if (s.blocks)
+        return (uint32_t)((s.n_blocks * kChunk + kBlock - 1) / kBlock);
     if (s.list)
         return (uint32_t)((s.n_fluid + kBlock - 1) / kBlock);
     return dense_blocks(s);
@@ -1028,7 +1279,11 @@ hipError_t launch_scatter3(const State3 &s, int cur, const double *fc, int fill_
 
 hipError_t launch_rest3(const State3 &s, void *lattice)
 {
-    const uint64_t n = (uint64_t)Q * (s.list ? (uint64_t)s.np : (uint64_t)s.nz * s.ny * s.pitch);
+    // (an empty block layout still holds one block of storage)
+    const uint64_t stored = s.blocks ? (uint64_t)(s.n_blocks > 0 ? s.n_blocks : 1) * kChunk
+                          : s.list   ? (uint64_t)s.np
+                                     : (uint64_t)s.nz * s.ny * s.pitch;
+    const uint64_t n = (uint64_t)Q * stored;
     uint64_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 65536)
         blocks = 65536;

@@ -35,6 +35,17 @@ struct State3 {
     const uint32_t *info = nullptr;
     const int32_t *edge = nullptr;
     const int32_t *fxyz = nullptr;
+    // TILED16 (blocks = 1): 4 x 4 x 4-node blocks holding a fluid node (all
+    // blocks with TILED16_ALL); populations [n_blocks][19][64], slot l = lx +
+    // 4 ly + 16 lz; bmeta [n_blocks][20] (the 18 neighbour block indices,
+    // n_blocks for a dropped block, and the all-fluid flag), bfluid [n_blocks + 1]
+    // (fluid bits per slot; entry n_blocks = 0), bxyz [n_blocks][3] (block
+    // coordinates).  See lbm::plan::blocks4.
+    int blocks = 0;
+    int64_t n_blocks = 0;
+    const uint32_t *bmeta = nullptr;
+    const uint64_t *bfluid = nullptr;
+    const int32_t *bxyz = nullptr;
     const uint8_t *type = nullptr;           // 0 fluid, 1 solid, 2 fluid next to a solid
     const uint32_t *nmask = nullptr;         // bit i-1 set <=> node x - c_i is solid
     const uint32_t *seg_interior = nullptr;  // per 256-node row segment: 1 = all type 0

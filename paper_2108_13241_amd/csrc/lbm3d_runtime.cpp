@@ -1,5 +1,6 @@
 // C ABI of the D3Q19 lattice: argument checks, geometry preprocessing (node
-// types, solid-neighbour bits, interior-segment flags; lbm_plan.cpp), device
+// types, solid-neighbour bits, interior-segment flags, the node list and the
+// 4 x 4 x 4 block table; lbm_plan.cpp), device
 // buffers and kernel sequencing.  All arithmetic of the method runs in the HIP
 // kernels.
 #include "lbm3d.h"
@@ -49,6 +50,7 @@ struct lbm3d_ctx {
     size_t device_bytes = 0;
     int pop_bytes = 8;
     int64_t n_fluid = 0;
+    bool keep_all = false;  // TILED16_ALL
     double *red_out = nullptr;
 };
 
@@ -130,7 +132,12 @@ struct Temp {
 
 size_t padded_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s.pitch; }
 // Nodes of the stored lattice: the padded mesh, or the padded node list.
-size_t stored_nodes(const lbm3d_ctx *c) { return c->s.list ? (size_t)c->s.np : padded_nodes(c); }
+size_t stored_nodes(const lbm3d_ctx *c)
+{
+    if (c->s.blocks)
+        return (size_t)std::max<int64_t>(c->s.n_blocks, 1) * 64;
+    return c->s.list ? (size_t)c->s.np : padded_nodes(c);
+}
 size_t canonical_bytes(const lbm3d_ctx *c) { return (size_t)Q * padded_nodes(c) * sizeof(double); }
 size_t field_nodes(const lbm3d_ctx *c) { return (size_t)c->s.nz * c->s.ny * c->s.nx; }
 
@@ -204,8 +211,11 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
         return fail_tl(LBM_ERR_INVALID, "unknown dtype");
     if ((int)layout < 0 || (int)layout > 4)
         return fail_tl(LBM_ERR_INVALID, "unknown layout");
-    if (layout != LBM_DENSE_AB && layout != LBM_DENSE_AA && layout != LBM_INDIRECT)
-        return fail_tl(LBM_ERR_UNSUPPORTED, "D3Q19 lattices take DENSE_AB, DENSE_AA or INDIRECT");
+    const bool blocks = layout == LBM_TILED16 || layout == LBM_TILED16_ALL;
+    if (blocks && (nx % 4 || ny % 4 || nz % 4))
+        return fail_tl(LBM_ERR_UNSUPPORTED,
+                       "the D3Q19 tiled layout (4 x 4 x 4 blocks) needs nx, ny and nz multiples "
+                       "of 4");
     const int64_t pitch = ((int64_t)nx + 63) / 64 * 64;
     // population offsets are 64-bit; node indices and lane column offsets are
     // 32-bit
@@ -253,7 +263,24 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
     };
     void *p = nullptr;
     int rc;
-    if (layout == LBM_INDIRECT) {
+    if (blocks) {
+        // 4 x 4 x 4 blocks holding a fluid node (all blocks: TILED16_ALL), with
+        // the block-neighbour table, per-slot fluid bits and block coordinates
+        lbm::plan::Blocks3 b =
+            lbm::plan::blocks4(node_type, nx, ny, nz, layout == LBM_TILED16_ALL);
+        s.blocks = 1;
+        s.n_blocks = b.n_blocks;
+        c->keep_all = layout == LBM_TILED16_ALL;
+        if ((rc = upload(b.meta.data(), b.meta.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the block table");
+        s.bmeta = (const uint32_t *)p;
+        if ((rc = upload(b.fluid.data(), b.fluid.size() * 8, &p)))
+            return fail_create(rc, "cannot upload the block fluid bits");
+        s.bfluid = (const uint64_t *)p;
+        if ((rc = upload(b.xyz.data(), b.xyz.size() * 4, &p)))
+            return fail_create(rc, "cannot upload the block coordinates");
+        s.bxyz = (const int32_t *)p;
+    } else if (layout == LBM_INDIRECT) {
         // fluid nodes only: the list with its coordinates and pull-source table
         s.list = 1;
         s.np = (c->n_fluid + 63) / 64 * 64;
@@ -574,13 +601,18 @@ int lbm3d_get_info(const lbm3d_ctx *c, lbm3d_info_t *info)
     info->ny = c->s.ny;
     info->nz = c->s.nz;
     info->dtype = c->s.dtype;
-    info->layout = c->s.list ? LBM_INDIRECT : c->s.aa ? LBM_DENSE_AA : LBM_DENSE_AB;
+    info->layout = c->s.blocks ? (c->keep_all ? LBM_TILED16_ALL : LBM_TILED16)
+                   : c->s.list ? LBM_INDIRECT
+                   : c->s.aa   ? LBM_DENSE_AA
+                               : LBM_DENSE_AB;
     info->n_nodes = (int64_t)c->s.nx * c->s.ny * c->s.nz;
     info->n_fluid = c->n_fluid;
     info->time_step = c->t;
     info->pop_bytes = c->pop_bytes;
-    // node list: eight row ranks and the solid bits (36 B) instead of the type byte
-    info->bytes_per_fluid_node = 2.0 * Q * c->pop_bytes + (c->s.list ? 36.0 : 1.0);
+    // node list: eight row ranks and the solid bits (36 B) instead of the type byte;
+    // blocks: the block table and fluid bits (88 B per 64 nodes)
+    info->bytes_per_fluid_node =
+        2.0 * Q * c->pop_bytes + (c->s.list ? 36.0 : c->s.blocks ? 88.0 / 64.0 : 1.0);
     info->device_bytes = c->device_bytes;
     return LBM_OK;
 }

@@ -281,5 +281,48 @@ Fluid3 fluid_list3(const uint8_t *mask, int nx, int ny, int nz, int64_t padded)
     return fl;
 }
 
+Blocks3 blocks4(const uint8_t *mask, int nx, int ny, int nz, bool keep_all)
+{
+    Blocks3 b;
+    const int bx_n = nx / 4, by_n = ny / 4, bz_n = nz / 4;
+    std::vector<int64_t> index_of((size_t)bx_n * by_n * bz_n, -1);
+    std::vector<uint64_t> fl;
+    for (int bz = 0; bz < bz_n; ++bz)
+        for (int by = 0; by < by_n; ++by)
+            for (int bx = 0; bx < bx_n; ++bx) {
+                uint64_t m = 0;
+                for (int l = 0; l < 64; ++l) {
+                    const int x = 4 * bx + (l & 3), y = 4 * by + ((l >> 2) & 3),
+                              z = 4 * bz + (l >> 4);
+                    if (mask[((size_t)z * ny + y) * nx + x] == 0)
+                        m |= uint64_t(1) << l;
+                }
+                if (m == 0 && !keep_all)
+                    continue;
+                index_of[((size_t)bz * by_n + by) * bx_n + bx] = b.n_blocks++;
+                b.xyz.push_back(bx);
+                b.xyz.push_back(by);
+                b.xyz.push_back(bz);
+                fl.push_back(m);
+            }
+    b.fluid = fl;
+    b.fluid.push_back(0);  // the dropped blocks
+    b.meta.assign((size_t)b.n_blocks * kBlockMetaWords, 0);
+    for (int64_t k = 0; k < b.n_blocks; ++k) {
+        const int bx = b.xyz[3 * k], by = b.xyz[3 * k + 1], bz = b.xyz[3 * k + 2];
+        bool interior = b.fluid[k] == ~uint64_t(0);
+        for (int j = 1; j < 19; ++j) {
+            const int ux = wrapi(bx + kHostCx3[j], bx_n), uy = wrapi(by + kHostCy3[j], by_n),
+                      uz = wrapi(bz + kHostCz3[j], bz_n);
+            const int64_t q = index_of[((size_t)uz * by_n + uy) * bx_n + ux];
+            const int64_t e = q < 0 ? b.n_blocks : q;
+            b.meta[(size_t)k * kBlockMetaWords + j - 1] = (uint32_t)e;
+            interior = interior && b.fluid[e] == ~uint64_t(0);
+        }
+        b.meta[(size_t)k * kBlockMetaWords + 18] = interior ? 1u : 0u;
+    }
+    return b;
+}
+
 }  // namespace plan
 }  // namespace lbm

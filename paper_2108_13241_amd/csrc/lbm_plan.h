@@ -113,5 +113,25 @@ void dense_types3(const uint8_t *mask, int nx, int ny, int nz, int pitch,
                   std::vector<uint8_t> &type, std::vector<uint32_t> &nbits,
                   std::vector<uint32_t> &seg);
 
+// D3Q19 block layout (TILED16 in 3-D): the mesh cut into 4 x 4 x 4-node blocks
+// (nx, ny, nz multiples of 4), in row-major block order (bx fastest), keeping
+// the blocks that hold a fluid node (keep_all: every block).  Node (lx, ly, lz)
+// of a block sits in slot l = lx + 4 ly + 16 lz.
+//   xyz[3 k + {0, 1, 2}]    block coordinates of kept block k;
+//   meta[kBlockMetaWords k + j - 1], j = 1..18: the kept index of the block at
+//                           (bx, by, bz) + c_j (periodic), or n_blocks when that
+//                           block was dropped (it holds no fluid node);
+//   meta[kBlockMetaWords k + 18] = 1 iff block k and its 18 neighbours hold
+//                           fluid nodes only (no bounce-back link); word 19 = 0;
+//   fluid[k] bit l set <=> slot l of block k is fluid; fluid[n_blocks] = 0.
+constexpr int kBlockMetaWords = 20;
+struct Blocks3 {
+    int64_t n_blocks = 0;
+    std::vector<int32_t> xyz;
+    std::vector<uint32_t> meta;
+    std::vector<uint64_t> fluid;
+};
+Blocks3 blocks4(const uint8_t *mask, int nx, int ny, int nz, bool keep_all);
+
 }  // namespace plan
 }  // namespace lbm

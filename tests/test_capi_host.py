@@ -111,7 +111,9 @@ def _create3(lib, nx, ny, nz, m, tau=0.8, force=None, dtype=0, layout=0):
 @pytest.mark.parametrize("args,status", [
     (dict(nx=0), -1), (dict(nz=0), -1), (dict(tau=0.5), -1), (dict(tau=float("nan")), -1),
     (dict(force=(0.0, float("inf"), 0.0)), -1), (dict(dtype=4), -1), (dict(dtype=-1), -1),
-    (dict(layout=7), -1), (dict(layout=2), -4), (dict(layout=4), -4),
+    (dict(layout=7), -1),
+    # the tiled layout (4 x 4 x 4 blocks) on a mesh whose ny = 10 is no multiple of 4
+    (dict(layout=2), -4), (dict(layout=4), -4),
     # nz * ny * pitch >= 2^31 nodes, or 19 * pitch >= 2^28, is refused before the
     # mask is read or anything is allocated
     (dict(nx=1024, ny=2048, nz=1024), -4), (dict(nx=14128700, ny=1, nz=1), -4),

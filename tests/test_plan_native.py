@@ -352,3 +352,110 @@ def test_fluid_list3(planner_list3, shape, frac):
         assert _decode_list3(n, info, row[22:30], row[30:48]) == nbr, n
     if frac < 0.5 and nx > 2:
         assert 0 < border < len(rows)
+
+
+DRIVER_BLOCKS3 = textwrap.dedent(r"""
+    #include <cstdio>
+    #include <vector>
+    #include "lbm_plan.h"
+    int main() {
+        int nx, ny, nz, keep_all;
+        if (std::scanf("%d %d %d %d", &nx, &ny, &nz, &keep_all) != 4) return 2;
+        std::vector<uint8_t> mask((size_t)nx * ny * nz);
+        for (auto &m : mask) { int v; if (std::scanf("%d", &v) != 1) return 2; m = (uint8_t)v; }
+        lbm::plan::Blocks3 b = lbm::plan::blocks4(mask.data(), nx, ny, nz, keep_all != 0);
+        if ((long)b.fluid.size() != b.n_blocks + 1 || b.fluid[b.n_blocks] != 0) return 3;
+        std::printf("%ld\n", (long)b.n_blocks);
+        for (long k = 0; k < b.n_blocks; ++k) {
+            std::printf("%d %d %d", b.xyz[3 * k], b.xyz[3 * k + 1], b.xyz[3 * k + 2]);
+            for (int w = 0; w < lbm::plan::kBlockMetaWords; ++w)
+                std::printf(" %u", b.meta[(size_t)k * lbm::plan::kBlockMetaWords + w]);
+            std::printf(" %llu\n", (unsigned long long)b.fluid[k]);
+        }
+        return 0;
+    }
+""")
+
+
+@pytest.fixture(scope="module")
+def planner_blocks3(tmp_path_factory):
+    d = tmp_path_factory.mktemp("plan_blocks3")
+    src = d / "drv.cpp"
+    src.write_text(DRIVER_BLOCKS3)
+    exe = d / "drv"
+    subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-I", CSRC, str(src),
+                    os.path.join(CSRC, "lbm_plan.cpp"), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+def _block_source(nb, k, l, i):
+    """The step kernel's pull-source rule for slot l of block k, direction i: the block across
+    the crossed faces (offset = -c_i on the crossed axes, a D3Q19 velocity) and the slot."""
+    lx, ly, lz = l & 3, (l >> 2) & 3, l >> 4
+    cx, cy, cz = CX3[i], CY3[i], CZ3[i]
+    X = (cx > 0 and lx == 0) or (cx < 0 and lx == 3)
+    Y = (cy > 0 and ly == 0) or (cy < 0 and ly == 3)
+    Z = (cz > 0 and lz == 0) or (cz < 0 and lz == 3)
+    off = (-cx if X else 0, -cy if Y else 0, -cz if Z else 0)
+    b = k if off == (0, 0, 0) else nb[[(CX3[j], CY3[j], CZ3[j]) for j in range(19)].index(off)]
+    slot = ((lx - cx) & 3) | (((ly - cy) & 3) << 2) | (((lz - cz) & 3) << 4)
+    return b, slot
+
+
+@pytest.mark.parametrize("shape,frac,keep_all", [((12, 8, 8), 0.3, False), ((8, 8, 4), 0.0, False),
+                                                 ((4, 4, 4), 0.5, False), ((16, 4, 8), 0.6, True),
+                                                 ((8, 12, 4), 1.0, False)])
+def test_blocks4(planner_blocks3, shape, frac, keep_all):
+    """D3Q19 4 x 4 x 4 block table against brute force: kept blocks (those with a fluid node,
+    or all), block-neighbour indices (a dropped block reads as n_blocks), per-slot fluid bits,
+    the all-fluid flag; and the step kernel's source rule applied to the table reaches, for
+    every fluid node and direction, the node x - c_i (periodic) with the right solidity.
+    Some shapes are one block wide in an axis, where a block is its own neighbour."""
+    nx, ny, nz = shape
+    m = synthetic.random_mask3(nx, ny, nz, seed=nx + 5 * ny + 11 * nz, solid_fraction=frac)
+    if frac > 0 and frac < 1:
+        m[:, :, 4:8] = 1  # whole solid blocks (dropped unless keep_all)
+    inp = f"{nx} {ny} {nz} {int(keep_all)}\n" + " ".join(str(int(v)) for v in m.ravel())
+    r = subprocess.run([planner_blocks3], input=inp, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.split("\n") if ln.strip()]
+    nb_n = int(lines[0])
+    rows = [list(map(int, ln.split())) for ln in lines[1:]]
+    bx_n, by_n, bz_n = nx // 4, ny // 4, nz // 4
+    blocks = [(bx, by, bz) for bz in range(bz_n) for by in range(by_n) for bx in range(bx_n)
+              if keep_all or (m[4 * bz:4 * bz + 4, 4 * by:4 * by + 4, 4 * bx:4 * bx + 4] == 0).any()]
+    assert nb_n == len(blocks) == len(rows)
+    index = {b: k for k, b in enumerate(blocks)}
+    fluid_bits = []
+    for k, row in enumerate(rows):
+        bx, by, bz = row[:3]
+        assert (bx, by, bz) == blocks[k]
+        bits = 0
+        for l in range(64):
+            if m[4 * bz + (l >> 4), 4 * by + ((l >> 2) & 3), 4 * bx + (l & 3)] == 0:
+                bits |= 1 << l
+        assert row[23] == bits
+        fluid_bits.append(bits)
+    fluid_bits.append(0)
+    for k, row in enumerate(rows):
+        bx, by, bz = row[:3]
+        meta = row[3:23]
+        for j in range(1, 19):
+            nbk = ((bx + CX3[j]) % bx_n, (by + CY3[j]) % by_n, (bz + CZ3[j]) % bz_n)
+            assert meta[j - 1] == index.get(nbk, nb_n), (k, j)
+        interior = all(fluid_bits[e] == (1 << 64) - 1 for e in [k] + meta[:18])
+        assert meta[18] == int(interior) and meta[19] == 0
+        nb = [k] + meta[:18]
+        for l in range(64):
+            x, y, z = 4 * bx + (l & 3), 4 * by + ((l >> 2) & 3), 4 * bz + (l >> 4)
+            if m[z, y, x]:
+                continue
+            for i in range(1, 19):
+                b, slot = _block_source(nb, k, l, i)
+                sx, sy, sz = (x - CX3[i]) % nx, (y - CY3[i]) % ny, (z - CZ3[i]) % nz
+                solid = m[sz, sy, sx] == 1
+                assert solid == (((fluid_bits[b] >> slot) & 1) == 0), (k, l, i)
+                if not solid:
+                    assert rows[b][:3] == [sx // 4, sy // 4, sz // 4], (k, l, i)
+                    assert slot == (sx & 3) | ((sy & 3) << 2) | ((sz & 3) << 4)
