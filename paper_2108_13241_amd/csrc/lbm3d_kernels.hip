@@ -1121,6 +1121,24 @@ __global__ __launch_bounds__(kBlock) void k_rest3(typename ST::mem *p, uint64_t 
     }
 }
 
+// Resident workgroups per CU (0: as many as registers allow), measured at
+// 256^3: the dense and AA steps on mostly interior lattices run faster with
+// fewer workgroups in flight (FP32 A-B 433 us at 3 per CU against 453 us
+// uncapped, AA 462 against 476 us; FP64 893 against 904 us, AA 943 against
+// 950 us); the block step on a sphere packing at fluid fraction 0.4 likewise
+// (FP64 482 against 495 us at 3, FP32 271 against 274 us at 5).  16-bit
+// storage gains nothing.
+inline int step3_cap(const State3 &s, size_t esize)
+{
+    if (esize == 2)
+        return 0;
+    if (s.blocks)
+        return esize == 8 ? 3 : 5;
+    if (s.list || s.interior_frac < 0.9)
+        return 0;
+    return 3;
+}
+
 template <class ST, bool TRT, bool MRT>
 void step_launch3(const State3 &s, int cur)
 {
@@ -1131,6 +1149,7 @@ void step_launch3(const State3 &s, int cur)
     const bool force = s.gx != 0.0 || s.gy != 0.0 || s.gz != 0.0;
     const R g[3] = {force ? (R)s.gx : R(0), force ? (R)s.gy : R(0), force ? (R)s.gz : R(0)};
     const Rates3<R> rt{(R)s.omega_m, (R)s.s_e, (R)s.s_eps, (R)s.s_q, (R)s.s_pi, (R)s.s_m};
+    const uint32_t dyn = lbm::occupancy_cap_lds(step3_cap(s, sizeof(M)), 0u);
     if (s.blocks) {
         const uint32_t nwg = (uint32_t)((s.n_blocks + 3) / 4);
         if (nwg == 0)
@@ -1138,7 +1157,7 @@ void step_launch3(const State3 &s, int cur)
         const M *src = (const M *)s.f[cur];
         M *dst = (M *)s.f[1 - cur];
         auto go = [&](auto kernel) {
-            kernel<<<nwg, kBlock, 0, s.stream>>>(src, dst, block_table(s), (uint32_t)s.n_blocks,
+            kernel<<<nwg, kBlock, dyn, s.stream>>>(src, dst, block_table(s), (uint32_t)s.n_blocks,
                                                  nwg, (R)s.omega, g[0], g[1], g[2], rt,
                                                  s.fullway);
         };
@@ -1168,7 +1187,7 @@ void step_launch3(const State3 &s, int cur)
     if (s.aa) {
         M *A = (M *)s.f[0];
         auto go = [&](auto kernel) {
-            kernel<<<nb, kBlock, 0, s.stream>>>(A, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
+            kernel<<<nb, kBlock, dyn, s.stream>>>(A, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
                                                 s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1],
                                                 g[2], rt);
         };
@@ -1183,7 +1202,7 @@ void step_launch3(const State3 &s, int cur)
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
     auto go = [&](auto kernel) {
-        kernel<<<nb, kBlock, 0, s.stream>>>(src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
+        kernel<<<nb, kBlock, dyn, s.stream>>>(src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
                                             s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1], g[2],
                                             rt, s.fullway);
     };

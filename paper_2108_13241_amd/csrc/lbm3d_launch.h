@@ -49,6 +49,7 @@ struct State3 {
     const uint8_t *type = nullptr;           // 0 fluid, 1 solid, 2 fluid next to a solid
     const uint32_t *nmask = nullptr;         // bit i-1 set <=> node x - c_i is solid
     const uint32_t *seg_interior = nullptr;  // per 256-node row segment: 1 = all type 0
+    double interior_frac = 0.0;              // fraction of all-interior segments (blocks)
     double omega = 1.0, gx = 0.0, gy = 0.0, gz = 0.0;
     int trt = 0;                             // 1: two-relaxation-time collision
     double omega_m = 1.0;                    // its antisymmetric relaxation rate

@@ -280,6 +280,10 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
         if ((rc = upload(b.xyz.data(), b.xyz.size() * 4, &p)))
             return fail_create(rc, "cannot upload the block coordinates");
         s.bxyz = (const int32_t *)p;
+        size_t inner = 0;
+        for (int64_t k = 0; k < b.n_blocks; ++k)
+            inner += b.meta[(size_t)k * lbm::plan::kBlockMetaWords + 18] != 0;
+        s.interior_frac = b.n_blocks ? (double)inner / (double)b.n_blocks : 0.0;
     } else if (layout == LBM_INDIRECT) {
         // fluid nodes only: the list with its coordinates and pull-source table
         s.list = 1;
@@ -316,6 +320,7 @@ int lbm3d_create(lbm3d_ctx **out, int32_t nx, int32_t ny, int32_t nz, const uint
         if ((rc = upload(seg.data(), seg.size() * 4, &p)))
             return fail_create(rc, "cannot upload the segment flags");
         s.seg_interior = (const uint32_t *)p;
+        s.interior_frac = lbm::plan::interior_fraction(seg);
     }
     const size_t lattice = (size_t)Q * stored_nodes(c) * c->pop_bytes;
     s.aa = layout == LBM_DENSE_AA ? 1 : 0;

@@ -448,6 +448,17 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n)
     return j * q + (j < r ? j : r) + k;
 }
 
+// Dynamic LDS bytes that cap a launch at `wg` resident workgroups per CU
+// (0: no cap), for a kernel with `static_lds` bytes of its own: each workgroup
+// then holds just over 1 / (wg + 1) of the CU's 160 KB of LDS.
+inline uint32_t occupancy_cap_lds(int wg, uint32_t static_lds)
+{
+    if (wg <= 0)
+        return 0u;
+    const uint32_t want = 163840u * 2u / (2u * (uint32_t)wg + 1u);
+    return want > static_lds ? want - static_lds : 0u;
+}
+
 // Periodic neighbour coordinates.
 __device__ __forceinline__ int wrap_dec(int a, int n) { return a == 0 ? n - 1 : a - 1; }
 __device__ __forceinline__ int wrap_inc(int a, int n) { return a == n - 1 ? 0 : a + 1; }

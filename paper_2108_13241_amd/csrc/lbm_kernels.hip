@@ -1116,6 +1116,27 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src
 
 // ---------------------------------------------------------------- dispatch --
 
+// Resident workgroups per CU for the dense streaming steps (0: as many as
+// registers and LDS allow), from measurements at 4096^2: with fewer workgroups
+// in flight, HBM serves the all-interior row segments faster (FP64 A-B 389 us
+// at 4 per CU against 405 us at 8; FP64 AA 414 against 434 us at 3; FP32 A-B
+// 192 against 197 us at 6, FP32 AA 207 against 215 us at 5), while lattices
+// with many boundary segments, whose per-node path waits on dependent loads,
+// lose by a low cap (FP64 A-B on porous discs at fluid fraction 0.5: 440 us at
+// 3, 383 at 4, 365 at 6, 369 uncapped).  16-bit storage gains nothing.
+inline int dense_ab_cap(size_t esize, double interior)
+{
+    if (esize == 8)
+        return interior >= 0.9 ? 4 : 6;
+    return esize == 4 ? 6 : 0;
+}
+inline int dense_aa_cap(size_t esize, double interior)
+{
+    if (interior < 0.9)
+        return 0;
+    return esize == 8 ? 3 : esize == 4 ? 5 : 0;
+}
+
 template <class ST, int PH>
 void step_launch(const DevState &s, int64_t t, int cur)
 {
@@ -1145,16 +1166,23 @@ void step_launch(const DevState &s, int64_t t, int cur)
                     k_step_dense_ab_direct<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(k);
                 }
             } else {
-                k_step_dense_ab<ST, PH><<<nblocks, kBlock, 0, s.stream>>>(k);
+                // static LDS of k_step_dense_ab: nine rows of 256 + 2 * (16 / sizeof(M))
+                const uint32_t lds = 9u * (kBlock + 2u * (16u / (uint32_t)sizeof(M))) *
+                                     (uint32_t)sizeof(M);
+                const uint32_t dyn =
+                    occupancy_cap_lds(dense_ab_cap(sizeof(M), s.interior_frac), lds);
+                k_step_dense_ab<ST, PH><<<nblocks, kBlock, dyn, s.stream>>>(k);
             }
-        } else if (t & 1) {
-            k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, 0, s.stream>>>(
-                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
-                s.pitch, bpr, nblocks, om, gx, gy, omm);
         } else {
-            k_step_dense_aa<ST, PH, false><<<nblocks, kBlock, 0, s.stream>>>(
-                (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx, s.ny,
-                s.pitch, bpr, nblocks, om, gx, gy, omm);
+            const uint32_t dyn = occupancy_cap_lds(dense_aa_cap(sizeof(M), s.interior_frac), 0u);
+            if (t & 1)
+                k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, dyn, s.stream>>>(
+                    (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx,
+                    s.ny, s.pitch, bpr, nblocks, om, gx, gy, omm);
+            else
+                k_step_dense_aa<ST, PH, false><<<nblocks, kBlock, dyn, s.stream>>>(
+                    (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx,
+                    s.ny, s.pitch, bpr, nblocks, om, gx, gy, omm);
         }
     } else if (s.layout == kTiled16) {
         const uint32_t nt = (uint32_t)s.n_tiles;

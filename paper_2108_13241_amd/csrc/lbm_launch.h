@@ -35,6 +35,7 @@ struct DevState {
     const uint8_t *type = nullptr;    // node-type codes (dense / tiled)
     const uint8_t *nmask = nullptr;   // solid-neighbour bits (dense / tiled)
     const uint32_t *seg_interior = nullptr;  // dense: per 256-node row segment, 1 = all interior
+    double interior_frac = 0.0;       // dense: fraction of the segments that are all interior
     const float *alpha = nullptr;     // drag coefficient, same indexing as type
                                       // (INDIRECT: per compacted node); may be null
     const int32_t *tile_xy = nullptr, *tile_nbr = nullptr;  // TILED16

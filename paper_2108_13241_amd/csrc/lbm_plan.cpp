@@ -57,6 +57,16 @@ void dense_segment_flags(const std::vector<uint8_t> &type, int nx, int ny, int p
         }
 }
 
+double interior_fraction(const std::vector<uint32_t> &flags)
+{
+    if (flags.empty())
+        return 0.0;
+    size_t n = 0;
+    for (uint32_t f : flags)
+        n += f != 0;
+    return (double)n / (double)flags.size();
+}
+
 Tiles tiles16(const uint8_t *mask, int nx, int ny, bool keep_all)
 {
     Tiles t;

@@ -29,6 +29,8 @@ void dense_types(const uint8_t *mask, int nx, int ny, int pitch, std::vector<uin
 // code 0), else 0.  Such segments need no node-type or neighbour reads.
 void dense_segment_flags(const std::vector<uint8_t> &type, int nx, int ny, int pitch, int seg,
                          std::vector<uint32_t> &flags);
+// Fraction of non-zero flags (0 for an empty vector).
+double interior_fraction(const std::vector<uint32_t> &flags);
 
 struct Tiles {
     int64_t n_tiles = 0;

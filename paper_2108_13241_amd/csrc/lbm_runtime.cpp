@@ -370,6 +370,7 @@ int lbm_create(lbm_ctx **out, int32_t nx, int32_t ny, const uint8_t *node_type, 
         if ((rc = upload(seg.data(), seg.size() * 4, &p)))
             return fail_create(rc, "cannot upload the segment flags");
         s.seg_interior = (const uint32_t *)p;
+        s.interior_frac = lbm::plan::interior_fraction(seg);
     } else if (layout == LBM_TILED16) {
         c->tiles = lbm::plan::tiles16(node_type, nx, ny, all_tiles);
         lbm::plan::tiled_types(node_type, nx, ny, c->tiles, type, nmask);
@@ -605,6 +606,7 @@ int lbm_set_boundaries(lbm_ctx *c, const uint8_t *bc, const double *value)
         lbm::plan::dense_segment_flags(type, nx, ny, s.pitch, 256, seg);
         LBM_HIP(c, hipMemcpyAsync((void *)s.seg_interior, seg.data(), seg.size() * 4,
                                   hipMemcpyHostToDevice, s.stream));
+        s.interior_frac = lbm::plan::interior_fraction(seg);
     }
     if (n_open) {
         LBM_HIP(c, hipMemcpyAsync(c->bc_buf, vals.data(), vals.size() * sizeof(double),
