@@ -14,8 +14,9 @@ interior row reads its left halo from column nx - 1.
 
 Compared with the FP64 oracle over the whole lattice after 12 steps: BGK with body force and
 drag field, TRT, MRT, open boundaries between walls, and full-way walls (FP64 max abs 1e-12,
-FP32 max relative 1e-5, as everywhere; wall slots included for full-way).  16-bit storage:
-bitwise equal to the indirect layout's kernel (one collision function) at 2000 x 1900.
+FP32 max relative 1e-5, as everywhere; wall slots included for full-way).  16-bit storage
+(two rows per workgroup): bitwise equal to the indirect layout's kernel (one collision
+function) at 2000 x 1901, whose last row pair holds a single row.
 """
 import numpy as np
 import pytest
@@ -132,7 +133,7 @@ def test_segment_kernel_vs_oracle(lbm, oracle_mod, dtype, case):
 @pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
 @pytest.mark.parametrize("case", ["force_drag", "trt", "open_walls"])
 def test_segment_kernel_16bit_bitwise(lbm, dtype, case):
-    nx, ny = 2000, 1900
+    nx, ny = 2000, 1901  # odd: the last row pair of the two-row kernel has one row
     assert _selects_segment_kernel(nx, ny, dtype)
     announce(f"segment kernel {nx}x{ny} {dtype} {case} bitwise vs indirect")
     m, bc, val, fields, alpha, g = _setup(case, nx, ny)
