@@ -1,0 +1,47 @@
+"""Every global store of every step kernel is a nontemporal (streaming) store.
+
+The step kernels write each population once and never read it back within the step, so
+their stores carry the nontemporal hint (`nt`), which keeps them from allocating in the
+caches.  The hint is a performance property that tests of the results cannot see, and
+compiler transformations can drop it (a restructured loop once lost it on the FP32 A-B
+kernel's LDS path, 8 % slower): this test compiles the step-kernel sources for gfx950 to
+assembly (host-side cross compilation, no GPU) and checks each `global_store` in the
+functions named k_step*.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2108_13241_amd", "csrc")
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("src", ["lbm_kernels.hip", "lbm3d_kernels.hip"])
+def test_step_kernel_stores_are_nontemporal(tmp_path, src):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    out = tmp_path / "k.s"
+    subprocess.run([HIPCC, "-O3", "-std=c++17", "-ffp-contract=on", "--offload-arch=gfx950",
+                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-x", "hip",
+                    "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", str(out)],
+                   check=True, capture_output=True)
+    asm = out.read_text()
+    checked = 0
+    bad = []
+    for m in re.finditer(r"^(_Z\S*k_step\S*):", asm, re.M):
+        name = m.group(1)
+        end = asm.index(".Lfunc_end", m.end())
+        for line in asm[m.end():end].split("\n"):
+            ins = line.strip()
+            if ins.startswith("global_store"):
+                checked += 1
+                if not re.search(r"\bnt\b", ins):
+                    bad.append((name, ins))
+    assert checked > 0
+    assert not bad, bad[:5]
