@@ -1,12 +1,16 @@
 // HIP kernels of the D3Q19 lattice (the three-dimensional lattice the paper
 // names as future work): the fused pull stream-and-collide step of
-// Algorithm 1 with halfway bounce-back walls, BGK collision (Eqs. 3-6 with the
-// D3Q19 weights) and Guo body forcing, on a dense two-lattice (A-B) layout,
-// plus initialisation, canonical views and FP64 reductions.
+// Algorithm 1 with halfway or full-way bounce-back walls, the BGK collision
+// (Eqs. 3-6 with the D3Q19 weights) or its TRT / MRT variants, and Guo body
+// forcing, on the dense two-lattice (A-B) layout (per node, or staged through
+// LDS per row segment), the in-place AA layout, the sparse fluid-node list and
+// the sparse 4 x 4 x 4-block tiled layout; plus initialisation, canonical views
+// and FP64 reductions.
 //
-// Layout: [nz][ny][pitch/64][19][64] (chunks of 64 nodes along x, each holding
-// its 19 populations as runs of 64); node types and solid-neighbour bits per
-// node [nz][ny][pitch]; one "all interior" flag per 256-node row segment.
+// Dense layout: [nz][ny][pitch/64][19][64] (chunks of 64 nodes along x, each
+// holding its 19 populations as runs of 64); node types and solid-neighbour
+// bits per node [nz][ny][pitch]; one "all interior" flag per 256-node row
+// segment.
 #include "lbm3d_launch.h"
 #include "lbm_device.h"
 
@@ -384,24 +388,20 @@ __device__ __forceinline__ uint32_t solid_bits3(uint8_t t, const uint32_t *__res
     return t == kBoundary ? nmask[n] << 1 : 0u;
 }
 
+// One node (x, y, z) of row r = z * ny + y of the dense A-B step; interior:
+// its 256-node row segment holds interior fluid nodes only.
 template <class ST, bool FORCE, bool TRT, bool MRT>
-__global__ __launch_bounds__(kBlock) void k_step3(
+__device__ __forceinline__ void step3_node(
     const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
-    const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask,
-    const uint32_t *__restrict__ seg_interior, int nx, int ny, int nz, int pitch, uint32_t bpr,
-    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy,
-    typename ST::real gz, Rates3<typename ST::real> rt, int fullway)
+    const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask, bool interior, int x,
+    int y, int z, uint32_t r, int nx, int ny, int nz, int pitch, typename ST::real omega,
+    typename ST::real gx, typename ST::real gy, typename ST::real gz,
+    const Rates3<typename ST::real> &rt, int fullway)
 {
     using R = typename ST::real;
-    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
-    const uint32_t r = L / bpr;  // row index z * ny + y
-    const int x = (int)(L - r * bpr) * kBlock + (int)threadIdx.x;
-    if (x >= nx)
-        return;
-    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
     const uint32_t n = r * (uint32_t)pitch + (uint32_t)x;
     uint32_t sm = 0;
-    if (!seg_interior[L]) {
+    if (!interior) {
         const uint8_t t = type[n];
         if (t == kSolid)
             return;
@@ -414,6 +414,136 @@ __global__ __launch_bounds__(kBlock) void k_step3(
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         store_nt(&elem(dst, a, i, 1, 1, 1), ST::st(f[i], i));
+}
+
+// Per-node A-B step (one node per lane, shifted loads straight from the
+// lattice): the kernel for lattices small enough that a step is bound by
+// latency rather than bandwidth.
+template <class ST, bool FORCE, bool TRT, bool MRT>
+__global__ __launch_bounds__(kBlock) void k_step3(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
+    const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask,
+    const uint32_t *__restrict__ seg_interior, int nx, int ny, int nz, int pitch, uint32_t bpr,
+    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy,
+    typename ST::real gz, Rates3<typename ST::real> rt, int fullway)
+{
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t r = L / bpr;  // row index z * ny + y
+    const int x = (int)(L - r * bpr) * kBlock + (int)threadIdx.x;
+    if (x >= nx)
+        return;
+    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
+    step3_node<ST, FORCE, TRT, MRT>(src, dst, type, nmask, seg_interior[L] != 0, x, y, z, r, nx,
+                                    ny, nz, pitch, omega, gx, gy, gz, rt, fullway);
+}
+
+// Bit masks of the directions with c_i.x (.y, .z) = +1 and -1: the velocity
+// components of a direction index held in a register, without a table.
+__device__ constexpr uint32_t dir_bits(const int (&c)[Q], int v)
+{
+    uint32_t b = 0;
+    for (int i = 0; i < Q; ++i)
+        if (c[i] == v)
+            b |= 1u << i;
+    return b;
+}
+__device__ __forceinline__ int comp_of(uint32_t plus, uint32_t minus, uint32_t i)
+{
+    return (int)((plus >> i) & 1u) - (int)((minus >> i) & 1u);
+}
+
+// A-B step through LDS: a workgroup updates one 256-node row segment of row
+// r = z * ny + y.  When the segment is all-interior and whole (x0 + 256 <=
+// nx), it first copies, for each direction i, the 256 source values of row
+// (y - c_i.y, z - c_i.z), columns x0 - c_i.x .., into LDS with aligned
+// 16-byte loads (each 64-node chunk run is contiguous), all in flight
+// together, plus the one column beyond the segment's end that the x-shifted
+// directions need; after a barrier every lane reads its 19 shifted sources
+// from LDS.  Other segments (solid or boundary nodes, or the row's partial last
+// segment) run the per-node path.
+template <class ST, bool FORCE, bool TRT, bool MRT>
+__global__ __launch_bounds__(kBlock) void k_step3_lds(
+    const typename ST::mem *__restrict__ src, typename ST::mem *__restrict__ dst,
+    const uint8_t *__restrict__ type, const uint32_t *__restrict__ nmask,
+    const uint32_t *__restrict__ seg_interior, int nx, int ny, int nz, int pitch, uint32_t bpr,
+    uint32_t nblocks, typename ST::real omega, typename ST::real gx, typename ST::real gy,
+    typename ST::real gz, Rates3<typename ST::real> rt, int fullway)
+{
+    using R = typename ST::real;
+    using M = typename ST::mem;
+    constexpr uint32_t kE = 16u / (uint32_t)sizeof(M);  // elements per 16-byte vector
+    constexpr uint32_t kVpc = kChunk / kE;             // vectors per 64-node chunk run
+    constexpr uint32_t kV = Q * 4u * kVpc;             // vectors per segment
+    constexpr uint32_t kRow = kBlock + 2u * kE;
+    // row i: [kE - 1] = column x0 - 1, [kE .. kE + 255] = the segment (16-byte
+    // aligned), [kE + 256] = column x0 + 256
+    __shared__ __align__(16) M stage[Q][kRow];
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t r = L / bpr;  // row index z * ny + y
+    const int x0 = (int)(L - r * bpr) * kBlock;
+    const int x = x0 + (int)threadIdx.x;
+    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
+    const bool inner = seg_interior[L] != 0;
+    if (!inner || x0 + kBlock > nx) {
+        if (x < nx)
+            step3_node<ST, FORCE, TRT, MRT>(src, dst, type, nmask, inner, x, y, z, r, nx, ny, nz,
+                                            pitch, omega, gx, gy, gz, rt, fullway);
+        return;
+    }
+    constexpr uint32_t PX = dir_bits(kCx, 1), NX = dir_bits(kCx, -1);
+    constexpr uint32_t PY = dir_bits(kCy, 1), NY = dir_bits(kCy, -1);
+    constexpr uint32_t PZ = dir_bits(kCz, 1), NZ = dir_bits(kCz, -1);
+    const uint32_t cpr = (uint32_t)pitch / kChunk;
+    const uint64_t rowel = (uint64_t)cpr * (Q * kChunk);  // elements per row
+    // first element of the source row of direction i: row (y - c_i.y, z - c_i.z)
+    auto src_row = [=](uint32_t i) -> uint64_t {
+        int ys = y - comp_of(PY, NY, i), zs = z - comp_of(PZ, NZ, i);
+        ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+        zs += zs < 0 ? nz : (zs >= nz ? -nz : 0);
+        return ((uint64_t)(uint32_t)zs * (uint32_t)ny + (uint32_t)ys) * rowel;
+    };
+    const uint32_t c0 = (uint32_t)x0 >> 6;
+    // halo: lane i (i = 1..18 with c_i.x != 0) fetches the column beyond the
+    // segment on the side direction i pulls from
+    M hv = M(0);
+    const uint32_t hi = threadIdx.x;
+    const int hcx = hi < (uint32_t)Q ? comp_of(PX, NX, hi) : 0;
+    if (hcx != 0) {
+        const int xs = hcx > 0 ? wrap_dec(x0, nx) : wrap_inc(x0 + kBlock - 1, nx);
+        hv = src[src_row(hi) + (uint64_t)hi * kChunk + col_off(xs)];
+    }
+    // the segment's runs: all loads in flight before any LDS write, no branch
+    // in between (indices past the last vector repeat the last one: the same
+    // value to the same place)
+    constexpr uint32_t kIter = (kV + kBlock - 1) / kBlock;
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u vv[kIter];
+    uint32_t dst_el[kIter];
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m) {
+        const uint32_t q = min(threadIdx.x + m * kBlock, kV - 1u);
+        const uint32_t i = q / (4u * kVpc), rr = q - i * (4u * kVpc);
+        const uint32_t cc = rr / kVpc, pc = rr - cc * kVpc;
+        const uint64_t off = src_row(i) + (uint64_t)(c0 + cc) * (Q * kChunk) +
+                             (uint64_t)i * kChunk + (uint64_t)pc * kE;
+        vv[m] = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(src + off));
+        dst_el[m] = i * kRow + kE + cc * kChunk + pc * kE;
+    }
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m)
+        *reinterpret_cast<v4u *>(&stage[0][0] + dst_el[m]) = vv[m];
+    if (hcx != 0)
+        stage[hi][hcx > 0 ? kE - 1 : kE + kBlock] = hv;
+    __syncthreads();
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        f[i] = ST::ld(stage[i][(int)kE + (int)threadIdx.x - kCx[i]], i);
+    collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
+    M *out = dst + (uint64_t)r * rowel + col_off(x);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        store_nt(out + (uint32_t)i * kChunk, ST::st(f[i], i));
 }
 
 // AA pattern (DENSE_AA: one lattice updated in place).  Even steps read node
@@ -1139,6 +1269,21 @@ inline int step3_cap(const State3 &s, size_t esize)
     return 3;
 }
 
+// Resident workgroups per CU of the LDS-staged dense step (0: as many as
+// registers and LDS allow), measured at 256^3: FP64 Taylor-Green 839 us at 2
+// per CU against 874 us at the 4 its LDS allows (sphere packing at fluid
+// fraction 0.4: 846 against 867 us), the MRT collision 865 us at 3 against 872
+// at 2; FP32 424 us at 4 against 440 us at 8 (sphere packing: 534 us at 3
+// against 575 us; MRT no gain); 16-bit storage gains nothing.
+inline int step3_lds_cap(const State3 &s, size_t esize)
+{
+    if (esize == 8)
+        return s.mrt ? 3 : 2;
+    if (esize == 4 && !s.mrt)
+        return s.interior_frac >= 0.9 ? 4 : 3;
+    return 0;
+}
+
 template <class ST, bool TRT, bool MRT>
 void step_launch3(const State3 &s, int cur)
 {
@@ -1201,15 +1346,25 @@ void step_launch3(const State3 &s, int cur)
     }
     const M *src = (const M *)s.f[cur];
     M *dst = (M *)s.f[1 - cur];
-    auto go = [&](auto kernel) {
-        kernel<<<nb, kBlock, dyn, s.stream>>>(src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
-                                            s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1], g[2],
-                                            rt, s.fullway);
+    // the LDS-staged kernel once a step moves 128 MiB or more (as for D2Q9)
+    const bool lds = 38.0 * (double)s.nz * s.ny * s.pitch * sizeof(M) >= 128.0 * (1 << 20);
+    auto go = [&](auto kernel, uint32_t dl) {
+        kernel<<<nb, kBlock, dl, s.stream>>>(src, dst, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
+                                           s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1], g[2],
+                                           rt, s.fullway);
     };
-    if (force)
-        go(k_step3<ST, true, TRT, MRT>);
-    else
-        go(k_step3<ST, false, TRT, MRT>);
+    if (lds) {
+        const uint32_t st = Q * (kBlock + 2u * (16u / (uint32_t)sizeof(M))) * (uint32_t)sizeof(M);
+        const uint32_t dl = lbm::occupancy_cap_lds(step3_lds_cap(s, sizeof(M)), st);
+        if (force)
+            go(k_step3_lds<ST, true, TRT, MRT>, dl);
+        else
+            go(k_step3_lds<ST, false, TRT, MRT>, dl);
+    } else if (force) {
+        go(k_step3<ST, true, TRT, MRT>, dyn);
+    } else {
+        go(k_step3<ST, false, TRT, MRT>, dyn);
+    }
 }
 
 template <class ST>
