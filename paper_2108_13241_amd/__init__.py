@@ -350,8 +350,8 @@ def _force3(g):
 
 
 class Lattice3D:
-    """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B, AA or
-    fluid-node-list ("indirect") layout; BGK, TRT or MRT collision with Guo forcing; halfway
+    """One D3Q19 lattice on the current GPU (a thin wrapper of lbm3d_ctx): dense A-B, AA,
+    fluid-node-list ("indirect") or 4 x 4 x 4-block tiled ("tiled16", "tiled16_all") layout; BGK, TRT or MRT collision with Guo forcing; halfway
     (or, except on AA, full-way) bounce-back.  Arrays are [nz, ny, nx]; canonical populations
     [19, nz, ny, nx] in the velocity order of include/lbm3d.h."""
 

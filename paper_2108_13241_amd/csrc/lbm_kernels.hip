@@ -1159,15 +1159,16 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src
 // registers and LDS allow), from measurements at 4096^2: with fewer workgroups
 // in flight, HBM serves the all-interior row segments faster (FP64 A-B 389 us
 // at 4 per CU against 405 us at 8; FP64 AA 414 against 434 us at 3; FP32 A-B
-// 192 against 197 us at 6, FP32 AA 207 against 215 us at 5), while lattices
-// with many boundary segments, whose per-node path waits on dependent loads,
-// lose by a low cap (FP64 A-B on porous discs at fluid fraction 0.5: 440 us at
-// 3, 383 at 4, 365 at 6, 369 uncapped).  16-bit storage gains nothing.
+// 192 against 197 us at 6, FP32 AA 207 against 215 us at 5), while on lattices
+// with many boundary segments, whose per-node path waits on dependent loads, a
+// cap gains at most 1-3 % and loses up to 16 % (porous discs at fluid fraction
+// 0.2, FP32: 170 against 147 us at 6; FP64 A-B at fraction 0.5: 440 us at 3,
+// 383 at 4), so they run uncapped.  16-bit storage gains nothing.
 inline int dense_ab_cap(size_t esize, double interior)
 {
-    if (esize == 8)
-        return interior >= 0.9 ? 4 : 6;
-    return esize == 4 ? 6 : 0;
+    if (interior < 0.9)
+        return 0;
+    return esize == 8 ? 4 : esize == 4 ? 6 : 0;
 }
 inline int dense_aa_cap(size_t esize, double interior)
 {
