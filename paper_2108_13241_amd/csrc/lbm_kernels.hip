@@ -1195,10 +1195,13 @@ void step_launch(const DevState &s, int64_t t, int cur)
                             gy,    omm,  s.fullway};
             // Kernel choice (measured): the per-node kernel while a step moves less
             // than 128 MiB (latency-bound: 1024 x 256 FP32 forward 4.8 us against
-            // 5.6 us through LDS); the two-row kernel for 16-bit MRT (109 us against
-            // 123 us at 4096^2); the LDS-staged kernel otherwise.
+            // 5.6 us through LDS); for 16-bit MRT on lattices with many boundary
+            // segments the two-row kernel without LDS (at 4096^2, against the
+            // one-row LDS kernel: 109 against 123 us); the LDS-staged kernel
+            // otherwise (16-bit MRT on interior lattices, two rows through LDS:
+            // 111 against 113 us).
             const bool small = 18.0 * (double)s.plane * sizeof(M) < 128.0 * (1 << 20);
-            if (small || (ST::kAligned && (PH & kMRT))) {
+            if (small || (ST::kAligned && (PH & kMRT) && s.interior_frac < 0.9)) {
                 if constexpr (ST::kAligned) {
                     k.nblocks = bpr * (uint32_t)((s.ny + 1) / 2);
                     k_step_dense_ab2<ST, PH><<<k.nblocks, kBlock, 0, s.stream>>>(k);

@@ -131,7 +131,7 @@ def test_segment_kernel_vs_oracle(lbm, oracle_mod, dtype, case):
 
 
 @pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
-@pytest.mark.parametrize("case", ["force_drag", "trt", "open_walls"])
+@pytest.mark.parametrize("case", ["force_drag", "trt", "mrt", "open_walls"])
 def test_segment_kernel_16bit_bitwise(lbm, dtype, case):
     nx, ny = 2000, 1901  # odd: the last row pair of the two-row kernel has one row
     assert _selects_segment_kernel(nx, ny, dtype)
