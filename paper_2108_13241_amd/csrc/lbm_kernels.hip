@@ -363,6 +363,76 @@ __device__ __forceinline__ void dense_ab_node(const DenseArgs<ST> &k, int x, int
     dense_collide_store<ST, PH>(k, a, n, f);
 }
 
+// AA pattern (single lattice A).  Even step: read A_i(x), write the
+// post-collision f_i to A_opp(i)(x).  Odd step: read f_i = A_opp(i)(x - c_i)
+// (A_i(x) if x - c_i is solid), write f_i to A_i(x + c_i) (A_opp(i)(x) if
+// x + c_i is solid).  Slot A_j(z) is read and written by one node only
+// (z - c_j if it is fluid, else z), so there is no race.  One node (x, y);
+// interior: its row segment holds interior fluid nodes only.
+template <class ST, int PH, bool ODD>
+__device__ __forceinline__ void aa_node(typename ST::mem *__restrict__ A,
+                                        const uint8_t *__restrict__ type,
+                                        const uint8_t *__restrict__ nmask,
+                                        const float *__restrict__ alpha,
+                                        const double *__restrict__ bc_val, int nx, int ny,
+                                        int pitch, typename ST::real omega, typename ST::real gx,
+                                        typename ST::real gy, const Rates<typename ST::real> &rt,
+                                        int x, int y, bool interior)
+{
+    using R = typename ST::real;
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
+                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0,
+                   MRT = (PH & kMRT) != 0;
+    const uint32_t n = (uint32_t)y * pitch + x;
+    const uint8_t t = interior ? (uint8_t)kFluid : type[n];
+    if (t == kSolid)
+        return;
+    const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
+    const unsigned open = OPEN ? open_code(t) : 0u;
+    R f[9];
+    if constexpr (!ODD) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            f[i] = ST::ld(dense_at(A, a, i, 1, 1), i);
+        if (OPEN && open)
+            apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
+                                                             DRAG ? (R)alpha[n] : R(0), rt);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            store_nt(&dense_at(A, a, kOpp[i], 1, 1), ST::st(f[i], i));
+    } else {
+        const unsigned sm = interior ? 0u : solid_bits(t, nmask, n);
+        if (sm == 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[i] = ST::ld(dense_at(A, a, kOpp[i], 1 - kCy[i], 1 - kCx[i]), i);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[i] = ST::ld(((sm >> i) & 1u) ? dense_at(A, a, i, 1, 1)
+                                               : dense_at(A, a, kOpp[i], 1 - kCy[i], 1 - kCx[i]),
+                              i);
+        }
+        if (OPEN && open)
+            apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
+        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
+                                                             DRAG ? (R)alpha[n] : R(0), rt);
+        // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
+        if (sm == 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                store_nt(&dense_at(A, a, i, 1 + kCy[i], 1 + kCx[i]), ST::st(f[i], i));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                store_nt(((sm >> kOpp[i]) & 1u) ? &dense_at(A, a, kOpp[i], 1, 1)
+                                                : &dense_at(A, a, i, 1 + kCy[i], 1 + kCx[i]),
+                         ST::st(f[i], i));
+        }
+    }
+}
+
 // Per-node A-B step (one node per lane, shifted loads straight from the
 // lattice): the kernel for lattices small enough that a step is bound by
 // latency rather than bandwidth, where staging a segment through LDS and a
@@ -523,6 +593,89 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab(const DenseArgs<ST> k)
     }
 }
 
+// Odd AA step through LDS (the A-B segment staging applied to the AA read
+// pattern): a workgroup updates one 256-node row segment; when the segment is
+// all-interior and whole it copies, for each direction i, the 256 values
+// A_opp(i) of row y - c_i.y, columns x0 - c_i.x .., into LDS with aligned
+// 16-byte loads (plus the halo column), reads its nine shifted sources from
+// LDS after one barrier and writes f_i to A_i(x + c_i) directly.  Elements of
+// the loaded runs that this segment does not use may be rewritten meanwhile by
+// the neighbouring segment (their only reader and writer is a node there);
+// every element it does use is read and written by its own node only.  Other
+// segments run the per-node AA step.
+template <class ST, int PH>
+__global__ __launch_bounds__(kBlock) void k_step_dense_aa_odd(const DenseArgs<ST> k)
+{
+    using R = typename ST::real;
+    using M = typename ST::mem;
+    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
+                   TRT = (PH & kTRT) != 0, MRT = (PH & kMRT) != 0;
+    constexpr uint32_t kE = 16u / (uint32_t)sizeof(M);  // elements per 16-byte vector
+    constexpr uint32_t kVpc = kChunk / kE;             // vectors per 64-node chunk run
+    constexpr uint32_t kV = 9u * 4u * kVpc;            // vectors per segment
+    constexpr uint32_t kRow = kBlock + 2 * kE;
+    __shared__ __align__(16) M stage[9][kRow];
+    M *__restrict__ A = k.dst;  // the single lattice (loads and stores)
+    const uint32_t L = xcd_remap(blockIdx.x, k.nblocks);
+    const int y = (int)(L / k.bpr);
+    const int x0 = (int)(L - (uint32_t)y * k.bpr) * kBlock;
+    const int x = x0 + (int)threadIdx.x;
+    const bool inner = k.seg_interior[L] != 0;
+    if (!inner || x0 + kBlock > k.nx) {
+        if (x < k.nx)
+            aa_node<ST, PH, true>(A, k.type, k.nmask, k.alpha, k.bc_val, k.nx, k.ny, k.pitch,
+                                  k.omega, k.gx, k.gy, k.rt, x, y, inner);
+        return;
+    }
+    const uint32_t cpr = (uint32_t)k.pitch / kChunk;
+    const uint64_t row = (uint64_t)cpr * (9u * kChunk);
+    const uint64_t rb[3] = {(uint64_t)wrap_dec(y, k.ny) * row, (uint64_t)y * row,
+                            (uint64_t)wrap_inc(y, k.ny) * row};
+    const uint32_t c0 = (uint32_t)x0 >> 6;
+    auto dcx = [](uint32_t i) { return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0); };
+    auto dcy = [](uint32_t i) { return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0); };
+    // opp(i) of a runtime index: 1 <-> 3, 2 <-> 4, 5 <-> 7, 6 <-> 8
+    auto dopp = [](uint32_t i) { return i == 0 ? 0u : (i < 5 ? ((i - 1u) ^ 2u) + 1u : ((i - 5u) ^ 2u) + 5u); };
+    M hv = M(0);
+    const uint32_t hi = threadIdx.x;
+    const int hcx = hi < 9u ? dcx(hi) : 0;
+    if (hcx != 0) {
+        const int xs = hcx > 0 ? wrap_dec(x0, k.nx) : wrap_inc(x0 + kBlock - 1, k.nx);
+        hv = A[rb[1 - dcy(hi)] + (uint64_t)dopp(hi) * kChunk + col_off(xs)];
+    }
+    constexpr uint32_t kIter = (kV + kBlock - 1) / kBlock;
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u vv[kIter];
+    uint32_t dst_el[kIter];
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m) {
+        const uint32_t q = min(threadIdx.x + m * kBlock, kV - 1u);
+        const uint32_t i = q / (4u * kVpc), rr = q - i * (4u * kVpc);
+        const uint32_t cc = rr / kVpc, pc = rr - cc * kVpc;
+        const uint64_t off = rb[1 - dcy(i)] + (uint64_t)(c0 + cc) * (9u * kChunk) +
+                             (uint64_t)dopp(i) * kChunk + (uint64_t)pc * kE;
+        vv[m] = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(A + off));
+        dst_el[m] = i * kRow + kE + cc * kChunk + pc * kE;
+    }
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m)
+        *reinterpret_cast<v4u *>(&stage[0][0] + dst_el[m]) = vv[m];
+    if (hcx != 0)
+        stage[hi][hcx > 0 ? kE - 1 : kE + kBlock] = hv;
+    __syncthreads();
+    R f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = ST::ld(stage[i][(int)kE + (int)threadIdx.x - kCx[i]], i);
+    const uint32_t n = (uint32_t)y * k.pitch + x;
+    collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, k.omega, k.gx, k.gy,
+                                                         DRAG ? (R)k.alpha[n] : R(0), k.rt);
+    const DenseRC a = dense_rc(x, y, k.nx, k.ny, cpr);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        store_nt(&dense_at(A, a, i, 1 + kCy[i], 1 + kCx[i]), ST::st(f[i], i));
+}
+
 // Two rows per workgroup (rows y0 = 2 p and y0 + 1 of one 256-column segment),
 // for the 16-bit storages: when both segments are all-interior and the wave is
 // full, the thread issues the loads of both rows before it computes either, so
@@ -561,11 +714,6 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_ab2(const DenseArgs<ST> k
         dense_ab_node<ST, PH>(k, x, y1, k.seg_interior[L1] != 0);
 }
 
-// AA pattern (single lattice A).  Even step: read A_i(x), write the
-// post-collision f_i to A_opp(i)(x).  Odd step: read f_i = A_opp(i)(x - c_i)
-// (A_i(x) if x - c_i is solid), write f_i to A_i(x + c_i) (A_opp(i)(x) if
-// x + c_i is solid).  Slot A_j(z) is read and written by one node only
-// (z - c_j if it is fluid, else z), so there is no race.
 template <class ST, int PH, bool ODD>
 __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
@@ -574,63 +722,12 @@ __global__ __launch_bounds__(kBlock) void k_step_dense_aa(
     uint32_t bpr, uint32_t nblocks, typename ST::real omega, typename ST::real gx,
     typename ST::real gy, Rates<typename ST::real> rt)
 {
-    using R = typename ST::real;
-    constexpr bool DRAG = (PH & 3) == kDragged, FORCE = (PH & 3) != kBGK,
-                   OPEN = (PH & kOpenBC) != 0, TRT = (PH & kTRT) != 0,
-                   MRT = (PH & kMRT) != 0;
     int x, y;
     uint32_t L;
     if (!dense_node(bpr, nblocks, nx, x, y, L))
         return;
-    const uint32_t n = (uint32_t)y * pitch + x;
-    const bool interior = seg_interior[L] != 0;
-    const uint8_t t = interior ? (uint8_t)kFluid : type[n];
-    if (t == kSolid)
-        return;
-    const DenseRC a = dense_rc(x, y, nx, ny, (uint32_t)pitch / kChunk);
-    const unsigned open = OPEN ? open_code(t) : 0u;
-    R f[9];
-    if constexpr (!ODD) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            f[i] = ST::ld(dense_at(A, a, i, 1, 1), i);
-        if (OPEN && open)
-            apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
-                                                             DRAG ? (R)alpha[n] : R(0), rt);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            store_nt(&dense_at(A, a, kOpp[i], 1, 1), ST::st(f[i], i));
-    } else {
-        const unsigned sm = interior ? 0u : solid_bits(t, nmask, n);
-        if (sm == 0) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                f[i] = ST::ld(dense_at(A, a, kOpp[i], 1 - kCy[i], 1 - kCx[i]), i);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                f[i] = ST::ld(((sm >> i) & 1u) ? dense_at(A, a, i, 1, 1)
-                                               : dense_at(A, a, kOpp[i], 1 - kCy[i], 1 - kCx[i]),
-                              i);
-        }
-        if (OPEN && open)
-            apply_open<R, ST::kShift>(f, open, bc_val + 2 * (size_t)n);
-        collide<R, DRAG, ST::kShift, FORCE, ST::kExact, TRT, MRT>(f, omega, gx, gy,
-                                                             DRAG ? (R)alpha[n] : R(0), rt);
-        // x + c_i is node x - c_opp(i): solid iff bit opp(i) is set
-        if (sm == 0) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                store_nt(&dense_at(A, a, i, 1 + kCy[i], 1 + kCx[i]), ST::st(f[i], i));
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                store_nt(((sm >> kOpp[i]) & 1u) ? &dense_at(A, a, kOpp[i], 1, 1)
-                                                : &dense_at(A, a, i, 1 + kCy[i], 1 + kCx[i]),
-                         ST::st(f[i], i));
-        }
-    }
+    aa_node<ST, PH, ODD>(A, type, nmask, alpha, bc_val, nx, ny, pitch, omega, gx, gy, rt, x, y,
+                         seg_interior[L] != 0);
 }
 
 // ------------------------------------------------------------- step: tiled --
@@ -1170,6 +1267,16 @@ inline int dense_ab_cap(size_t esize, double interior)
         return 0;
     return esize == 8 ? 4 : esize == 4 ? 6 : 0;
 }
+// The odd AA step through LDS (measured at 4096^2, AA step pairs): FP64 at 3
+// workgroups per CU 398 us per step against 412 us uncapped (414 us with the
+// per-node odd kernel), FP32 at 6 190 against 193 us (207 us); 16-bit storage
+// uncapped (108 against 120 us).
+inline int dense_aa_odd_cap(size_t esize, double interior)
+{
+    if (interior < 0.9)
+        return 0;
+    return esize == 8 ? 3 : esize == 4 ? 6 : 0;
+}
 inline int dense_aa_cap(size_t esize, double interior)
 {
     if (interior < 0.9)
@@ -1231,7 +1338,18 @@ void step_launch(const DevState &s, int64_t t, int cur)
             }
         } else {
             const uint32_t dyn = occupancy_cap_lds(dense_aa_cap(sizeof(M), s.interior_frac), 0u);
-            if (t & 1)
+            const bool small = 18.0 * (double)s.plane * sizeof(M) < 128.0 * (1 << 20);
+            if ((t & 1) && !small) {
+                // odd steps of large lattices through LDS
+                const DenseArgs<ST> k{nullptr, (M *)s.f[0], s.type, s.nmask, s.seg_interior,
+                                      s.alpha, s.bc_val, s.nx, s.ny, s.pitch, bpr, nblocks,
+                                      om, gx, gy, omm, 0};
+                const uint32_t lds = 9u * (kBlock + 2u * (16u / (uint32_t)sizeof(M))) *
+                                     (uint32_t)sizeof(M);
+                const uint32_t dl =
+                    occupancy_cap_lds(dense_aa_odd_cap(sizeof(M), s.interior_frac), lds);
+                k_step_dense_aa_odd<ST, PH><<<nblocks, kBlock, dl, s.stream>>>(k);
+            } else if (t & 1)
                 k_step_dense_aa<ST, PH, true><<<nblocks, kBlock, dyn, s.stream>>>(
                     (M *)s.f[0], s.type, s.nmask, s.seg_interior, s.alpha, s.bc_val, s.nx,
                     s.ny, s.pitch, bpr, nblocks, om, gx, gy, omm);

@@ -16,7 +16,8 @@ Compared with the FP64 oracle over the whole lattice after 12 steps: BGK with bo
 drag field, TRT, MRT, open boundaries between walls, and full-way walls (FP64 max abs 1e-12,
 FP32 max relative 1e-5, as everywhere; wall slots included for full-way).  16-bit storage
 (two rows per workgroup): bitwise equal to the indirect layout's kernel (one collision
-function) at 2000 x 1901, whose last row pair holds a single row.
+function) at 2000 x 1901, whose last row pair holds a single row.  The AA layout's odd
+step runs the same staging (its own kernel) and is compared with the oracle after 13 steps.
 """
 import numpy as np
 import pytest
@@ -70,7 +71,7 @@ def _setup(case, nx, ny):
     return m, bc, val, fields, alpha, g
 
 
-def _run_gpu(lbm, case, m, bc, val, fields, alpha, g, dtype, layout="dense_ab"):
+def _run_gpu(lbm, case, m, bc, val, fields, alpha, g, dtype, layout="dense_ab", steps=STEPS):
     lat = lbm.Lattice(m, 0.7, force=g, dtype=dtype, layout=layout)
     if case == "trt":
         lat.set_trt(3.0 / 16.0)
@@ -83,13 +84,13 @@ def _run_gpu(lbm, case, m, bc, val, fields, alpha, g, dtype, layout="dense_ab"):
     lat.init_equilibrium(*fields)
     if alpha is not None:
         lat.set_porosity(alpha)
-    lat.step(STEPS)
+    lat.step(steps)
     f = lat.get_populations()
     lat.close()
     return f
 
 
-def _run_oracle(oracle_mod, case, m, bc, val, fields, alpha, g):
+def _run_oracle(oracle_mod, case, m, bc, val, fields, alpha, g, steps=STEPS):
     f0 = oracle_mod.init(m, *fields, bc=bc, value=val)
     if case == "fullway":
         f0 = oracle_mod.fullway_fill(m, f0)
@@ -99,7 +100,7 @@ def _run_oracle(oracle_mod, case, m, bc, val, fields, alpha, g):
         kw["tau_minus"] = oracle_mod.trt_tau_minus(0.7, 3.0 / 16.0)
     if case == "mrt":
         kw["mrt"] = RATES
-    return oracle_mod.run(m, f0, 0.7, STEPS, g=g, alpha=a64, bc=bc, value=val,
+    return oracle_mod.run(m, f0, 0.7, steps, g=g, alpha=a64, bc=bc, value=val,
                           fullway=case == "fullway", **kw)
 
 
@@ -126,6 +127,22 @@ def test_segment_kernel_vs_oracle(lbm, oracle_mod, dtype, case):
         err = fp_error_w(got, ref, m, dtype)
     else:
         err = fp_error(got, ref, m, dtype)
+    print(f"max error {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["force_drag", "mrt", "open_walls"])
+def test_segment_kernel_aa_vs_oracle(lbm, oracle_mod, dtype, case):
+    """The AA layout's odd step through LDS (the same segment staging, reading A_opp(i) from
+    x - c_i, writing A_i(x + c_i)) on the same geometry, 13 steps (ending on an odd step)."""
+    nx, ny = SHAPES[dtype]
+    assert _selects_segment_kernel(nx, ny, dtype)
+    announce(f"segment kernel AA {nx}x{ny} {dtype} {case}")
+    m, bc, val, fields, alpha, g = _setup(case, nx, ny)
+    got = _run_gpu(lbm, case, m, bc, val, fields, alpha, g, dtype, layout="dense_aa", steps=13)
+    ref = _run_oracle(oracle_mod, case, m, bc, val, fields, alpha, g, steps=13)
+    err = (fp_error_w if case == "open_walls" else fp_error)(got, ref, m, dtype)
     print(f"max error {err:.3e}")
     assert err <= TOL[dtype]
 
