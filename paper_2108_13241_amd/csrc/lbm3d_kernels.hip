@@ -578,23 +578,19 @@ __device__ __forceinline__ void local3(const typename ST::mem *s, const Addr &a,
         f[i] = ST::ld(elem(sp, a, i, 1, 1, 1), i);
 }
 
+// One node of the AA step (row r = z * ny + y); interior: its 256-node row
+// segment holds interior fluid nodes only.
 template <class ST, bool FORCE, bool TRT, bool MRT, bool ODD>
-__global__ __launch_bounds__(kBlock) void k_step3_aa(
+__device__ __forceinline__ void step3_aa_node(
     typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
-    const uint32_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior, int nx, int ny,
-    int nz, int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega,
-    typename ST::real gx, typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt)
+    const uint32_t *__restrict__ nmask, bool interior, int x, int y, int z, uint32_t r, int nx,
+    int ny, int nz, int pitch, typename ST::real omega, typename ST::real gx,
+    typename ST::real gy, typename ST::real gz, const Rates3<typename ST::real> &rt)
 {
     using R = typename ST::real;
-    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
-    const uint32_t r = L / bpr;  // row index z * ny + y
-    const int x = (int)(L - r * bpr) * kBlock + (int)threadIdx.x;
-    if (x >= nx)
-        return;
-    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
     const uint32_t n = r * (uint32_t)pitch + (uint32_t)x;
     uint32_t sm = 0;
-    if (!seg_interior[L]) {
+    if (!interior) {
         const uint8_t t = type[n];
         if (t == kSolid)
             return;
@@ -618,6 +614,109 @@ __global__ __launch_bounds__(kBlock) void k_step3_aa(
         for (int i = 0; i < Q; ++i)
             store_nt(&elem(A, a, kOpp[i], 1, 1, 1), ST::st(f[i], i));
     }
+}
+
+template <class ST, bool FORCE, bool TRT, bool MRT, bool ODD>
+__global__ __launch_bounds__(kBlock) void k_step3_aa(
+    typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
+    const uint32_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior, int nx, int ny,
+    int nz, int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega,
+    typename ST::real gx, typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt)
+{
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t r = L / bpr;  // row index z * ny + y
+    const int x = (int)(L - r * bpr) * kBlock + (int)threadIdx.x;
+    if (x >= nx)
+        return;
+    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
+    step3_aa_node<ST, FORCE, TRT, MRT, ODD>(A, type, nmask, seg_interior[L] != 0, x, y, z, r, nx,
+                                            ny, nz, pitch, omega, gx, gy, gz, rt);
+}
+
+// Odd AA step through LDS (the staging of k_step3_lds applied to the AA read
+// pattern): for each direction i the segment's values A_opp(i) of row
+// (y - c_i.y, z - c_i.z), columns x0 - c_i.x .., go into LDS with aligned
+// 16-byte loads; after one barrier every lane reads its 19 sources and writes
+// f_i to A_i(x + c_i) directly.  Loaded elements that this segment does not use
+// may be rewritten meanwhile by the neighbouring segment (their only reader and
+// writer is a node there); every element it uses is read and written by its
+// own node only.  Other segments run the per-node AA step.
+template <class ST, bool FORCE, bool TRT, bool MRT>
+__global__ __launch_bounds__(kBlock) void k_step3_aa_odd(
+    typename ST::mem *__restrict__ A, const uint8_t *__restrict__ type,
+    const uint32_t *__restrict__ nmask, const uint32_t *__restrict__ seg_interior, int nx, int ny,
+    int nz, int pitch, uint32_t bpr, uint32_t nblocks, typename ST::real omega,
+    typename ST::real gx, typename ST::real gy, typename ST::real gz, Rates3<typename ST::real> rt)
+{
+    using R = typename ST::real;
+    using M = typename ST::mem;
+    constexpr uint32_t kE = 16u / (uint32_t)sizeof(M);
+    constexpr uint32_t kVpc = kChunk / kE;
+    constexpr uint32_t kV = Q * 4u * kVpc;
+    constexpr uint32_t kRow = kBlock + 2u * kE;
+    __shared__ __align__(16) M stage[Q][kRow];
+    const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t r = L / bpr;  // row index z * ny + y
+    const int x0 = (int)(L - r * bpr) * kBlock;
+    const int x = x0 + (int)threadIdx.x;
+    const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
+    const bool inner = seg_interior[L] != 0;
+    if (!inner || x0 + kBlock > nx) {
+        if (x < nx)
+            step3_aa_node<ST, FORCE, TRT, MRT, true>(A, type, nmask, inner, x, y, z, r, nx, ny,
+                                                     nz, pitch, omega, gx, gy, gz, rt);
+        return;
+    }
+    constexpr uint32_t PX = dir_bits(kCx, 1), NX = dir_bits(kCx, -1);
+    constexpr uint32_t PY = dir_bits(kCy, 1), NY = dir_bits(kCy, -1);
+    constexpr uint32_t PZ = dir_bits(kCz, 1), NZ = dir_bits(kCz, -1);
+    const uint32_t cpr = (uint32_t)pitch / kChunk;
+    const uint64_t rowel = (uint64_t)cpr * (Q * kChunk);
+    auto src_row = [=](uint32_t i) -> uint64_t {
+        int ys = y - comp_of(PY, NY, i), zs = z - comp_of(PZ, NZ, i);
+        ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+        zs += zs < 0 ? nz : (zs >= nz ? -nz : 0);
+        return ((uint64_t)(uint32_t)zs * (uint32_t)ny + (uint32_t)ys) * rowel;
+    };
+    // opp(i) of a runtime index: the pairs (1, 2), (3, 4), .., (17, 18)
+    auto dopp = [](uint32_t i) { return i == 0 ? 0u : ((i - 1u) ^ 1u) + 1u; };
+    const uint32_t c0 = (uint32_t)x0 >> 6;
+    M hv = M(0);
+    const uint32_t hi = threadIdx.x;
+    const int hcx = hi < (uint32_t)Q ? comp_of(PX, NX, hi) : 0;
+    if (hcx != 0) {
+        const int xs = hcx > 0 ? wrap_dec(x0, nx) : wrap_inc(x0 + kBlock - 1, nx);
+        hv = A[src_row(hi) + (uint64_t)dopp(hi) * kChunk + col_off(xs)];
+    }
+    constexpr uint32_t kIter = (kV + kBlock - 1) / kBlock;
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u vv[kIter];
+    uint32_t dst_el[kIter];
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m) {
+        const uint32_t q = min(threadIdx.x + m * kBlock, kV - 1u);
+        const uint32_t i = q / (4u * kVpc), rr = q - i * (4u * kVpc);
+        const uint32_t cc = rr / kVpc, pc = rr - cc * kVpc;
+        const uint64_t off = src_row(i) + (uint64_t)(c0 + cc) * (Q * kChunk) +
+                             (uint64_t)dopp(i) * kChunk + (uint64_t)pc * kE;
+        vv[m] = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(A + off));
+        dst_el[m] = i * kRow + kE + cc * kChunk + pc * kE;
+    }
+#pragma unroll
+    for (uint32_t m = 0; m < kIter; ++m)
+        *reinterpret_cast<v4u *>(&stage[0][0] + dst_el[m]) = vv[m];
+    if (hcx != 0)
+        stage[hi][hcx > 0 ? kE - 1 : kE + kBlock] = hv;
+    __syncthreads();
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        f[i] = ST::ld(stage[i][(int)kE + (int)threadIdx.x - kCx[i]], i);
+    collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
+    const Addr a = addr_of(x, y, z, nx, ny, nz, cpr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        store_nt(&elem(A, a, i, 1 + kCz[i], 1 + kCy[i], 1 + kCx[i]), ST::st(f[i], i));
 }
 
 // INDIRECT (node list): element of direction i of list node n in the chunked
@@ -1284,6 +1383,16 @@ inline int step3_lds_cap(const State3 &s, size_t esize)
     return 0;
 }
 
+// The odd AA step through LDS, measured at 256^3 (AA step pairs): FP64 at 2
+// workgroups per CU 923 us per step (933 uncapped, 943 with the per-node odd
+// kernel), FP32 at 4 454 us (457, 464); 16-bit uncapped 238 us (247).
+inline int step3_aa_odd_cap(const State3 &s, size_t esize)
+{
+    if (esize == 2 || s.interior_frac < 0.9)
+        return 0;
+    return esize == 8 ? 2 : 4;
+}
+
 template <class ST, bool TRT, bool MRT>
 void step_launch3(const State3 &s, int cur)
 {
@@ -1331,17 +1440,26 @@ void step_launch3(const State3 &s, int cur)
     }
     if (s.aa) {
         M *A = (M *)s.f[0];
-        auto go = [&](auto kernel) {
-            kernel<<<nb, kBlock, dyn, s.stream>>>(A, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
-                                                s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1],
-                                                g[2], rt);
+        auto go = [&](auto kernel, uint32_t dl) {
+            kernel<<<nb, kBlock, dl, s.stream>>>(A, s.type, s.nmask, s.seg_interior, s.nx, s.ny,
+                                               s.nz, s.pitch, bpr, nb, (R)s.omega, g[0], g[1],
+                                               g[2], rt);
         };
-        if (force)
-            cur ? go(k_step3_aa<ST, true, TRT, MRT, true>)
-                : go(k_step3_aa<ST, true, TRT, MRT, false>);
-        else
-            cur ? go(k_step3_aa<ST, false, TRT, MRT, true>)
-                : go(k_step3_aa<ST, false, TRT, MRT, false>);
+        // odd steps of large lattices through LDS (as for the A-B step)
+        const bool lds = 38.0 * (double)s.nz * s.ny * s.pitch * sizeof(M) >= 128.0 * (1 << 20);
+        if (cur && lds) {
+            const uint32_t st =
+                Q * (kBlock + 2u * (16u / (uint32_t)sizeof(M))) * (uint32_t)sizeof(M);
+            const uint32_t dl = lbm::occupancy_cap_lds(step3_aa_odd_cap(s, sizeof(M)), st);
+            force ? go(k_step3_aa_odd<ST, true, TRT, MRT>, dl)
+                  : go(k_step3_aa_odd<ST, false, TRT, MRT>, dl);
+        } else if (force) {
+            cur ? go(k_step3_aa<ST, true, TRT, MRT, true>, dyn)
+                : go(k_step3_aa<ST, true, TRT, MRT, false>, dyn);
+        } else {
+            cur ? go(k_step3_aa<ST, false, TRT, MRT, true>, dyn)
+                : go(k_step3_aa<ST, false, TRT, MRT, false>, dyn);
+        }
         return;
     }
     const M *src = (const M *)s.f[cur];

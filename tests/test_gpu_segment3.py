@@ -13,6 +13,8 @@ all-interior while rows through the box mix both paths.  Compared with the FP64 
 over the whole lattice after 5 steps: BGK with a body force along all three axes, TRT, MRT and
 full-way walls (FP64 max abs 1e-12, FP32 max relative 1e-5, as everywhere; wall slots included
 for full-way).  16-bit storage: bitwise equal to the node-list layout (one collision function).
+The AA layout's odd step runs the same staging (its own kernel): oracle parity after an odd
+step count, and 16-bit bitwise equality with the node list.
 """
 import numpy as np
 import pytest
@@ -101,13 +103,30 @@ def test_segment3_vs_oracle(lbm, oracle_mod, dtype, case):
     assert err <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["bgk_force", "trt"])
+def test_segment3_aa_vs_oracle(lbm, oracle_mod, dtype, case):
+    """The AA layout's odd step through LDS (reads A_opp(i) from x - c_i, writes A_i(x + c_i)),
+    5 steps (ending on an odd step, whose canonical view is the odd read)."""
+    shape = SHAPES[dtype]
+    assert _selects_segment_kernel(*shape, dtype)
+    announce(f"d3q19 segment kernel AA {shape} {dtype} {case}")
+    m, fields = _setup(shape)
+    got = _run_gpu(lbm, m, fields, dtype, case, layout="dense_aa")
+    kw = {"tau_minus": oracle_mod.trt_tau_minus(0.7, 0.25)} if case == "trt" else {}
+    ref = oracle_mod.run3(m, oracle_mod.init3(m, *fields), 0.7, STEPS, g=G, **kw)
+    err = fp_error(got, ref, m, dtype)
+    print(f"max error {err:.3e}")
+    assert err <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
-@pytest.mark.parametrize("case", ["bgk_force", "mrt"])
+@pytest.mark.parametrize("case", ["bgk_force", "mrt", "aa"])
 def test_segment3_16bit_bitwise(lbm, dtype, case):
     shape = SHAPES[dtype]
     assert _selects_segment_kernel(*shape, dtype)
     announce(f"d3q19 segment kernel {shape} {dtype} {case} bitwise vs node list")
     m, fields = _setup(shape)
-    a = _run_gpu(lbm, m, fields, dtype, case)
+    a = _run_gpu(lbm, m, fields, dtype, case, layout="dense_aa" if case == "aa" else "dense_ab")
     b = _run_gpu(lbm, m, fields, dtype, case, layout="indirect")
     assert np.array_equal(a, b)
