@@ -75,7 +75,9 @@ typedef enum {
  *             tiles, empty ones included, in row-major tile order, run by the
  *             TILED16 kernels (memory and launch cover every tile).  Reported
  *             as TILED16_ALL by lbm_get_info.  Requires nx and ny to be
- *             multiples of 16. */
+ *             multiples of 16.
+ * The D3Q19 interface (lbm3d.h) takes TILED16 / TILED16_ALL as its tiled
+ * layout in 4 x 4 x 4-node blocks (nx, ny, nz multiples of 4). */
 typedef enum {
     LBM_DENSE_AB = 0,
     LBM_DENSE_AA = 1,
