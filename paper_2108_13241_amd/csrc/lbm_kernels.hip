@@ -1301,13 +1301,15 @@ void step_launch(const DevState &s, int64_t t, int cur)
                             s.nx,  s.ny, s.pitch, bpr,   nblocks,        om,      gx,
                             gy,    omm,  s.fullway};
             // Kernel choice (measured): the per-node kernel while a step moves less
-            // than 128 MiB (latency-bound: 1024 x 256 FP32 forward 4.8 us against
-            // 5.6 us through LDS); for 16-bit MRT on lattices with many boundary
-            // segments the two-row kernel without LDS (at 4096^2, against the
-            // one-row LDS kernel: 109 against 123 us); the LDS-staged kernel
-            // otherwise (16-bit MRT on interior lattices, two rows through LDS:
-            // 111 against 113 us).
-            const bool small = 18.0 * (double)s.plane * sizeof(M) < 128.0 * (1 << 20);
+            // than 32 MiB (latency-bound: 1024 x 256 FP32 forward, 19 MB, 4.5 us
+            // against 5.7 us through LDS; 512^2 FP32, 19 MB, 60.8 against 57.5
+            // GLUPS; from 38 MB on the LDS kernel wins: 512^2 FP64 37.9 against
+            // 31.5 GLUPS, 1024^2 FP32 67.8 against 62.5, 1448^2 FP16 123 against
+            // 110); for 16-bit MRT on lattices with many boundary segments the
+            // two-row kernel without LDS (at 4096^2, against the one-row LDS
+            // kernel: 109 against 123 us); the LDS-staged kernel otherwise (16-bit
+            // MRT on interior lattices, two rows through LDS: 111 against 113 us).
+            const bool small = 18.0 * (double)s.plane * sizeof(M) < 32.0 * (1 << 20);
             if (small || (ST::kAligned && (PH & kMRT) && s.interior_frac < 0.9)) {
                 if constexpr (ST::kAligned) {
                     k.nblocks = bpr * (uint32_t)((s.ny + 1) / 2);
@@ -1338,6 +1340,9 @@ void step_launch(const DevState &s, int64_t t, int cur)
             }
         } else {
             const uint32_t dyn = occupancy_cap_lds(dense_aa_cap(sizeof(M), s.interior_frac), 0u);
+            // the odd AA step goes through LDS from 128 MiB per step on (below, in
+            // the Infinity Cache regime, the per-node kernel measured 8-10 % faster:
+            // 512^2 FP64 AA 38.7 against 34.7 GLUPS, 1024^2 FP16 132 against 122)
             const bool small = 18.0 * (double)s.plane * sizeof(M) < 128.0 * (1 << 20);
             if ((t & 1) && !small) {
                 // odd steps of large lattices through LDS

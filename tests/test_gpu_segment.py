@@ -1,8 +1,8 @@
 """The LDS-staged dense A-B step on lattices large enough to select it, element by element.
 
 The dense A-B launcher picks the LDS-staged segment kernel once a step moves at least
-128 MiB (18 population planes of the padded lattice); smaller lattices run the per-node
-kernel that the other parity tests cover.  Inside the segment kernel, whole all-interior
+32 MiB (18 population planes of the padded lattice), the AA layout's odd step its LDS kernel
+from 128 MiB; smaller lattices run the per-node kernels that the other parity tests cover.  Inside the segment kernel, whole all-interior
 256-node row segments are staged through LDS (with the halo column on either side, which
 wraps around the periodic x edge), and every other segment (solids or solid neighbours, open
 boundary nodes, the row's partial last segment) takes the per-node path.
@@ -33,9 +33,14 @@ BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 RATES = (1.19, 1.4, 1.64)
 
 
-def _selects_segment_kernel(nx, ny, dtype):
+def _step_bytes(nx, ny, dtype):
     pitch = (nx + 63) // 64 * 64
-    return 18 * pitch * ny * BYTES[dtype] >= 128 * 2**20
+    return 18 * pitch * ny * BYTES[dtype]
+
+
+def _selects_segment_kernel(nx, ny, dtype):
+    """Both LDS kernels (A-B from 32 MiB per step, the odd AA step from 128 MiB)."""
+    return _step_bytes(nx, ny, dtype) >= 128 * 2**20
 
 
 @pytest.fixture(scope="module")
@@ -51,7 +56,8 @@ def lbm():
 def _box_mask(nx, ny, seed):
     rng = np.random.default_rng(seed)
     m = np.zeros((ny, nx), np.uint8)
-    m[100:700, 260:500] = (rng.random((600, 240)) < 0.2).astype(np.uint8)
+    box = m[100:700, 260:500]
+    box[...] = (rng.random(box.shape) < 0.2).astype(np.uint8)
     return m
 
 
@@ -127,6 +133,22 @@ def test_segment_kernel_vs_oracle(lbm, oracle_mod, dtype, case):
         err = fp_error_w(got, ref, m, dtype)
     else:
         err = fp_error(got, ref, m, dtype)
+    print(f"max error {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,shape", [("f64", (700, 400)), ("f32", (1000, 600))])
+@pytest.mark.parametrize("case", ["force_drag", "open_walls"])
+def test_segment_kernel_mid_size(lbm, oracle_mod, dtype, shape, case):
+    """Lattices between the two switches (32 to 128 MiB per step): the A-B step through LDS.
+    At ny = 400 / 600 the solid box is cut at the lattice's last row."""
+    nx, ny = shape
+    assert 32 * 2**20 <= _step_bytes(nx, ny, dtype) < 128 * 2**20
+    announce(f"segment kernel mid-size {nx}x{ny} {dtype} {case}")
+    m, bc, val, fields, alpha, g = _setup(case, nx, ny)
+    got = _run_gpu(lbm, case, m, bc, val, fields, alpha, g, dtype)
+    ref = _run_oracle(oracle_mod, case, m, bc, val, fields, alpha, g)
+    err = (fp_error_w if case == "open_walls" else fp_error)(got, ref, m, dtype)
     print(f"max error {err:.3e}")
     assert err <= TOL[dtype]
 
