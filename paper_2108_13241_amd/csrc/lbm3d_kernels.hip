@@ -573,9 +573,12 @@ __device__ __forceinline__ void local3(const typename ST::mem *s, const Addr &a,
 {
     using M = typename ST::mem;
     M *sp = const_cast<M *>(s);
+    // Nontemporal loads: each slot is read once per even step (measured at
+    // 256^3: 3 % shorter AA step pairs in FP64 and FP32; the same hint made the
+    // D2Q9 gathers slower, so they keep plain loads).
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        f[i] = ST::ld(elem(sp, a, i, 1, 1, 1), i);
+        f[i] = ST::ld(lbm::load_nt(&elem(sp, a, i, 1, 1, 1)), i);
 }
 
 // One node of the AA step (row r = z * ny + y); interior: its 256-node row
@@ -1351,7 +1354,7 @@ __global__ __launch_bounds__(kBlock) void k_rest3(typename ST::mem *p, uint64_t 
 }
 
 // Resident workgroups per CU (0: as many as registers allow), measured at
-// 256^3: the dense and AA steps on mostly interior lattices run faster with
+// 256^3: the per-node dense and AA steps on mostly interior lattices run faster with
 // fewer workgroups in flight (FP32 A-B 433 us at 3 per CU against 453 us
 // uncapped, AA 462 against 476 us; FP64 893 against 904 us, AA 943 against
 // 950 us); the block step on a sphere packing at fluid fraction 0.4 likewise
@@ -1381,6 +1384,17 @@ inline int step3_lds_cap(const State3 &s, size_t esize)
     if (esize == 4 && !s.mrt)
         return s.interior_frac >= 0.9 ? 4 : 3;
     return 0;
+}
+
+// The even AA step (local reads with nontemporal loads, local writes) on
+// mostly interior lattices, measured at 256^3 (AA step pairs with the odd step
+// through LDS): 2 workgroups per CU FP64 891 us per step, FP32 436 us (3: 898,
+// 440; 4: 899, 444; uncapped 899, 452).
+inline int step3_aa_even_cap(const State3 &s, size_t esize)
+{
+    if (esize == 2 || s.interior_frac < 0.9)
+        return 0;
+    return 2;
 }
 
 // The odd AA step through LDS, measured at 256^3 (AA step pairs): FP64 at 2
@@ -1453,12 +1467,14 @@ void step_launch3(const State3 &s, int cur)
             const uint32_t dl = lbm::occupancy_cap_lds(step3_aa_odd_cap(s, sizeof(M)), st);
             force ? go(k_step3_aa_odd<ST, true, TRT, MRT>, dl)
                   : go(k_step3_aa_odd<ST, false, TRT, MRT>, dl);
-        } else if (force) {
-            cur ? go(k_step3_aa<ST, true, TRT, MRT, true>, dyn)
-                : go(k_step3_aa<ST, true, TRT, MRT, false>, dyn);
         } else {
-            cur ? go(k_step3_aa<ST, false, TRT, MRT, true>, dyn)
-                : go(k_step3_aa<ST, false, TRT, MRT, false>, dyn);
+            const uint32_t de = lbm::occupancy_cap_lds(step3_aa_even_cap(s, sizeof(M)), 0u);
+            if (force)
+                cur ? go(k_step3_aa<ST, true, TRT, MRT, true>, dyn)
+                    : go(k_step3_aa<ST, true, TRT, MRT, false>, de);
+            else
+                cur ? go(k_step3_aa<ST, false, TRT, MRT, true>, dyn)
+                    : go(k_step3_aa<ST, false, TRT, MRT, false>, de);
         }
         return;
     }

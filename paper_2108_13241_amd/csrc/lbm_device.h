@@ -570,4 +570,17 @@ __device__ __forceinline__ void store_nt<__bf16>(__bf16 *p, __bf16 v)
     __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short *)p);
 }
 
+// Streaming load (nontemporal hint), for populations that a kernel reads once
+// and nothing reuses from the cache.
+template <class T>
+__device__ __forceinline__ T load_nt(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+template <>
+__device__ __forceinline__ __bf16 load_nt<__bf16>(const __bf16 *p)
+{
+    return __builtin_bit_cast(__bf16, __builtin_nontemporal_load((const unsigned short *)p));
+}
+
 }  // namespace lbm
