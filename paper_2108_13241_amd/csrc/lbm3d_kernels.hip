@@ -717,9 +717,21 @@ __global__ __launch_bounds__(kBlock) void k_step3_aa_odd(
         f[i] = ST::ld(stage[i][(int)kE + (int)threadIdx.x - kCx[i]], i);
     collide3<R, ST::kShift, FORCE, TRT, MRT>(f, omega, gx, gy, gz, rt);
     const Addr a = addr_of(x, y, z, nx, ny, nz, cpr);
+    // The ten directions with c_x != 0 store runs shifted by one element, so two
+    // wavefronts share each 64-element run.  With 16- and 32-bit storage these
+    // stores go through the cache without the streaming hint, which lets the
+    // halves meet there (256^3 AA step pairs: FP32 436.0 -> 425.3 us, FP16 233.3
+    // -> 228.4 us); FP64 keeps the hint (889.1 against 891.5 us).  The D2Q9 odd
+    // step measured slower without it at every storage type.
+    // (Two separate store expressions: one shared pointer let the compiler
+    // merge the branches' stores and drop the hint from all of them.)
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        store_nt(&elem(A, a, i, 1 + kCz[i], 1 + kCy[i], 1 + kCx[i]), ST::st(f[i], i));
+    for (int i = 0; i < Q; ++i) {
+        if (sizeof(M) == 8 || kCx[i] == 0)
+            store_nt(&elem(A, a, i, 1 + kCz[i], 1 + kCy[i], 1 + kCx[i]), ST::st(f[i], i));
+        else
+            elem(A, a, i, 1 + kCz[i], 1 + kCy[i], 1 + kCx[i]) = ST::st(f[i], i);
+    }
 }
 
 // INDIRECT (node list): element of direction i of list node n in the chunked

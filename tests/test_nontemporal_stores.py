@@ -7,6 +7,10 @@ compiler transformations can drop it (a restructured loop once lost it on the FP
 kernel's LDS path, 8 % slower): this test compiles the step-kernel sources for gfx950 to
 assembly (host-side cross compilation, no GPU) and checks each `global_store` in the
 functions named k_step*.
+
+One deliberate exception: the D3Q19 AA odd step through LDS with 16- or 32-bit storage
+writes its ten directions with c_x != 0 (runs shifted by one element, each 64-element run
+shared by two wavefronts) without the hint, so exactly ten of its stores are plain.
 """
 import os
 import re
@@ -33,15 +37,25 @@ def test_step_kernel_stores_are_nontemporal(tmp_path, src):
                    check=True, capture_output=True)
     asm = out.read_text()
     checked = 0
+    excepted = 0
     bad = []
     for m in re.finditer(r"^(_Z\S*k_step\S*):", asm, re.M):
         name = m.group(1)
         end = asm.index(".Lfunc_end", m.end())
+        plain = []
         for line in asm[m.end():end].split("\n"):
             ins = line.strip()
             if ins.startswith("global_store"):
                 checked += 1
                 if not re.search(r"\bnt\b", ins):
-                    bad.append((name, ins))
+                    plain.append((name, ins))
+        if "k_step3_aa_odd" in name and "Shifted" in name:
+            excepted += 1
+            if len(plain) != 10:
+                bad.append((name, f"{len(plain)} plain stores, expected the 10 with c_x != 0"))
+        else:
+            bad.extend(plain)
     assert checked > 0
+    if src == "lbm3d_kernels.hip":
+        assert excepted > 0
     assert not bad, bad[:5]
