@@ -1370,15 +1370,18 @@ __global__ __launch_bounds__(kBlock) void k_rest3(typename ST::mem *p, uint64_t 
 // fewer workgroups in flight (FP32 A-B 433 us at 3 per CU against 453 us
 // uncapped, AA 462 against 476 us; FP64 893 against 904 us, AA 943 against
 // 950 us); the block step on a sphere packing at fluid fraction 0.4 likewise
-// (FP64 482 against 495 us at 3, FP32 271 against 274 us at 5).  16-bit
-// storage gains nothing.
+// (FP64 482 against 495 us at 3, FP32 271 against 274 us at 5), and the
+// node-list step there (FP64 406.2 against 410.5 us at 3, FP32 227.7 against
+// 230.9 us at 5; 4: 408.8, 228.4).  16-bit storage gains nothing.
 inline int step3_cap(const State3 &s, size_t esize)
 {
     if (esize == 2)
         return 0;
     if (s.blocks)
         return esize == 8 ? 3 : 5;
-    if (s.list || s.interior_frac < 0.9)
+    if (s.list)
+        return esize == 8 ? 3 : 5;
+    if (s.interior_frac < 0.9)
         return 0;
     return 3;
 }
@@ -1454,7 +1457,7 @@ void step_launch3(const State3 &s, int cur)
         const M *src = (const M *)s.f[cur];
         M *dst = (M *)s.f[1 - cur];
         auto go = [&](auto kernel) {
-            kernel<<<nbl, kBlock, 0, s.stream>>>(src, dst, list_table(s), (uint32_t)s.n_fluid,
+            kernel<<<nbl, kBlock, dyn, s.stream>>>(src, dst, list_table(s), (uint32_t)s.n_fluid,
                                                  nbl, (R)s.omega, g[0], g[1], g[2], rt,
                                                  s.fullway);
         };
