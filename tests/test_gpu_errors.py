@@ -1,4 +1,4 @@
-"""Failure handling through the C ABI on a GPU machine: every rejected call returns its documented
+"""Failure handling through the C ABI on a GPU: every rejected call returns its documented
 status, leaves the context usable, and no kernel is launched with bad arguments."""
 import ctypes
 
