@@ -14,7 +14,8 @@ over the whole lattice after 5 steps: BGK with a body force along all three axes
 full-way walls (FP64 max abs 1e-12, FP32 max relative 1e-5, as everywhere; wall slots included
 for full-way).  16-bit storage: bitwise equal to the node-list layout (one collision function).
 The AA layout's odd step runs the same staging (its own kernel): oracle parity after an odd
-step count, and 16-bit bitwise equality with the node list.
+step count, and 16-bit bitwise equality with the node list.  16-bit MRT stages two y rows per
+workgroup (its own kernel); an odd ny case covers the single last row.
 """
 import numpy as np
 import pytest
@@ -130,3 +131,17 @@ def test_segment3_16bit_bitwise(lbm, dtype, case):
     a = _run_gpu(lbm, m, fields, dtype, case, layout="dense_aa" if case == "aa" else "dense_ab")
     b = _run_gpu(lbm, m, fields, dtype, case, layout="indirect")
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
+def test_segment3_16bit_mrt_two_rows_odd_ny(lbm, dtype):
+    """16-bit MRT on a mostly interior lattice runs two y rows per workgroup; with ny odd the
+    last row of every z plane is a pair of one (per-node path).  Bitwise equal to the node list."""
+    shape = (300, 97, 64)
+    assert _selects_segment_kernel(*shape, dtype)
+    announce(f"d3q19 two-row segment kernel {shape} {dtype} mrt bitwise vs node list")
+    m, fields = _setup(shape)
+    a = _run_gpu(lbm, m, fields, dtype, "mrt", layout="dense_ab")
+    b = _run_gpu(lbm, m, fields, dtype, "mrt", layout="indirect")
+    assert np.array_equal(a, b)
+
